@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the SFMM gravity solve on one MI355X.
+
+Workload: one n = 1.5 polytrope (Lane-Emden, R = 1, M = 1) of 10^6 equal-mass
+particles, softening lengths from the 58th nearest neighbour, FP64, expansion
+order p = 3, opening angle 0.5, leaf size 10.  A step is one full solve --
+keys, sort, tree, moments, per-leaf walk, M2L/L2L/L2P, P2P, output and the
+momentum reduction -- with the inputs already resident in HBM.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" fields for the
+dominant kernel's fraction of the chip's peak and the CPU oracle's rate).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle gravity evals/sec (SFMM, N=1e6, theta=0.5); serving p50/p99 latency"
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs x 128 flop/clk x 2.4 GHz)
+P2P_FLOPS_PER_PAIR = 22      # far-pair branch of the P2P kernel (FMA = 2, rsqrt = 1)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--order", type=int, default=3)
+    ap.add_argument("--leaf-size", type=int, default=10)
+    ap.add_argument("--cpu-leaves", type=int, default=1500,
+                    help="leaves the CPU oracle walks for the baseline and the parity sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "a multi-GPU solve is not part of it.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_05804_amd as sfmm
+    import workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    log(f"generating polytrope N={args.n}")
+    x, m, h = workloads.polytrope(args.n, seed=2)
+    xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
+    solver = sfmm.Solver(leaf_size=args.leaf_size)
+    acc = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty((args.n,), dtype=torch.float64, device="cuda")
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        solver.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot)
+    torch.cuda.synchronize()
+    st = solver.stats()
+    log(f"timed {args.steps} steps")
+    solver.timing_start(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = solver.timing_stop()
+    dt = (t1 - t0) / args.steps
+    value = args.n / dt
+    st = solver.stats()
+    mom = float(np.linalg.norm(st["momentum"]) / st["momentum_abs"])
+    ph_mean = {k: float(np.mean([p[k] for p in phases])) for k in sfmm.PHASES}
+    log("phase ms: " + ", ".join(f"{k}={v:.3f}" for k, v in ph_mean.items()))
+
+    # algorithmic work of the arithmetic kernels
+    p = args.order
+    far_flops = (st["n_m2l"] * (sfmm.FLOPS["m2l"][p] + 1) + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
+                 + args.n * sfmm.FLOPS["l2p"][p])
+    near_flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR
+    work = {"far": far_flops, "near": near_flops}
+    dom = max(("far", "near"), key=lambda k: ph_mean[k])
+    achieved = work[dom] / (ph_mean[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": {"far": "k_far (M2L+L2L+L2P)",
+                                           "near": "k_near (P2P)"}[dom],
+                "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": work[dom]}
+    per_phase = {k: {"ms": round(v, 4)} for k, v in ph_mean.items()}
+    for k in ("far", "near"):
+        tf = work[k] / (ph_mean[k] * 1e-3) / 1e12
+        per_phase[k].update(tflops=round(tf, 3), frac=round(tf / PEAK_FP64_TFLOPS, 4))
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"n=1.5 polytrope, N={args.n}, h from 58 neighbours, seed 2",
+                   "N": args.n, "theta": args.theta, "order": p, "leaf_size": args.leaf_size,
+                   "precision": "fp64", "G": 1.0, "r_kern": 2.0},
+        "roofline": roofline,
+        "phases": per_phase,
+        "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l", "n_l2l",
+                                      "n_p2p_leaf_pairs", "n_p2p_pairs")},
+        "momentum_residual": mom,
+    }
+
+    if not args.no_cpu:
+        import oracle
+
+        a_gpu = acc.cpu().numpy()
+        p_gpu = pot.cpu().numpy()
+        log("cpu oracle: tree build")
+        c0 = time.perf_counter()
+        t = oracle.Tree(x, m, h, leaf_size=args.leaf_size, order=p)
+        c1 = time.perf_counter()
+        rng = np.random.default_rng(0)
+        nl = t.num_leaves
+        leaves = t.leaves()
+        pick = rng.choice(nl, min(args.cpu_leaves, nl), replace=False)
+        nd = t.nodes()
+        perm = t.perm()
+        tg = perm[nd["lo"][leaves[pick]]]  # one particle per picked leaf
+        log(f"cpu oracle: {len(pick)} leaves")
+        c2 = time.perf_counter()
+        oa, op, ost = t.solve(args.theta, targets=tg)
+        c3 = time.perf_counter()
+        per_leaf = (c3 - c2) / max(ost["n_leaves_done"], 1)
+        t_full = (c1 - c0) + per_leaf * nl
+        nb = np.linalg.norm(oa, axis=1)
+        err = np.linalg.norm(a_gpu[tg] - oa, axis=1) / nb
+        perr = np.abs(p_gpu[tg] - op) / np.abs(op)
+        result["cpu_baseline"] = {
+            "value": args.n / t_full, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": (f"serial FP64 oracle: full tree + moments for all {args.n} particles "
+                       f"({c1 - c0:.1f} s) plus the per-leaf walk/M2L/L2L/L2P/P2P of "
+                       f"{ost['n_leaves_done']} random leaves ({c3 - c2:.1f} s), "
+                       f"extrapolated to all {nl} leaves")}
+        result["parity_sample"] = {"targets": int(len(tg)), "max_rel_acc_err": float(err.max()),
+                                   "max_rel_pot_err": float(perr.max())}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

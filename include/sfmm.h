@@ -1,0 +1,168 @@
+/*
+ * sfmm.h -- C ABI of libsfmm.so, the MI355X (gfx950) symmetric fast multipole
+ * (SFMM) gravity solve with adaptive cubic-spline softening.
+ *
+ * Method: Bernard, David-Cleris, Price & Lau, "Momentum-conserving
+ * self-gravity in the Phantom SPH code" (arXiv 2602.05804).  One solve
+ * computes, for every particle i,
+ *   acc_i = -G sum_j m_j g_ij (x_i - x_j),   pot_i = -G sum_j m_j psi_ij
+ * (Sect. 2, Eqs. directsum/softdirectsum) approximated as the paper's SFMM:
+ *   - a tree over the particles (here a Morton binary radix tree);
+ *   - node mass moments (Sect. 2.1 Eq. massmom; Appendix A.1 Eq. massmomtrans);
+ *   - for every leaf, the dual tree walk of Sect. 3 (Algorithms 1 and 2): the
+ *     multipole acceptance criterion on the opening angle plus the softening
+ *     criterion on R_kern * max(h_max); accepted node pairs become Cartesian
+ *     M2L interactions (Sect. 2.2, Eq. dmkdeffmm) on the leaf's ancestors,
+ *     rejected leaf pairs become direct softened particle pairs (P2P);
+ *   - the ancestors' field moments are carried down the leaf's branch with
+ *     the translation of Appendix A.2 (Eq. gravmtranslat) and evaluated at
+ *     the particles (L2P).
+ * Every node-node interaction is pairwise, so linear momentum is conserved
+ * to rounding (Newton's third law).
+ *
+ * Conventions shared by every entry point:
+ *   - Particle arrays are DEVICE pointers in the caller's order:
+ *       x   [n][3] row-major FP64 positions,
+ *       m   [n]    FP64 masses (> 0),
+ *       h   [n]    FP64 softening lengths (> 0; kernel support R_kern * h),
+ *       acc [n][3] FP64 accelerations (written),
+ *       pot [n]    FP64 potentials (written).
+ *     The caller owns them; the library never frees or keeps them past a call.
+ *   - The context owns its workspace (tree, lists, expansions).  The
+ *     workspace only grows, is reused by later solves and is released by
+ *     sfmm_destroy.
+ *   - Work is enqueued on the context's HIP stream.  sfmm_solve synchronises
+ *     that stream at two points (to size the tree and the interaction lists)
+ *     and returns once the results are enqueued; they are valid after the
+ *     next synchronisation of the stream.
+ *   - Errors are returned as negative sfmm_status values; no C++ exception
+ *     crosses this boundary.  After an error the outputs are undefined.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef SFMM_H
+#define SFMM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfmm_ctx sfmm_ctx;
+
+typedef enum {
+  SFMM_OK = 0,
+  SFMM_EINVAL = -1,       /* bad argument (sizes, pointers, theta, config)          */
+  SFMM_ENOMEM = -2,       /* device allocation failed                               */
+  SFMM_EDEVICE = -3,      /* a HIP call failed                                      */
+  SFMM_EUNSUPPORTED = -4, /* expansion order or precision not built in              */
+  SFMM_ENONFINITE = -5    /* a position is not finite, or m <= 0, or h <= 0         */
+} sfmm_status;
+
+typedef enum { SFMM_FP64 = 0 } sfmm_precision;
+
+typedef struct {
+  double G;                   /* gravitational constant (default 1)                   */
+  int leaf_size;              /* a node with <= leaf_size particles is a leaf (10)    */
+  double r_kern;              /* kernel support radius in units of h (2, cubic spline) */
+  int include_self_potential; /* add -G m_i psi(0, h_i) to pot_i (1)                  */
+  int check_inputs;           /* validate m, h and positions on the device (1)        */
+} sfmm_config;
+
+/* Solve statistics of the last sfmm_solve on a context (host copy). */
+typedef struct {
+  int64_t n;                /* particles                                            */
+  int64_t num_nodes;        /* tree nodes (internal + leaves)                       */
+  int64_t num_leaves;
+  int32_t max_depth;        /* depth of the deepest leaf (root = 0)                 */
+  int64_t n_m2l;            /* M2L evaluations, replication over leaves included    */
+  int64_t n_l2l;            /* L2L translations carried out down the branches       */
+  int64_t n_p2p_leaf_pairs; /* (target leaf, source leaf) P2P list entries          */
+  int64_t n_p2p_pairs;      /* ordered particle pairs summed directly               */
+  double momentum[3];       /* sum_i m_i acc_i (FP64), valid after a stream sync    */
+  double momentum_abs;      /* sum_i |m_i acc_i|                                    */
+} sfmm_stats;
+
+/* Fill *cfg with the defaults listed above.  Returns SFMM_EINVAL if cfg is NULL. */
+int sfmm_config_default(sfmm_config* cfg);
+
+/* Create a context on HIP device `device` that enqueues its work on
+ * `hip_stream` (a hipStream_t; NULL = the default stream).  cfg may be NULL
+ * (defaults).  On success *out owns nothing yet; the first build allocates. */
+int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config* cfg);
+
+/* Release every device buffer of the context; ctx may be NULL. */
+int sfmm_destroy(sfmm_ctx* ctx);
+
+/* Change the stream later calls enqueue on.  Work enqueued afterwards waits
+ * (on the device, through an event) for the work already queued on the
+ * previous stream, since both use the context's workspace. */
+int sfmm_set_stream(sfmm_ctx* ctx, void* hip_stream);
+
+/* Build the tree of (x, m, h): Morton keys, radix sort, binary radix tree,
+ * node geometry (centre of mass, size, h_max) and mass moments up to
+ * `order` (Sect. 2.1 Eq. massmom via Appendix A.1 Eq. massmomtrans).
+ * n == 0 is a no-op.  Errors: SFMM_EINVAL (n < 0, NULL pointer with n > 0,
+ * n >= 2^30, order outside 0..4), SFMM_ENONFINITE (check_inputs set and an
+ * input is invalid), SFMM_ENOMEM, SFMM_EDEVICE. */
+int sfmm_build(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+               int order);
+
+/* Build, walk and evaluate: acc and pot for every particle (see the header
+ * comment).  theta is the critical opening angle (0 < theta < 1), order the
+ * expansion order p (0..4; p = 3 is the tuned one), precision SFMM_FP64.
+ * n == 0: OK, nothing written.  n == 1: acc = 0, pot = self term only.
+ * Errors: as sfmm_build, plus SFMM_EINVAL for theta outside (0, 1) or a
+ * NULL acc/pot with n > 0, SFMM_EUNSUPPORTED for an unknown precision. */
+int sfmm_solve(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+               double theta, int order, int precision, double* acc, double* pot);
+
+/* Copy the statistics of the last solve (synchronises the stream). */
+int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out);
+
+/* ---- introspection (parity tests): HOST output buffers ----------------
+ * Valid after sfmm_build/sfmm_solve; each call synchronises the stream.
+ * sfmm_get_tree: perm [n] (sorted position -> caller index), keys [n],
+ *   per node lo/cnt (particle range in sorted order), child (index of the
+ *   left child, the right one follows it; -1 for a leaf), parent (-1 for the
+ *   root), geometry s [nn][3], mass, l (size), hmax, and the moments
+ *   Q [nn][ncoef] (ncoef = (p+1)(p+2)(p+3)/6, graded order: degree, then
+ *   the x exponent descending, then the y exponent descending).  Any output
+ *   pointer may be NULL.  Node 0 is the root. */
+int sfmm_get_tree(sfmm_ctx* ctx, int64_t* num_nodes, int64_t* num_leaves, int32_t* perm,
+                  uint64_t* keys, int32_t* lo, int32_t* cnt, int32_t* child, int32_t* parent,
+                  double* s, double* mass, double* l, double* hmax, double* Q);
+/* Leaf node ids in Morton order and their depths (arrays of num_leaves). */
+int sfmm_get_leaves(sfmm_ctx* ctx, int32_t* leaf_node, int32_t* leaf_depth);
+/* Interaction lists of the last solve for leaf index `leaf` (0..num_leaves-1):
+ * M2L entries as (depth of the target ancestor, source node), grouped by
+ * depth, and P2P source leaves.  Returns the counts in *n_m2l / *n_p2p and
+ * copies at most cap_m2l / cap_p2p entries. */
+int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t* m2l_src,
+                        int64_t cap_m2l, int64_t* n_m2l, int32_t* p2p_src, int64_t cap_p2p,
+                        int64_t* n_p2p);
+
+/* ---- phase timing --------------------------------------------------------
+ * Phases of one solve, in order: 0 tree (keys, sort, tree, geometry,
+ * moments), 1 walk count pass, 2 walk fill pass, 3 far field (M2L + L2L +
+ * L2P), 4 near field (P2P + output), 5 momentum reduction.  Between
+ * sfmm_timing_start and sfmm_timing_stop each solve records a pair of HIP
+ * events around every phase on the context's stream (no extra
+ * synchronisation).  sfmm_timing_stop synchronises, writes the durations in
+ * milliseconds to ms[k * SFMM_NUM_PHASES + phase] for the first
+ * min(recorded, cap) solves, stores the number recorded in *nsolves and
+ * frees the events.  Solves beyond max_solves are not timed. */
+#define SFMM_NUM_PHASES 6
+int sfmm_timing_start(sfmm_ctx* ctx, int max_solves);
+int sfmm_timing_stop(sfmm_ctx* ctx, double* ms, int cap, int* nsolves);
+const char* sfmm_phase_name(int phase);
+
+/* Human-readable text of a status code (static storage). */
+const char* sfmm_strerror(int status);
+
+/* Text of the last error on this context (empty when none). */
+const char* sfmm_last_error(const sfmm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,557 @@
+// k_tree.hip -- tree construction on the GPU.
+//
+//   bbox + Morton keys  cubic box, 21-bit cells per axis, x > y > z interleave
+//   radix sort          stable LSD sort of (key, caller index), 8-bit digits
+//   binary radix tree   Karras-style parallel build on the sorted keys; equal
+//                       keys split on the bits of their sorted positions
+//   leaf collapse       a node with <= leaf_size particles is a leaf
+//   geometry + moments  leaves sum their particles; internal nodes combine
+//                       their two children bottom-up (M2M, Appendix A.1)
+//   node size l         largest distance from the centre of mass to a
+//                       particle of the node (read of Sect. 3's l_tgt/l_src)
+//
+// The whole library is compiled with -ffp-contract=off: the centres of mass,
+// sizes and the acceptance test below round exactly as written, so every
+// node-pair decision matches a CPU evaluation of the same formulas.
+#include "sfmm_internal.h"
+
+namespace sfmm {
+namespace {
+
+constexpr int BBOX_THREADS = 256;
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// per-block min/max of each axis; input validation on the side
+__global__ __launch_bounds__(BBOX_THREADS) void k_bbox_partial(int n, const double* __restrict__ x,
+                                                               const double* __restrict__ m,
+                                                               const double* __restrict__ h,
+                                                               double* __restrict__ part,
+                                                               int* status, int check) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int i = blockIdx.x * BBOX_THREADS + threadIdx.x; i < n; i += gridDim.x * BBOX_THREADS) {
+    for (int d = 0; d < 3; ++d) {
+      double v = x[3 * (int64_t)i + d];
+      mn[d] = fmin(mn[d], v);
+      mx[d] = fmax(mx[d], v);
+      if (check && !isfinite(v)) bad = 1;
+    }
+    if (check && !(m[i] > 0.0 && h[i] > 0.0 && isfinite(m[i]) && isfinite(h[i]))) bad = 1;
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
+  __shared__ double sh[6][BBOX_THREADS / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 0; d < 3; ++d) {
+    double a = wave_min(mn[d]), b = wave_max(mx[d]);
+    if (lane == 0) { sh[d][w] = a; sh[3 + d][w] = b; }
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = sh[threadIdx.x][0];
+    for (int k = 1; k < BBOX_THREADS / 64; ++k)
+      v = threadIdx.x < 3 ? fmin(v, sh[threadIdx.x][k]) : fmax(v, sh[threadIdx.x][k]);
+    part[6 * blockIdx.x + threadIdx.x] = v;
+  }
+}
+
+// box[0..2] = min corner, box[3] = cube extent, box[4] = 2^21 / extent (0 if flat)
+__global__ void k_bbox_final(int nb, const double* __restrict__ part, double* __restrict__ box) {
+  if (threadIdx.x != 0) return;
+  double mn[3], mx[3];
+  for (int d = 0; d < 3; ++d) { mn[d] = part[d]; mx[d] = part[3 + d]; }
+  for (int b = 1; b < nb; ++b)
+    for (int d = 0; d < 3; ++d) {
+      mn[d] = fmin(mn[d], part[6 * b + d]);
+      mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
+    }
+  double ext = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double e = mx[d] - mn[d];
+    if (e > ext) ext = e;
+  }
+  for (int d = 0; d < 3; ++d) box[d] = mn[d];
+  box[3] = ext;
+  box[4] = ext > 0.0 ? 2097152.0 / ext : 0.0;
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+__global__ void k_keys(int n, const double* __restrict__ x, const double* __restrict__ box,
+                       uint64_t* __restrict__ key, uint32_t* __restrict__ idx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double scale = box[4];
+  uint64_t c[3] = {0, 0, 0};
+  if (box[3] > 0.0) {
+    for (int d = 0; d < 3; ++d) {
+      double f = floor((x[3 * (int64_t)i + d] - box[d]) * scale);
+      c[d] = f > 2097151.0 ? 2097151ull : (uint64_t)f;
+    }
+  }
+  key[i] = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+  idx[i] = (uint32_t)i;
+}
+
+// ---- radix sort -----------------------------------------------------------
+__global__ __launch_bounds__(RS_THREADS) void k_radix_hist(int n, const uint64_t* __restrict__ key,
+                                                           int shift, uint32_t* __restrict__ hist,
+                                                           int nb) {
+  __shared__ uint32_t cnt[256];
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t i = base + r * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Stable scatter: elements of the tile are ranked in their original order;
+// equal digits inside a wave are found with eight ballots.
+__global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
+    int n, const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
+    const uint32_t* __restrict__ offs, int nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[RS_THREADS / 64][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  run[t] = 0;
+  base[t] = offs[(int64_t)t * nb + blockIdx.x];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    for (int q = 0; q < RS_THREADS / 64; ++q) wc[q][t] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * RS_TILE + r * RS_THREADS + t;
+    const bool valid = i < n;
+    uint64_t k = valid ? kin[i] : 0ull;
+    uint32_t v = valid ? vin[i] : 0u;
+    uint32_t d = (uint32_t)((k >> shift) & 255u);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = base[d] + run[d] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][d];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int q = 0; q < RS_THREADS / 64; ++q) add += wc[q][t];
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+__global__ void k_gather(int n, const uint32_t* __restrict__ perm, const double* __restrict__ x,
+                         const double* __restrict__ m, const double* __restrict__ h,
+                         double* __restrict__ xs, double* __restrict__ ys,
+                         double* __restrict__ zs, double* __restrict__ ms,
+                         double* __restrict__ hs) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = perm[i];
+  xs[i] = x[3 * j];
+  ys[i] = x[3 * j + 1];
+  zs[i] = x[3 * j + 2];
+  ms[i] = m[j];
+  hs[i] = h[j];
+}
+
+// ---- binary radix tree (Karras 2012) ----------------------------------------
+// delta = length of the common prefix of the augmented keys (key, position)
+__device__ __forceinline__ int delta(const uint64_t* __restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  uint64_t a = k[i], b = k[j];
+  if (a != b) return __clzll((long long)(a ^ b));
+  return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+}
+
+// internal node i (0..n-2); child codes: >= 0 internal node, < 0 leaf -(pos+1)
+__global__ void k_karras(int n, const uint64_t* __restrict__ key, int leaf_size,
+                         int32_t* __restrict__ kfirst, int32_t* __restrict__ klast,
+                         int32_t* __restrict__ kleft, int32_t* __restrict__ kright,
+                         int32_t* __restrict__ kpar, int32_t* __restrict__ kside,
+                         uint32_t* __restrict__ kept) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = (delta(key, n, i, i + 1) - delta(key, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = delta(key, n, i, i - d);
+  int lmax = 2;
+  while (delta(key, n, i, i + lmax * d) > dmin) lmax *= 2;
+  int l = 0;
+  for (int t = lmax / 2; t >= 1; t /= 2)
+    if (delta(key, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = delta(key, n, i, j);
+  int s = 0;
+  for (int div = 2;; div *= 2) {
+    int t = (l + div - 1) / div;
+    if (delta(key, n, i, i + (s + t) * d) > dnode) s += t;
+    if (t <= 1) break;
+  }
+  const int gamma = i + s * d + (d < 0 ? -1 : 0);
+  const int first = min(i, j), last = max(i, j);
+  const int left = (first == gamma) ? -(gamma + 1) : gamma;
+  const int right = (last == gamma + 1) ? -(gamma + 2) : gamma + 1;
+  kfirst[i] = first;
+  klast[i] = last;
+  kleft[i] = left;
+  kright[i] = right;
+  if (left >= 0) { kpar[left] = i; kside[left] = 0; }
+  if (right >= 0) { kpar[right] = i; kside[right] = 1; }
+  kept[i] = (last - first + 1) > leaf_size ? 1u : 0u;
+  if (i == 0) kpar[0] = -1;
+}
+
+// final node ids: root 0; the children of the kept internal node with
+// compact index c sit at 1 + 2c (left) and 2 + 2c (right)
+__device__ __forceinline__ int final_id(int i, const int32_t* kpar, const int32_t* kside,
+                                        const uint32_t* cidx) {
+  return i == 0 ? 0 : 1 + 2 * (int)cidx[kpar[i]] + kside[i];
+}
+
+__global__ void k_assign(int n, int leaf_size, const int32_t* __restrict__ kfirst,
+                         const int32_t* __restrict__ klast, const int32_t* __restrict__ kleft,
+                         const int32_t* __restrict__ kright, const int32_t* __restrict__ kpar,
+                         const int32_t* __restrict__ kside, const uint32_t* __restrict__ cidx,
+                         NodeInfo* __restrict__ info, uint32_t* __restrict__ leaf_flag,
+                         int32_t* __restrict__ leaf_at) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int first = kfirst[i], last = klast[i];
+  if (last - first + 1 <= leaf_size) return;  // not a kept internal node
+  const int me = final_id(i, kpar, kside, cidx);
+  const int par = i == 0 ? -1 : final_id(kpar[i], kpar, kside, cidx);
+  const int base = 1 + 2 * (int)cidx[i];
+  NodeInfo ni;
+  ni.lo = first; ni.cnt = last - first + 1; ni.child = base; ni.parent = par;
+  info[me] = ni;
+  const int ch[2] = {kleft[i], kright[i]};
+  for (int side = 0; side < 2; ++side) {
+    int c = ch[side], lo, cnt;
+    if (c < 0) { lo = -c - 1; cnt = 1; }
+    else { lo = kfirst[c]; cnt = klast[c] - kfirst[c] + 1; }
+    if (cnt <= leaf_size) {
+      NodeInfo li;
+      li.lo = lo; li.cnt = cnt; li.child = -1; li.parent = me;
+      info[base + side] = li;
+      leaf_flag[lo] = 1u;
+      leaf_at[lo] = base + side;
+    }
+  }
+}
+
+__global__ void k_leaf_fill(int n, const uint32_t* __restrict__ leaf_flag,
+                            const uint32_t* __restrict__ leaf_scan,
+                            const int32_t* __restrict__ leaf_at, int32_t* __restrict__ leaf_node) {
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  if (leaf_flag[p]) leaf_node[leaf_scan[p]] = leaf_at[p];
+}
+
+__global__ void k_single_leaf(int n, NodeInfo* info, int32_t* leaf_node) {
+  NodeInfo ni;
+  ni.lo = 0; ni.cnt = n; ni.child = -1; ni.parent = -1;
+  info[0] = ni;
+  leaf_node[0] = 0;
+}
+
+__global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
+                             const NodeInfo* __restrict__ info, int32_t* __restrict__ leaf_depth,
+                             int32_t* __restrict__ p_leaf, int* maxdepth) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nleaves) return;
+  const int node = leaf_node[l];
+  int d = 0;
+  for (int v = info[node].parent; v >= 0; v = info[v].parent) ++d;
+  leaf_depth[l] = d;
+  atomicMax(maxdepth, d);
+  const NodeInfo ni = info[node];
+  for (int p = ni.lo; p < ni.lo + ni.cnt; ++p) p_leaf[p] = l;
+}
+
+// ---- geometry, moments (bottom-up) ------------------------------------------
+template <int P>
+__global__ void k_upsweep(int nleaves, const int32_t* __restrict__ leaf_node,
+                          const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                          const double* __restrict__ ys, const double* __restrict__ zs,
+                          const double* __restrict__ ms, const double* __restrict__ hs,
+                          double* rec, uint32_t* visit) {
+  using E = Exp<P>;
+  constexpr int NQ = E::NQ;
+  constexpr int RS = rec_stride(P);
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nleaves) return;
+  int v = leaf_node[l];
+  {
+    const NodeInfo ni = info[v];
+    double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
+    for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
+      const double mj = ms[j];
+      M += mj;
+      S0 += mj * xs[j];
+      S1 += mj * ys[j];
+      S2 += mj * zs[j];
+      hm = fmax(hm, hs[j]);
+    }
+    const double s0 = S0 / M, s1 = S1 / M, s2 = S2 / M;
+    double d2max = 0.0;
+    double Q[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
+    for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
+      const double b[3] = {xs[j] - s0, ys[j] - s1, zs[j] - s2};
+      const double d2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+      d2max = fmax(d2max, d2);
+      E::p2m_add(b, ms[j], Q);
+    }
+    double* r = rec + (int64_t)v * RS;
+    r[0] = s0; r[1] = s1; r[2] = s2; r[3] = sqrt(d2max); r[4] = hm; r[5] = M;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
+  }
+  // climb: the second child to finish computes the parent
+  for (;;) {
+    const int p = info[v].parent;
+    if (p < 0) break;
+    __threadfence();
+    const uint32_t old =
+        __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) break;
+    __threadfence();
+    const int c = info[p].child;
+    const double* rl = rec + (int64_t)c * RS;
+    const double* rr = rec + (int64_t)(c + 1) * RS;
+    const double ML = rl[5];
+    const double MR = rr[5];
+    double sl[3], sr[3];
+    for (int d = 0; d < 3; ++d) {
+      sl[d] = rl[d];
+      sr[d] = rr[d];
+    }
+    const double M = ML + MR;
+    double s[3];
+    for (int d = 0; d < 3; ++d) s[d] = (ML * sl[d] + MR * sr[d]) / M;
+    const double hm = fmax(rl[4], rr[4]);
+    double Q[NQ], Qc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
+    {
+      const double g[3] = {sl[0] - s[0], sl[1] - s[1], sl[2] - s[2]};
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) Qc[k] = rl[8 + k];
+      E::m2m_add(g, Qc, Q);
+    }
+    {
+      const double g[3] = {sr[0] - s[0], sr[1] - s[1], sr[2] - s[2]};
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) Qc[k] = rr[8 + k];
+      E::m2m_add(g, Qc, Q);
+    }
+    double* r = rec + (int64_t)p * RS;
+    r[0] = s[0]; r[1] = s[1]; r[2] = s[2]; r[4] = hm; r[5] = M;
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
+    v = p;
+  }
+}
+
+__global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
+                               uint32_t* __restrict__ chunks) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  const NodeInfo ni = info[v];
+  chunks[v] = ni.child >= 0 ? (uint32_t)((ni.cnt + kExtentChunk - 1) / kExtentChunk) : 0u;
+}
+
+// one wave per chunk of an internal node: largest squared distance to the
+// node's centre of mass, folded in with an integer max on the FP64 bits
+// (non-negative doubles order like their bit patterns)
+template <int RS>
+__global__ __launch_bounds__(256) void k_extent(int nn, int nitems, const NodeInfo* __restrict__ info,
+                                                const uint32_t* __restrict__ chunk_off,
+                                                const double* __restrict__ xs,
+                                                const double* __restrict__ ys,
+                                                const double* __restrict__ zs,
+                                                const double* __restrict__ rec,
+                                                unsigned long long* l2bits) {
+  const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= nitems) return;
+  // node = last v with chunk_off[v] <= item
+  int lo = 0, hi = nn - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (chunk_off[mid] <= (uint32_t)item) lo = mid; else hi = mid - 1;
+  }
+  const int v = lo;
+  const NodeInfo ni = info[v];
+  const int c = item - (int)chunk_off[v];
+  const int beg = ni.lo + c * kExtentChunk;
+  const int end = min(ni.lo + ni.cnt, beg + kExtentChunk);
+  const double s0 = rec[(int64_t)v * RS], s1 = rec[(int64_t)v * RS + 1], s2 = rec[(int64_t)v * RS + 2];
+  double d2max = 0.0;
+  for (int j = beg + lane; j < end; j += 64) {
+    const double dx = xs[j] - s0, dy = ys[j] - s1, dz = zs[j] - s2;
+    d2max = fmax(d2max, dx * dx + dy * dy + dz * dz);
+  }
+  d2max = wave_max(d2max);
+  if (lane == 0) atomicMax(&l2bits[v], (unsigned long long)__double_as_longlong(d2max));
+}
+
+template <int RS>
+__global__ void k_extent_final(int nn, const NodeInfo* __restrict__ info,
+                               const unsigned long long* __restrict__ l2bits, double* rec) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  if (info[v].child < 0) return;
+  rec[(int64_t)v * RS + 3] = sqrt(__longlong_as_double((long long)l2bits[v]));
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int bbox_blocks(int64_t n) {
+  int64_t b = (n + BBOX_THREADS * 8 - 1) / (BBOX_THREADS * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+void launch_bbox(int n, const double* x, const double* m, const double* h, double* part,
+                 double* box, int* status, int check, hipStream_t s) {
+  int nb = bbox_blocks(n);
+  k_bbox_partial<<<nb, BBOX_THREADS, 0, s>>>(n, x, m, h, part, status, check);
+  k_bbox_final<<<1, 64, 0, s>>>(nb, part, box);
+}
+
+void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint32_t* idx,
+                 hipStream_t s) {
+  k_keys<<<blocks_for(n, 256), 256, 0, s>>>(n, x, box, key, idx);
+}
+
+int radix_blocks(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
+
+void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
+                uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s) {
+  const int nb = radix_blocks(n);
+  uint64_t *kin = key0, *kout = key1;
+  uint32_t *vin = val0, *vout = val1;
+  for (int shift = 0; shift < 64; shift += 8) {  // 8 passes: result lands in key0/val0
+    k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
+    scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+    k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+}
+
+void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
+                   const double* h, double* xs, double* ys, double* zs, double* ms,
+                   double* hs, hipStream_t s) {
+  k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs);
+}
+
+void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,
+                   int32_t* kleft, int32_t* kright, int32_t* kpar, int32_t* kside,
+                   uint32_t* kept, hipStream_t s) {
+  k_karras<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, key, leaf_size, kfirst, klast, kleft,
+                                                  kright, kpar, kside, kept);
+}
+
+void launch_assign(int n, int leaf_size, const int32_t* kfirst, const int32_t* klast,
+                   const int32_t* kleft, const int32_t* kright, const int32_t* kpar,
+                   const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
+                   uint32_t* leaf_flag, int32_t* leaf_at, hipStream_t s) {
+  k_assign<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, leaf_size, kfirst, klast, kleft, kright,
+                                                  kpar, kside, cidx, info, leaf_flag, leaf_at);
+}
+
+void launch_leaf_fill(int n, const uint32_t* leaf_flag, const uint32_t* leaf_scan,
+                      const int32_t* leaf_at, int32_t* leaf_node, hipStream_t s) {
+  k_leaf_fill<<<blocks_for(n, 256), 256, 0, s>>>(n, leaf_flag, leaf_scan, leaf_at, leaf_node);
+}
+
+void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s) {
+  k_single_leaf<<<1, 1, 0, s>>>(n, info, leaf_node);
+}
+
+void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                       int32_t* leaf_depth, int32_t* p_leaf, int* maxdepth, hipStream_t s) {
+  k_leaf_depth<<<blocks_for(nleaves, 256), 256, 0, s>>>(nleaves, leaf_node, info, leaf_depth,
+                                                        p_leaf, maxdepth);
+}
+
+void launch_upsweep(int order, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                    const double* xs, const double* ys, const double* zs, const double* ms,
+                    const double* hs, double* rec, uint32_t* visit, hipStream_t s) {
+  const unsigned nb = blocks_for(nleaves, 128);
+  switch (order) {
+    case 0: k_upsweep<0><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+    case 1: k_upsweep<1><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+    case 2: k_upsweep<2><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+    case 3: k_upsweep<3><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+    case 4: k_upsweep<4><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+  }
+}
+
+void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s) {
+  k_extent_count<<<blocks_for(nn, 256), 256, 0, s>>>(nn, info, chunks);
+}
+
+void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
+                   const uint32_t* chunk_off, const double* xs, const double* ys,
+                   const double* zs, double* rec, unsigned long long* l2bits, hipStream_t s) {
+  if (nitems <= 0) return;
+  const unsigned nb = blocks_for(nitems, 4);
+  switch (rec_stride(order)) {
+    case 16: k_extent<16><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
+    case 24: k_extent<24><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
+    case 32: k_extent<32><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
+    case 48: k_extent<48><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
+  }
+}
+
+void launch_extent_final(int order, int nn, const NodeInfo* info,
+                         const unsigned long long* l2bits, double* rec, hipStream_t s) {
+  const unsigned nb = blocks_for(nn, 256);
+  switch (rec_stride(order)) {
+    case 16: k_extent_final<16><<<nb, 256, 0, s>>>(nn, info, l2bits, rec); break;
+    case 24: k_extent_final<24><<<nb, 256, 0, s>>>(nn, info, l2bits, rec); break;
+    case 32: k_extent_final<32><<<nb, 256, 0, s>>>(nn, info, l2bits, rec); break;
+    case 48: k_extent_final<48><<<nb, 256, 0, s>>>(nn, info, l2bits, rec); break;
+  }
+}
+
+}  // namespace sfmm

@@ -1,0 +1,630 @@
+// sfmm_api.hip -- the C ABI of libsfmm.so (declared in include/sfmm.h):
+// argument checks, the context's workspace and the order of the phases.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sfmm.h"
+#include "sfmm_internal.h"
+
+using namespace sfmm;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+// every device buffer of a context, grown on demand and reused
+enum BufId {
+  B_BOXPART, B_BOX, B_STATUS, B_SMALL,
+  B_KEY0, B_KEY1, B_VAL0, B_VAL1, B_HIST, B_SCANTMP,
+  B_XS, B_YS, B_ZS, B_MS, B_HS,
+  B_KFIRST, B_KLAST, B_KLEFT, B_KRIGHT, B_KPAR, B_KSIDE, B_KEPT,
+  B_LFLAG, B_LAT, B_INFO, B_REC, B_VISIT, B_L2BITS, B_CHUNK,
+  B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
+  B_LDOFF, B_DEPTHCNT, B_M2LCNT, B_P2PCNT, B_PAIRCNT, B_M2L, B_P2P,
+  B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
+  B_COUNT
+};
+
+// small device scalars (B_SMALL, u64 slots)
+enum SmallId { S_NKEPT = 0, S_NLEAVES, S_MAXDEPTH, S_NITEMS, S_M2LTOT, S_P2PTOT, S_PAIRTOT,
+               S_DOFFTOT, S_SORTTOT, S_L2LTOT, S_COUNT };
+
+}  // namespace
+
+struct sfmm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  sfmm_config cfg{};
+  std::string err;
+  DevBuf buf[B_COUNT];
+  // tree state of the last build
+  int64_t n = 0;
+  int order = -1;
+  int64_t nn = 0, nleaves = 0;
+  int maxdepth = 0;
+  uint64_t m2l_total = 0, p2p_total = 0, pair_total = 0, l2l_total = 0;
+  // phase timing: SFMM_NUM_PHASES event pairs per timed solve
+  std::vector<hipEvent_t> events;
+  int timing_cap = 0, timing_used = 0;
+  bool timing = false;
+  hipEvent_t order_ev = nullptr;  // orders work across a stream change
+  bool have_tree = false, have_lists = false, have_mom = false;
+  sfmm_stats stats{};
+};
+
+namespace {
+
+int fail(sfmm_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, SFMM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// make buffer `id` hold at least `bytes`; contents are not preserved
+int ensure(sfmm_ctx* ctx, int id, size_t bytes) {
+  DevBuf& b = ctx->buf[id];
+  if (bytes == 0) bytes = 8;
+  if (b.cap >= bytes) return SFMM_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    (void)e;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = bytes + bytes / 4;  // grow with slack
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, SFMM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+  }
+  b.cap = want;
+  return SFMM_OK;
+}
+
+template <typename T>
+T* P(sfmm_ctx* ctx, int id) {
+  return static_cast<T*>(ctx->buf[id].p);
+}
+
+void free_events(sfmm_ctx* ctx) {
+  for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+  ctx->events.clear();
+  ctx->timing = false;
+  ctx->timing_cap = ctx->timing_used = 0;
+}
+
+void phase_mark(sfmm_ctx* ctx, int phase, int end) {
+  if (!ctx->timing || ctx->timing_used >= ctx->timing_cap) return;
+  hipEvent_t e = ctx->events[(size_t)ctx->timing_used * 2 * SFMM_NUM_PHASES + 2 * phase + end];
+  (void)hipEventRecord(e, ctx->stream);
+}
+
+int set_device(sfmm_ctx* ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  return SFMM_OK;
+}
+
+int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const double* h,
+             int order) {
+  if (n64 < 0 || n64 >= (int64_t(1) << 30)) return fail(ctx, SFMM_EINVAL, "n out of range");
+  if (order < 0 || order > kMaxOrder) return fail(ctx, SFMM_EINVAL, "order must be 0..4");
+  ctx->have_tree = ctx->have_lists = ctx->have_mom = false;
+  ctx->n = n64;
+  ctx->order = order;
+  if (n64 == 0) {
+    ctx->nn = ctx->nleaves = 0;
+    ctx->maxdepth = 0;
+    ctx->have_tree = true;
+    return SFMM_OK;
+  }
+  if (!x || !m || !h) return fail(ctx, SFMM_EINVAL, "NULL particle array");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  const int n = (int)n64;
+  const hipStream_t s = ctx->stream;
+  const int leaf_size = ctx->cfg.leaf_size;
+  const int RS = rec_stride(order);
+  const int nmax_nodes = 2 * n;  // 1 + 2 * (kept internal) <= 2n - 1
+  // ---- workspace
+  struct { int id; size_t bytes; } need[] = {
+      {B_BOXPART, sizeof(double) * 6 * bbox_blocks(n)}, {B_BOX, sizeof(double) * 8},
+      {B_STATUS, sizeof(int) * 4}, {B_SMALL, sizeof(uint64_t) * S_COUNT},
+      {B_KEY0, sizeof(uint64_t) * n}, {B_KEY1, sizeof(uint64_t) * n},
+      {B_VAL0, sizeof(uint32_t) * n}, {B_VAL1, sizeof(uint32_t) * n},
+      {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(n)},
+      {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(n), 2 * (int64_t)n + 2))},
+      {B_XS, sizeof(double) * n}, {B_YS, sizeof(double) * n}, {B_ZS, sizeof(double) * n},
+      {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n},
+      {B_KFIRST, sizeof(int32_t) * n}, {B_KLAST, sizeof(int32_t) * n},
+      {B_KLEFT, sizeof(int32_t) * n}, {B_KRIGHT, sizeof(int32_t) * n},
+      {B_KPAR, sizeof(int32_t) * n}, {B_KSIDE, sizeof(int32_t) * n},
+      {B_KEPT, sizeof(uint32_t) * (n + 1)},
+      {B_LFLAG, sizeof(uint32_t) * (n + 1)}, {B_LAT, sizeof(int32_t) * n},
+      {B_INFO, sizeof(NodeInfo) * nmax_nodes}, {B_REC, sizeof(double) * RS * (size_t)nmax_nodes},
+      {B_VISIT, sizeof(uint32_t) * nmax_nodes}, {B_L2BITS, sizeof(uint64_t) * nmax_nodes},
+      {B_CHUNK, sizeof(uint32_t) * (nmax_nodes + 1)},
+      {B_LEAFNODE, sizeof(int32_t) * n}, {B_LEAFDEPTH, sizeof(int32_t) * n},
+      {B_PLEAF, sizeof(int32_t) * n},
+  };
+  for (auto& q : need)
+    if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+  int* status = P<int>(ctx, B_STATUS);
+  uint64_t* small = P<uint64_t>(ctx, B_SMALL);
+  phase_mark(ctx, 0, 0);
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int) * 4, s));
+  HIPCHK(hipMemsetAsync(small, 0, sizeof(uint64_t) * S_COUNT, s));
+  // ---- keys, sort, gather
+  launch_bbox(n, x, m, h, P<double>(ctx, B_BOXPART), P<double>(ctx, B_BOX), status,
+              ctx->cfg.check_inputs, s);
+  launch_keys(n, x, P<double>(ctx, B_BOX), P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), s);
+  radix_sort(n, P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), P<uint64_t>(ctx, B_KEY1),
+             P<uint32_t>(ctx, B_VAL1), P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
+             reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+  const uint64_t* key = P<uint64_t>(ctx, B_KEY0);
+  const uint32_t* perm = P<uint32_t>(ctx, B_VAL0);
+  launch_gather(n, perm, x, m, h, P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
+                P<double>(ctx, B_MS), P<double>(ctx, B_HS), s);
+  NodeInfo* info = P<NodeInfo>(ctx, B_INFO);
+  int32_t* leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+  // ---- topology
+  if (n <= leaf_size) {
+    launch_single_leaf(n, info, leaf_node, s);
+  } else {
+    launch_karras(n, key, leaf_size, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
+                  P<int32_t>(ctx, B_KLEFT), P<int32_t>(ctx, B_KRIGHT), P<int32_t>(ctx, B_KPAR),
+                  P<int32_t>(ctx, B_KSIDE), P<uint32_t>(ctx, B_KEPT), s);
+    uint32_t* cidx = P<uint32_t>(ctx, B_KEPT);
+    scan_u32(cidx, cidx, n - 1, reinterpret_cast<uint32_t*>(small + S_NKEPT),
+             P<uint32_t>(ctx, B_SCANTMP), s);
+    HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_LFLAG), 0, sizeof(uint32_t) * (n + 1), s));
+    launch_assign(n, leaf_size, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
+                  P<int32_t>(ctx, B_KLEFT), P<int32_t>(ctx, B_KRIGHT), P<int32_t>(ctx, B_KPAR),
+                  P<int32_t>(ctx, B_KSIDE), cidx, info, P<uint32_t>(ctx, B_LFLAG),
+                  P<int32_t>(ctx, B_LAT), s);
+    // leaf_flag -> leaf index (scan into KFIRST's storage, no longer needed)
+    uint32_t* lscan = reinterpret_cast<uint32_t*>(P<int32_t>(ctx, B_KFIRST));
+    scan_u32(P<uint32_t>(ctx, B_LFLAG), lscan, n, reinterpret_cast<uint32_t*>(small + S_NLEAVES),
+             P<uint32_t>(ctx, B_SCANTMP), s);
+    launch_leaf_fill(n, P<uint32_t>(ctx, B_LFLAG), lscan, P<int32_t>(ctx, B_LAT), leaf_node, s);
+  }
+  // ---- sizes to the host (one synchronisation)
+  uint64_t hsmall[S_COUNT];
+  int hstatus[4];
+  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hstatus[0] & ST_NONFINITE)
+    return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
+  if (n <= leaf_size) {
+    ctx->nn = 1;
+    ctx->nleaves = 1;
+  } else {
+    const uint32_t nkept = (uint32_t)(hsmall[S_NKEPT] & 0xffffffffu);
+    ctx->nn = 1 + 2 * (int64_t)nkept;
+    ctx->nleaves = (int64_t)(hsmall[S_NLEAVES] & 0xffffffffu);
+  }
+  const int nn = (int)ctx->nn, nl = (int)ctx->nleaves;
+  int* maxd_dev = reinterpret_cast<int*>(small + S_MAXDEPTH);
+  launch_leaf_depth(nl, leaf_node, info, P<int32_t>(ctx, B_LEAFDEPTH), P<int32_t>(ctx, B_PLEAF),
+                    maxd_dev, s);
+  // ---- geometry and moments
+  HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_VISIT), 0, sizeof(uint32_t) * nn, s));
+  launch_upsweep(order, nl, leaf_node, info, P<double>(ctx, B_XS), P<double>(ctx, B_YS),
+                 P<double>(ctx, B_ZS), P<double>(ctx, B_MS), P<double>(ctx, B_HS),
+                 P<double>(ctx, B_REC), P<uint32_t>(ctx, B_VISIT), s);
+  if (nn > 1) {
+    uint32_t* chunk = P<uint32_t>(ctx, B_CHUNK);
+    launch_extent_count(nn, info, chunk, s);
+    scan_u32(chunk, chunk, nn, reinterpret_cast<uint32_t*>(small + S_NITEMS),
+             P<uint32_t>(ctx, B_SCANTMP), s);
+    HIPCHK(hipMemsetAsync(P<uint64_t>(ctx, B_L2BITS), 0, sizeof(uint64_t) * nn, s));
+  }
+  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
+  if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
+  if (nn > 1) {
+    const int nitems = (int)(hsmall[S_NITEMS] & 0xffffffffu);
+    launch_extent(order, nn, nitems, info, P<uint32_t>(ctx, B_CHUNK), P<double>(ctx, B_XS),
+                  P<double>(ctx, B_YS), P<double>(ctx, B_ZS), P<double>(ctx, B_REC),
+                  reinterpret_cast<unsigned long long*>(P<uint64_t>(ctx, B_L2BITS)), s);
+    launch_extent_final(order, nn, info, reinterpret_cast<unsigned long long*>(P<uint64_t>(ctx, B_L2BITS)),
+                        P<double>(ctx, B_REC), s);
+  }
+  phase_mark(ctx, 0, 1);
+  HIPCHK(hipGetLastError());
+  ctx->have_tree = true;
+  return SFMM_OK;
+}
+
+int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, double* pot) {
+  int rc;
+  const hipStream_t s = ctx->stream;
+  const int n = (int)ctx->n, nl = (int)ctx->nleaves;
+  const int RS = rec_stride(ctx->order);
+  uint64_t* small = P<uint64_t>(ctx, B_SMALL);
+  int* status = P<int>(ctx, B_STATUS);
+  // per-(leaf, depth) count storage
+  struct { int id; size_t bytes; } need[] = {
+      {B_LDOFF, sizeof(uint64_t) * (nl + 1)}, {B_M2LCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_P2PCNT, sizeof(uint64_t) * (nl + 1)}, {B_PAIRCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_L2LCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_FAR, sizeof(double) * 4 * (size_t)n},
+      {B_MOMPART, sizeof(double) * 4 * momentum_blocks(n)}, {B_MOM, sizeof(double) * 4},
+      {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(nl + 1)},
+  };
+  for (auto& q : need)
+    if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+  uint64_t* ldoff = P<uint64_t>(ctx, B_LDOFF);
+  phase_mark(ctx, 1, 0);
+  launch_leaf_doff(nl, P<int32_t>(ctx, B_LEAFDEPTH), ldoff, s);
+  scan_u64(ldoff, ldoff, nl, small + S_DOFFTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+  // depth counts need sum(d+1) <= nl * (maxdepth + 1)
+  if ((rc = ensure(ctx, B_DEPTHCNT, sizeof(uint32_t) * (size_t)nl * (ctx->maxdepth + 1))))
+    return rc;
+  WalkArgs w{};
+  w.nleaves = nl;
+  w.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+  w.leaf_depth = P<int32_t>(ctx, B_LEAFDEPTH);
+  w.info = P<NodeInfo>(ctx, B_INFO);
+  w.rec = P<double>(ctx, B_REC);
+  w.stride = RS;
+  w.theta2 = theta * theta;
+  w.r_kern = ctx->cfg.r_kern;
+  w.leaf_doff = ldoff;
+  w.depth_cnt = P<uint32_t>(ctx, B_DEPTHCNT);
+  w.m2l_cnt = P<uint64_t>(ctx, B_M2LCNT);
+  w.p2p_cnt = P<uint64_t>(ctx, B_P2PCNT);
+  w.pair_cnt = P<uint64_t>(ctx, B_PAIRCNT);
+  w.l2l_cnt = P<uint64_t>(ctx, B_L2LCNT);
+  w.status = status;
+  launch_walk(w, ctx->maxdepth, false, s);
+  scan_u64(w.m2l_cnt, w.m2l_cnt, nl, small + S_M2LTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+  scan_u64(w.p2p_cnt, w.p2p_cnt, nl, small + S_P2PTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+  scan_u64(w.pair_cnt, w.pair_cnt, nl, small + S_PAIRTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+  scan_u64(w.l2l_cnt, w.l2l_cnt, nl, small + S_L2LTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+  // the totals also close the offset arrays: off[nl] = total
+  HIPCHK(hipMemcpyAsync(w.m2l_cnt + nl, small + S_M2LTOT, sizeof(uint64_t),
+                        hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(w.p2p_cnt + nl, small + S_P2PTOT, sizeof(uint64_t),
+                        hipMemcpyDeviceToDevice, s));
+  phase_mark(ctx, 1, 1);
+  uint64_t hsmall[S_COUNT];
+  int hstatus[4];
+  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hstatus[0] & (ST_DEPTH | ST_OVERFLOW))
+    return fail(ctx, SFMM_EDEVICE, "walk stack overflow (tree depth)");
+  ctx->m2l_total = hsmall[S_M2LTOT];
+  ctx->p2p_total = hsmall[S_P2PTOT];
+  ctx->pair_total = hsmall[S_PAIRTOT];
+  ctx->l2l_total = hsmall[S_L2LTOT];
+  if ((rc = ensure(ctx, B_M2L, sizeof(uint32_t) * ctx->m2l_total))) return rc;
+  if ((rc = ensure(ctx, B_P2P, sizeof(int32_t) * ctx->p2p_total))) return rc;
+  w.m2l_list = P<uint32_t>(ctx, B_M2L);
+  w.p2p_list = P<int32_t>(ctx, B_P2P);
+  phase_mark(ctx, 2, 0);
+  launch_walk(w, ctx->maxdepth, true, s);
+  phase_mark(ctx, 2, 1);
+  ctx->have_lists = true;
+  // ---- far field, near field, output
+  FarArgs f{};
+  f.nleaves = nl;
+  f.leaf_node = w.leaf_node;
+  f.leaf_depth = w.leaf_depth;
+  f.info = w.info;
+  f.rec = w.rec;
+  f.m2l_off = w.m2l_cnt;
+  f.m2l_list = w.m2l_list;
+  f.xs = P<double>(ctx, B_XS);
+  f.ys = P<double>(ctx, B_YS);
+  f.zs = P<double>(ctx, B_ZS);
+  f.far = P<double>(ctx, B_FAR);
+  phase_mark(ctx, 3, 0);
+  launch_far(ctx->order, f, s);
+  phase_mark(ctx, 3, 1);
+  NearArgs a{};
+  a.n = n;
+  a.p_leaf = P<int32_t>(ctx, B_PLEAF);
+  a.info = w.info;
+  a.p2p_off = w.p2p_cnt;
+  a.p2p_list = w.p2p_list;
+  a.xs = f.xs; a.ys = f.ys; a.zs = f.zs;
+  a.ms = P<double>(ctx, B_MS);
+  a.hs = P<double>(ctx, B_HS);
+  a.far = f.far;
+  a.perm = P<uint32_t>(ctx, B_VAL0);
+  a.G = ctx->cfg.G;
+  a.include_self = ctx->cfg.include_self_potential;
+  a.acc = acc;
+  a.pot = pot;
+  phase_mark(ctx, 4, 0);
+  launch_near(a, s);
+  phase_mark(ctx, 4, 1);
+  phase_mark(ctx, 5, 0);
+  launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
+  phase_mark(ctx, 5, 1);
+  if (ctx->timing && ctx->timing_used < ctx->timing_cap) ctx->timing_used++;
+  HIPCHK(hipGetLastError());
+  ctx->have_mom = true;
+  return SFMM_OK;
+}
+
+const char* kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP error",
+                             "unsupported", "non-finite or non-positive input"};
+
+}  // namespace
+
+extern "C" {
+
+int sfmm_config_default(sfmm_config* cfg) {
+  if (!cfg) return SFMM_EINVAL;
+  cfg->G = 1.0;
+  cfg->leaf_size = 10;
+  cfg->r_kern = 2.0;
+  cfg->include_self_potential = 1;
+  cfg->check_inputs = 1;
+  return SFMM_OK;
+}
+
+int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config* cfg) {
+  if (!out) return SFMM_EINVAL;
+  *out = nullptr;
+  sfmm_config c;
+  sfmm_config_default(&c);
+  if (cfg) c = *cfg;
+  if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
+      !std::isfinite(c.r_kern))
+    return SFMM_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return SFMM_EDEVICE;
+  }
+  sfmm_ctx* ctx = new (std::nothrow) sfmm_ctx();
+  if (!ctx) return SFMM_ENOMEM;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->cfg = c;
+  *out = ctx;
+  return SFMM_OK;
+}
+
+int sfmm_destroy(sfmm_ctx* ctx) {
+  if (!ctx) return SFMM_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
+  free_events(ctx);
+  if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
+  for (auto& b : ctx->buf)
+    if (b.p) (void)hipFree(b.p);
+  delete ctx;
+  return SFMM_OK;
+}
+
+int sfmm_set_stream(sfmm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return SFMM_EINVAL;
+  hipStream_t ns = static_cast<hipStream_t>(hip_stream);
+  if (ns == ctx->stream) return SFMM_OK;
+  // the workspace is shared: work enqueued on the new stream must not start
+  // before what is still queued on the old one
+  HIPCHK(hipSetDevice(ctx->device));
+  if (!ctx->order_ev) HIPCHK(hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(ctx->order_ev, ctx->stream));
+  HIPCHK(hipStreamWaitEvent(ns, ctx->order_ev, 0));
+  ctx->stream = ns;
+  return SFMM_OK;
+}
+
+int sfmm_build(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+               int order) {
+  if (!ctx) return SFMM_EINVAL;
+  ctx->err.clear();
+  return do_build(ctx, n, x, m, h, order);
+}
+
+int sfmm_solve(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+               double theta, int order, int precision, double* acc, double* pot) {
+  if (!ctx) return SFMM_EINVAL;
+  ctx->err.clear();
+  if (!(theta > 0.0 && theta < 1.0)) return fail(ctx, SFMM_EINVAL, "theta must be in (0, 1)");
+  if (precision != SFMM_FP64) return fail(ctx, SFMM_EUNSUPPORTED, "unknown precision");
+  if (n > 0 && (!acc || !pot)) return fail(ctx, SFMM_EINVAL, "NULL output array");
+  int rc = do_build(ctx, n, x, m, h, order);
+  if (rc) return rc;
+  if (n == 0) return SFMM_OK;
+  return do_walk_and_eval(ctx, theta, m, acc, pot);
+}
+
+int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
+  if (!ctx || !out) return SFMM_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->n = ctx->n;
+  out->num_nodes = ctx->nn;
+  out->num_leaves = ctx->nleaves;
+  out->max_depth = ctx->maxdepth;
+  if (ctx->have_lists) {
+    out->n_m2l = (int64_t)ctx->m2l_total;
+    out->n_l2l = (int64_t)ctx->l2l_total;
+    out->n_p2p_leaf_pairs = (int64_t)ctx->p2p_total;
+    out->n_p2p_pairs = (int64_t)ctx->pair_total;
+  }
+  if (ctx->have_mom && ctx->n > 0) {
+    double mom[4];
+    if (hipMemcpyAsync(mom, ctx->buf[B_MOM].p, sizeof(mom), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(ctx, SFMM_EDEVICE, "momentum copy failed");
+    out->momentum[0] = mom[0];
+    out->momentum[1] = mom[1];
+    out->momentum[2] = mom[2];
+    out->momentum_abs = mom[3];
+  }
+  return SFMM_OK;
+}
+
+int sfmm_get_tree(sfmm_ctx* ctx, int64_t* num_nodes, int64_t* num_leaves, int32_t* perm,
+                  uint64_t* keys, int32_t* lo, int32_t* cnt, int32_t* child, int32_t* parent,
+                  double* s, double* mass, double* l, double* hmax, double* Q) {
+  if (!ctx) return SFMM_EINVAL;
+  if (!ctx->have_tree) return fail(ctx, SFMM_EINVAL, "no tree built");
+  if (num_nodes) *num_nodes = ctx->nn;
+  if (num_leaves) *num_leaves = ctx->nleaves;
+  const int64_t n = ctx->n, nn = ctx->nn;
+  if (n == 0) return SFMM_OK;
+  const hipStream_t st = ctx->stream;
+  HIPCHK(hipStreamSynchronize(st));
+  if (perm) HIPCHK(hipMemcpy(perm, ctx->buf[B_VAL0].p, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  if (keys) HIPCHK(hipMemcpy(keys, ctx->buf[B_KEY0].p, sizeof(uint64_t) * n, hipMemcpyDeviceToHost));
+  if (lo || cnt || child || parent) {
+    NodeInfo* tmp = static_cast<NodeInfo*>(std::malloc(sizeof(NodeInfo) * nn));
+    if (!tmp) return SFMM_ENOMEM;
+    hipError_t e = hipMemcpy(tmp, ctx->buf[B_INFO].p, sizeof(NodeInfo) * nn, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { std::free(tmp); return fail(ctx, SFMM_EDEVICE, "copy failed"); }
+    for (int64_t v = 0; v < nn; ++v) {
+      if (lo) lo[v] = tmp[v].lo;
+      if (cnt) cnt[v] = tmp[v].cnt;
+      if (child) child[v] = tmp[v].child;
+      if (parent) parent[v] = tmp[v].parent;
+    }
+    std::free(tmp);
+  }
+  if (s || mass || l || hmax || Q) {
+    const int RS = rec_stride(ctx->order), NQ = ncoef(ctx->order);
+    double* tmp = static_cast<double*>(std::malloc(sizeof(double) * RS * nn));
+    if (!tmp) return SFMM_ENOMEM;
+    hipError_t e = hipMemcpy(tmp, ctx->buf[B_REC].p, sizeof(double) * RS * nn, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { std::free(tmp); return fail(ctx, SFMM_EDEVICE, "copy failed"); }
+    for (int64_t v = 0; v < nn; ++v) {
+      const double* r = tmp + v * RS;
+      if (s) { s[3 * v] = r[0]; s[3 * v + 1] = r[1]; s[3 * v + 2] = r[2]; }
+      if (l) l[v] = r[3];
+      if (hmax) hmax[v] = r[4];
+      if (mass) mass[v] = r[5];
+      if (Q) for (int k = 0; k < NQ; ++k) Q[v * NQ + k] = r[8 + k];
+    }
+    std::free(tmp);
+  }
+  return SFMM_OK;
+}
+
+int sfmm_get_leaves(sfmm_ctx* ctx, int32_t* leaf_node, int32_t* leaf_depth) {
+  if (!ctx) return SFMM_EINVAL;
+  if (!ctx->have_tree) return fail(ctx, SFMM_EINVAL, "no tree built");
+  if (ctx->nleaves == 0) return SFMM_OK;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (leaf_node)
+    HIPCHK(hipMemcpy(leaf_node, ctx->buf[B_LEAFNODE].p, sizeof(int32_t) * ctx->nleaves,
+                     hipMemcpyDeviceToHost));
+  if (leaf_depth)
+    HIPCHK(hipMemcpy(leaf_depth, ctx->buf[B_LEAFDEPTH].p, sizeof(int32_t) * ctx->nleaves,
+                     hipMemcpyDeviceToHost));
+  return SFMM_OK;
+}
+
+int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t* m2l_src,
+                        int64_t cap_m2l, int64_t* n_m2l, int32_t* p2p_src, int64_t cap_p2p,
+                        int64_t* n_p2p) {
+  if (!ctx) return SFMM_EINVAL;
+  if (!ctx->have_lists) return fail(ctx, SFMM_EINVAL, "no lists (run sfmm_solve first)");
+  if (leaf < 0 || leaf >= ctx->nleaves) return fail(ctx, SFMM_EINVAL, "leaf out of range");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  uint64_t mo[2], po[2];
+  HIPCHK(hipMemcpy(mo, P<uint64_t>(ctx, B_M2LCNT) + leaf, sizeof(mo), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(po, P<uint64_t>(ctx, B_P2PCNT) + leaf, sizeof(po), hipMemcpyDeviceToHost));
+  const int64_t nm = (int64_t)(mo[1] - mo[0]), np = (int64_t)(po[1] - po[0]);
+  if (n_m2l) *n_m2l = nm;
+  if (n_p2p) *n_p2p = np;
+  const int64_t cm = std::min<int64_t>(nm, cap_m2l < 0 ? 0 : cap_m2l);
+  if (cm > 0 && (m2l_depth || m2l_src)) {
+    uint32_t* tmp = static_cast<uint32_t*>(std::malloc(sizeof(uint32_t) * cm));
+    if (!tmp) return SFMM_ENOMEM;
+    hipError_t e = hipMemcpy(tmp, P<uint32_t>(ctx, B_M2L) + mo[0], sizeof(uint32_t) * cm,
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) { std::free(tmp); return fail(ctx, SFMM_EDEVICE, "copy failed"); }
+    for (int64_t k = 0; k < cm; ++k) {
+      if (m2l_depth) m2l_depth[k] = (int32_t)(tmp[k] >> kSrcBits);
+      if (m2l_src) m2l_src[k] = (int32_t)(tmp[k] & kSrcMask);
+    }
+    std::free(tmp);
+  }
+  const int64_t cp = std::min<int64_t>(np, cap_p2p < 0 ? 0 : cap_p2p);
+  if (cp > 0 && p2p_src)
+    HIPCHK(hipMemcpy(p2p_src, P<int32_t>(ctx, B_P2P) + po[0], sizeof(int32_t) * cp,
+                     hipMemcpyDeviceToHost));
+  return SFMM_OK;
+}
+
+int sfmm_timing_start(sfmm_ctx* ctx, int max_solves) {
+  if (!ctx || max_solves < 1 || max_solves > 100000) return SFMM_EINVAL;
+  free_events(ctx);
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t ne = (size_t)max_solves * 2 * SFMM_NUM_PHASES;
+  ctx->events.resize(ne, nullptr);
+  for (size_t k = 0; k < ne; ++k) {
+    hipError_t e = hipEventCreate(&ctx->events[k]);
+    if (e != hipSuccess) {
+      ctx->events.resize(k);
+      free_events(ctx);
+      return fail(ctx, SFMM_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  ctx->timing_cap = max_solves;
+  ctx->timing_used = 0;
+  ctx->timing = true;
+  return SFMM_OK;
+}
+
+int sfmm_timing_stop(sfmm_ctx* ctx, double* ms, int cap, int* nsolves) {
+  if (!ctx) return SFMM_EINVAL;
+  if (nsolves) *nsolves = ctx->timing_used;
+  int rc = SFMM_OK;
+  if (ctx->timing_used > 0 && ms && cap > 0) {
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) rc = SFMM_EDEVICE;
+    const int k_max = std::min(cap, ctx->timing_used);
+    for (int k = 0; k < k_max && rc == SFMM_OK; ++k)
+      for (int p = 0; p < SFMM_NUM_PHASES; ++p) {
+        float t = 0.f;
+        const size_t b = (size_t)k * 2 * SFMM_NUM_PHASES + 2 * p;
+        if (hipEventElapsedTime(&t, ctx->events[b], ctx->events[b + 1]) != hipSuccess) {
+          (void)hipGetLastError();
+          t = -1.f;
+        }
+        ms[(size_t)k * SFMM_NUM_PHASES + p] = t;
+      }
+  }
+  free_events(ctx);
+  return rc;
+}
+
+const char* sfmm_phase_name(int phase) {
+  static const char* names[SFMM_NUM_PHASES] = {"tree", "walk_count", "walk_fill",
+                                               "far", "near", "momentum"};
+  return (phase >= 0 && phase < SFMM_NUM_PHASES) ? names[phase] : "unknown";
+}
+
+const char* sfmm_strerror(int status) {
+  if (status > 0 || status < -5) return "unknown status";
+  return kStatusText[-status];
+}
+
+const char* sfmm_last_error(const sfmm_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// sfmm_internal.h -- device data layout and launch wrappers of libsfmm.so.
+//
+// Layout in HBM (all arrays owned by the context workspace):
+//   particles, sorted by Morton key: xs, ys, zs, ms, hs   FP64 SoA, n each
+//   perm       u32[n]   sorted position -> caller index
+//   NodeInfo   {lo, cnt, child, parent} per node (16 B); the two children of
+//              an internal node are adjacent (child, child + 1)
+//   rec        FP64 node records, REC_STRIDE(P) doubles per node:
+//                [0..2] centre of mass, [3] size l, [4] h_max, [5] mass,
+//                [8 .. 8+NQ) mass moments Q~ (graded multi-index order)
+//   leaf_node / leaf_depth   i32 per leaf, Morton order
+//   M2L lists  u32 per entry: depth of the target ancestor (7 bits) | source
+//              node (25 bits), grouped by depth inside each leaf's segment
+//   P2P lists  i32 source leaf node per entry
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "expansions_gen.h"
+
+namespace sfmm {
+
+struct NodeInfo {
+  int32_t lo, cnt, child, parent;
+};
+
+constexpr int kDepthBits = 7;
+constexpr int kSrcBits = 25;
+constexpr uint32_t kSrcMask = (1u << kSrcBits) - 1u;
+constexpr int kMaxDepthCap = (1 << kDepthBits) - 1;  // 127; radix trees stay below 96
+constexpr int kMaxOrder = 4;
+
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
+
+// ---- status bits written by kernels --------------------------------------
+enum : int { ST_NONFINITE = 1, ST_DEPTH = 2, ST_OVERFLOW = 4 };
+
+// ---- scan ------------------------------------------------------------------
+// Exclusive prefix sum of `in` (n entries) into `out` (may alias in); the
+// grand total is written to *total.  tmp must hold scan_tmp_elems(n) T's.
+size_t scan_tmp_elems(int64_t n);
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
+              hipStream_t s);
+void scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total, uint64_t* tmp,
+              hipStream_t s);
+
+// ---- tree ------------------------------------------------------------------
+int bbox_blocks(int64_t n);
+void launch_bbox(int n, const double* x, const double* m, const double* h, double* part,
+                 double* box, int* status, int check, hipStream_t s);
+void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint32_t* idx,
+                 hipStream_t s);
+int radix_blocks(int64_t n);
+// sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1)
+void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
+                uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s);
+void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
+                   const double* h, double* xs, double* ys, double* zs, double* ms,
+                   double* hs, hipStream_t s);
+void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,
+                   int32_t* kleft, int32_t* kright, int32_t* kpar, int32_t* kside,
+                   uint32_t* kept, hipStream_t s);
+void launch_assign(int n, int leaf_size, const int32_t* kfirst, const int32_t* klast,
+                   const int32_t* kleft, const int32_t* kright, const int32_t* kpar,
+                   const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
+                   uint32_t* leaf_flag, int32_t* leaf_at, hipStream_t s);
+void launch_leaf_fill(int n, const uint32_t* leaf_flag, const uint32_t* leaf_scan,
+                      const int32_t* leaf_at, int32_t* leaf_node, hipStream_t s);
+void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s);
+void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                       int32_t* leaf_depth, int32_t* p_leaf, int* maxdepth, hipStream_t s);
+void launch_upsweep(int order, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                    const double* xs, const double* ys, const double* zs, const double* ms,
+                    const double* hs, double* rec, uint32_t* visit, hipStream_t s);
+void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s);
+void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
+                   const uint32_t* chunk_off, const double* xs, const double* ys,
+                   const double* zs, double* rec, unsigned long long* l2bits, hipStream_t s);
+void launch_extent_final(int order, int nn, const NodeInfo* info,
+                         const unsigned long long* l2bits, double* rec, hipStream_t s);
+constexpr int kExtentChunk = 2048;
+
+// ---- walk (Algorithms 1 and 2) ---------------------------------------------
+struct WalkArgs {
+  int nleaves;
+  const int32_t* leaf_node;
+  const int32_t* leaf_depth;
+  const NodeInfo* info;
+  const double* rec;
+  int stride;
+  double theta2, r_kern;
+  const uint64_t* leaf_doff;   // per-leaf offset into the per-depth count array
+  uint32_t* depth_cnt;         // [sum (d+1)] M2L counts per (leaf, depth)
+  uint64_t* m2l_cnt;           // [nleaves] (count pass) -> offsets after the scan
+  uint64_t* p2p_cnt;           // [nleaves] idem
+  uint64_t* pair_cnt;          // [nleaves] particle pairs (statistics)
+  uint64_t* l2l_cnt;           // [nleaves] L2L translations (statistics)
+  uint32_t* m2l_list;
+  int32_t* p2p_list;
+  int* status;
+};
+void launch_walk(const WalkArgs& a, int maxdepth, bool fill, hipStream_t s);
+void launch_leaf_doff(int nleaves, const int32_t* leaf_depth, uint64_t* out, hipStream_t s);
+
+// ---- far field: M2L + L2L chain + L2P ----------------------------------------
+struct FarArgs {
+  int nleaves;
+  const int32_t* leaf_node;
+  const int32_t* leaf_depth;
+  const NodeInfo* info;
+  const double* rec;
+  const uint64_t* m2l_off;  // [nleaves + 1]
+  const uint32_t* m2l_list;
+  const double *xs, *ys, *zs;
+  double* far;  // [n][4]: field x, y, z, potential (before the -G factor)
+};
+void launch_far(int order, const FarArgs& a, hipStream_t s);
+
+// ---- near field (P2P) + output in the caller's order ----------------------
+struct NearArgs {
+  int n;
+  const int32_t* p_leaf;
+  const NodeInfo* info;
+  const uint64_t* p2p_off;  // [nleaves + 1]
+  const int32_t* p2p_list;
+  const double *xs, *ys, *zs, *ms, *hs;
+  const double* far;
+  const uint32_t* perm;
+  double G;
+  int include_self;
+  double* acc;  // caller order [n][3]
+  double* pot;  // caller order [n]
+};
+void launch_near(const NearArgs& a, hipStream_t s);
+
+// ---- momentum diagnostics ----------------------------------------------------
+int momentum_blocks(int64_t n);
+void launch_momentum(int n, const double* m, const double* acc, double* part, double* out,
+                     hipStream_t s);
+
+}  // namespace sfmm

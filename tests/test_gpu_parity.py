@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (FP64 path):
+  * tree: identical permutation, keys and node ranges; centres of mass,
+    masses, sizes and h_max bit-identical (the same formulas, rounded the
+    same way, decide every acceptance test); moments within 1e-13 of the
+    node's largest moment (the GPU translates children's moments, the oracle
+    sums particles directly);
+  * interaction lists: per leaf, the same (depth, source) M2L entries in the
+    same order and the same P2P source leaves;
+  * accelerations and potentials within 1e-12 relative per particle, with
+    the relative error taken against max(|a|, 1e-6 rms |a|);
+  * momentum |sum m a| / sum |m a| <= 1e-14.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def P(torch):
+    import paper_2602_05804_amd as P
+
+    return P
+
+
+def rel_err(a, b):
+    nb = np.linalg.norm(b, axis=1)
+    floor = 1e-6 * np.sqrt((nb ** 2).mean())
+    return np.linalg.norm(a - b, axis=1) / np.maximum(nb, floor)
+
+
+def dev(torch, *arrs):
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda() for a in arrs]
+
+
+def gpu_solve(torch, P, x, m, h, theta=0.5, order=3, solver=None, **cfg):
+    s = solver or P.Solver(**cfg)
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=theta, order=order)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), pot.cpu().numpy(), s
+
+
+def pot_err(p, q):
+    return np.abs(p - q).max() / np.abs(q).max()
+
+
+def test_tree_parity(torch, P, orc):
+    print("case: tree parity, plummer N=4096 seed 1", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    s = P.Solver()
+    s.build(*dev(torch, x, m, h), order=3)
+    g = s.tree(order=3)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    assert np.array_equal(g["perm"].astype(np.int64), t.perm())
+    assert np.array_equal(g["keys"], t.keys())
+    nd = t.nodes()
+    assert len(g["lo"]) == t.num_nodes
+    omap = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(nd["lo"], nd["hi"]))}
+    gi = np.array([omap[(int(a), int(a + c))] for a, c in zip(g["lo"], g["cnt"])])
+    assert np.array_equal(g["s"], nd["s"][gi])
+    assert np.array_equal(g["mass"], nd["mass"][gi])
+    assert np.array_equal(g["l"], nd["l"][gi])
+    assert np.array_equal(g["hmax"], nd["hmax"][gi])
+    Qo = t.moments()[gi]
+    scale = np.abs(Qo).max(axis=1, keepdims=True)
+    assert np.all(np.abs(g["Q"] - Qo) <= 1e-13 * scale)
+    # structure: children adjacent, leaves flagged consistently
+    internal = g["child"] >= 0
+    assert np.all((g["child"] >= 0) == (nd["left"][gi] >= 0))
+    c = g["child"][internal]
+    assert np.array_equal(g["lo"][c], g["lo"][internal])
+    assert np.array_equal(g["lo"][c + 1], g["lo"][c] + g["cnt"][c])
+    s.close()
+
+
+def _lists_equal(s, t, g, leaf_nodes, theta):
+    nd = t.nodes()
+    omap = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(nd["lo"], nd["hi"]))}
+    g2o = np.array([omap[(int(a), int(a + c))] for a, c in zip(g["lo"], g["cnt"])])
+    for li, node in enumerate(leaf_nodes):
+        dep, src, p2p = s.leaf_lists(li)
+        odep, osrc, op2p = t.leaf_lists(g2o[node], theta)
+        # oracle entries grouped by depth keeping their discovery order
+        order = np.argsort(odep, kind="stable")
+        assert np.array_equal(dep, odep[order])
+        assert np.array_equal(g2o[src], osrc[order])
+        assert np.array_equal(g2o[p2p], op2p)
+
+
+def test_lists_parity(torch, P, orc):
+    print("case: list parity, plummer N=4096 seed 1", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5)
+    g = s.tree(order=3)
+    leaf_nodes, depths = s.leaves()
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    assert len(leaf_nodes) == t.num_leaves
+    _lists_equal(s, t, g, leaf_nodes, 0.5)
+    st = s.stats()
+    ost = t.solve(0.5)[2]
+    assert st["n_m2l"] == ost["n_m2l"]
+    assert st["n_p2p_pairs"] == ost["n_p2p_pairs"]
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+def test_solve_parity_plummer(torch, P, orc, theta):
+    print(f"case: solve parity plummer N=4096 theta={theta}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta)
+    oa, op = orc.sfmm_solve(x, m, h, theta=theta)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 4])
+def test_solve_parity_orders(torch, P, orc, order):
+    print(f"case: solve parity order={order}", flush=True)
+    x, m, h = workloads.plummer(3000, seed=2)
+    acc, pot, _ = gpu_solve(torch, P, x, m, h, theta=0.6, order=order)
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.6, order=order)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+
+
+@pytest.mark.parametrize("n,leaf_size", [(1000, 10), (4097, 10), (12345, 10), (5000, 1),
+                                         (5000, 16)])
+def test_solve_parity_sizes(torch, P, orc, n, leaf_size):
+    print(f"case: ragged n={n} leaf_size={leaf_size}", flush=True)
+    x, m, h = workloads.polytrope(n, seed=3)
+    acc, pot, _ = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=leaf_size)
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=leaf_size)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+
+
+def test_theta_to_zero_equals_direct(torch, P, orc):
+    print("case: theta->0 direct", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=1e-9)
+    da, dp = orc.direct(x, m, h)
+    # only zero-size nodes (single particles) still pass the opening-angle
+    # test; their M2L is exact
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    mt, ms, _, _ = t.mutual_pairs(1e-9)
+    assert np.all(t.nodes()["l"][mt] + t.nodes()["l"][ms] == 0.0)
+    assert rel_err(acc, da).max() < TOL
+    assert pot_err(pot, dp) < TOL
+
+
+def test_duplicates_and_clumps(torch, P, orc):
+    print("case: duplicate positions", flush=True)
+    rng = np.random.default_rng(4)
+    base = rng.normal(size=(300, 3))
+    x = np.concatenate([base, base, base[:50], np.zeros((40, 3)), rng.normal(size=(500, 3))])
+    n = len(x)
+    m = rng.uniform(0.5, 1.5, n) / n
+    h = rng.uniform(0.01, 0.2, n)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=4)
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=4)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+
+
+def test_edge_cases(torch, P, orc):
+    print("case: edge cases", flush=True)
+    s = P.Solver()
+    e = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    z = torch.empty((0,), dtype=torch.float64, device="cuda")
+    a, p = s.solve(e, z, z)
+    assert a.shape == (0, 3)
+    # one particle
+    acc, pot, _ = gpu_solve(torch, P, [[0.1, 0.2, 0.3]], [2.0], [0.5], solver=s)
+    assert np.all(acc == 0) and pot[0] == pytest.approx(-2.0 * 1.4 / 0.5, rel=1e-15)
+    # at most leaf_size particles: one leaf, direct sum
+    x, m, h = workloads.plummer(10, seed=5)
+    acc, pot, _ = gpu_solve(torch, P, x, m, h, solver=s)
+    da, dp = orc.direct(x, m, h)
+    assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
+    # coincident particles
+    x = np.zeros((25, 3)); m = np.full(25, 0.5); h = np.full(25, 0.1)
+    acc, pot, _ = gpu_solve(torch, P, x, m, h, solver=s)
+    assert np.all(acc == 0)
+    assert pot == pytest.approx(np.full(25, -25 * 0.5 * 1.4 / 0.1), rel=1e-14)
+
+
+def test_invalid_inputs(torch, P):
+    print("case: invalid inputs", flush=True)
+    s = P.Solver()
+    x, m, h = dev(torch, *workloads.plummer(100, seed=6))
+    for th in (0.0, 1.0, -0.5, float("nan")):
+        with pytest.raises(P.SfmmError):
+            s.solve(x, m, h, theta=th)
+    with pytest.raises(P.SfmmError):
+        s.solve(x, m, h, order=5)
+    hb = h.clone(); hb[7] = 0.0
+    with pytest.raises(P.SfmmError, match="non-finite"):
+        s.solve(x, m, hb)
+    xb = x.clone(); xb[3, 1] = float("nan")
+    with pytest.raises(P.SfmmError, match="non-finite"):
+        s.solve(xb, m, h)
+    mb = m.clone(); mb[0] = -1.0
+    with pytest.raises(P.SfmmError, match="non-finite"):
+        s.solve(x, mb, h)
+    # the context still works after errors
+    acc, pot = s.solve(x, m, h)
+    assert torch.isfinite(acc).all()
+
+
+def test_deterministic_and_stream(torch, P):
+    print("case: determinism + side stream", flush=True)
+    x, m, h = dev(torch, *workloads.polytrope(20000, seed=7))
+    s = P.Solver()
+    a1, p1 = s.solve(x, m, h)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a2, p2 = s.solve(x, m, h)
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a1, a2) and torch.equal(p1, p2)
+
+
+def test_full_size_sampled(torch, P, orc):
+    """1e6-particle n=1.5 polytrope (the benchmark workload), FP64, p=3,
+    theta=0.5: sampled leaves against the oracle, all particles against the
+    momentum bound."""
+    print("case: full-size polytrope N=1e6 sampled", flush=True)
+    x, m, h = workloads.polytrope(1_000_000, seed=2)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5)
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+    rng = np.random.default_rng(0)
+    tg = rng.choice(len(m), 256, replace=False)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    oa, op, _ = t.solve(0.5, targets=tg)
+    nb = np.linalg.norm(oa, axis=1)
+    err = np.linalg.norm(acc[tg] - oa, axis=1) / nb
+    assert err.max() < TOL
+    assert (np.abs(pot[tg] - op) / np.abs(op)).max() < TOL
