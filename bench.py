@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--order", type=int, default=3)
     ap.add_argument("--leaf-size", type=int, default=10)
+    ap.add_argument("--walk", choices=["level", "leaf"], default="level",
+                    help="level: each (ancestor, source) test once per level; "
+                         "leaf: Algorithm 1 with one stack walk per leaf")
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -61,7 +64,7 @@ def main():
     log(f"generating polytrope N={args.n}")
     x, m, h = workloads.polytrope(args.n, seed=2)
     xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
-    solver = sfmm.Solver(leaf_size=args.leaf_size)
+    solver = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk)
     acc = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty((args.n,), dtype=torch.float64, device="cuda")
     log(f"warmup {args.warmup}")
@@ -110,7 +113,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"n=1.5 polytrope, N={args.n}, h from 58 neighbours, seed 2",
                    "N": args.n, "theta": args.theta, "order": p, "leaf_size": args.leaf_size,
-                   "precision": "fp64", "G": 1.0, "r_kern": 2.0},
+                   "precision": "fp64", "G": 1.0, "r_kern": 2.0, "walk": args.walk},
         "roofline": roofline,
         "phases": per_phase,
         "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l", "n_l2l",

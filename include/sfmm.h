@@ -60,12 +60,21 @@ typedef enum {
 
 typedef enum { SFMM_FP64 = 0 } sfmm_precision;
 
+/* How the interaction lists are found (both give every leaf the same pairs):
+ * SFMM_WALK_LEVEL  each (ancestor, source) test is made once, level by level
+ *                  from the root, and every leaf's list is the union of its
+ *                  ancestors' lists (default);
+ * SFMM_WALK_LEAF   Algorithm 1 literally: every leaf walks from (root, root)
+ *                  with its own stack. */
+typedef enum { SFMM_WALK_LEVEL = 0, SFMM_WALK_LEAF = 1 } sfmm_walk_mode;
+
 typedef struct {
   double G;                   /* gravitational constant (default 1)                   */
   int leaf_size;              /* a node with <= leaf_size particles is a leaf (10)    */
   double r_kern;              /* kernel support radius in units of h (2, cubic spline) */
   int include_self_potential; /* add -G m_i psi(0, h_i) to pot_i (1)                  */
   int check_inputs;           /* validate m, h and positions on the device (1)        */
+  int walk_mode;              /* sfmm_walk_mode (SFMM_WALK_LEVEL)                     */
 } sfmm_config;
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */

@@ -13,7 +13,7 @@
 namespace sfmm {
 namespace {
 
-template <int P>
+template <int P, bool NODE>
 __global__ __launch_bounds__(128) void k_far(FarArgs a) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
@@ -32,8 +32,8 @@ __global__ __launch_bounds__(128) void k_far(FarArgs a) {
 #pragma unroll
   for (int q = 0; q < NL; ++q) L[q] = 0.0;
   bool have = false;
-  uint64_t e = a.m2l_off[l];
-  const uint64_t end = a.m2l_off[l + 1];
+  uint64_t e = NODE ? 0 : a.m2l_off[l];
+  const uint64_t end = NODE ? 0 : a.m2l_off[l + 1];
   int v = 0;
   double sv[3] = {rec[0], rec[1], rec[2]};
   for (int k = 0; k <= d; ++k) {
@@ -49,9 +49,16 @@ __global__ __launch_bounds__(128) void k_far(FarArgs a) {
       v = nv;
       sv[0] = sn[0]; sv[1] = sn[1]; sv[2] = sn[2];
     }
-    while (e < end) {
-      const uint32_t ent = a.m2l_list[e];
-      if ((int)(ent >> kSrcBits) != k) break;
+    uint64_t ne = end;
+    const uint32_t* list = a.m2l_list;
+    if (NODE) {
+      e = a.node_m2l_off[v];
+      ne = e + a.node_m2l_cnt[v];
+      list = a.node_m2l_pool;
+    }
+    while (e < ne) {
+      const uint32_t ent = list[e];
+      if (!NODE && (int)(ent >> kSrcBits) != k) break;
       const double* rs = rec + (int64_t)(ent & kSrcMask) * RS;
       const double r[3] = {rs[0] - sv[0], rs[1] - sv[1], rs[2] - sv[2]};
       double Q[NQ];
@@ -73,16 +80,22 @@ __global__ __launch_bounds__(128) void k_far(FarArgs a) {
 
 }  // namespace
 
-void launch_far(int order, const FarArgs& a, hipStream_t s) {
-  if (a.nleaves <= 0) return;
+template <bool NODE>
+void far_dispatch(int order, const FarArgs& a, hipStream_t s) {
   const unsigned nb = (unsigned)((a.nleaves + 127) / 128);
   switch (order) {
-    case 0: k_far<0><<<nb, 128, 0, s>>>(a); break;
-    case 1: k_far<1><<<nb, 128, 0, s>>>(a); break;
-    case 2: k_far<2><<<nb, 128, 0, s>>>(a); break;
-    case 3: k_far<3><<<nb, 128, 0, s>>>(a); break;
-    case 4: k_far<4><<<nb, 128, 0, s>>>(a); break;
+    case 0: k_far<0, NODE><<<nb, 128, 0, s>>>(a); break;
+    case 1: k_far<1, NODE><<<nb, 128, 0, s>>>(a); break;
+    case 2: k_far<2, NODE><<<nb, 128, 0, s>>>(a); break;
+    case 3: k_far<3, NODE><<<nb, 128, 0, s>>>(a); break;
+    case 4: k_far<4, NODE><<<nb, 128, 0, s>>>(a); break;
   }
+}
+
+void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  if (node_lists) far_dispatch<true>(order, a, s);
+  else far_dispatch<false>(order, a, s);
 }
 
 }  // namespace sfmm

@@ -37,16 +37,28 @@ __device__ __forceinline__ void soft(double r, double hinv, double& g, double& p
   }
 }
 
+template <bool NODE>
 __global__ __launch_bounds__(256) void k_near(NearArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const double xi = a.xs[i], yi = a.ys[i], zi = a.zs[i], hi = a.hs[i];
   const double hinv_i = 1.0 / hi;
   const int leaf = a.p_leaf[i];
-  const uint64_t e0 = a.p2p_off[leaf], e1 = a.p2p_off[leaf + 1];
+  uint64_t e0, e1;
+  const int32_t* list;
+  if (NODE) {
+    const int node = a.leaf_node[leaf];
+    e0 = a.node_p2p_off[node];
+    e1 = e0 + a.node_p2p_cnt[node];
+    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    e0 = a.p2p_off[leaf];
+    e1 = a.p2p_off[leaf + 1];
+    list = a.p2p_list;
+  }
   double fx = 0.0, fy = 0.0, fz = 0.0, ph = 0.0;
   for (uint64_t e = e0; e < e1; ++e) {
-    const NodeInfo si = a.info[a.p2p_list[e]];
+    const NodeInfo si = a.info[list[e]];
     for (int j = si.lo; j < si.lo + si.cnt; ++j) {
       if (j == i) continue;
       const double dx = xi - a.xs[j], dy = yi - a.ys[j], dz = zi - a.zs[j];
@@ -118,18 +130,29 @@ __global__ __launch_bounds__(MOM_THREADS) void k_momentum_partial(int n, const d
   if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_momentum_final(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  if (threadIdx.x >= 4) return;
+__global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __restrict__ part,
+                                                        double* __restrict__ out) {
+  // fixed summation tree: thread t sums partials t, t+64, ... of component
+  // t / 64, then a fixed pairwise reduction
+  __shared__ double sh[256];
+  const int c = threadIdx.x >> 6, t = threadIdx.x & 63;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[4 * b + threadIdx.x];
-  out[threadIdx.x] = s;
+  for (int b = t; b < nb; b += 64) s += part[4 * b + c];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 32; w > 0; w >>= 1) {
+    if (t < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (t == 0) out[c] = sh[threadIdx.x];
 }
 
 }  // namespace
 
-void launch_near(const NearArgs& a, hipStream_t s) {
+void launch_near(bool node_lists, const NearArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
-  k_near<<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
 }
 
 int momentum_blocks(int64_t n) {
@@ -143,7 +166,7 @@ void launch_momentum(int n, const double* m, const double* acc, double* part, do
                      hipStream_t s) {
   const int nb = momentum_blocks(n);
   k_momentum_partial<<<nb, MOM_THREADS, 0, s>>>(n, m, acc, part);
-  k_momentum_final<<<1, 64, 0, s>>>(nb, part, out);
+  k_momentum_final<<<1, 256, 0, s>>>(nb, part, out);
 }
 
 }  // namespace sfmm

@@ -1,0 +1,372 @@
+// k_nodewalk.hip -- level-synchronous form of the dual tree walk.
+//
+// In Algorithm 1 (Sect. 3) every leaf walks from (root, root) down its own
+// branch; the pairs a leaf tests against its ancestor p_k, and their outcome,
+// depend only on p_k, so all leaves below p_k repeat them.  Here each node
+// is visited once, level by level from the root:
+//   tested(v) = expand(opened(parent(v)))   (a leaf source stays, an
+//               internal source is replaced by its two children; for the
+//               root, tested = {root})
+// and each tested source is, as in Algorithm 2,
+//   the node itself            -> opened
+//   accepted (MAC + softening) -> M2L entry of v
+//   otherwise                  -> opened
+// An internal v hands its opened list to its children.  A leaf v lowers
+// its opened sources in place: a leaf source becomes a P2P entry, an
+// internal one is replaced by its children and tested against v again.
+// The list of leaf L in Algorithm 1 is exactly the concatenation of the
+// M2L lists of p_0 .. p_d plus L's P2P list (same pairs; the order inside a
+// depth differs).
+//
+// One wave (a 64-thread block) per node; lanes take 64 sources at a time.
+// Each level runs three kernels: a count pass (list sizes per node), a
+// one-block scan that places every node's lists after those of the nodes
+// before it (running pool totals stay on the device), and a fill pass that
+// repeats the tests and writes in lane order.  The layout of the pools is
+// therefore the same on every run.
+#include "sfmm_internal.h"
+
+namespace sfmm {
+namespace {
+
+__device__ __forceinline__ bool accept(const double* __restrict__ rt, const double* __restrict__ rs,
+                                       double theta2, double r_kern) {
+  const double dx = rs[0] - rt[0];
+  const double dy = rs[1] - rt[1];
+  const double dz = rs[2] - rt[2];
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double lsum = rt[3] + rs[3];
+  const double hm = fmax(rt[4], rs[4]);
+  const double rsum = lsum + r_kern * hm;
+  return (lsum * lsum < theta2 * d2) && (d2 >= rsum * rsum);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// exclusive prefix over the wave of a small non-negative count (< 8) and the
+// wave total
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t c, uint32_t& total) {
+  const uint64_t lt = lanemask_lt();
+  uint32_t pre = 0;
+  total = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    const uint64_t m = __ballot((c >> b) & 1u);
+    pre += (uint32_t)__popcll(m & lt) << b;
+    total += (uint32_t)__popcll(m) << b;
+  }
+  return pre;
+}
+
+__global__ void k_node_depth(int nn, const NodeInfo* __restrict__ info, int32_t* __restrict__ depth,
+                             uint64_t* __restrict__ key, uint32_t* __restrict__ ids) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  int d = 0;
+  for (int u = info[v].parent; u >= 0; u = info[u].parent) ++d;
+  depth[v] = d;
+  key[v] = (uint64_t)min(d, 255);
+  ids[v] = (uint32_t)v;
+}
+
+__global__ void k_level_offsets(int nlev, int nb, int nn, const uint32_t* __restrict__ hist,
+                                uint32_t* __restrict__ level_off) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > nlev) return;
+  level_off[k] = k < nlev ? hist[(int64_t)k * nb] : (uint32_t)nn;
+}
+
+// ---- one level -----------------------------------------------------------------
+struct Emit {
+  // reserved bases (uniform) and running offsets
+  uint32_t m2l_base, open_base, p2p_base;
+  uint32_t m2l_run, open_run, p2p_run;
+};
+
+template <bool WRITE>
+__device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint32_t s0, uint32_t s1,
+                                           uint32_t nm, uint32_t sel_m, uint32_t no,
+                                           uint32_t sel_o, bool to_p2p) {
+  // nm entries (first from s0 if sel_m & 1, then s1 if sel_m & 2) go to M2L;
+  // no entries to the opened (or P2P) list likewise
+  uint32_t tm, to;
+  const uint32_t pm = wave_prefix(nm, tm);
+  const uint32_t po = wave_prefix(no, to);
+  if (WRITE) {
+    uint32_t k = e.m2l_base + e.m2l_run + pm;
+    if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
+    if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
+    if (to_p2p) {
+      uint32_t q = e.p2p_base + e.p2p_run + po;
+      if (sel_o & 1u) { if (q < a.p2p_cap) a.p2p_pool[q] = s0; ++q; }
+      if (sel_o & 2u) { if (q < a.p2p_cap) a.p2p_pool[q] = s1; }
+    } else {
+      uint32_t q = e.open_base + e.open_run + po;
+      if (sel_o & 1u) { if (q < a.open_cap) a.open_pool[q] = s0; ++q; }
+      if (sel_o & 2u) { if (q < a.open_cap) a.open_pool[q] = s1; }
+    }
+  }
+  e.m2l_run += tm;
+  if (to_p2p) e.p2p_run += to; else e.open_run += to;
+}
+
+// classification of one tested source against target v
+// returns 0 = M2L, 1 = opened
+__device__ __forceinline__ int classify(const NodeWalkArgs& a, int v, const double* rv, uint32_t s) {
+  if ((int)s == v) return 1;
+  return accept(rv, a.rec + (int64_t)s * a.stride, a.theta2, a.r_kern) ? 0 : 1;
+}
+
+template <bool WRITE>
+__device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
+                              uint32_t nsrc, Emit& e) {
+  for (uint32_t base = 0; base < nsrc; base += 64) {
+    const uint32_t i = base + (threadIdx.x & 63);
+    uint32_t t0 = 0, t1 = 0;
+    int nt = 0;
+    if (i < nsrc) {
+      const uint32_t s = src[i];
+      const int c = a.info[s].child;
+      if (c < 0) { t0 = s; nt = 1; }
+      else { t0 = (uint32_t)c; t1 = (uint32_t)c + 1u; nt = 2; }
+    }
+    uint32_t selm = 0, selo = 0, nm = 0, no = 0;
+    if (nt >= 1) { if (classify(a, v, rv, t0) == 0) { selm |= 1u; ++nm; } else { selo |= 1u; ++no; } }
+    if (nt >= 2) { if (classify(a, v, rv, t1) == 0) { selm |= 2u; ++nm; } else { selo |= 2u; ++no; } }
+    emit_lists<WRITE>(a, e, t0, t1, nm, selm, no, selo, false);
+  }
+}
+
+// leaf target: tested sources from the parent's opened list, 64 at a time;
+// after each chunk the lowering stack (in LDS) is drained, 64 entries per
+// step, so the stack stays within a few chunks per tree level
+template <bool WRITE>
+__device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv, uint32_t t0,
+                                          uint32_t t1, int nt, Emit& e, uint32_t* stk,
+                                          uint32_t& sp) {
+  uint32_t selm = 0, selp = 0, nm = 0, np = 0, npush = 0;
+  uint32_t push[4];
+  for (int q = 0; q < nt; ++q) {
+    const uint32_t t = q ? t1 : t0;
+    if (classify(a, v, rv, t) == 0) { selm |= 1u << q; ++nm; continue; }
+    const int c = a.info[t].child;
+    if (c < 0) { selp |= 1u << q; ++np; }
+    else { push[npush++] = (uint32_t)c; push[npush++] = (uint32_t)c + 1u; }
+  }
+  emit_lists<WRITE>(a, e, t0, t1, nm, selm, np, selp, true);
+  uint32_t tpush;
+  const uint32_t pp = wave_prefix(npush, tpush);
+  if (sp + tpush > a.stack_cap) return false;
+  for (uint32_t q = 0; q < npush; ++q) stk[sp + pp + q] = push[q];
+  __syncthreads();
+  sp += tpush;
+  return true;
+}
+
+template <bool WRITE>
+__device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
+                          uint32_t nsrc, bool root, Emit& e, uint32_t* stk, int* status) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t n0 = root ? 1u : nsrc;
+  uint32_t sp = 0;
+  bool ok = true;
+  for (uint32_t base = 0; base < n0 && ok; base += 64) {
+    uint32_t t0 = 0, t1 = 0;
+    int nt = 0;
+    const uint32_t i = base + lane;
+    if (i < n0) {
+      if (root) { t0 = (uint32_t)v; nt = 1; }
+      else {
+        const uint32_t s = src[i];
+        const int c = a.info[s].child;
+        if (c < 0) { t0 = s; nt = 1; }
+        else { t0 = (uint32_t)c; t1 = (uint32_t)c + 1u; nt = 2; }
+      }
+    }
+    ok = leaf_step<WRITE>(a, v, rv, t0, t1, nt, e, stk, sp);
+    while (ok && sp > 0) {
+      const uint32_t k = sp < 64u ? sp : 64u;
+      uint32_t t = 0;
+      const int n1 = lane < k ? 1 : 0;
+      if (n1) t = stk[sp - k + lane];
+      __syncthreads();
+      sp -= k;
+      ok = leaf_step<WRITE>(a, v, rv, t, 0u, n1, e, stk, sp);
+    }
+  }
+  if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
+}
+
+// count (FILL = false) or fill (FILL = true) pass of one level
+template <bool FILL>
+__global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level) {
+  extern __shared__ uint32_t stk[];
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t idx = beg + blockIdx.x;
+  if (idx >= end) return;
+  const int v = a.level_nodes[idx];
+  const NodeInfo vi = a.info[v];
+  const double* rv = a.rec + (int64_t)v * a.stride;
+  const bool root = vi.parent < 0;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t* src = nullptr;
+  uint32_t nsrc = 0;
+  if (!root) {
+    const uint32_t po = a.open_off[vi.parent];
+    nsrc = a.open_cnt[vi.parent];
+    src = a.open_pool + po;
+    if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
+  }
+  Emit e{};
+  if (FILL) {
+    // absolute pool offsets from the level scan: low word M2L, high word
+    // the opened (internal node) or P2P (leaf) list
+    const uint64_t off = a.lvl_off[idx];
+    e.m2l_base = (uint32_t)off;
+    const uint32_t hi = (uint32_t)(off >> 32);
+    if (lane == 0) a.m2l_off[v] = e.m2l_base;
+    if (vi.child >= 0) {
+      e.open_base = hi;
+      if (lane == 0) a.open_off[v] = e.open_base;
+    } else {
+      e.p2p_base = hi;
+      if (lane == 0) { a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
+    }
+  }
+  if (vi.child >= 0) {
+    if (root) {
+      // (root, root) is opened: both root children meet both root children
+      if (lane == 0) {
+        if (FILL) { if (e.open_base < a.open_cap) a.open_pool[e.open_base] = (uint32_t)v; }
+        else { a.m2l_cnt[v] = 0; a.open_cnt[v] = 1; a.lvl_cnt[idx] = 1ull << 32; }
+      }
+      return;
+    }
+    walk_internal<FILL>(a, v, rv, src, nsrc, e);
+    if (!FILL && lane == 0) {
+      a.m2l_cnt[v] = e.m2l_run;
+      a.open_cnt[v] = e.open_run;
+      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)e.open_run << 32);  // bit 63 clear: internal
+    }
+  } else {
+    walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
+    if (!FILL && lane == 0) {
+      a.m2l_cnt[v] = e.m2l_run;
+      a.p2p_cnt[v] = e.p2p_run;
+      a.open_cnt[v] = 0;
+      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)e.p2p_run << 32) | (1ull << 63);
+    }
+  }
+}
+
+// Places one level's lists: a scan, in level order, of the packed counts
+// (bits 0-31 M2L, 32-62 the opened list of an internal node or the P2P
+// list of a leaf, bit 63 set for a leaf) into absolute pool offsets, after
+// everything placed by earlier levels; then the running pool sizes advance.
+// One block.
+constexpr int SCAN_T = 1024;
+constexpr int SCAN_I = 4;
+__global__ __launch_bounds__(SCAN_T) void k_nodewalk_scan(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  __shared__ uint32_t sm[SCAN_T], so[SCAN_T], sp[SCAN_T];
+  __shared__ uint32_t carry[3];
+  if (threadIdx.x < 3) carry[threadIdx.x] = a.run[threadIdx.x];
+  __syncthreads();
+  for (uint32_t base = beg; base < end; base += SCAN_T * SCAN_I) {
+    uint64_t v[SCAN_I];
+    uint32_t cm = 0, co = 0, cp = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_I; ++q) {
+      const uint32_t i = base + threadIdx.x * SCAN_I + q;
+      v[q] = i < end ? a.lvl_cnt[i] : 0ull;
+      const uint32_t b = (uint32_t)(v[q] >> 32) & 0x7fffffffu;
+      cm += (uint32_t)v[q];
+      if (v[q] >> 63) cp += b; else co += b;
+    }
+    sm[threadIdx.x] = cm; so[threadIdx.x] = co; sp[threadIdx.x] = cp;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+      uint32_t xm = 0, xo = 0, xp = 0;
+      if ((int)threadIdx.x >= off) {
+        xm = sm[threadIdx.x - off]; xo = so[threadIdx.x - off]; xp = sp[threadIdx.x - off];
+      }
+      __syncthreads();
+      sm[threadIdx.x] += xm; so[threadIdx.x] += xo; sp[threadIdx.x] += xp;
+      __syncthreads();
+    }
+    uint32_t rm = carry[0] + sm[threadIdx.x] - cm;
+    uint32_t ro = carry[1] + so[threadIdx.x] - co;
+    uint32_t rp = carry[2] + sp[threadIdx.x] - cp;
+#pragma unroll
+    for (int q = 0; q < SCAN_I; ++q) {
+      const uint32_t i = base + threadIdx.x * SCAN_I + q;
+      const uint32_t b = (uint32_t)(v[q] >> 32) & 0x7fffffffu;
+      const bool leaf = (v[q] >> 63) != 0;
+      if (i < end) a.lvl_off[i] = (uint64_t)rm | ((uint64_t)(leaf ? rp : ro) << 32);
+      rm += (uint32_t)v[q];
+      if (leaf) rp += b; else ro += b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry[0] += sm[SCAN_T - 1];
+      carry[1] += so[SCAN_T - 1];
+      carry[2] += sp[SCAN_T - 1];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) a.run[threadIdx.x] = carry[threadIdx.x];
+}
+
+__global__ void k_leaf_stats(LeafStatArgs a) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.nleaves) return;
+  const int leaf = a.leaf_node[l];
+  const int d = a.leaf_depth[l];
+  const NodeInfo li = a.info[leaf];
+  int v = 0;
+  uint64_t m2l = a.m2l_cnt[0];
+  int kfirst = m2l > 0 ? 0 : -1;
+  for (int k = 1; k <= d; ++k) {
+    const int c = a.info[v].child;
+    v = (li.lo < a.info[c + 1].lo) ? c : c + 1;
+    const uint32_t mc = a.m2l_cnt[v];
+    if (mc > 0 && kfirst < 0) kfirst = k;
+    m2l += mc;
+  }
+  uint64_t src = 0;
+  const uint32_t off = a.p2p_off[leaf], cnt = a.p2p_cnt[leaf];
+  for (uint32_t q = 0; q < cnt; ++q) src += (uint64_t)a.info[a.p2p_pool[off + q]].cnt;
+  a.m2l[l] = m2l;
+  a.l2l[l] = kfirst < 0 ? 0u : (uint64_t)(d - kfirst);
+  a.pairs[l] = src * (uint64_t)li.cnt - (uint64_t)li.cnt;
+}
+
+}  // namespace
+
+void launch_leaf_stats(const LeafStatArgs& a, hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  k_leaf_stats<<<(a.nleaves + 127) / 128, 128, 0, s>>>(a);
+}
+
+void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* key,
+                       uint32_t* ids, hipStream_t s) {
+  k_node_depth<<<(nn + 255) / 256, 256, 0, s>>>(nn, info, depth, key, ids);
+}
+
+void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
+                          uint32_t* level_off, hipStream_t s) {
+  k_level_offsets<<<(nlev + 1 + 255) / 256, 256, 0, s>>>(nlev, nb, nn, hist_scanned, level_off);
+}
+
+void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s) {
+  if (nodes_in_level <= 0) return;
+  const size_t lds = a.stack_cap * sizeof(uint32_t);
+  k_nodewalk_pass<false><<<nodes_in_level, 64, lds, s>>>(a, level);
+  k_nodewalk_scan<<<1, SCAN_T, 0, s>>>(a, level);
+  k_nodewalk_pass<true><<<nodes_in_level, 64, lds, s>>>(a, level);
+}
+
+}  // namespace sfmm

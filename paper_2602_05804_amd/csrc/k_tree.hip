@@ -66,15 +66,26 @@ __global__ __launch_bounds__(BBOX_THREADS) void k_bbox_partial(int n, const doub
 }
 
 // box[0..2] = min corner, box[3] = cube extent, box[4] = 2^21 / extent (0 if flat)
-__global__ void k_bbox_final(int nb, const double* __restrict__ part, double* __restrict__ box) {
-  if (threadIdx.x != 0) return;
-  double mn[3], mx[3];
-  for (int d = 0; d < 3; ++d) { mn[d] = part[d]; mx[d] = part[3 + d]; }
-  for (int b = 1; b < nb; ++b)
+__global__ __launch_bounds__(256) void k_bbox_final(int nb, const double* __restrict__ part,
+                                                    double* __restrict__ box) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += 256)
     for (int d = 0; d < 3; ++d) {
       mn[d] = fmin(mn[d], part[6 * b + d]);
       mx[d] = fmax(mx[d], part[6 * b + 3 + d]);
     }
+  __shared__ double sh[6][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 0; d < 3; ++d) {
+    const double a = wave_min(mn[d]), c = wave_max(mx[d]);
+    if (lane == 0) { sh[d][w] = a; sh[3 + d][w] = c; }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int d = 0; d < 3; ++d) {
+    mn[d] = fmin(fmin(sh[d][0], sh[d][1]), fmin(sh[d][2], sh[d][3]));
+    mx[d] = fmax(fmax(sh[3 + d][0], sh[3 + d][1]), fmax(sh[3 + d][2], sh[3 + d][3]));
+  }
   double ext = 0.0;
   for (int d = 0; d < 3; ++d) {
     double e = mx[d] - mn[d];
@@ -300,21 +311,27 @@ __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
   for (int p = ni.lo; p < ni.lo + ni.cnt; ++p) p_leaf[p] = l;
 }
 
-// ---- geometry, moments (bottom-up) ------------------------------------------
+// ---- geometry, moments (bottom-up, one launch per depth) ------------------
+// A leaf sums its particles in sorted order; an internal node combines its
+// two children (children first: the deepest level is launched first).
 template <int P>
-__global__ void k_upsweep(int nleaves, const int32_t* __restrict__ leaf_node,
-                          const NodeInfo* __restrict__ info, const double* __restrict__ xs,
-                          const double* __restrict__ ys, const double* __restrict__ zs,
-                          const double* __restrict__ ms, const double* __restrict__ hs,
-                          double* rec, uint32_t* visit) {
+__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
+                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                             const double* __restrict__ ys, const double* __restrict__ zs,
+                             const double* __restrict__ ms, const double* __restrict__ hs,
+                             double* __restrict__ rec) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int RS = rec_stride(P);
-  int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= nleaves) return;
-  int v = leaf_node[l];
-  {
-    const NodeInfo ni = info[v];
+  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  const int v = level_nodes[idx];
+  const NodeInfo ni = info[v];
+  double* r = rec + (int64_t)v * RS;
+  double Q[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
+  if (ni.child < 0) {
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double mj = ms[j];
@@ -326,64 +343,38 @@ __global__ void k_upsweep(int nleaves, const int32_t* __restrict__ leaf_node,
     }
     const double s0 = S0 / M, s1 = S1 / M, s2 = S2 / M;
     double d2max = 0.0;
-    double Q[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double b[3] = {xs[j] - s0, ys[j] - s1, zs[j] - s2};
       const double d2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
       d2max = fmax(d2max, d2);
       E::p2m_add(b, ms[j], Q);
     }
-    double* r = rec + (int64_t)v * RS;
     r[0] = s0; r[1] = s1; r[2] = s2; r[3] = sqrt(d2max); r[4] = hm; r[5] = M;
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
-  }
-  // climb: the second child to finish computes the parent
-  for (;;) {
-    const int p = info[v].parent;
-    if (p < 0) break;
-    __threadfence();
-    const uint32_t old =
-        __hip_atomic_fetch_add(&visit[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0u) break;
-    __threadfence();
-    const int c = info[p].child;
-    const double* rl = rec + (int64_t)c * RS;
-    const double* rr = rec + (int64_t)(c + 1) * RS;
-    const double ML = rl[5];
-    const double MR = rr[5];
-    double sl[3], sr[3];
-    for (int d = 0; d < 3; ++d) {
-      sl[d] = rl[d];
-      sr[d] = rr[d];
-    }
+  } else {
+    const double* rl = rec + (int64_t)ni.child * RS;
+    const double* rr = rl + RS;
+    const double ML = rl[5], MR = rr[5];
     const double M = ML + MR;
     double s[3];
-    for (int d = 0; d < 3; ++d) s[d] = (ML * sl[d] + MR * sr[d]) / M;
+    for (int d = 0; d < 3; ++d) s[d] = (ML * rl[d] + MR * rr[d]) / M;
     const double hm = fmax(rl[4], rr[4]);
-    double Q[NQ], Qc[NQ];
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
+    double Qc[NQ];
     {
-      const double g[3] = {sl[0] - s[0], sl[1] - s[1], sl[2] - s[2]};
+      const double g[3] = {rl[0] - s[0], rl[1] - s[1], rl[2] - s[2]};
 #pragma unroll
       for (int k = 0; k < NQ; ++k) Qc[k] = rl[8 + k];
       E::m2m_add(g, Qc, Q);
     }
     {
-      const double g[3] = {sr[0] - s[0], sr[1] - s[1], sr[2] - s[2]};
+      const double g[3] = {rr[0] - s[0], rr[1] - s[1], rr[2] - s[2]};
 #pragma unroll
       for (int k = 0; k < NQ; ++k) Qc[k] = rr[8 + k];
       E::m2m_add(g, Qc, Q);
     }
-    double* r = rec + (int64_t)p * RS;
     r[0] = s[0]; r[1] = s[1]; r[2] = s[2]; r[4] = hm; r[5] = M;
-#pragma unroll
-    for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
-    v = p;
   }
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
 }
 
 __global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
@@ -453,7 +444,7 @@ void launch_bbox(int n, const double* x, const double* m, const double* h, doubl
                  double* box, int* status, int check, hipStream_t s) {
   int nb = bbox_blocks(n);
   k_bbox_partial<<<nb, BBOX_THREADS, 0, s>>>(n, x, m, h, part, status, check);
-  k_bbox_final<<<1, 64, 0, s>>>(nb, part, box);
+  k_bbox_final<<<1, 256, 0, s>>>(nb, part, box);
 }
 
 void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint32_t* idx,
@@ -462,6 +453,15 @@ void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint3
 }
 
 int radix_blocks(int64_t n) { return (int)((n + RS_TILE - 1) / RS_TILE); }
+
+void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
+                hipStream_t s) {
+  const int nb = radix_blocks(n);
+  k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
+  scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+  k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
+}
 
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
                 uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s) {
@@ -513,16 +513,21 @@ void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* in
                                                         p_leaf, maxdepth);
 }
 
-void launch_upsweep(int order, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
-                    const double* xs, const double* ys, const double* zs, const double* ms,
-                    const double* hs, double* rec, uint32_t* visit, hipStream_t s) {
-  const unsigned nb = blocks_for(nleaves, 128);
-  switch (order) {
-    case 0: k_upsweep<0><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
-    case 1: k_upsweep<1><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
-    case 2: k_upsweep<2><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
-    case 3: k_upsweep<3><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
-    case 4: k_upsweep<4><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec, visit); break;
+void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
+                     const int32_t* level_nodes, const NodeInfo* info, const double* xs,
+                     const double* ys, const double* zs, const double* ms, const double* hs,
+                     double* rec, hipStream_t s) {
+  for (int k = maxdepth; k >= 0; --k) {
+    const uint32_t beg = level_off_host[k], end = level_off_host[k + 1];
+    if (end <= beg) continue;
+    const unsigned nb = blocks_for(end - beg, 128);
+    switch (order) {
+      case 0: k_geom_level<0><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 1: k_geom_level<1><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 2: k_geom_level<2><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 3: k_geom_level<3><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 4: k_geom_level<4><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+    }
   }
 }
 

@@ -27,10 +27,13 @@ enum BufId {
   B_KEY0, B_KEY1, B_VAL0, B_VAL1, B_HIST, B_SCANTMP,
   B_XS, B_YS, B_ZS, B_MS, B_HS,
   B_KFIRST, B_KLAST, B_KLEFT, B_KRIGHT, B_KPAR, B_KSIDE, B_KEPT,
-  B_LFLAG, B_LAT, B_INFO, B_REC, B_VISIT, B_L2BITS, B_CHUNK,
+  B_LFLAG, B_LAT, B_INFO, B_REC, B_L2BITS, B_CHUNK,
   B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
   B_LDOFF, B_DEPTHCNT, B_M2LCNT, B_P2PCNT, B_PAIRCNT, B_M2L, B_P2P,
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
+  B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES,
+  B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
+  B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_COUNT
 };
 
@@ -57,6 +60,11 @@ struct sfmm_ctx {
   int timing_cap = 0, timing_used = 0;
   bool timing = false;
   hipEvent_t order_ev = nullptr;  // orders work across a stream change
+  // level walk: nodes per depth (host copy) and pool capacities
+  std::vector<uint32_t> level_off;
+  uint64_t m2l_cap = 0, open_cap = 0, p2p_cap = 0;
+  uint32_t stack_cap = 0;
+  bool stats_pending = false;  // level walk: totals still on the device
   bool have_tree = false, have_lists = false, have_mom = false;
   sfmm_stats stats{};
 };
@@ -123,7 +131,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
              int order) {
   if (n64 < 0 || n64 >= (int64_t(1) << 30)) return fail(ctx, SFMM_EINVAL, "n out of range");
   if (order < 0 || order > kMaxOrder) return fail(ctx, SFMM_EINVAL, "order must be 0..4");
-  ctx->have_tree = ctx->have_lists = ctx->have_mom = false;
+  ctx->have_tree = ctx->have_lists = ctx->have_mom = ctx->stats_pending = false;
   ctx->n = n64;
   ctx->order = order;
   if (n64 == 0) {
@@ -156,7 +164,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
       {B_KEPT, sizeof(uint32_t) * (n + 1)},
       {B_LFLAG, sizeof(uint32_t) * (n + 1)}, {B_LAT, sizeof(int32_t) * n},
       {B_INFO, sizeof(NodeInfo) * nmax_nodes}, {B_REC, sizeof(double) * RS * (size_t)nmax_nodes},
-      {B_VISIT, sizeof(uint32_t) * nmax_nodes}, {B_L2BITS, sizeof(uint64_t) * nmax_nodes},
+      {B_L2BITS, sizeof(uint64_t) * nmax_nodes},
       {B_CHUNK, sizeof(uint32_t) * (nmax_nodes + 1)},
       {B_LEAFNODE, sizeof(int32_t) * n}, {B_LEAFDEPTH, sizeof(int32_t) * n},
       {B_PLEAF, sizeof(int32_t) * n},
@@ -219,14 +227,29 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     ctx->nleaves = (int64_t)(hsmall[S_NLEAVES] & 0xffffffffu);
   }
   const int nn = (int)ctx->nn, nl = (int)ctx->nleaves;
+  // node depths and nodes grouped by depth (level walk): one stable radix
+  // pass on the depth
+  {
+    struct { int id; size_t bytes; } need2[] = {
+        {B_NDEPTH, sizeof(int32_t) * nn}, {B_LEVNODES, sizeof(uint32_t) * nn},
+        {B_LEVKEY0, sizeof(uint64_t) * nn}, {B_LEVKEY1, sizeof(uint64_t) * nn},
+        {B_LEVIDS, sizeof(uint32_t) * nn}, {B_LEVOFF, sizeof(uint32_t) * (kMaxDepthCap + 2)},
+        {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(nn)},
+        {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(nn), 2 * (int64_t)n + 2))}};
+    for (auto& q : need2)
+      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+    launch_node_depth(nn, info, P<int32_t>(ctx, B_NDEPTH), P<uint64_t>(ctx, B_LEVKEY0),
+                      P<uint32_t>(ctx, B_LEVIDS), s);
+    radix_pass(nn, P<uint64_t>(ctx, B_LEVKEY0), P<uint32_t>(ctx, B_LEVIDS),
+               P<uint64_t>(ctx, B_LEVKEY1), P<uint32_t>(ctx, B_LEVNODES), 0,
+               P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
+               reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+    launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn, P<uint32_t>(ctx, B_HIST),
+                         P<uint32_t>(ctx, B_LEVOFF), s);
+  }
   int* maxd_dev = reinterpret_cast<int*>(small + S_MAXDEPTH);
   launch_leaf_depth(nl, leaf_node, info, P<int32_t>(ctx, B_LEAFDEPTH), P<int32_t>(ctx, B_PLEAF),
                     maxd_dev, s);
-  // ---- geometry and moments
-  HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_VISIT), 0, sizeof(uint32_t) * nn, s));
-  launch_upsweep(order, nl, leaf_node, info, P<double>(ctx, B_XS), P<double>(ctx, B_YS),
-                 P<double>(ctx, B_ZS), P<double>(ctx, B_MS), P<double>(ctx, B_HS),
-                 P<double>(ctx, B_REC), P<uint32_t>(ctx, B_VISIT), s);
   if (nn > 1) {
     uint32_t* chunk = P<uint32_t>(ctx, B_CHUNK);
     launch_extent_count(nn, info, chunk, s);
@@ -235,9 +258,17 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     HIPCHK(hipMemsetAsync(P<uint64_t>(ctx, B_L2BITS), 0, sizeof(uint64_t) * nn, s));
   }
   HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  ctx->level_off.resize(kMaxDepthCap + 2);
+  HIPCHK(hipMemcpyAsync(ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
+                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
   if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
+  // ---- geometry and moments, level by level from the deepest
+  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(),
+                  reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
+                  P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
+                  P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_REC), s);
   if (nn > 1) {
     const int nitems = (int)(hsmall[S_NITEMS] & 0xffffffffu);
     launch_extent(order, nn, nitems, info, P<uint32_t>(ctx, B_CHUNK), P<double>(ctx, B_XS),
@@ -252,26 +283,14 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   return SFMM_OK;
 }
 
-int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, double* pot) {
+// Algorithm 1 per leaf: count pass, list sizes to the host, fill pass
+int walk_per_leaf(sfmm_ctx* ctx, double theta) {
   int rc;
   const hipStream_t s = ctx->stream;
-  const int n = (int)ctx->n, nl = (int)ctx->nleaves;
-  const int RS = rec_stride(ctx->order);
+  const int nl = (int)ctx->nleaves;
   uint64_t* small = P<uint64_t>(ctx, B_SMALL);
   int* status = P<int>(ctx, B_STATUS);
-  // per-(leaf, depth) count storage
-  struct { int id; size_t bytes; } need[] = {
-      {B_LDOFF, sizeof(uint64_t) * (nl + 1)}, {B_M2LCNT, sizeof(uint64_t) * (nl + 1)},
-      {B_P2PCNT, sizeof(uint64_t) * (nl + 1)}, {B_PAIRCNT, sizeof(uint64_t) * (nl + 1)},
-      {B_L2LCNT, sizeof(uint64_t) * (nl + 1)},
-      {B_FAR, sizeof(double) * 4 * (size_t)n},
-      {B_MOMPART, sizeof(double) * 4 * momentum_blocks(n)}, {B_MOM, sizeof(double) * 4},
-      {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(nl + 1)},
-  };
-  for (auto& q : need)
-    if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
   uint64_t* ldoff = P<uint64_t>(ctx, B_LDOFF);
-  phase_mark(ctx, 1, 0);
   launch_leaf_doff(nl, P<int32_t>(ctx, B_LEAFDEPTH), ldoff, s);
   scan_u64(ldoff, ldoff, nl, small + S_DOFFTOT, P<uint64_t>(ctx, B_SCANTMP), s);
   // depth counts need sum(d+1) <= nl * (maxdepth + 1)
@@ -283,7 +302,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   w.leaf_depth = P<int32_t>(ctx, B_LEAFDEPTH);
   w.info = P<NodeInfo>(ctx, B_INFO);
   w.rec = P<double>(ctx, B_REC);
-  w.stride = RS;
+  w.stride = rec_stride(ctx->order);
   w.theta2 = theta * theta;
   w.r_kern = ctx->cfg.r_kern;
   w.leaf_doff = ldoff;
@@ -322,29 +341,147 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   phase_mark(ctx, 2, 0);
   launch_walk(w, ctx->maxdepth, true, s);
   phase_mark(ctx, 2, 1);
+  return SFMM_OK;
+}
+
+// level-synchronous walk: one launch per depth; pools grow and the walk is
+// repeated if a list pool or a lowering stack was too small
+int walk_levels(sfmm_ctx* ctx, double theta) {
+  int rc;
+  const hipStream_t s = ctx->stream;
+  const int nn = (int)ctx->nn, nl = (int)ctx->nleaves;
+  uint64_t* small = P<uint64_t>(ctx, B_SMALL);
+  int* status = P<int>(ctx, B_STATUS);
+  const int node_arrays[] = {B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT};
+  for (int id : node_arrays)
+    if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
+  if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint64_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
+  if (ctx->m2l_cap == 0) {
+    ctx->m2l_cap = 48ull * nn + 1024;
+    ctx->open_cap = 48ull * nn + 1024;
+    ctx->p2p_cap = 48ull * nl + 1024;
+  }
+  const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
+  if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
+  const uint64_t kPoolMax = 0xF0000000ull;
+  for (int attempt = 0;; ++attempt) {
+    if (ctx->m2l_cap > kPoolMax || ctx->open_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
+      return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed 2^32 entries");
+    if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
+    if ((rc = ensure(ctx, B_OPENPOOL, sizeof(uint32_t) * ctx->open_cap))) return rc;
+    if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
+    uint32_t* tot = P<uint32_t>(ctx, B_WALKTOT);
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 4, s));
+    HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+    NodeWalkArgs a{};
+    a.info = P<NodeInfo>(ctx, B_INFO);
+    a.rec = P<double>(ctx, B_REC);
+    a.stride = rec_stride(ctx->order);
+    a.theta2 = theta * theta;
+    a.r_kern = ctx->cfg.r_kern;
+    a.level_nodes = P<int32_t>(ctx, B_LEVNODES);
+    a.level_off = P<uint32_t>(ctx, B_LEVOFF);
+    a.m2l_off = P<uint32_t>(ctx, B_NM2LOFF);
+    a.m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
+    a.open_off = P<uint32_t>(ctx, B_NOPENOFF);
+    a.open_cnt = P<uint32_t>(ctx, B_NOPENCNT);
+    a.p2p_off = P<uint32_t>(ctx, B_NP2POFF);
+    a.p2p_cnt = P<uint32_t>(ctx, B_NP2PCNT);
+    a.m2l_pool = P<uint32_t>(ctx, B_M2LPOOL);
+    a.open_pool = P<uint32_t>(ctx, B_OPENPOOL);
+    a.p2p_pool = P<uint32_t>(ctx, B_P2PPOOL);
+    a.m2l_cap = (uint32_t)ctx->m2l_cap;
+    a.open_cap = (uint32_t)ctx->open_cap;
+    a.p2p_cap = (uint32_t)ctx->p2p_cap;
+    a.lvl_cnt = P<uint64_t>(ctx, B_LVLCNT);
+    a.lvl_off = P<uint64_t>(ctx, B_LVLOFF);
+    a.run = tot;
+    a.stack_cap = ctx->stack_cap;
+    a.status = status;
+    for (int k = 0; k <= ctx->maxdepth; ++k)
+      launch_nodewalk_level(a, k, (int)(ctx->level_off[k + 1] - ctx->level_off[k]), s);
+    uint32_t htot[4];
+    int hstatus[4];
+    HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const bool pool_over = htot[0] > ctx->m2l_cap || htot[1] > ctx->open_cap ||
+                           htot[2] > ctx->p2p_cap;
+    const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
+    if (!pool_over && !stack_over) {
+      ctx->p2p_total = htot[2];
+      return SFMM_OK;
+    }
+    if (attempt >= 6) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
+    if (pool_over) {
+      ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, htot[0] + htot[0] / 4 + 1024);
+      ctx->open_cap = std::max<uint64_t>(ctx->open_cap, htot[1] + htot[1] / 4 + 1024);
+      ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, htot[2] + htot[2] / 4 + 1024);
+    }
+    if (stack_over) {
+      if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
+      ctx->stack_cap = std::min<uint32_t>(16384, ctx->stack_cap * 4);
+    }
+  }
+}
+
+int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, double* pot) {
+  int rc;
+  const hipStream_t s = ctx->stream;
+  const int n = (int)ctx->n, nl = (int)ctx->nleaves;
+  uint64_t* small = P<uint64_t>(ctx, B_SMALL);
+  struct { int id; size_t bytes; } need[] = {
+      {B_LDOFF, sizeof(uint64_t) * (nl + 1)}, {B_M2LCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_P2PCNT, sizeof(uint64_t) * (nl + 1)}, {B_PAIRCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_L2LCNT, sizeof(uint64_t) * (nl + 1)},
+      {B_FAR, sizeof(double) * 4 * (size_t)n},
+      {B_MOMPART, sizeof(double) * 4 * momentum_blocks(n)}, {B_MOM, sizeof(double) * 4},
+      {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(nl + 1)},
+  };
+  for (auto& q : need)
+    if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+  const bool level = ctx->cfg.walk_mode == SFMM_WALK_LEVEL;
+  phase_mark(ctx, 1, 0);
+  if (level) {
+    if ((rc = walk_levels(ctx, theta))) return rc;
+    phase_mark(ctx, 1, 1);
+    phase_mark(ctx, 2, 0);
+    phase_mark(ctx, 2, 1);
+  } else {
+    if ((rc = walk_per_leaf(ctx, theta))) return rc;
+  }
   ctx->have_lists = true;
   // ---- far field, near field, output
   FarArgs f{};
   f.nleaves = nl;
-  f.leaf_node = w.leaf_node;
-  f.leaf_depth = w.leaf_depth;
-  f.info = w.info;
-  f.rec = w.rec;
-  f.m2l_off = w.m2l_cnt;
-  f.m2l_list = w.m2l_list;
+  f.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+  f.leaf_depth = P<int32_t>(ctx, B_LEAFDEPTH);
+  f.info = P<NodeInfo>(ctx, B_INFO);
+  f.rec = P<double>(ctx, B_REC);
+  f.m2l_off = P<uint64_t>(ctx, B_M2LCNT);
+  f.m2l_list = P<uint32_t>(ctx, B_M2L);
+  f.node_m2l_off = P<uint32_t>(ctx, B_NM2LOFF);
+  f.node_m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
+  f.node_m2l_pool = P<uint32_t>(ctx, B_M2LPOOL);
   f.xs = P<double>(ctx, B_XS);
   f.ys = P<double>(ctx, B_YS);
   f.zs = P<double>(ctx, B_ZS);
   f.far = P<double>(ctx, B_FAR);
   phase_mark(ctx, 3, 0);
-  launch_far(ctx->order, f, s);
+  launch_far(ctx->order, level, f, s);
   phase_mark(ctx, 3, 1);
   NearArgs a{};
   a.n = n;
   a.p_leaf = P<int32_t>(ctx, B_PLEAF);
-  a.info = w.info;
-  a.p2p_off = w.p2p_cnt;
-  a.p2p_list = w.p2p_list;
+  a.info = f.info;
+  a.p2p_off = P<uint64_t>(ctx, B_P2PCNT);
+  a.p2p_list = P<int32_t>(ctx, B_P2P);
+  a.leaf_node = f.leaf_node;
+  a.node_p2p_off = P<uint32_t>(ctx, B_NP2POFF);
+  a.node_p2p_cnt = P<uint32_t>(ctx, B_NP2PCNT);
+  a.node_p2p_pool = P<uint32_t>(ctx, B_P2PPOOL);
   a.xs = f.xs; a.ys = f.ys; a.zs = f.zs;
   a.ms = P<double>(ctx, B_MS);
   a.hs = P<double>(ctx, B_HS);
@@ -355,14 +492,17 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   a.acc = acc;
   a.pot = pot;
   phase_mark(ctx, 4, 0);
-  launch_near(a, s);
+  launch_near(level, a, s);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
   phase_mark(ctx, 5, 1);
   if (ctx->timing && ctx->timing_used < ctx->timing_cap) ctx->timing_used++;
   HIPCHK(hipGetLastError());
+  // statistics totals of the level walk are read lazily (sfmm_get_stats)
+  if (level) ctx->stats_pending = true;
   ctx->have_mom = true;
+  (void)small;
   return SFMM_OK;
 }
 
@@ -380,6 +520,7 @@ int sfmm_config_default(sfmm_config* cfg) {
   cfg->r_kern = 2.0;
   cfg->include_self_potential = 1;
   cfg->check_inputs = 1;
+  cfg->walk_mode = SFMM_WALK_LEVEL;
   return SFMM_OK;
 }
 
@@ -390,7 +531,7 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   sfmm_config_default(&c);
   if (cfg) c = *cfg;
   if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
-      !std::isfinite(c.r_kern))
+      !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF))
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -460,6 +601,37 @@ int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
   out->num_nodes = ctx->nn;
   out->num_leaves = ctx->nleaves;
   out->max_depth = ctx->maxdepth;
+  if (ctx->have_lists && ctx->stats_pending) {
+    // the level walk's per-leaf totals are only computed when asked for
+    const int nl = (int)ctx->nleaves;
+    const hipStream_t s = ctx->stream;
+    uint64_t* small = P<uint64_t>(ctx, B_SMALL);
+    LeafStatArgs ls{};
+    ls.nleaves = nl;
+    ls.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+    ls.leaf_depth = P<int32_t>(ctx, B_LEAFDEPTH);
+    ls.info = P<NodeInfo>(ctx, B_INFO);
+    ls.m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
+    ls.p2p_off = P<uint32_t>(ctx, B_NP2POFF);
+    ls.p2p_cnt = P<uint32_t>(ctx, B_NP2PCNT);
+    ls.p2p_pool = P<uint32_t>(ctx, B_P2PPOOL);
+    ls.m2l = P<uint64_t>(ctx, B_M2LCNT);
+    ls.l2l = P<uint64_t>(ctx, B_L2LCNT);
+    ls.pairs = P<uint64_t>(ctx, B_PAIRCNT);
+    launch_leaf_stats(ls, s);
+    scan_u64(ls.m2l, ls.m2l, nl, small + S_M2LTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+    scan_u64(ls.l2l, ls.l2l, nl, small + S_L2LTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+    scan_u64(ls.pairs, ls.pairs, nl, small + S_PAIRTOT, P<uint64_t>(ctx, B_SCANTMP), s);
+    uint64_t hsmall[S_COUNT];
+    if (hipMemcpyAsync(hsmall, ctx->buf[B_SMALL].p, sizeof(hsmall), hipMemcpyDeviceToHost,
+                       ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(ctx, SFMM_EDEVICE, "statistics copy failed");
+    ctx->m2l_total = hsmall[S_M2LTOT];
+    ctx->l2l_total = hsmall[S_L2LTOT];
+    ctx->pair_total = hsmall[S_PAIRTOT];
+    ctx->stats_pending = false;
+  }
   if (ctx->have_lists) {
     out->n_m2l = (int64_t)ctx->m2l_total;
     out->n_l2l = (int64_t)ctx->l2l_total;
@@ -546,6 +718,45 @@ int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t
   if (!ctx->have_lists) return fail(ctx, SFMM_EINVAL, "no lists (run sfmm_solve first)");
   if (leaf < 0 || leaf >= ctx->nleaves) return fail(ctx, SFMM_EINVAL, "leaf out of range");
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->cfg.walk_mode == SFMM_WALK_LEVEL) {
+    // the leaf's list is its ancestors' node lists, root first, then its P2P list
+    const int64_t nn = ctx->nn;
+    std::vector<NodeInfo> info(nn);
+    std::vector<uint32_t> moff(nn), mcnt(nn);
+    int32_t node = 0;
+    HIPCHK(hipMemcpy(info.data(), ctx->buf[B_INFO].p, sizeof(NodeInfo) * nn, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(moff.data(), ctx->buf[B_NM2LOFF].p, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(mcnt.data(), ctx->buf[B_NM2LCNT].p, sizeof(uint32_t) * nn, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&node, P<int32_t>(ctx, B_LEAFNODE) + leaf, sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> dep, src;
+    int v = 0, k = 0;
+    for (;;) {
+      std::vector<uint32_t> seg(mcnt[v]);
+      if (mcnt[v])
+        HIPCHK(hipMemcpy(seg.data(), P<uint32_t>(ctx, B_M2LPOOL) + moff[v], sizeof(uint32_t) * mcnt[v],
+                         hipMemcpyDeviceToHost));
+      for (uint32_t e : seg) { dep.push_back(k); src.push_back((int32_t)e); }
+      if (v == node) break;
+      const int c = info[v].child;
+      if (c < 0) return fail(ctx, SFMM_EDEVICE, "inconsistent tree");
+      v = (info[node].lo < info[c + 1].lo) ? c : c + 1;
+      ++k;
+    }
+    uint32_t po2[2];
+    HIPCHK(hipMemcpy(&po2[0], P<uint32_t>(ctx, B_NP2POFF) + node, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&po2[1], P<uint32_t>(ctx, B_NP2PCNT) + node, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (n_m2l) *n_m2l = (int64_t)dep.size();
+    if (n_p2p) *n_p2p = po2[1];
+    for (int64_t q = 0; q < (int64_t)dep.size() && q < cap_m2l; ++q) {
+      if (m2l_depth) m2l_depth[q] = dep[q];
+      if (m2l_src) m2l_src[q] = src[q];
+    }
+    const int64_t cp = std::min<int64_t>(po2[1], cap_p2p < 0 ? 0 : cap_p2p);
+    if (cp > 0 && p2p_src)
+      HIPCHK(hipMemcpy(p2p_src, P<uint32_t>(ctx, B_P2PPOOL) + po2[0], sizeof(int32_t) * cp,
+                       hipMemcpyDeviceToHost));
+    return SFMM_OK;
+  }
   uint64_t mo[2], po[2];
   HIPCHK(hipMemcpy(mo, P<uint64_t>(ctx, B_M2LCNT) + leaf, sizeof(mo), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(po, P<uint64_t>(ctx, B_P2PCNT) + leaf, sizeof(po), hipMemcpyDeviceToHost));

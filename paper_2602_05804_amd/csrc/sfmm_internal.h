@@ -56,6 +56,11 @@ int radix_blocks(int64_t n);
 // sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1)
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
                 uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s);
+// one stable pass on the 8-bit digit at `shift`; hist holds 256 * radix_blocks(n)
+// counters and, after the pass, their exclusive scan (digit-major)
+void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
+                hipStream_t s);
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
                    double* hs, hipStream_t s);
@@ -71,9 +76,11 @@ void launch_leaf_fill(int n, const uint32_t* leaf_flag, const uint32_t* leaf_sca
 void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s);
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                        int32_t* leaf_depth, int32_t* p_leaf, int* maxdepth, hipStream_t s);
-void launch_upsweep(int order, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
-                    const double* xs, const double* ys, const double* zs, const double* ms,
-                    const double* hs, double* rec, uint32_t* visit, hipStream_t s);
+// geometry and moments, deepest level first (level_off_host: host copy)
+void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
+                     const int32_t* level_nodes, const NodeInfo* info, const double* xs,
+                     const double* ys, const double* zs, const double* ms, const double* hs,
+                     double* rec, hipStream_t s);
 void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s);
 void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
                    const uint32_t* chunk_off, const double* xs, const double* ys,
@@ -104,6 +111,44 @@ struct WalkArgs {
 void launch_walk(const WalkArgs& a, int maxdepth, bool fill, hipStream_t s);
 void launch_leaf_doff(int nleaves, const int32_t* leaf_depth, uint64_t* out, hipStream_t s);
 
+// ---- level-synchronous node walk -------------------------------------------------
+struct NodeWalkArgs {
+  const NodeInfo* info;
+  const double* rec;
+  int stride;
+  double theta2, r_kern;
+  const int32_t* level_nodes;  // nodes grouped by depth
+  const uint32_t* level_off;   // [levels + 1]
+  // per node (node-indexed): M2L list, opened list (internal), P2P list (leaf)
+  uint32_t *m2l_off, *m2l_cnt, *open_off, *open_cnt, *p2p_off, *p2p_cnt;
+  uint32_t *m2l_pool, *open_pool, *p2p_pool;
+  uint32_t m2l_cap, open_cap, p2p_cap;
+  uint64_t* lvl_cnt;  // [nn] packed counts in level order (low: M2L, high: opened/P2P)
+  uint64_t* lvl_off;  // [nn] their exclusive scan within the level
+  uint32_t* run;      // [3] running pool sizes: M2L, opened, P2P
+  uint32_t stack_cap;  // LDS lowering stack, entries
+  int* status;
+};
+// node depth as a sort key (u64) and node ids (u32) for the bucketing by depth
+void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* key,
+                       uint32_t* ids, hipStream_t s);
+// level_off[k] = first position of depth k in the depth-sorted node list,
+// read from the scanned radix histogram (digit-major, nb blocks)
+void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
+                          uint32_t* level_off, hipStream_t s);
+void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
+
+// per-leaf statistics of node lists: replicated M2L count, L2L count, pairs
+struct LeafStatArgs {
+  int nleaves;
+  const int32_t* leaf_node;
+  const int32_t* leaf_depth;
+  const NodeInfo* info;
+  const uint32_t *m2l_cnt, *p2p_off, *p2p_cnt, *p2p_pool;
+  uint64_t *m2l, *l2l, *pairs;  // per leaf
+};
+void launch_leaf_stats(const LeafStatArgs& a, hipStream_t s);
+
 // ---- far field: M2L + L2L chain + L2P ----------------------------------------
 struct FarArgs {
   int nleaves;
@@ -111,20 +156,23 @@ struct FarArgs {
   const int32_t* leaf_depth;
   const NodeInfo* info;
   const double* rec;
-  const uint64_t* m2l_off;  // [nleaves + 1]
+  const uint64_t* m2l_off;  // [nleaves + 1]  (per-leaf lists)
   const uint32_t* m2l_list;
+  const uint32_t *node_m2l_off, *node_m2l_cnt, *node_m2l_pool;  // (node lists)
   const double *xs, *ys, *zs;
   double* far;  // [n][4]: field x, y, z, potential (before the -G factor)
 };
-void launch_far(int order, const FarArgs& a, hipStream_t s);
+void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s);
 
 // ---- near field (P2P) + output in the caller's order ----------------------
 struct NearArgs {
   int n;
   const int32_t* p_leaf;
   const NodeInfo* info;
-  const uint64_t* p2p_off;  // [nleaves + 1]
+  const uint64_t* p2p_off;  // [nleaves + 1]  (per-leaf lists)
   const int32_t* p2p_list;
+  const int32_t* leaf_node;  // (node lists)
+  const uint32_t *node_p2p_off, *node_p2p_cnt, *node_p2p_pool;
   const double *xs, *ys, *zs, *ms, *hs;
   const double* far;
   const uint32_t* perm;
@@ -133,7 +181,7 @@ struct NearArgs {
   double* acc;  // caller order [n][3]
   double* pot;  // caller order [n]
 };
-void launch_near(const NearArgs& a, hipStream_t s);
+void launch_near(bool node_lists, const NearArgs& a, hipStream_t s);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);

@@ -89,40 +89,49 @@ def test_tree_parity(torch, P, orc):
     s.close()
 
 
-def _lists_equal(s, t, g, leaf_nodes, theta):
+def _lists_equal(s, t, g, leaf_nodes, theta, same_order):
     nd = t.nodes()
     omap = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(nd["lo"], nd["hi"]))}
     g2o = np.array([omap[(int(a), int(a + c))] for a, c in zip(g["lo"], g["cnt"])])
     for li, node in enumerate(leaf_nodes):
         dep, src, p2p = s.leaf_lists(li)
         odep, osrc, op2p = t.leaf_lists(g2o[node], theta)
-        # oracle entries grouped by depth keeping their discovery order
-        order = np.argsort(odep, kind="stable")
-        assert np.array_equal(dep, odep[order])
-        assert np.array_equal(g2o[src], osrc[order])
-        assert np.array_equal(g2o[p2p], op2p)
+        if same_order:
+            # Algorithm 1 per leaf: the oracle's entries grouped by depth, in
+            # their discovery order
+            order = np.argsort(odep, kind="stable")
+            assert np.array_equal(dep, odep[order])
+            assert np.array_equal(g2o[src], osrc[order])
+            assert np.array_equal(g2o[p2p], op2p)
+        else:
+            # level walk: the same (depth, source) pairs, visited level by level
+            assert sorted(zip(dep.tolist(), g2o[src].tolist())) == sorted(
+                zip(odep.tolist(), osrc.tolist()))
+            assert sorted(g2o[p2p].tolist()) == sorted(op2p.tolist())
 
 
-def test_lists_parity(torch, P, orc):
-    print("case: list parity, plummer N=4096 seed 1", flush=True)
+@pytest.mark.parametrize("walk", ["level", "leaf"])
+def test_lists_parity(torch, P, orc, walk):
+    print(f"case: list parity, plummer N=4096 seed 1, walk={walk}", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, walk=walk)
     g = s.tree(order=3)
     leaf_nodes, depths = s.leaves()
     t = orc.Tree(x, m, h, leaf_size=10, order=3)
     assert len(leaf_nodes) == t.num_leaves
-    _lists_equal(s, t, g, leaf_nodes, 0.5)
+    _lists_equal(s, t, g, leaf_nodes, 0.5, same_order=(walk == "leaf"))
     st = s.stats()
     ost = t.solve(0.5)[2]
     assert st["n_m2l"] == ost["n_m2l"]
     assert st["n_p2p_pairs"] == ost["n_p2p_pairs"]
 
 
-@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
-def test_solve_parity_plummer(torch, P, orc, theta):
-    print(f"case: solve parity plummer N=4096 theta={theta}", flush=True)
+@pytest.mark.parametrize("theta,walk", [(0.3, "level"), (0.5, "level"), (0.7, "level"),
+                                        (0.5, "leaf"), (0.7, "leaf")])
+def test_solve_parity_plummer(torch, P, orc, theta, walk):
+    print(f"case: solve parity plummer N=4096 theta={theta} walk={walk}", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta, walk=walk)
     oa, op = orc.sfmm_solve(x, m, h, theta=theta)
     assert rel_err(acc, oa).max() < TOL
     assert pot_err(pot, op) < TOL
@@ -151,6 +160,18 @@ def test_solve_parity_sizes(torch, P, orc, n, leaf_size):
     assert pot_err(pot, op) < TOL
 
 
+def test_large_softening_all_pairs(torch, P, orc):
+    """Kernels wider than the system: no M2L at all, every leaf pair is P2P."""
+    print("case: all-P2P (huge h)", flush=True)
+    x, m, h = workloads.plummer(2000, seed=9)
+    h = np.full(2000, 1e3)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.9)
+    da, dp = orc.direct(x, m, h)
+    st = s.stats()
+    assert st["n_m2l"] == 0 and st["n_p2p_leaf_pairs"] == st["num_leaves"] ** 2
+    assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
+
+
 def test_theta_to_zero_equals_direct(torch, P, orc):
     print("case: theta->0 direct", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
@@ -165,15 +186,16 @@ def test_theta_to_zero_equals_direct(torch, P, orc):
     assert pot_err(pot, dp) < TOL
 
 
-def test_duplicates_and_clumps(torch, P, orc):
-    print("case: duplicate positions", flush=True)
+@pytest.mark.parametrize("walk", ["level", "leaf"])
+def test_duplicates_and_clumps(torch, P, orc, walk):
+    print(f"case: duplicate positions walk={walk}", flush=True)
     rng = np.random.default_rng(4)
     base = rng.normal(size=(300, 3))
     x = np.concatenate([base, base, base[:50], np.zeros((40, 3)), rng.normal(size=(500, 3))])
     n = len(x)
     m = rng.uniform(0.5, 1.5, n) / n
     h = rng.uniform(0.01, 0.2, n)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=4)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=4, walk=walk)
     oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=4)
     assert rel_err(acc, oa).max() < TOL
     assert pot_err(pot, op) < TOL
