@@ -2,42 +2,89 @@
 // down the branch and L2P at the leaf's particles (Sect. 2.2, Algorithm 1's
 // propagate_to_next_parent, Appendix A.2).
 //
-// One thread per leaf.  The leaf's M2L list is grouped by the depth of the
-// target ancestor, so the thread keeps one local expansion in registers:
-// at depth k it re-centres the expansion from p_{k-1} to p_k (exact for the
-// polynomial) and adds the M2L of every source listed for p_k.  Leaves of a
-// wave share their upper ancestors, so the upper part of the lists is the
-// same for all lanes and the source records are read once per wave.
+// A group of SPLIT lanes per leaf.  The leaf's M2L list is grouped by the
+// depth of the target ancestor; the lanes of the group take every SPLIT-th
+// entry of each depth and keep a partial local expansion in registers: at
+// depth k it is re-centred from p_{k-1} to p_k (exact for the polynomial)
+// and the lane's M2L terms for p_k are added.  Re-centring is linear, so the
+// group's partial expansions are summed at the leaf and evaluated at its
+// particles.  Every leaf still evaluates all M2L interactions of all of its
+// ancestors.  Neighbouring leaves (Morton order) share their upper
+// ancestors, so lanes mostly read the same source records.
 #include "sfmm_internal.h"
 
 namespace sfmm {
 namespace {
 
-template <int P, bool NODE>
-__global__ __launch_bounds__(128) void k_far(FarArgs a) {
+template <int P, bool NODE, int SPLIT, int WAVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_far(FarArgs a) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int NL = E::NL;
   constexpr int RS = rec_stride(P);
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= a.nleaves) return;
+  const int lane = threadIdx.x;
+  const int sub = lane % SPLIT;
+  const int l = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
+  const bool active = l < a.nleaves;
   const NodeInfo* __restrict__ info = a.info;
   const double* __restrict__ rec = a.rec;
-  const int leaf = a.leaf_node[l];
-  const int d = a.leaf_depth[l];
+  const int leaf = active ? a.leaf_node[l] : 0;
+  const int d = active ? a.leaf_depth[l] : -1;
   const int lo = info[leaf].lo;
-  const int cnt = info[leaf].cnt;
+  const int cnt = active ? info[leaf].cnt : 0;
 
   double L[NL];
 #pragma unroll
   for (int q = 0; q < NL; ++q) L[q] = 0.0;
   bool have = false;
-  uint64_t e = NODE ? 0 : a.m2l_off[l];
-  const uint64_t end = NODE ? 0 : a.m2l_off[l + 1];
-  int v = 0;
+  // list range of depth k for this lane: entries base + sub, base + sub + SPLIT, ...
+  const uint32_t* list = NODE ? a.node_m2l_pool : a.m2l_list;
+  const uint32_t* dc = NODE ? nullptr : a.depth_cnt + (active ? a.leaf_doff[l] : 0);
+  uint64_t seg = NODE ? 0 : (active ? a.m2l_off[l] : 0);  // per-leaf lists: start of depth k
+  uint64_t e = 0, ne = 0;
+  int v = 0, k = 0;
   double sv[3] = {rec[0], rec[1], rec[2]};
-  for (int k = 0; k <= d; ++k) {
-    if (k > 0) {
+  if (d >= 0) {
+    if (NODE) { e = a.node_m2l_off[0]; ne = e + a.node_m2l_cnt[0]; }
+    else { e = seg; ne = seg + dc[0]; }
+    e += sub;
+  }
+  // one loop per lane: an M2L while the current depth has entries left,
+  // else a step down the branch (L2L), until the leaf's list is done.  The
+  // source record of the next entry and the list index of the one after it
+  // are loaded while the current M2L is computed.
+  double cs[3], cq[NQ];
+  uint32_t idx_next = 0;
+  auto load_rec = [&](uint32_t ent, double* sd, double* qd) {
+    const double* rs = rec + (int64_t)(ent & kSrcMask) * RS;
+    sd[0] = rs[0]; sd[1] = rs[1]; sd[2] = rs[2];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) qd[q] = rs[8 + q];
+  };
+  // at the top of the loop, when e < ne: (cs, cq) hold entry e's source and
+  // idx_next the list index of the following entry (the last one repeated
+  // when there is none)
+  auto start_depth = [&]() {
+    if (e < ne) {
+      load_rec(list[e], cs, cq);
+      idx_next = list[e + SPLIT < ne ? e + SPLIT : ne - 1];
+    }
+  };
+  start_depth();
+  for (;;) {
+    if (e < ne) {
+      const uint64_t en = e + SPLIT;
+      double ns[3], nq[NQ];
+      load_rec(idx_next, ns, nq);
+      idx_next = list[en + SPLIT < ne ? en + SPLIT : ne - 1];
+      const double r[3] = {cs[0] - sv[0], cs[1] - sv[1], cs[2] - sv[2]};
+      E::m2l_add(r, cq, L);
+      have = true;
+      e = en;
+      cs[0] = ns[0]; cs[1] = ns[1]; cs[2] = ns[2];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) cq[q] = nq[q];
+    } else if (k < d) {
       const int c = info[v].child;
       const int nv = (lo < info[c + 1].lo) ? c : c + 1;
       const double* rn = rec + (int64_t)nv * RS;
@@ -48,28 +95,31 @@ __global__ __launch_bounds__(128) void k_far(FarArgs a) {
       }
       v = nv;
       sv[0] = sn[0]; sv[1] = sn[1]; sv[2] = sn[2];
-    }
-    uint64_t ne = end;
-    const uint32_t* list = a.m2l_list;
-    if (NODE) {
-      e = a.node_m2l_off[v];
-      ne = e + a.node_m2l_cnt[v];
-      list = a.node_m2l_pool;
-    }
-    while (e < ne) {
-      const uint32_t ent = list[e];
-      if (!NODE && (int)(ent >> kSrcBits) != k) break;
-      const double* rs = rec + (int64_t)(ent & kSrcMask) * RS;
-      const double r[3] = {rs[0] - sv[0], rs[1] - sv[1], rs[2] - sv[2]};
-      double Q[NQ];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) Q[q] = rs[8 + q];
-      E::m2l_add(r, Q, L);
-      have = true;
-      ++e;
+      ++k;
+      if (NODE) {
+        e = a.node_m2l_off[v];
+        ne = e + a.node_m2l_cnt[v];
+      } else {
+        seg += dc[k - 1];
+        e = seg;
+        ne = seg + dc[k];
+      }
+      e += sub;
+      start_depth();
+    } else {
+      break;
     }
   }
-  for (int j = lo; j < lo + cnt; ++j) {
+  // the SPLIT lanes of a leaf hold partial expansions about the same centre
+#pragma unroll
+  for (int o = SPLIT / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] += __shfl_xor(L[q], o, 64);
+    // every lane must take part in the shuffle (no short-circuit around it)
+    const int other = __shfl_xor((int)have, o, 64);
+    have = have || other != 0;
+  }
+  for (int j = lo + sub; j < lo + cnt; j += SPLIT) {
     const double off[3] = {a.xs[j] - sv[0], a.ys[j] - sv[1], a.zs[j] - sv[2]};
     double f[3] = {0.0, 0.0, 0.0}, phi = 0.0;
     if (have) E::l2p(off, L, f, phi);
@@ -80,22 +130,34 @@ __global__ __launch_bounds__(128) void k_far(FarArgs a) {
 
 }  // namespace
 
-template <bool NODE>
+template <bool NODE, int SPLIT, int WAVES>
 void far_dispatch(int order, const FarArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.nleaves + 127) / 128);
+  const unsigned nb = (unsigned)((a.nleaves + 64 / SPLIT - 1) / (64 / SPLIT));
   switch (order) {
-    case 0: k_far<0, NODE><<<nb, 128, 0, s>>>(a); break;
-    case 1: k_far<1, NODE><<<nb, 128, 0, s>>>(a); break;
-    case 2: k_far<2, NODE><<<nb, 128, 0, s>>>(a); break;
-    case 3: k_far<3, NODE><<<nb, 128, 0, s>>>(a); break;
-    case 4: k_far<4, NODE><<<nb, 128, 0, s>>>(a); break;
+    case 0: k_far<0, NODE, SPLIT, WAVES><<<nb, 64, 0, s>>>(a); break;
+    case 1: k_far<1, NODE, SPLIT, WAVES><<<nb, 64, 0, s>>>(a); break;
+    case 2: k_far<2, NODE, SPLIT, WAVES><<<nb, 64, 0, s>>>(a); break;
+    case 3: k_far<3, NODE, SPLIT, WAVES><<<nb, 64, 0, s>>>(a); break;
+    case 4: k_far<4, NODE, SPLIT, WAVES><<<nb, 64, 0, s>>>(a); break;
   }
 }
 
-void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s) {
+// variant: lanes per leaf (1, 2, 4) x register budget (1 or 2 waves per SIMD)
+template <bool NODE>
+void far_variant(int order, int variant, const FarArgs& a, hipStream_t s) {
+  switch (variant) {
+    case 0: far_dispatch<NODE, 4, 1>(order, a, s); break;
+    case 1: far_dispatch<NODE, 4, 2>(order, a, s); break;
+    case 2: far_dispatch<NODE, 2, 1>(order, a, s); break;
+    case 3: far_dispatch<NODE, 1, 1>(order, a, s); break;
+    default: far_dispatch<NODE, 4, 1>(order, a, s); break;
+  }
+}
+
+void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipStream_t s) {
   if (a.nleaves <= 0) return;
-  if (node_lists) far_dispatch<true>(order, a, s);
-  else far_dispatch<false>(order, a, s);
+  if (node_lists) far_variant<true>(order, variant, a, s);
+  else far_variant<false>(order, variant, a, s);
 }
 
 }  // namespace sfmm

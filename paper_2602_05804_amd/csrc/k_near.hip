@@ -37,6 +37,23 @@ __device__ __forceinline__ void soft(double r, double hinv, double& g, double& p
   }
 }
 
+// g = f(q)/(q h^3) and psi = psi(q)/h for one particle's kernel at q = r/h,
+// without branches; qi = 1/q (= h/r), rinv = 1/r, rinv3 = 1/r^3
+__device__ __forceinline__ void soft_sel(double q, double hinv, double qi, double rinv,
+                                         double rinv3, double& g, double& psi) {
+  const double q2 = q * q;
+  const double h3 = hinv * hinv * hinv;
+  const double gA = h3 * fma(q2, fma(0.5, q, -1.2), 4.0 / 3.0);
+  const double pA = hinv * fma(q2, fma(q2, fma(-0.1, q, 0.3), -2.0 / 3.0), 1.4);
+  const double qi3 = qi * qi * qi;
+  const double gB = h3 * (fma(q, fma(q, fma(q, -1.0 / 6.0, 1.2), -3.0), 8.0 / 3.0) -
+                          qi3 * (1.0 / 15.0));
+  const double pB = hinv * (fma(q2, fma(q, fma(q, fma(q, 1.0 / 30.0, -0.3), 1.0), -4.0 / 3.0), 1.6) -
+                            qi * (1.0 / 15.0));
+  g = q >= 2.0 ? rinv3 : (q < 1.0 ? gA : gB);
+  psi = q >= 2.0 ? rinv : (q < 1.0 ? pA : pB);
+}
+
 template <bool NODE>
 __global__ __launch_bounds__(256) void k_near(NearArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -107,6 +124,129 @@ __global__ __launch_bounds__(256) void k_near(NearArgs a) {
   a.pot[o] = -G * (fr[3] + ph);
 }
 
+// ---- wave per target leaf ----------------------------------------------------
+// The leaf's particles (at most LS) are wave-uniform and held in registers;
+// the lanes walk the flattened list of source particles of the leaf's P2P
+// sources, 64 at a time, and each lane accumulates the field of its source on
+// every target.  A butterfly reduction then gives each target its total.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int LS, bool NODE>
+__global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
+  const int lane = threadIdx.x;
+  const int l = blockIdx.x;
+  const int node = a.leaf_node[l];
+  const NodeInfo ti = a.info[node];
+  const int nt = ti.cnt;
+  // targets in LDS (read back as broadcasts): x, y, z, 1/h, h
+  __shared__ double tg[LS][5];
+  if (lane < nt) {
+    const int j = ti.lo + lane;
+    tg[lane][0] = a.xs[j]; tg[lane][1] = a.ys[j]; tg[lane][2] = a.zs[j];
+    tg[lane][3] = a.his[j]; tg[lane][4] = a.hs[j];
+  }
+  __syncthreads();
+  double fx[LS], fy[LS], fz[LS], ph[LS];
+#pragma unroll
+  for (int i = 0; i < LS; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+  uint64_t e0, e1;
+  const int32_t* list;
+  if (NODE) {
+    e0 = a.node_p2p_off[node];
+    e1 = e0 + a.node_p2p_cnt[node];
+    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    e0 = a.p2p_off[l];
+    e1 = a.p2p_off[l + 1];
+    list = a.p2p_list;
+  }
+  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+    // 64 list entries: their particle ranges, flattened by a prefix scan
+    int cnt = 0, lo = 0;
+    if (c0 + lane < e1) {
+      const NodeInfo si = a.info[list[c0 + lane]];
+      cnt = si.cnt;
+      lo = si.lo;
+    }
+    const int incl = wave_incl_scan(cnt);
+    const int pre = incl - cnt;
+    const int total = __shfl(incl, 63, 64);
+    for (int f0 = 0; f0 < total; f0 += 64) {
+      const int f = f0 + lane;
+      // owner lane k: the last lane with pre <= f (binary search over lanes)
+      int k = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int pk = __shfl(pre, k + step, 64);
+        if (pk <= f) k += step;
+      }
+      const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+      if (f >= total) continue;
+      const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j], mj = a.ms[j];
+      const double hj = a.hs[j], hjinv = a.his[j];
+      const double hj2inv = hjinv * hjinv;
+#pragma unroll
+      for (int i = 0; i < LS; ++i) {
+        if (i >= nt) break;
+        const double w = (j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
+        const double thi = tg[i][3];
+        const double dx = tg[i][0] - xj, dy = tg[i][1] - yj, dz = tg[i][2] - zj;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+        const double rinv3 = rinv * rinv * rinv;
+        double gs = rinv3, ps = rinv;  // both kernels at q >= 2
+        const bool inside = (r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0);
+        if (__ballot(inside)) {
+          const double r = r2 * rinv;
+          double g1, p1, g2, p2;
+          soft_sel(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
+          soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
+          if (inside) {
+            gs = 0.5 * (g1 + g2);
+            ps = 0.5 * (p1 + p2);
+          }
+        }
+        const double mg = w * gs;
+        fx[i] = fma(mg, dx, fx[i]);
+        fy[i] = fma(mg, dy, fy[i]);
+        fz[i] = fma(mg, dz, fz[i]);
+        ph[i] = fma(w, ps, ph[i]);
+      }
+    }
+  }
+  const double G = a.G;
+#pragma unroll
+  for (int i = 0; i < LS; ++i) {
+    if (i >= nt) break;
+    const double sx = wave_sum(fx[i]), sy = wave_sum(fy[i]), sz = wave_sum(fz[i]);
+    double sp = wave_sum(ph[i]);
+    if (lane == i) {
+      const int j = ti.lo + i;
+      if (a.include_self) sp = fma(a.ms[j], 1.4 * tg[i][3], sp);
+      const double* fr = a.far + 4 * (int64_t)j;
+      const int64_t o = a.perm[j];
+      a.acc[3 * o] = -G * (fr[0] + sx);
+      a.acc[3 * o + 1] = -G * (fr[1] + sy);
+      a.acc[3 * o + 2] = -G * (fr[2] + sz);
+      a.pot[o] = -G * (fr[3] + sp);
+    }
+  }
+}
+
 constexpr int MOM_THREADS = 256;
 
 __global__ __launch_bounds__(MOM_THREADS) void k_momentum_partial(int n, const double* __restrict__ m,
@@ -149,10 +289,20 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
-void launch_near(bool node_lists, const NearArgs& a, hipStream_t s) {
+void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
-  if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
-  else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  const unsigned nbl = (unsigned)a.nleaves;
+  if (variant == 1) leaf_size = 1 << 20;  // particle per thread
+  if (leaf_size <= 10) {
+    if (node_lists) k_p2p_leaf<10, true><<<nbl, 64, 0, s>>>(a);
+    else k_p2p_leaf<10, false><<<nbl, 64, 0, s>>>(a);
+  } else if (leaf_size <= 16) {
+    if (node_lists) k_p2p_leaf<16, true><<<nbl, 64, 0, s>>>(a);
+    else k_p2p_leaf<16, false><<<nbl, 64, 0, s>>>(a);
+  } else {
+    if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+    else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+  }
 }
 
 int momentum_blocks(int64_t n) {

@@ -187,7 +187,7 @@ __global__ void k_gather(int n, const uint32_t* __restrict__ perm, const double*
                          const double* __restrict__ m, const double* __restrict__ h,
                          double* __restrict__ xs, double* __restrict__ ys,
                          double* __restrict__ zs, double* __restrict__ ms,
-                         double* __restrict__ hs) {
+                         double* __restrict__ hs, double* __restrict__ his) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t j = perm[i];
@@ -196,6 +196,7 @@ __global__ void k_gather(int n, const uint32_t* __restrict__ perm, const double*
   zs[i] = x[3 * j + 2];
   ms[i] = m[j];
   hs[i] = h[j];
+  his[i] = 1.0 / h[j];
 }
 
 // ---- binary radix tree (Karras 2012) ----------------------------------------
@@ -479,8 +480,8 @@ void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t*
 
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
-                   double* hs, hipStream_t s) {
-  k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs);
+                   double* hs, double* his, hipStream_t s) {
+  k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs, his);
 }
 
 void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,

@@ -25,7 +25,7 @@ struct DevBuf {
 enum BufId {
   B_BOXPART, B_BOX, B_STATUS, B_SMALL,
   B_KEY0, B_KEY1, B_VAL0, B_VAL1, B_HIST, B_SCANTMP,
-  B_XS, B_YS, B_ZS, B_MS, B_HS,
+  B_XS, B_YS, B_ZS, B_MS, B_HS, B_HIS,
   B_KFIRST, B_KLAST, B_KLEFT, B_KRIGHT, B_KPAR, B_KSIDE, B_KEPT,
   B_LFLAG, B_LAT, B_INFO, B_REC, B_L2BITS, B_CHUNK,
   B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
@@ -65,6 +65,8 @@ struct sfmm_ctx {
   uint64_t m2l_cap = 0, open_cap = 0, p2p_cap = 0;
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
+  int far_variant = 0;         // kernel shape of the far field (SFMM_FAR_VARIANT)
+  int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
   sfmm_stats stats{};
 };
@@ -157,7 +159,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
       {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(n)},
       {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(n), 2 * (int64_t)n + 2))},
       {B_XS, sizeof(double) * n}, {B_YS, sizeof(double) * n}, {B_ZS, sizeof(double) * n},
-      {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n},
+      {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n}, {B_HIS, sizeof(double) * n},
       {B_KFIRST, sizeof(int32_t) * n}, {B_KLAST, sizeof(int32_t) * n},
       {B_KLEFT, sizeof(int32_t) * n}, {B_KRIGHT, sizeof(int32_t) * n},
       {B_KPAR, sizeof(int32_t) * n}, {B_KSIDE, sizeof(int32_t) * n},
@@ -186,7 +188,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   const uint64_t* key = P<uint64_t>(ctx, B_KEY0);
   const uint32_t* perm = P<uint32_t>(ctx, B_VAL0);
   launch_gather(n, perm, x, m, h, P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
-                P<double>(ctx, B_MS), P<double>(ctx, B_HS), s);
+                P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_HIS), s);
   NodeInfo* info = P<NodeInfo>(ctx, B_INFO);
   int32_t* leaf_node = P<int32_t>(ctx, B_LEAFNODE);
   // ---- topology
@@ -462,6 +464,8 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   f.rec = P<double>(ctx, B_REC);
   f.m2l_off = P<uint64_t>(ctx, B_M2LCNT);
   f.m2l_list = P<uint32_t>(ctx, B_M2L);
+  f.depth_cnt = P<uint32_t>(ctx, B_DEPTHCNT);
+  f.leaf_doff = P<uint64_t>(ctx, B_LDOFF);
   f.node_m2l_off = P<uint32_t>(ctx, B_NM2LOFF);
   f.node_m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
   f.node_m2l_pool = P<uint32_t>(ctx, B_M2LPOOL);
@@ -470,10 +474,11 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   f.zs = P<double>(ctx, B_ZS);
   f.far = P<double>(ctx, B_FAR);
   phase_mark(ctx, 3, 0);
-  launch_far(ctx->order, level, f, s);
+  launch_far(ctx->order, level, ctx->far_variant, f, s);
   phase_mark(ctx, 3, 1);
   NearArgs a{};
   a.n = n;
+  a.nleaves = nl;
   a.p_leaf = P<int32_t>(ctx, B_PLEAF);
   a.info = f.info;
   a.p2p_off = P<uint64_t>(ctx, B_P2PCNT);
@@ -485,6 +490,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   a.xs = f.xs; a.ys = f.ys; a.zs = f.zs;
   a.ms = P<double>(ctx, B_MS);
   a.hs = P<double>(ctx, B_HS);
+  a.his = P<double>(ctx, B_HIS);
   a.far = f.far;
   a.perm = P<uint32_t>(ctx, B_VAL0);
   a.G = ctx->cfg.G;
@@ -492,7 +498,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   a.acc = acc;
   a.pot = pot;
   phase_mark(ctx, 4, 0);
-  launch_near(level, a, s);
+  launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, s);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
@@ -543,6 +549,8 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->cfg = c;
+  if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
+  if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
   *out = ctx;
   return SFMM_OK;
 }

@@ -63,7 +63,7 @@ void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                 hipStream_t s);
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
-                   double* hs, hipStream_t s);
+                   double* hs, double* his, hipStream_t s);
 void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,
                    int32_t* kleft, int32_t* kright, int32_t* kpar, int32_t* kside,
                    uint32_t* kept, hipStream_t s);
@@ -158,22 +158,27 @@ struct FarArgs {
   const double* rec;
   const uint64_t* m2l_off;  // [nleaves + 1]  (per-leaf lists)
   const uint32_t* m2l_list;
+  const uint32_t* depth_cnt;  // per-leaf lists: entries per (leaf, depth)
+  const uint64_t* leaf_doff;  //   at depth_cnt + leaf_doff[leaf]
   const uint32_t *node_m2l_off, *node_m2l_cnt, *node_m2l_pool;  // (node lists)
   const double *xs, *ys, *zs;
   double* far;  // [n][4]: field x, y, z, potential (before the -G factor)
 };
-void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s);
+// variant: 0 = 4 lanes per leaf (default), 1 = idem with a two-wave register
+// budget, 2 = 2 lanes per leaf, 3 = one lane per leaf
+void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipStream_t s);
 
 // ---- near field (P2P) + output in the caller's order ----------------------
 struct NearArgs {
   int n;
+  int nleaves;
   const int32_t* p_leaf;
   const NodeInfo* info;
   const uint64_t* p2p_off;  // [nleaves + 1]  (per-leaf lists)
   const int32_t* p2p_list;
   const int32_t* leaf_node;  // (node lists)
   const uint32_t *node_p2p_off, *node_p2p_cnt, *node_p2p_pool;
-  const double *xs, *ys, *zs, *ms, *hs;
+  const double *xs, *ys, *zs, *ms, *hs, *his;  // his = 1/h
   const double* far;
   const uint32_t* perm;
   double G;
@@ -181,7 +186,8 @@ struct NearArgs {
   double* acc;  // caller order [n][3]
   double* pot;  // caller order [n]
 };
-void launch_near(bool node_lists, const NearArgs& a, hipStream_t s);
+// wave-per-leaf kernel for leaf_size <= 16, particle-per-thread otherwise
+void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);
