@@ -58,7 +58,14 @@ typedef enum {
   SFMM_ENONFINITE = -5    /* a position is not finite, or m <= 0, or h <= 0         */
 } sfmm_status;
 
-typedef enum { SFMM_FP64 = 0 } sfmm_precision;
+/* SFMM_FP64   every step in FP64.
+ * SFMM_FP32C  tree geometry, moments, the L2L chain, L2P and all sums in
+ *             FP64; the M2L contractions of targets at depth >= fp64_top_depth
+ *             and the P2P pair terms in FP32 (pair separations formed from
+ *             FP32 leaf-relative offsets plus the FP32-rounded FP64 difference
+ *             of the two leaf centres, so each pair stays antisymmetric), each
+ *             term added into an FP64 accumulator. */
+typedef enum { SFMM_FP64 = 0, SFMM_FP32C = 1 } sfmm_precision;
 
 /* How the interaction lists are found (both give every leaf the same pairs):
  * SFMM_WALK_LEVEL  each (ancestor, source) test is made once, level by level
@@ -75,6 +82,7 @@ typedef struct {
   int include_self_potential; /* add -G m_i psi(0, h_i) to pot_i (1)                  */
   int check_inputs;           /* validate m, h and positions on the device (1)        */
   int walk_mode;              /* sfmm_walk_mode (SFMM_WALK_LEVEL)                     */
+  int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
 } sfmm_config;
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
@@ -118,7 +126,8 @@ int sfmm_build(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
 
 /* Build, walk and evaluate: acc and pot for every particle (see the header
  * comment).  theta is the critical opening angle (0 < theta < 1), order the
- * expansion order p (0..4; p = 3 is the tuned one), precision SFMM_FP64.
+ * expansion order p (0..4; p = 3 is the tuned one), precision SFMM_FP64 or
+ * SFMM_FP32C (sfmm_precision).
  * n == 0: OK, nothing written.  n == 1: acc = 0, pot = self term only.
  * Errors: as sfmm_build, plus SFMM_EINVAL for theta outside (0, 1) or a
  * NULL acc/pot with n > 0, SFMM_EUNSUPPORTED for an unknown precision. */

@@ -34,8 +34,8 @@ FLOPS = {
     "l2p": {0: 4, 1: 31, 2: 88, 3: 184, 4: 329},
 }
 
-SFMM_FP64 = 0
-_PRECISION = {"fp64": SFMM_FP64}
+SFMM_FP64, SFMM_FP32C = 0, 1
+_PRECISION = {"fp64": SFMM_FP64, "fp32c": SFMM_FP32C}
 
 
 class SfmmError(RuntimeError):
@@ -45,7 +45,7 @@ class SfmmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("G", C.c_double), ("leaf_size", C.c_int), ("r_kern", C.c_double),
                 ("include_self_potential", C.c_int), ("check_inputs", C.c_int),
-                ("walk_mode", C.c_int)]
+                ("walk_mode", C.c_int), ("fp64_top_depth", C.c_int)]
 
 
 WALK_MODES = {"level": 0, "leaf": 1}
@@ -105,7 +105,7 @@ class Solver:
 
     def __init__(self, device: int = 0, G: float = 1.0, leaf_size: int = 10,
                  r_kern: float = 2.0, include_self_potential: bool = True,
-                 check_inputs: bool = True, walk: str = "level"):
+                 check_inputs: bool = True, walk: str = "level", fp64_top_depth: int = 8):
         import torch
 
         if not torch.cuda.is_available():
@@ -113,7 +113,7 @@ class Solver:
         self._torch = torch
         self.device = int(device)
         self.cfg = Config(G, leaf_size, r_kern, int(include_self_potential), int(check_inputs),
-                          WALK_MODES[walk])
+                          WALK_MODES[walk], int(fp64_top_depth))
         self._ctx = C.c_void_p(0)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self._check(lib().sfmm_create(C.byref(self._ctx), self.device, C.c_void_p(stream),

@@ -222,6 +222,21 @@ def gen(P):
     L.append("  }")
     out += L
     out.append(f"  static constexpr int FLOPS_M2L = {c.flops()};  // + one rsqrt")
+    # same contraction in FP32 (r and Q rounded to FP32), each term added to
+    # the FP64 local expansion
+    Lm = []
+    for line in L:
+        line = line.replace("static void m2l_add(const double* r, const double* Q, double* local)",
+                            "static void m2l_add_f32(const float* r, const float* Q, double* local)")
+        line = line.replace("const double ", "const float ").replace("double D[", "float D[")
+        line = line.replace("double s = ", "float s = ")
+        line = line.replace("rsqrt(r2)", "__frsqrt_rn(r2)")
+        line = line.replace("fma(", "fmaf(")
+        import re as _re
+        line = _re.sub(r"(-?\d+\.\d+(e-?\d+)?)", r"\1f", line) if ("D[" in line and "=" in line and "local" not in line) or "sn" in line else line
+        line = line.replace("local[", "local[").replace("] += s;", "] += (double)s;").replace("] -= s;", "] -= (double)s;")
+        Lm.append(line)
+    out += Lm
 
     # ---- L2L (in place)
     c = Counter()

@@ -1,0 +1,393 @@
+// k_f32c.hip -- the FP32-compensated form (SFMM_FP32C) of the far field and
+// of P2P.
+//
+// Geometry, moments, the L2L chain and L2P stay in FP64.  The bulk terms run
+// in FP32 and every term is added into an FP64 accumulator, which bounds the
+// summation error below that of an FP32 hi/lo (TwoSum) pair at a lower cost
+// here (an FP64 add issues at the FP32 rate).
+//   M2L  targets at depth < top: FP64 as in k_far; deeper targets: the
+//        separation of the two centres is formed in FP64 and rounded, the
+//        moments are an FP32 copy, the derivatives and the contraction are
+//        FP32 (Exp<P>::m2l_add_f32).
+//   P2P  each particle carries its FP32 offset from its leaf's centre; a pair
+//        (i in A, j in B) uses d = fl32(c_A - c_B) + (o_i - o_j), which is
+//        exactly minus the separation seen from j, so each pair force is
+//        antisymmetric.
+#include "sfmm_internal.h"
+
+namespace sfmm {
+namespace {
+
+template <int P>
+__global__ void k_prep_nodes32(int nn, const double* __restrict__ rec,
+                               const int32_t* __restrict__ node_depth, float* __restrict__ rec32) {
+  constexpr int NQ = Exp<P>::NQ;
+  constexpr int RS = rec_stride(P), RS32 = rec32_stride(P);
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  const double* r = rec + (int64_t)v * RS;
+  float* o = rec32 + (int64_t)v * RS32;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) o[k] = (float)r[8 + k];
+  o[NQ] = __int_as_float(node_depth[v]);
+}
+
+template <int RS>
+__global__ void k_prep_particles32(int nleaves, const int32_t* __restrict__ leaf_node,
+                                   const NodeInfo* __restrict__ info, const double* __restrict__ rec,
+                                   const double* __restrict__ xs, const double* __restrict__ ys,
+                                   const double* __restrict__ zs, const double* __restrict__ ms,
+                                   const double* __restrict__ hs, float4* __restrict__ pf,
+                                   float2* __restrict__ ph) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nleaves) return;
+  const int v = leaf_node[l];
+  const NodeInfo ni = info[v];
+  const double* r = rec + (int64_t)v * RS;
+  for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
+    pf[j] = make_float4((float)(xs[j] - r[0]), (float)(ys[j] - r[1]), (float)(zs[j] - r[2]),
+                        (float)ms[j]);
+    ph[j] = make_float2((float)hs[j], (float)(1.0 / hs[j]));
+  }
+}
+
+// ---- far field -----------------------------------------------------------------
+template <int P, bool NODE, int SPLIT>
+__global__ __launch_bounds__(64) void k_far32(FarArgs a, const float* __restrict__ rec32, int top) {
+  using E = Exp<P>;
+  constexpr int NQ = E::NQ;
+  constexpr int NL = E::NL;
+  constexpr int RS = rec_stride(P), RS32 = rec32_stride(P);
+  const int lane = threadIdx.x;
+  const int sub = lane % SPLIT;
+  const int l = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
+  const bool active = l < a.nleaves;
+  const NodeInfo* __restrict__ info = a.info;
+  const double* __restrict__ rec = a.rec;
+  const int leaf = active ? a.leaf_node[l] : 0;
+  const int d = active ? a.leaf_depth[l] : -1;
+  const int lo = info[leaf].lo;
+  const int cnt = active ? info[leaf].cnt : 0;
+
+  double L[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) L[q] = 0.0;
+  bool have = false;
+  const uint32_t* list = NODE ? a.node_m2l_pool : a.m2l_list;
+  const uint32_t* dc = NODE ? nullptr : a.depth_cnt + (active ? a.leaf_doff[l] : 0);
+  uint64_t seg = NODE ? 0 : (active ? a.m2l_off[l] : 0);
+  uint64_t e = 0, ne = 0;
+  int v = 0, k = 0;
+  double sv[3] = {rec[0], rec[1], rec[2]};
+  if (d >= 0) {
+    if (NODE) { e = a.node_m2l_off[0]; ne = e + a.node_m2l_cnt[0]; }
+    else { e = seg; ne = seg + dc[0]; }
+    e += sub;
+  }
+  // FP32 entries: source centre (FP64) and FP32 moments of the current entry,
+  // with the next entry prefetched
+  double cs[3] = {0.0, 0.0, 0.0};
+  float cq[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) cq[q] = 0.f;
+  uint32_t idx_next = 0;
+  auto load32 = [&](uint32_t ent, double* sd, float* qd) {
+    const uint32_t s = ent & kSrcMask;
+    const double* rs = rec + (int64_t)s * RS;
+    sd[0] = rs[0]; sd[1] = rs[1]; sd[2] = rs[2];
+    const float* r32 = rec32 + (int64_t)s * RS32;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) qd[q] = r32[q];
+  };
+  auto start_depth = [&]() {
+    if (k >= top && e < ne) {
+      load32(list[e], cs, cq);
+      idx_next = list[e + SPLIT < ne ? e + SPLIT : ne - 1];
+    }
+  };
+  start_depth();
+  for (;;) {
+    if (e < ne) {
+      if (k < top) {
+        const double* rs = rec + (int64_t)(list[e] & kSrcMask) * RS;
+        const double r[3] = {rs[0] - sv[0], rs[1] - sv[1], rs[2] - sv[2]};
+        double Q[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Q[q] = rs[8 + q];
+        E::m2l_add(r, Q, L);
+        e += SPLIT;
+      } else {
+        const uint64_t en = e + SPLIT;
+        double ns[3];
+        float nq[NQ];
+        load32(idx_next, ns, nq);
+        idx_next = list[en + SPLIT < ne ? en + SPLIT : ne - 1];
+        const float r[3] = {(float)(cs[0] - sv[0]), (float)(cs[1] - sv[1]), (float)(cs[2] - sv[2])};
+        E::m2l_add_f32(r, cq, L);
+        e = en;
+        cs[0] = ns[0]; cs[1] = ns[1]; cs[2] = ns[2];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) cq[q] = nq[q];
+      }
+      have = true;
+    } else if (k < d) {
+      const int c = info[v].child;
+      const int nv = (lo < info[c + 1].lo) ? c : c + 1;
+      const double* rn = rec + (int64_t)nv * RS;
+      const double sn[3] = {rn[0], rn[1], rn[2]};
+      if (have) {
+        const double hv[3] = {sn[0] - sv[0], sn[1] - sv[1], sn[2] - sv[2]};
+        E::l2l(hv, L);
+      }
+      v = nv;
+      sv[0] = sn[0]; sv[1] = sn[1]; sv[2] = sn[2];
+      ++k;
+      if (NODE) {
+        e = a.node_m2l_off[v];
+        ne = e + a.node_m2l_cnt[v];
+      } else {
+        seg += dc[k - 1];
+        e = seg;
+        ne = seg + dc[k];
+      }
+      e += sub;
+      start_depth();
+    } else {
+      break;
+    }
+  }
+#pragma unroll
+  for (int o = SPLIT / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] += __shfl_xor(L[q], o, 64);
+    const int other = __shfl_xor((int)have, o, 64);
+    have = have || other != 0;
+  }
+  for (int j = lo + sub; j < lo + cnt; j += SPLIT) {
+    const double off[3] = {a.xs[j] - sv[0], a.ys[j] - sv[1], a.zs[j] - sv[2]};
+    double f[3] = {0.0, 0.0, 0.0}, phi = 0.0;
+    if (have) E::l2p(off, L, f, phi);
+    double* o = a.far + 4 * (int64_t)j;
+    o[0] = f[0]; o[1] = f[1]; o[2] = f[2]; o[3] = phi;
+  }
+}
+
+// ---- P2P ------------------------------------------------------------------------
+__device__ __forceinline__ void soft32(float q, float hinv, float qi, float rinv, float rinv3,
+                                       float& g, float& psi) {
+  const float q2 = q * q;
+  const float h3 = hinv * hinv * hinv;
+  const float gA = h3 * fmaf(q2, fmaf(0.5f, q, -1.2f), 4.0f / 3.0f);
+  const float pA = hinv * fmaf(q2, fmaf(q2, fmaf(-0.1f, q, 0.3f), -2.0f / 3.0f), 1.4f);
+  const float qi3 = qi * qi * qi;
+  const float gB = h3 * (fmaf(q, fmaf(q, fmaf(q, -1.0f / 6.0f, 1.2f), -3.0f), 8.0f / 3.0f) -
+                         qi3 * (1.0f / 15.0f));
+  const float pB = hinv * (fmaf(q2, fmaf(q, fmaf(q, fmaf(q, 1.0f / 30.0f, -0.3f), 1.0f), -4.0f / 3.0f), 1.6f) -
+                           qi * (1.0f / 15.0f));
+  g = q >= 2.0f ? rinv3 : (q < 1.0f ? gA : gB);
+  psi = q >= 2.0f ? rinv : (q < 1.0f ? pA : pB);
+}
+
+__device__ __forceinline__ int wave_incl_scan32(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int LS, bool NODE, int RS>
+__global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __restrict__ pf,
+                                                   const float2* __restrict__ phh) {
+  const int lane = threadIdx.x;
+  const int l = blockIdx.x;
+  const int node = a.leaf_node[l];
+  const NodeInfo ti = a.info[node];
+  const int nt = ti.cnt;
+  const double* rt = a.rec + (int64_t)node * RS;
+  const double ct0 = rt[0], ct1 = rt[1], ct2 = rt[2];
+  __shared__ float tg[LS][5];  // offset x, y, z, 1/h, h
+  if (lane < nt) {
+    const float4 o = pf[ti.lo + lane];
+    const float2 hh = phh[ti.lo + lane];
+    tg[lane][0] = o.x; tg[lane][1] = o.y; tg[lane][2] = o.z;
+    tg[lane][3] = hh.y; tg[lane][4] = hh.x;
+  }
+  __syncthreads();
+  double fx[LS], fy[LS], fz[LS], ph[LS];
+#pragma unroll
+  for (int i = 0; i < LS; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+  uint64_t e0, e1;
+  const int32_t* list;
+  if (NODE) {
+    e0 = a.node_p2p_off[node];
+    e1 = e0 + a.node_p2p_cnt[node];
+    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    e0 = a.p2p_off[l];
+    e1 = a.p2p_off[l + 1];
+    list = a.p2p_list;
+  }
+  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+    int cnt = 0, lo = 0;
+    float dcx = 0.f, dcy = 0.f, dcz = 0.f;
+    if (c0 + lane < e1) {
+      const int src = list[c0 + lane];
+      const NodeInfo si = a.info[src];
+      cnt = si.cnt;
+      lo = si.lo;
+      const double* rs = a.rec + (int64_t)src * RS;
+      dcx = (float)(ct0 - rs[0]);
+      dcy = (float)(ct1 - rs[1]);
+      dcz = (float)(ct2 - rs[2]);
+    }
+    const int incl = wave_incl_scan32(cnt);
+    const int pre = incl - cnt;
+    const int total = __shfl(incl, 63, 64);
+    for (int f0 = 0; f0 < total; f0 += 64) {
+      const int f = f0 + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int pk = __shfl(pre, k + step, 64);
+        if (pk <= f) k += step;
+      }
+      const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+      const float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
+      if (f >= total) continue;
+      const float4 oj = pf[j];
+      const float2 hj = phh[j];
+      const float hj2inv = hj.y * hj.y;
+#pragma unroll
+      for (int i = 0; i < LS; ++i) {
+        if (i >= nt) break;
+        const float w = (j == ti.lo + i) ? 0.f : oj.w;
+        const float thi = tg[i][3];
+        const float dx = cx + (tg[i][0] - oj.x);
+        const float dy = cy + (tg[i][1] - oj.y);
+        const float dz = cz + (tg[i][2] - oj.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const float rinv = r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
+        const float rinv3 = rinv * rinv * rinv;
+        float gs = rinv3, ps = rinv;
+        const bool inside = (r2 * (thi * thi) < 4.0f) || (r2 * hj2inv < 4.0f);
+        if (__ballot(inside)) {
+          const float r = r2 * rinv;
+          float g1, p1, g2, p2;
+          soft32(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
+          soft32(r * hj.y, hj.y, hj.x * rinv, rinv, rinv3, g2, p2);
+          if (inside) {
+            gs = 0.5f * (g1 + g2);
+            ps = 0.5f * (p1 + p2);
+          }
+        }
+        const float mg = w * gs;
+        fx[i] += (double)(mg * dx);
+        fy[i] += (double)(mg * dy);
+        fz[i] += (double)(mg * dz);
+        ph[i] += (double)(w * ps);
+      }
+    }
+  }
+  const double G = a.G;
+#pragma unroll
+  for (int i = 0; i < LS; ++i) {
+    if (i >= nt) break;
+    const double sx = wave_sum64(fx[i]), sy = wave_sum64(fy[i]), sz = wave_sum64(fz[i]);
+    double sp = wave_sum64(ph[i]);
+    if (lane == i) {
+      const int j = ti.lo + i;
+      if (a.include_self) sp = fma(a.ms[j], 1.4 * a.his[j], sp);
+      const double* fr = a.far + 4 * (int64_t)j;
+      const int64_t o = a.perm[j];
+      a.acc[3 * o] = -G * (fr[0] + sx);
+      a.acc[3 * o + 1] = -G * (fr[1] + sy);
+      a.acc[3 * o + 2] = -G * (fr[2] + sz);
+      a.pot[o] = -G * (fr[3] + sp);
+    }
+  }
+}
+
+constexpr int kFarSplit32 = 2;
+
+template <int P>
+void far32_order(bool node_lists, const FarArgs& a, const float* rec32, int top, hipStream_t s) {
+  const unsigned nb = (unsigned)((a.nleaves + 64 / kFarSplit32 - 1) / (64 / kFarSplit32));
+  if (node_lists) k_far32<P, true, kFarSplit32><<<nb, 64, 0, s>>>(a, rec32, top);
+  else k_far32<P, false, kFarSplit32><<<nb, 64, 0, s>>>(a, rec32, top);
+}
+
+template <int RS>
+void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info, const double* rec,
+                    const double* xs, const double* ys, const double* zs, const double* ms,
+                    const double* hs, float4* pf, float2* ph, hipStream_t s) {
+  k_prep_particles32<RS><<<(nleaves + 127) / 128, 128, 0, s>>>(nleaves, leaf_node, info, rec, xs, ys,
+                                                               zs, ms, hs, pf, ph);
+}
+
+template <int LS, int RS>
+void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, hipStream_t s) {
+  if (node_lists) k_p2p_leaf32<LS, true, RS><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
+  else k_p2p_leaf32<LS, false, RS><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
+}
+
+}  // namespace
+
+void launch_prep32(int order, int nn, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                   const double* rec, const int32_t* node_depth, const double* xs, const double* ys,
+                   const double* zs, const double* ms, const double* hs, float* rec32, float4* pf,
+                   float2* ph, hipStream_t s) {
+  const unsigned nb = (unsigned)((nn + 255) / 256);
+  switch (order) {
+    case 0: k_prep_nodes32<0><<<nb, 256, 0, s>>>(nn, rec, node_depth, rec32); break;
+    case 1: k_prep_nodes32<1><<<nb, 256, 0, s>>>(nn, rec, node_depth, rec32); break;
+    case 2: k_prep_nodes32<2><<<nb, 256, 0, s>>>(nn, rec, node_depth, rec32); break;
+    case 3: k_prep_nodes32<3><<<nb, 256, 0, s>>>(nn, rec, node_depth, rec32); break;
+    case 4: k_prep_nodes32<4><<<nb, 256, 0, s>>>(nn, rec, node_depth, rec32); break;
+  }
+  switch (rec_stride(order)) {
+    case 16: prep_particles<16>(nleaves, leaf_node, info, rec, xs, ys, zs, ms, hs, pf, ph, s); break;
+    case 24: prep_particles<24>(nleaves, leaf_node, info, rec, xs, ys, zs, ms, hs, pf, ph, s); break;
+    case 32: prep_particles<32>(nleaves, leaf_node, info, rec, xs, ys, zs, ms, hs, pf, ph, s); break;
+    case 48: prep_particles<48>(nleaves, leaf_node, info, rec, xs, ys, zs, ms, hs, pf, ph, s); break;
+  }
+}
+
+void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec32, int top,
+                  hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  switch (order) {
+    case 0: far32_order<0>(node_lists, a, rec32, top, s); break;
+    case 1: far32_order<1>(node_lists, a, rec32, top, s); break;
+    case 2: far32_order<2>(node_lists, a, rec32, top, s); break;
+    case 3: far32_order<3>(node_lists, a, rec32, top, s); break;
+    case 4: far32_order<4>(node_lists, a, rec32, top, s); break;
+  }
+}
+
+bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
+                   const float2* ph, hipStream_t s) {
+  if (a.n <= 0) return true;
+  const int RS = rec_stride(order);
+  if (leaf_size > 16) return false;
+#define SFMM_P2P32(LS)                                                  \
+  switch (RS) {                                                         \
+    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, s); break;            \
+    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, s); break;            \
+    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, s); break;            \
+    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, s); break;            \
+  }
+  if (leaf_size <= 10) { SFMM_P2P32(10) } else { SFMM_P2P32(16) }
+#undef SFMM_P2P32
+  return true;
+}
+
+}  // namespace sfmm

@@ -34,6 +34,7 @@ enum BufId {
   B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
+  B_REC32, B_PF32, B_PH32,
   B_COUNT
 };
 
@@ -429,7 +430,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   }
 }
 
-int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, double* pot) {
+int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m, double* acc,
+                     double* pot) {
   int rc;
   const hipStream_t s = ctx->stream;
   const int n = (int)ctx->n, nl = (int)ctx->nleaves;
@@ -473,8 +475,25 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   f.ys = P<double>(ctx, B_YS);
   f.zs = P<double>(ctx, B_ZS);
   f.far = P<double>(ctx, B_FAR);
+  const bool f32 = precision == SFMM_FP32C;
+  if (f32) {
+    if (ctx->cfg.leaf_size > 16)
+      return fail(ctx, SFMM_EUNSUPPORTED, "SFMM_FP32C needs leaf_size <= 16");
+    struct { int id; size_t bytes; } need3[] = {
+        {B_REC32, sizeof(float) * rec32_stride(ctx->order) * (size_t)ctx->nn},
+        {B_PF32, sizeof(float4) * (size_t)n}, {B_PH32, sizeof(float2) * (size_t)n}};
+    for (auto& q : need3)
+      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+  }
   phase_mark(ctx, 3, 0);
-  launch_far(ctx->order, level, ctx->far_variant, f, s);
+  if (f32) {
+    launch_prep32(ctx->order, (int)ctx->nn, nl, f.leaf_node, f.info, f.rec, P<int32_t>(ctx, B_NDEPTH),
+                  f.xs, f.ys, f.zs, P<double>(ctx, B_MS), P<double>(ctx, B_HS),
+                  P<float>(ctx, B_REC32), P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), s);
+    launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
+  } else {
+    launch_far(ctx->order, level, ctx->far_variant, f, s);
+  }
   phase_mark(ctx, 3, 1);
   NearArgs a{};
   a.n = n;
@@ -492,13 +511,16 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, const double* m, double* acc, 
   a.hs = P<double>(ctx, B_HS);
   a.his = P<double>(ctx, B_HIS);
   a.far = f.far;
+  a.rec = f.rec;
   a.perm = P<uint32_t>(ctx, B_VAL0);
   a.G = ctx->cfg.G;
   a.include_self = ctx->cfg.include_self_potential;
   a.acc = acc;
   a.pot = pot;
   phase_mark(ctx, 4, 0);
-  launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, s);
+  if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, a, P<float4>(ctx, B_PF32),
+                        P<float2>(ctx, B_PH32), s);
+  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, s);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
@@ -527,6 +549,7 @@ int sfmm_config_default(sfmm_config* cfg) {
   cfg->include_self_potential = 1;
   cfg->check_inputs = 1;
   cfg->walk_mode = SFMM_WALK_LEVEL;
+  cfg->fp64_top_depth = 8;
   return SFMM_OK;
 }
 
@@ -537,7 +560,8 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   sfmm_config_default(&c);
   if (cfg) c = *cfg;
   if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
-      !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF))
+      !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
+      c.fp64_top_depth < 0 || c.fp64_top_depth > 128)
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -594,12 +618,13 @@ int sfmm_solve(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
   if (!ctx) return SFMM_EINVAL;
   ctx->err.clear();
   if (!(theta > 0.0 && theta < 1.0)) return fail(ctx, SFMM_EINVAL, "theta must be in (0, 1)");
-  if (precision != SFMM_FP64) return fail(ctx, SFMM_EUNSUPPORTED, "unknown precision");
+  if (precision != SFMM_FP64 && precision != SFMM_FP32C)
+    return fail(ctx, SFMM_EUNSUPPORTED, "unknown precision");
   if (n > 0 && (!acc || !pot)) return fail(ctx, SFMM_EINVAL, "NULL output array");
   int rc = do_build(ctx, n, x, m, h, order);
   if (rc) return rc;
   if (n == 0) return SFMM_OK;
-  return do_walk_and_eval(ctx, theta, m, acc, pot);
+  return do_walk_and_eval(ctx, theta, precision, m, acc, pot);
 }
 
 int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {

@@ -33,6 +33,8 @@ constexpr int kMaxOrder = 4;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
+// FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
+__host__ __device__ constexpr int rec32_stride(int p) { return ((ncoef(p) + 1 + 7) / 8) * 8; }
 
 // ---- status bits written by kernels --------------------------------------
 enum : int { ST_NONFINITE = 1, ST_DEPTH = 2, ST_OVERFLOW = 4 };
@@ -180,6 +182,7 @@ struct NearArgs {
   const uint32_t *node_p2p_off, *node_p2p_cnt, *node_p2p_pool;
   const double *xs, *ys, *zs, *ms, *hs, *his;  // his = 1/h
   const double* far;
+  const double* rec;  // node records (leaf centres, FP32C)
   const uint32_t* perm;
   double G;
   int include_self;
@@ -188,6 +191,18 @@ struct NearArgs {
 };
 // wave-per-leaf kernel for leaf_size <= 16, particle-per-thread otherwise
 void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s);
+
+// ---- FP32-compensated form ------------------------------------------------------
+// FP32 moments per node and FP32 leaf-relative particle offsets (+ mass, h, 1/h)
+void launch_prep32(int order, int nn, int nleaves, const int32_t* leaf_node, const NodeInfo* info,
+                   const double* rec, const int32_t* node_depth, const double* xs, const double* ys,
+                   const double* zs, const double* ms, const double* hs, float* rec32, float4* pf,
+                   float2* ph, hipStream_t s);
+void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec32, int top,
+                  hipStream_t s);
+// false when leaf_size > 16 (not built)
+bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
+                   const float2* ph, hipStream_t s);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);

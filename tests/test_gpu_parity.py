@@ -276,3 +276,46 @@ def test_full_size_sampled(torch, P, orc):
     err = np.linalg.norm(acc[tg] - oa, axis=1) / nb
     assert err.max() < TOL
     assert (np.abs(pot[tg] - op) / np.abs(op)).max() < TOL
+
+
+# ---- FP32-compensated form ---------------------------------------------------
+def _rms_rel(a, b):
+    nb = np.linalg.norm(b, axis=1)
+    return float(np.sqrt(((np.linalg.norm(a - b, axis=1) / nb) ** 2).mean()))
+
+
+@pytest.mark.parametrize("top", [8, 0])
+def test_fp32c_plummer(torch, P, orc, top):
+    """FP32 terms with FP64 sums: RMS relative error <= 1e-6 against the FP64
+    oracle of the same method, momentum residual <= 1e-7."""
+    print(f"case: fp32c plummer N=4096 top={top}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    s = P.Solver(fp64_top_depth=top)
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    assert _rms_rel(acc, oa) <= 1e-6
+    assert rel_err(acc, oa).max() <= 1e-4
+    assert np.sqrt((((pot - op) / op) ** 2).mean()) <= 1e-6
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+
+
+def test_fp32c_binary_polytrope(torch, P, orc):
+    """Two n=1.5 stars (the binary-polytrope shape at reduced N), sampled."""
+    print("case: fp32c binary polytrope 2x30000", flush=True)
+    x, m, h, _ = workloads.binary_polytrope(30000)
+    s = P.Solver()
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    rng = np.random.default_rng(1)
+    tg = rng.choice(len(m), 1500, replace=False)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    oa, op, _ = t.solve(0.5, targets=tg)
+    assert _rms_rel(acc[tg], oa) <= 1e-6
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
