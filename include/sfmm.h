@@ -134,6 +134,23 @@ int sfmm_build(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
 int sfmm_solve(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
                double theta, int order, int precision, double* acc, double* pot);
 
+/* Solve k independent systems together (the packed launch of the serving
+ * loop).  System s owns particles [offsets[s], offsets[s+1]) of the
+ * concatenated device arrays x, m, h, acc, pot; offsets is a HOST array of
+ * k+1 non-decreasing values starting at 0.  Every phase runs once for the
+ * whole set: the keys are sorted by (system, key, position), no tree node over
+ * two systems becomes a leaf or is walked, and each system's walk starts at
+ * its own root.  Each system therefore gets the tree, interaction lists and
+ * results it would get alone: bit for bit in SFMM_FP64; in SFMM_FP32C the
+ * fp64_top_depth levels count from the root of the whole set, so a packed
+ * system may run a few more of its top levels in FP64 than alone (results
+ * within the FP32C bound).  Momentum is conserved per system.  Needs
+ * SFMM_WALK_LEVEL.  Errors: as sfmm_solve, plus SFMM_EINVAL
+ * for k < 1 or bad offsets, SFMM_EUNSUPPORTED with SFMM_WALK_LEAF. */
+int sfmm_solve_batch(sfmm_ctx* ctx, int k, const int64_t* offsets, const double* x,
+                     const double* m, const double* h, double theta, int order, int precision,
+                     double* acc, double* pot);
+
 /* Copy the statistics of the last solve (synchronises the stream). */
 int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out);
 
@@ -173,6 +190,17 @@ int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t
 int sfmm_timing_start(sfmm_ctx* ctx, int max_solves);
 int sfmm_timing_stop(sfmm_ctx* ctx, double* ms, int cap, int* nsolves);
 const char* sfmm_phase_name(int phase);
+
+/* Device bytes the context holds (its workspace), for footprint models. */
+int sfmm_workspace_bytes(const sfmm_ctx* ctx, uint64_t* out);
+
+/* One leapfrog update of a system on `hip_stream` (device arrays [n][3]):
+ * v += kick * acc, then x += drift * v.  A kick-drift-kick step of length dt
+ * is (dt/2, dt) before the solve and (dt/2, 0) after it; consecutive steps
+ * merge the two half kicks into (dt, dt).  Used by the serving loop, which
+ * evolves each request for a few steps. */
+int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const double* acc,
+                  double kick, double drift);
 
 /* Human-readable text of a status code (static storage). */
 const char* sfmm_strerror(int status);

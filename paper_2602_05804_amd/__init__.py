@@ -21,8 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libsfmm.so")
 
 # every entry point declared in include/sfmm.h
 EXPORTED = ("sfmm_config_default", "sfmm_create", "sfmm_destroy", "sfmm_set_stream",
-            "sfmm_build", "sfmm_solve", "sfmm_get_stats", "sfmm_get_tree", "sfmm_get_leaves",
+            "sfmm_build", "sfmm_solve", "sfmm_solve_batch", "sfmm_get_stats", "sfmm_get_tree", "sfmm_get_leaves",
             "sfmm_get_leaf_lists", "sfmm_timing_start", "sfmm_timing_stop", "sfmm_phase_name",
+            "sfmm_workspace_bytes", "sfmm_leapfrog",
             "sfmm_strerror", "sfmm_last_error")
 PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum")
 
@@ -76,6 +77,7 @@ def lib():
         L.sfmm_set_stream.argtypes = [vp, vp]
         L.sfmm_build.argtypes = [vp, i64, vp, vp, vp, C.c_int]
         L.sfmm_solve.argtypes = [vp, i64, vp, vp, vp, d, C.c_int, C.c_int, vp, vp]
+        L.sfmm_solve_batch.argtypes = [vp, C.c_int, vp, vp, vp, vp, d, C.c_int, C.c_int, vp, vp]
         L.sfmm_get_stats.argtypes = [vp, vp]
         L.sfmm_get_tree.argtypes = [vp] * 14
         L.sfmm_get_leaves.argtypes = [vp, vp, vp]
@@ -84,6 +86,8 @@ def lib():
         L.sfmm_timing_stop.argtypes = [vp, vp, C.c_int, vp]
         L.sfmm_phase_name.restype = C.c_char_p
         L.sfmm_phase_name.argtypes = [C.c_int]
+        L.sfmm_workspace_bytes.argtypes = [vp, vp]
+        L.sfmm_leapfrog.argtypes = [vp, i64, vp, vp, vp, d, d]
         L.sfmm_strerror.restype = C.c_char_p
         L.sfmm_strerror.argtypes = [C.c_int]
         L.sfmm_last_error.restype = C.c_char_p
@@ -164,6 +168,35 @@ class Solver:
                     "sfmm_solve")
         return acc, pot
 
+    def solve_batch(self, systems, theta: float = 0.5, order: int = 3, precision: str = "fp64"):
+        """Solve several independent systems in one pass; systems is a list of
+        (x, m, h) device tensors.  Returns a list of (acc, pot), each exactly
+        what a solve of that system alone returns."""
+        import numpy as np
+
+        torch = self._torch
+        if len(systems) == 0:
+            return []
+        for i, (x, m, h) in enumerate(systems):
+            if not (x.dim() == 2 and x.shape[1] == 3 and m.shape == (x.shape[0],)
+                    and h.shape == (x.shape[0],)):
+                raise SfmmError(f"system {i}: x must be [n, 3] and m, h [n]")
+        xs = torch.cat([s[0] for s in systems]).contiguous()
+        ms = torch.cat([s[1] for s in systems]).contiguous()
+        hs = torch.cat([s[2] for s in systems]).contiguous()
+        n = self._inputs(xs, ms, hs)
+        if precision not in _PRECISION:
+            raise SfmmError(f"unknown precision {precision!r}")
+        off = np.zeros(len(systems) + 1, dtype=np.int64)
+        off[1:] = np.cumsum([s[1].shape[0] for s in systems])
+        acc = torch.empty((n, 3), dtype=torch.float64, device=xs.device)
+        pot = torch.empty((n,), dtype=torch.float64, device=xs.device)
+        self._check(lib().sfmm_solve_batch(self._ctx, len(systems), off.ctypes.data_as(C.c_void_p),
+                                           _ptr(xs), _ptr(ms), _ptr(hs), float(theta), int(order),
+                                           _PRECISION[precision], _ptr(acc), _ptr(pot)),
+                    "sfmm_solve_batch")
+        return [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(systems))]
+
     def stats(self) -> dict:
         st = Stats()
         self._check(lib().sfmm_get_stats(self._ctx, C.byref(st)), "sfmm_get_stats")
@@ -233,6 +266,11 @@ class Solver:
                     "sfmm_get_leaf_lists")
         return dep, src, p2p
 
+    def workspace_bytes(self) -> int:
+        out = C.c_uint64(0)
+        self._check(lib().sfmm_workspace_bytes(self._ctx, C.byref(out)), "sfmm_workspace_bytes")
+        return out.value
+
     def close(self):
         if getattr(self, "_ctx", None):
             lib().sfmm_destroy(self._ctx)
@@ -243,6 +281,16 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def leapfrog(x, v, acc, kick: float, drift: float):
+    """v += kick * acc; x += drift * v (device tensors [n,3], current stream)."""
+    import torch
+
+    rc = lib().sfmm_leapfrog(C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream),
+                             x.shape[0], _ptr(x), _ptr(v), _ptr(acc), float(kick), float(drift))
+    if rc != 0:
+        raise SfmmError(f"sfmm_leapfrog: {lib().sfmm_strerror(rc).decode()}")
 
 
 _default: dict = {}

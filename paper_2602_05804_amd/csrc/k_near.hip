@@ -305,6 +305,24 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   }
 }
 
+// leapfrog update of one system: v += kick * acc; x += drift * v
+__global__ void k_leapfrog(int64_t n3, double* __restrict__ x, double* __restrict__ v,
+                           const double* __restrict__ acc, double kick, double drift) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  // separate multiply and add (no contraction), as the update is written
+  const double vi = v[i] + kick * acc[i];
+  v[i] = vi;
+  x[i] = x[i] + drift * vi;
+}
+
+void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double kick, double drift,
+                     hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t n3 = 3 * n;
+  k_leapfrog<<<(unsigned)((n3 + 255) / 256), 256, 0, s>>>(n3, x, v, acc, kick, drift);
+}
+
 int momentum_blocks(int64_t n) {
   int64_t b = (n + MOM_THREADS * 8 - 1) / (MOM_THREADS * 8);
   if (b < 1) b = 1;

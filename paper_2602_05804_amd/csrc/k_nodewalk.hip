@@ -210,7 +210,10 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   const double* rv = a.rec + (int64_t)v * a.stride;
-  const bool root = vi.parent < 0;
+  // a node over two systems (several systems solved together) is never
+  // walked; the walk of each system starts at its own root
+  const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
+  const bool root = flag == 1;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t* src = nullptr;
   uint32_t nsrc = 0;
@@ -219,6 +222,21 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
     nsrc = a.open_cnt[vi.parent];
     src = a.open_pool + po;
     if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
+  }
+  if (flag == 0) {
+    if (lane == 0) {
+      if (FILL) {
+        a.m2l_off[v] = (uint32_t)a.lvl_off[idx];
+        a.open_off[v] = (uint32_t)(a.lvl_off[idx] >> 32);
+        a.p2p_off[v] = 0;
+      } else {
+        a.m2l_cnt[v] = 0;
+        a.open_cnt[v] = 0;
+        a.p2p_cnt[v] = 0;
+        a.lvl_cnt[idx] = vi.child >= 0 ? 0ull : (1ull << 63);
+      }
+    }
+    return;
   }
   Emit e{};
   if (FILL) {

@@ -96,6 +96,119 @@ __global__ __launch_bounds__(256) void k_bbox_final(int nb, const double* __rest
   box[4] = ext > 0.0 ? 2097152.0 / ext : 0.0;
 }
 
+// ---- several systems (forest) -----------------------------------------------
+// box of system s: one block per system; same box[] layout as k_bbox_final
+__global__ __launch_bounds__(256) void k_bbox_sys(const int64_t* __restrict__ off,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ m,
+                                                  const double* __restrict__ h,
+                                                  double* __restrict__ boxes, int* status,
+                                                  int check) {
+  const int sidx = blockIdx.x;
+  const int64_t b = off[sidx], e = off[sidx + 1];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int bad = 0;
+  for (int64_t i = b + threadIdx.x; i < e; i += 256) {
+    for (int d = 0; d < 3; ++d) {
+      const double v = x[3 * i + d];
+      mn[d] = fmin(mn[d], v);
+      mx[d] = fmax(mx[d], v);
+      if (check && !isfinite(v)) bad = 1;
+    }
+    if (check && !(m[i] > 0.0 && h[i] > 0.0 && isfinite(m[i]) && isfinite(h[i]))) bad = 1;
+  }
+  if (bad) atomicOr(status, ST_NONFINITE);
+  __shared__ double sh[6][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = 0; d < 3; ++d) {
+    const double a = wave_min(mn[d]), c = wave_max(mx[d]);
+    if (lane == 0) { sh[d][w] = a; sh[3 + d][w] = c; }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  double ext = 0.0;
+  double* box = boxes + 8 * sidx;
+  for (int d = 0; d < 3; ++d) {
+    const double lo = fmin(fmin(sh[d][0], sh[d][1]), fmin(sh[d][2], sh[d][3]));
+    const double hi = fmax(fmax(sh[3 + d][0], sh[3 + d][1]), fmax(sh[3 + d][2], sh[3 + d][3]));
+    box[d] = lo;
+    if (hi - lo > ext) ext = hi - lo;
+  }
+  box[3] = ext;
+  box[4] = ext > 0.0 ? 2097152.0 / ext : 0.0;
+}
+
+__device__ __forceinline__ uint64_t spread3(uint64_t v);
+
+// Morton key of each particle in its own system's box; sys[i] = its system
+__global__ void k_keys_sys(int n, int nsys, const int64_t* __restrict__ off,
+                           const double* __restrict__ x, const double* __restrict__ boxes,
+                           uint64_t* __restrict__ key, uint32_t* __restrict__ idx,
+                           uint32_t* __restrict__ sys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int lo = 0, hi = nsys - 1;  // last s with off[s] <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  const double* box = boxes + 8 * lo;
+  uint64_t c[3] = {0, 0, 0};
+  if (box[3] > 0.0) {
+    for (int d = 0; d < 3; ++d) {
+      const double f = floor((x[3 * (int64_t)i + d] - box[d]) * box[4]);
+      c[d] = f > 2097151.0 ? 2097151ull : (uint64_t)f;
+    }
+  }
+  key[i] = (spread3(c[0]) << 2) | (spread3(c[1]) << 1) | spread3(c[2]);
+  idx[i] = (uint32_t)i;
+  sys[i] = (uint32_t)lo;
+}
+
+// after the key sort: the system of each key-sorted position, as a sort key
+__global__ void k_sys_sortkey(int n, const uint32_t* __restrict__ perm1,
+                              const uint32_t* __restrict__ sys, uint64_t* __restrict__ skey,
+                              uint32_t* __restrict__ pos) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  skey[i] = sys[perm1[i]];
+  pos[i] = (uint32_t)i;
+}
+
+// final order = (system, key, caller index): gather permutation, keys, systems
+__global__ void k_sys_final(int n, const uint32_t* __restrict__ q, const uint32_t* __restrict__ perm1,
+                            const uint64_t* __restrict__ key1, const uint32_t* __restrict__ sys,
+                            uint32_t* __restrict__ perm, uint64_t* __restrict__ key,
+                            uint32_t* __restrict__ sys_sorted) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = q[i];
+  const uint32_t o = perm1[p];
+  perm[i] = o;
+  key[i] = key1[p];
+  sys_sorted[i] = sys[o];
+}
+
+__global__ void k_sys_start(int nsys, const int64_t* __restrict__ off, int32_t* __restrict__ start) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < nsys) start[s] = (int32_t)off[s];
+}
+
+// 0: the node spans two systems (never walked); 1: the root of a system; 2: other
+__global__ void k_node_flags(int nn, const NodeInfo* __restrict__ info,
+                             const uint32_t* __restrict__ sys, uint8_t* __restrict__ flag) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  const NodeInfo ni = info[v];
+  const bool within = !sys || sys[ni.lo] == sys[ni.lo + ni.cnt - 1];
+  bool root = ni.parent < 0;
+  if (!root && sys) {
+    const NodeInfo pi = info[ni.parent];
+    root = sys[pi.lo] != sys[pi.lo + pi.cnt - 1];
+  }
+  flag[v] = !within ? 0 : (root ? 1 : 2);
+}
+
 __device__ __forceinline__ uint64_t spread3(uint64_t v) {
   v &= 0x1fffffull;
   v = (v | (v << 32)) & 0x1f00000000ffffull;
@@ -200,35 +313,45 @@ __global__ void k_gather(int n, const uint32_t* __restrict__ perm, const double*
 }
 
 // ---- binary radix tree (Karras 2012) ----------------------------------------
-// delta = length of the common prefix of the augmented keys (key, position)
-__device__ __forceinline__ int delta(const uint64_t* __restrict__ k, int n, int i, int j) {
+// delta = length of the common prefix of the augmented keys
+// (system, key, position within the system); sys == nullptr: one system
+__device__ __forceinline__ int delta(const uint64_t* __restrict__ k, const uint32_t* __restrict__ sys,
+                                     const int32_t* __restrict__ sys_start, int n, int i, int j) {
   if (j < 0 || j >= n) return -1;
-  uint64_t a = k[i], b = k[j];
-  if (a != b) return __clzll((long long)(a ^ b));
-  return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+  uint32_t si = 0, sj = 0;
+  if (sys) {
+    si = sys[i];
+    sj = sys[j];
+    if (si != sj) return __clz((int)(si ^ sj));
+  }
+  const uint64_t a = k[i], b = k[j];
+  if (a != b) return 32 + __clzll((long long)(a ^ b));
+  const int s0 = sys ? sys_start[si] : 0;
+  return 96 + __clz((int)((uint32_t)(i - s0) ^ (uint32_t)(j - s0)));
 }
 
 // internal node i (0..n-2); child codes: >= 0 internal node, < 0 leaf -(pos+1)
-__global__ void k_karras(int n, const uint64_t* __restrict__ key, int leaf_size,
+__global__ void k_karras(int n, const uint64_t* __restrict__ key, const uint32_t* __restrict__ sys,
+                         const int32_t* __restrict__ sys_start, int leaf_size,
                          int32_t* __restrict__ kfirst, int32_t* __restrict__ klast,
                          int32_t* __restrict__ kleft, int32_t* __restrict__ kright,
                          int32_t* __restrict__ kpar, int32_t* __restrict__ kside,
                          uint32_t* __restrict__ kept) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
-  const int d = (delta(key, n, i, i + 1) - delta(key, n, i, i - 1)) >= 0 ? 1 : -1;
-  const int dmin = delta(key, n, i, i - d);
+  const int d = (delta(key, sys, sys_start, n, i, i + 1) - delta(key, sys, sys_start, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = delta(key, sys, sys_start, n, i, i - d);
   int lmax = 2;
-  while (delta(key, n, i, i + lmax * d) > dmin) lmax *= 2;
+  while (delta(key, sys, sys_start, n, i, i + lmax * d) > dmin) lmax *= 2;
   int l = 0;
   for (int t = lmax / 2; t >= 1; t /= 2)
-    if (delta(key, n, i, i + (l + t) * d) > dmin) l += t;
+    if (delta(key, sys, sys_start, n, i, i + (l + t) * d) > dmin) l += t;
   const int j = i + l * d;
-  const int dnode = delta(key, n, i, j);
+  const int dnode = delta(key, sys, sys_start, n, i, j);
   int s = 0;
   for (int div = 2;; div *= 2) {
     int t = (l + div - 1) / div;
-    if (delta(key, n, i, i + (s + t) * d) > dnode) s += t;
+    if (delta(key, sys, sys_start, n, i, i + (s + t) * d) > dnode) s += t;
     if (t <= 1) break;
   }
   const int gamma = i + s * d + (d < 0 ? -1 : 0);
@@ -241,7 +364,9 @@ __global__ void k_karras(int n, const uint64_t* __restrict__ key, int leaf_size,
   kright[i] = right;
   if (left >= 0) { kpar[left] = i; kside[left] = 0; }
   if (right >= 0) { kpar[right] = i; kside[right] = 1; }
-  kept[i] = (last - first + 1) > leaf_size ? 1u : 0u;
+  // a node over particles of two systems never becomes a leaf
+  const bool spans = sys && sys[first] != sys[last];
+  kept[i] = ((last - first + 1) > leaf_size || spans) ? 1u : 0u;
   if (i == 0) kpar[0] = -1;
 }
 
@@ -252,7 +377,8 @@ __device__ __forceinline__ int final_id(int i, const int32_t* kpar, const int32_
   return i == 0 ? 0 : 1 + 2 * (int)cidx[kpar[i]] + kside[i];
 }
 
-__global__ void k_assign(int n, int leaf_size, const int32_t* __restrict__ kfirst,
+__global__ void k_assign(int n, int leaf_size, const uint32_t* __restrict__ sys,
+                         const int32_t* __restrict__ kfirst,
                          const int32_t* __restrict__ klast, const int32_t* __restrict__ kleft,
                          const int32_t* __restrict__ kright, const int32_t* __restrict__ kpar,
                          const int32_t* __restrict__ kside, const uint32_t* __restrict__ cidx,
@@ -261,7 +387,8 @@ __global__ void k_assign(int n, int leaf_size, const int32_t* __restrict__ kfirs
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n - 1) return;
   const int first = kfirst[i], last = klast[i];
-  if (last - first + 1 <= leaf_size) return;  // not a kept internal node
+  const bool spans = sys && sys[first] != sys[last];
+  if (last - first + 1 <= leaf_size && !spans) return;  // not a kept internal node
   const int me = final_id(i, kpar, kside, cidx);
   const int par = i == 0 ? -1 : final_id(kpar[i], kpar, kside, cidx);
   const int base = 1 + 2 * (int)cidx[i];
@@ -273,7 +400,8 @@ __global__ void k_assign(int n, int leaf_size, const int32_t* __restrict__ kfirs
     int c = ch[side], lo, cnt;
     if (c < 0) { lo = -c - 1; cnt = 1; }
     else { lo = kfirst[c]; cnt = klast[c] - kfirst[c] + 1; }
-    if (cnt <= leaf_size) {
+    const bool child_spans = sys && sys[lo] != sys[lo + cnt - 1];
+    if (cnt <= leaf_size && !child_spans) {
       NodeInfo li;
       li.lo = lo; li.cnt = cnt; li.child = -1; li.parent = me;
       info[base + side] = li;
@@ -478,24 +606,48 @@ void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t*
   }
 }
 
+void launch_sys_keys(int n, int nsys, const int64_t* off, const double* x, const double* m,
+                     const double* h, double* boxes, int* status, int check, uint64_t* key,
+                     uint32_t* idx, uint32_t* sys, int32_t* sys_start, hipStream_t s) {
+  k_bbox_sys<<<nsys, 256, 0, s>>>(off, x, m, h, boxes, status, check);
+  k_keys_sys<<<blocks_for(n, 256), 256, 0, s>>>(n, nsys, off, x, boxes, key, idx, sys);
+  k_sys_start<<<blocks_for(nsys, 256), 256, 0, s>>>(nsys, off, sys_start);
+}
+
+void launch_sys_sortkey(int n, const uint32_t* perm1, const uint32_t* sys, uint64_t* skey,
+                        uint32_t* pos, hipStream_t s) {
+  k_sys_sortkey<<<blocks_for(n, 256), 256, 0, s>>>(n, perm1, sys, skey, pos);
+}
+
+void launch_sys_final(int n, const uint32_t* q, const uint32_t* perm1, const uint64_t* key1,
+                      const uint32_t* sys, uint32_t* perm, uint64_t* key, uint32_t* sys_sorted,
+                      hipStream_t s) {
+  k_sys_final<<<blocks_for(n, 256), 256, 0, s>>>(n, q, perm1, key1, sys, perm, key, sys_sorted);
+}
+
+void launch_node_flags(int nn, const NodeInfo* info, const uint32_t* sys, uint8_t* flag,
+                       hipStream_t s) {
+  k_node_flags<<<blocks_for(nn, 256), 256, 0, s>>>(nn, info, sys, flag);
+}
+
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
                    double* hs, double* his, hipStream_t s) {
   k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs, his);
 }
 
-void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,
-                   int32_t* kleft, int32_t* kright, int32_t* kpar, int32_t* kside,
-                   uint32_t* kept, hipStream_t s) {
-  k_karras<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, key, leaf_size, kfirst, klast, kleft,
-                                                  kright, kpar, kside, kept);
+void launch_karras(int n, const uint64_t* key, const uint32_t* sys, const int32_t* sys_start,
+                   int leaf_size, int32_t* kfirst, int32_t* klast, int32_t* kleft,
+                   int32_t* kright, int32_t* kpar, int32_t* kside, uint32_t* kept, hipStream_t s) {
+  k_karras<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, key, sys, sys_start, leaf_size, kfirst, klast,
+                                                  kleft, kright, kpar, kside, kept);
 }
 
-void launch_assign(int n, int leaf_size, const int32_t* kfirst, const int32_t* klast,
-                   const int32_t* kleft, const int32_t* kright, const int32_t* kpar,
-                   const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
+void launch_assign(int n, int leaf_size, const uint32_t* sys, const int32_t* kfirst,
+                   const int32_t* klast, const int32_t* kleft, const int32_t* kright,
+                   const int32_t* kpar, const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
                    uint32_t* leaf_flag, int32_t* leaf_at, hipStream_t s) {
-  k_assign<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, leaf_size, kfirst, klast, kleft, kright,
+  k_assign<<<blocks_for(n - 1, 256), 256, 0, s>>>(n, leaf_size, sys, kfirst, klast, kleft, kright,
                                                   kpar, kside, cidx, info, leaf_flag, leaf_at);
 }
 

@@ -35,6 +35,7 @@ enum BufId {
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
+  B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_COUNT
 };
 
@@ -66,6 +67,7 @@ struct sfmm_ctx {
   uint64_t m2l_cap = 0, open_cap = 0, p2p_cap = 0;
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
+  int nsys = 1;                // systems of the last build (a forest when > 1)
   int far_variant = 0;         // kernel shape of the far field (SFMM_FAR_VARIANT)
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
@@ -131,12 +133,13 @@ int set_device(sfmm_ctx* ctx) {
 }
 
 int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const double* h,
-             int order) {
+             int order, int nsys = 1, const int64_t* offsets = nullptr) {
   if (n64 < 0 || n64 >= (int64_t(1) << 30)) return fail(ctx, SFMM_EINVAL, "n out of range");
   if (order < 0 || order > kMaxOrder) return fail(ctx, SFMM_EINVAL, "order must be 0..4");
   ctx->have_tree = ctx->have_lists = ctx->have_mom = ctx->stats_pending = false;
   ctx->n = n64;
   ctx->order = order;
+  ctx->nsys = nsys;
   if (n64 == 0) {
     ctx->nn = ctx->nleaves = 0;
     ctx->maxdepth = 0;
@@ -180,12 +183,53 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   HIPCHK(hipMemsetAsync(status, 0, sizeof(int) * 4, s));
   HIPCHK(hipMemsetAsync(small, 0, sizeof(uint64_t) * S_COUNT, s));
   // ---- keys, sort, gather
-  launch_bbox(n, x, m, h, P<double>(ctx, B_BOXPART), P<double>(ctx, B_BOX), status,
-              ctx->cfg.check_inputs, s);
-  launch_keys(n, x, P<double>(ctx, B_BOX), P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), s);
-  radix_sort(n, P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), P<uint64_t>(ctx, B_KEY1),
-             P<uint32_t>(ctx, B_VAL1), P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
-             reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+  const uint32_t* sys_sorted = nullptr;
+  const int32_t* sys_start = nullptr;
+  if (nsys <= 1) {
+    launch_bbox(n, x, m, h, P<double>(ctx, B_BOXPART), P<double>(ctx, B_BOX), status,
+                ctx->cfg.check_inputs, s);
+    launch_keys(n, x, P<double>(ctx, B_BOX), P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), s);
+    radix_sort(n, P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), P<uint64_t>(ctx, B_KEY1),
+               P<uint32_t>(ctx, B_VAL1), P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
+               reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+  } else {
+    // several systems: each keyed in its own box, sorted by (system, key, index)
+    struct { int id; size_t bytes; } need1[] = {
+        {B_SYSOFF, sizeof(int64_t) * (nsys + 1)}, {B_BOXES, sizeof(double) * 8 * nsys},
+        {B_SYS, sizeof(uint32_t) * n}, {B_SYSS, sizeof(uint32_t) * n},
+        {B_SYSSTART, sizeof(int32_t) * nsys}, {B_SKEY0, sizeof(uint64_t) * n},
+        {B_SKEY1, sizeof(uint64_t) * n}, {B_SPOS0, sizeof(uint32_t) * n},
+        {B_SPOS1, sizeof(uint32_t) * n}};
+    for (auto& q : need1)
+      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+    HIPCHK(hipMemcpyAsync(P<int64_t>(ctx, B_SYSOFF), offsets, sizeof(int64_t) * (nsys + 1),
+                          hipMemcpyHostToDevice, s));
+    launch_sys_keys(n, nsys, P<int64_t>(ctx, B_SYSOFF), x, m, h, P<double>(ctx, B_BOXES), status,
+                    ctx->cfg.check_inputs, P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0),
+                    P<uint32_t>(ctx, B_SYS), P<int32_t>(ctx, B_SYSSTART), s);
+    radix_sort(n, P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_VAL0), P<uint64_t>(ctx, B_KEY1),
+               P<uint32_t>(ctx, B_VAL1), P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
+               reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+    launch_sys_sortkey(n, P<uint32_t>(ctx, B_VAL0), P<uint32_t>(ctx, B_SYS), P<uint64_t>(ctx, B_SKEY0),
+                       P<uint32_t>(ctx, B_SPOS0), s);
+    uint64_t *ka = P<uint64_t>(ctx, B_SKEY0), *kb = P<uint64_t>(ctx, B_SKEY1);
+    uint32_t *va = P<uint32_t>(ctx, B_SPOS0), *vb = P<uint32_t>(ctx, B_SPOS1);
+    for (int shift = 0; shift < 32 && ((uint64_t)(nsys - 1) >> shift) != 0; shift += 8) {
+      radix_pass(n, ka, va, kb, vb, shift, P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
+                 reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
+    // final permutation and keys into the spare buffers, then back in place
+    launch_sys_final(n, va, P<uint32_t>(ctx, B_VAL0), P<uint64_t>(ctx, B_KEY0), P<uint32_t>(ctx, B_SYS),
+                     vb, kb, P<uint32_t>(ctx, B_SYSS), s);
+    HIPCHK(hipMemcpyAsync(P<uint32_t>(ctx, B_VAL0), vb, sizeof(uint32_t) * n,
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(P<uint64_t>(ctx, B_KEY0), kb, sizeof(uint64_t) * n,
+                          hipMemcpyDeviceToDevice, s));
+    sys_sorted = P<uint32_t>(ctx, B_SYSS);
+    sys_start = P<int32_t>(ctx, B_SYSSTART);
+  }
   const uint64_t* key = P<uint64_t>(ctx, B_KEY0);
   const uint32_t* perm = P<uint32_t>(ctx, B_VAL0);
   launch_gather(n, perm, x, m, h, P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
@@ -193,17 +237,17 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   NodeInfo* info = P<NodeInfo>(ctx, B_INFO);
   int32_t* leaf_node = P<int32_t>(ctx, B_LEAFNODE);
   // ---- topology
-  if (n <= leaf_size) {
+  if (n <= leaf_size && nsys <= 1) {
     launch_single_leaf(n, info, leaf_node, s);
   } else {
-    launch_karras(n, key, leaf_size, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
+    launch_karras(n, key, sys_sorted, sys_start, leaf_size, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
                   P<int32_t>(ctx, B_KLEFT), P<int32_t>(ctx, B_KRIGHT), P<int32_t>(ctx, B_KPAR),
                   P<int32_t>(ctx, B_KSIDE), P<uint32_t>(ctx, B_KEPT), s);
     uint32_t* cidx = P<uint32_t>(ctx, B_KEPT);
     scan_u32(cidx, cidx, n - 1, reinterpret_cast<uint32_t*>(small + S_NKEPT),
              P<uint32_t>(ctx, B_SCANTMP), s);
     HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_LFLAG), 0, sizeof(uint32_t) * (n + 1), s));
-    launch_assign(n, leaf_size, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
+    launch_assign(n, leaf_size, sys_sorted, P<int32_t>(ctx, B_KFIRST), P<int32_t>(ctx, B_KLAST),
                   P<int32_t>(ctx, B_KLEFT), P<int32_t>(ctx, B_KRIGHT), P<int32_t>(ctx, B_KPAR),
                   P<int32_t>(ctx, B_KSIDE), cidx, info, P<uint32_t>(ctx, B_LFLAG),
                   P<int32_t>(ctx, B_LAT), s);
@@ -221,7 +265,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   HIPCHK(hipStreamSynchronize(s));
   if (hstatus[0] & ST_NONFINITE)
     return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
-  if (n <= leaf_size) {
+  if (n <= leaf_size && nsys <= 1) {
     ctx->nn = 1;
     ctx->nleaves = 1;
   } else {
@@ -249,6 +293,10 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
     launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn, P<uint32_t>(ctx, B_HIST),
                          P<uint32_t>(ctx, B_LEVOFF), s);
+  }
+  if (nsys > 1) {
+    if ((rc = ensure(ctx, B_NFLAG, sizeof(uint8_t) * nn))) return rc;
+    launch_node_flags(nn, info, sys_sorted, P<uint8_t>(ctx, B_NFLAG), s);
   }
   int* maxd_dev = reinterpret_cast<int*>(small + S_MAXDEPTH);
   launch_leaf_depth(nl, leaf_node, info, P<int32_t>(ctx, B_LEAFDEPTH), P<int32_t>(ctx, B_PLEAF),
@@ -361,11 +409,12 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint64_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
-  if (ctx->m2l_cap == 0) {
-    ctx->m2l_cap = 48ull * nn + 1024;
-    ctx->open_cap = 48ull * nn + 1024;
-    ctx->p2p_cap = 48ull * nl + 1024;
-  }
+  // pools keep the size of the largest walk so far, and never start below a
+  // per-node estimate for this tree (a context may go from a small system to
+  // a large one)
+  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 48ull * nn + 1024);
+  ctx->open_cap = std::max<uint64_t>(ctx->open_cap, 48ull * nn + 1024);
+  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + 1024);
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
   const uint64_t kPoolMax = 0xF0000000ull;
@@ -385,6 +434,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.theta2 = theta * theta;
     a.r_kern = ctx->cfg.r_kern;
     a.level_nodes = P<int32_t>(ctx, B_LEVNODES);
+    a.node_flag = ctx->nsys > 1 ? P<uint8_t>(ctx, B_NFLAG) : nullptr;
     a.level_off = P<uint32_t>(ctx, B_LEVOFF);
     a.m2l_off = P<uint32_t>(ctx, B_NM2LOFF);
     a.m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
@@ -417,11 +467,16 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       ctx->p2p_total = htot[2];
       return SFMM_OK;
     }
-    if (attempt >= 6) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
+    if (attempt >= 8) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
     if (pool_over) {
-      ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, htot[0] + htot[0] / 4 + 1024);
-      ctx->open_cap = std::max<uint64_t>(ctx->open_cap, htot[1] + htot[1] / 4 + 1024);
-      ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, htot[2] + htot[2] / 4 + 1024);
+      // a truncated level under-reports the levels below it, so the totals
+      // are lower bounds: grow at least twofold
+      auto grow = [](uint64_t cap, uint64_t need) {
+        return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
+      };
+      ctx->m2l_cap = grow(ctx->m2l_cap, htot[0]);
+      ctx->open_cap = grow(ctx->open_cap, htot[1]);
+      ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
     }
     if (stack_over) {
       if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
@@ -447,6 +502,8 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   for (auto& q : need)
     if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
   const bool level = ctx->cfg.walk_mode == SFMM_WALK_LEVEL;
+  if (!level && ctx->nsys > 1)
+    return fail(ctx, SFMM_EUNSUPPORTED, "several systems need SFMM_WALK_LEVEL");
   phase_mark(ctx, 1, 0);
   if (level) {
     if ((rc = walk_levels(ctx, theta))) return rc;
@@ -622,6 +679,32 @@ int sfmm_solve(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
     return fail(ctx, SFMM_EUNSUPPORTED, "unknown precision");
   if (n > 0 && (!acc || !pot)) return fail(ctx, SFMM_EINVAL, "NULL output array");
   int rc = do_build(ctx, n, x, m, h, order);
+  if (rc) return rc;
+  if (n == 0) return SFMM_OK;
+  return do_walk_and_eval(ctx, theta, precision, m, acc, pot);
+}
+
+int sfmm_solve_batch(sfmm_ctx* ctx, int k, const int64_t* offsets, const double* x,
+                     const double* m, const double* h, double theta, int order, int precision,
+                     double* acc, double* pot) {
+  if (!ctx) return SFMM_EINVAL;
+  ctx->err.clear();
+  if (k < 1 || k > (1 << 24) || !offsets) return fail(ctx, SFMM_EINVAL, "bad system count");
+  if (offsets[0] != 0) return fail(ctx, SFMM_EINVAL, "offsets[0] must be 0");
+  int nonempty = 0, only = 0;
+  for (int s = 0; s < k; ++s) {
+    if (offsets[s + 1] < offsets[s]) return fail(ctx, SFMM_EINVAL, "offsets must not decrease");
+    if (offsets[s + 1] > offsets[s]) { ++nonempty; only = s; }
+  }
+  (void)only;
+  const int64_t n = offsets[k];
+  if (!(theta > 0.0 && theta < 1.0)) return fail(ctx, SFMM_EINVAL, "theta must be in (0, 1)");
+  if (precision != SFMM_FP64 && precision != SFMM_FP32C)
+    return fail(ctx, SFMM_EUNSUPPORTED, "unknown precision");
+  if (n > 0 && (!acc || !pot)) return fail(ctx, SFMM_EINVAL, "NULL output array");
+  // one non-empty system is an ordinary solve of the concatenated arrays
+  int rc = nonempty <= 1 ? do_build(ctx, n, x, m, h, order)
+                         : do_build(ctx, n, x, m, h, order, k, offsets);
   if (rc) return rc;
   if (n == 0) return SFMM_OK;
   return do_walk_and_eval(ctx, theta, precision, m, acc, pot);
@@ -862,6 +945,21 @@ const char* sfmm_phase_name(int phase) {
   static const char* names[SFMM_NUM_PHASES] = {"tree", "walk_count", "walk_fill",
                                                "far", "near", "momentum"};
   return (phase >= 0 && phase < SFMM_NUM_PHASES) ? names[phase] : "unknown";
+}
+
+int sfmm_workspace_bytes(const sfmm_ctx* ctx, uint64_t* out) {
+  if (!ctx || !out) return SFMM_EINVAL;
+  uint64_t b = 0;
+  for (const auto& q : ctx->buf) b += q.cap;
+  *out = b;
+  return SFMM_OK;
+}
+
+int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const double* acc,
+                  double kick, double drift) {
+  if (n < 0 || (n > 0 && (!x || !v || !acc))) return SFMM_EINVAL;
+  launch_leapfrog(n, x, v, acc, kick, drift, static_cast<hipStream_t>(hip_stream));
+  return hipGetLastError() == hipSuccess ? SFMM_OK : SFMM_EDEVICE;
 }
 
 const char* sfmm_strerror(int status) {

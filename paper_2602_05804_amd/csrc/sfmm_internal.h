@@ -66,13 +66,27 @@ void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
                    double* hs, double* his, hipStream_t s);
-void launch_karras(int n, const uint64_t* key, int leaf_size, int32_t* kfirst, int32_t* klast,
-                   int32_t* kleft, int32_t* kright, int32_t* kpar, int32_t* kside,
-                   uint32_t* kept, hipStream_t s);
-void launch_assign(int n, int leaf_size, const int32_t* kfirst, const int32_t* klast,
-                   const int32_t* kleft, const int32_t* kright, const int32_t* kpar,
-                   const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
+// sys / sys_start: system of each sorted position and first position of each
+// system (nullptr for a single system)
+void launch_karras(int n, const uint64_t* key, const uint32_t* sys, const int32_t* sys_start,
+                   int leaf_size, int32_t* kfirst, int32_t* klast, int32_t* kleft,
+                   int32_t* kright, int32_t* kpar, int32_t* kside, uint32_t* kept, hipStream_t s);
+void launch_assign(int n, int leaf_size, const uint32_t* sys, const int32_t* kfirst,
+                   const int32_t* klast, const int32_t* kleft, const int32_t* kright,
+                   const int32_t* kpar, const int32_t* kside, const uint32_t* cidx, NodeInfo* info,
                    uint32_t* leaf_flag, int32_t* leaf_at, hipStream_t s);
+// several systems: per-system boxes and keys, then (system, key) order
+void launch_sys_keys(int n, int nsys, const int64_t* off, const double* x, const double* m,
+                     const double* h, double* boxes, int* status, int check, uint64_t* key,
+                     uint32_t* idx, uint32_t* sys, int32_t* sys_start, hipStream_t s);
+void launch_sys_sortkey(int n, const uint32_t* perm1, const uint32_t* sys, uint64_t* skey,
+                        uint32_t* pos, hipStream_t s);
+void launch_sys_final(int n, const uint32_t* q, const uint32_t* perm1, const uint64_t* key1,
+                      const uint32_t* sys, uint32_t* perm, uint64_t* key, uint32_t* sys_sorted,
+                      hipStream_t s);
+// per node: 0 spans two systems, 1 root of a system, 2 other
+void launch_node_flags(int nn, const NodeInfo* info, const uint32_t* sys, uint8_t* flag,
+                       hipStream_t s);
 void launch_leaf_fill(int n, const uint32_t* leaf_flag, const uint32_t* leaf_scan,
                       const int32_t* leaf_at, int32_t* leaf_node, hipStream_t s);
 void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s);
@@ -120,6 +134,7 @@ struct NodeWalkArgs {
   int stride;
   double theta2, r_kern;
   const int32_t* level_nodes;  // nodes grouped by depth
+  const uint8_t* node_flag;    // 0 spans systems (skipped), 1 walk root, 2 other
   const uint32_t* level_off;   // [levels + 1]
   // per node (node-indexed): M2L list, opened list (internal), P2P list (leaf)
   uint32_t *m2l_off, *m2l_cnt, *open_off, *open_cnt, *p2p_off, *p2p_cnt;
@@ -203,6 +218,9 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
 // false when leaf_size > 16 (not built)
 bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
                    const float2* ph, hipStream_t s);
+
+void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double kick, double drift,
+                     hipStream_t s);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);
