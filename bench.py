@@ -51,6 +51,9 @@ def main():
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests in the serving run (Poisson arrivals at 200/s, N log-uniform "
+                         "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -173,7 +176,46 @@ def main():
                        f"extrapolated to all {nl} leaves")}
         result["parity_sample"] = {"targets": int(len(tg)), "max_rel_acc_err": float(err.max()),
                                    "rms_rel_acc_err": rms, "max_rel_pot_err": float(perr.max())}
+    if args.serve_requests > 0:
+        result["serving"] = serving(args)
     print(json.dumps(result), flush=True)
+
+
+def serving(args):
+    """Continuous batching of a stream of independent solves: FP64 and FP32C
+    on the same arrival trace with the HBM budget at 0.8 x free memory, then
+    FP64 again under a small budget so that admission queues requests."""
+    import torch
+
+    import workloads
+    from paper_2602_05804_amd import serve
+
+    log(f"serving: generating {args.serve_requests} requests")
+    reqs = workloads.serving_stream(count=args.serve_requests, seed=7, rate=200.0,
+                                    nmin=1e3, nmax=1e6)
+    ntot = sum(len(q.m) for q in reqs)
+    out = {"requests": len(reqs), "particles": ntot, "rate_per_s": 200.0, "steps_per_request": 4,
+           "trace": "Poisson arrivals at 200/s, N = 10^U(3,6), Plummer/polytrope alternating, "
+                    "seed 7"}
+    runs = [("fp64", None), ("fp32c", None), ("fp64", 3_000_000)]
+    for prec, small_budget_n in runs:
+        ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
+                               leaf_size=args.leaf_size)
+        free, _ = torch.cuda.mem_get_info()
+        budget = 0.8 * free if small_budget_n is None else ex.footprint(small_budget_n)
+        jobs = serve.jobs_from_stream(reqs, steps=4)
+        log(f"serving: {prec}, budget {budget / 2**30:.1f} GiB "
+            f"({ex.bytes_per_particle} B/particle)")
+        rep = serve.Server(ex, hbm_budget=budget).run(jobs)
+        summ = rep.summary()
+        summ["hbm_budget_gib"] = budget / 2 ** 30
+        summ["bytes_per_particle"] = ex.bytes_per_particle
+        key = prec if small_budget_n is None else f"{prec}_small_budget"
+        out[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+        log(f"serving {key}: " + ", ".join(f"{k}={v}" for k, v in out[key].items()))
+        del ex
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

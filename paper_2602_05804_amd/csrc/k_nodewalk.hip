@@ -215,14 +215,8 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
   const bool root = flag == 1;
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t* src = nullptr;
-  uint32_t nsrc = 0;
-  if (!root) {
-    const uint32_t po = a.open_off[vi.parent];
-    nsrc = a.open_cnt[vi.parent];
-    src = a.open_pool + po;
-    if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
-  }
+  // (the top node of several systems has no parent: nothing below may read
+  // a parent's lists before this branch returns)
   if (flag == 0) {
     if (lane == 0) {
       if (FILL) {
@@ -237,6 +231,14 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
       }
     }
     return;
+  }
+  const uint32_t* src = nullptr;
+  uint32_t nsrc = 0;
+  if (!root) {
+    const uint32_t po = a.open_off[vi.parent];
+    nsrc = a.open_cnt[vi.parent];
+    src = a.open_pool + po;
+    if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
   }
   Emit e{};
   if (FILL) {

@@ -158,6 +158,10 @@ class GpuExecutor:
         small = [j for j in jobs if j.n <= self.small_n]
         large = [j for j in jobs if j.n > self.small_n]
         errors = {}
+        # accelerations of the previous step are read by this step's kicks on
+        # other streams than the one they were allocated on: hold them until
+        # every stream of the step has finished
+        keep = [j.state.get("acc") for j in jobs]
 
         def run_small():
             try:
@@ -200,6 +204,7 @@ class GpuExecutor:
         for j in jobs:
             if j.rid in errors:
                 j.error = errors[j.rid]
+        del keep
 
 
 @dataclass
@@ -213,9 +218,11 @@ class Report:
     particle_solves: int
     max_active: int
     ticks: int
+    tick_s: List[float] = field(default_factory=list)
 
     def summary(self) -> dict:
         lat = np.array(self.latencies_s) if self.latencies_s else np.array([math.nan])
+        tk = np.array(self.tick_s) if self.tick_s else np.array([math.nan])
         return {"completed": self.completed, "failed": self.failed, "rejected": self.rejected,
                 "makespan_s": self.makespan_s,
                 "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
@@ -223,6 +230,8 @@ class Report:
                 "solves_per_s": self.solves / self.makespan_s if self.makespan_s > 0 else 0.0,
                 "particles_per_s": (self.particle_solves / self.makespan_s
                                     if self.makespan_s > 0 else 0.0),
+                "p50_step_ms": float(np.percentile(tk, 50) * 1e3),
+                "p99_step_ms": float(np.percentile(tk, 99) * 1e3),
                 "max_active": self.max_active, "ticks": self.ticks}
 
 
@@ -244,6 +253,7 @@ class Server:
         used = 0.0
         t0 = self.clock()
         solves = psolves = ticks = max_act = rejected = 0
+        tick_s: List[float] = []
         while pending or queue or active:
             now = self.clock() - t0 if realtime else math.inf
             while pending and pending[0].arrival <= now:
@@ -278,7 +288,9 @@ class Server:
                     time.sleep(max(0.0, min(0.01, pending[0].arrival - (self.clock() - t0))))
                 continue
             max_act = max(max_act, len(active))
+            ts = self.clock()
             self.ex.step(active)
+            tick_s.append(self.clock() - ts)
             ticks += 1
             solves += len(active)
             psolves += sum(j.n for j in active)
@@ -297,7 +309,7 @@ class Server:
         lat = [j.finished_at - j.arrival for j in ok]
         return Report(completed=len(ok), failed=len(done) - len(ok) - rejected, rejected=rejected,
                       makespan_s=makespan, latencies_s=lat, solves=solves,
-                      particle_solves=psolves, max_active=max_act, ticks=ticks)
+                      particle_solves=psolves, max_active=max_act, ticks=ticks, tick_s=tick_s)
 
 
 def jobs_from_stream(requests, steps: int = 4) -> List[Job]:
