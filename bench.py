@@ -27,6 +27,47 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs x 128 flop/clk x 2.4 
 P2P_FLOPS_PER_PAIR = 22      # far-pair branch of the P2P kernel (FMA = 2, rsqrt = 1)
 
 
+# dominant kernel of each phase: name prefix in the profiler's output and the
+# sources whose hash must match the profiled build for its counters to apply
+KERNELS = {
+    ("fp64", "far"): ("void k_far<", ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
+                      "k_far: per-leaf M2L + L2L chain + L2P"),
+    ("fp64", "near"): ("void k_p2p_leaf<", ["k_near.hip", "sfmm_internal.h"],
+                       "k_p2p_leaf: softened P2P, one wave per leaf"),
+    ("fp32c", "far"): ("void k_far32<", ["k_f32c.hip", "expansions_gen.h", "sfmm_internal.h"],
+                       "k_far32: per-leaf M2L (FP32 terms, FP64 sums) + L2L + L2P"),
+    ("fp32c", "near"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
+                        "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
+}
+
+
+def measured_traffic(args, kern):
+    """HBM bytes per launch of the kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size),
+    or None when there is none for this workload or the kernel's sources
+    have changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    n_tag = f"{args.n:.0e}".replace("+0", "").replace("+", "")
+    tag = f"{args.workload}_{n_tag}_{args.precision}"
+    if not os.path.exists(path):
+        return None
+    entry = json.load(open(path)).get(tag)
+    if entry is None:
+        return None
+    for name, rec in entry["kernels"].items():
+        if not name.startswith(kern[0]) or rec.get("sources") != kern[1]:
+            continue
+        h = hashlib.sha256()
+        for fn in kern[1]:
+            with open(os.path.join(ROOT, "paper_2602_05804_amd", "csrc", fn), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() == rec["sources_sha256"]:
+            return round(rec["bytes_per_dispatch"])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -51,6 +92,9 @@ def main():
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the workload, copy a buffer of this many MiB three times "
+                         "(a plain copy kernel of known size, to scale HBM counters)")
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving run (Poisson arrivals at 200/s, N log-uniform "
                          "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
@@ -69,6 +113,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib * 2 ** 20 // 8
+        src = torch.ones(nb, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.calib_copy_mib} MiB read + written")
+        del src, dst
     log(f"generating {args.workload} N={args.n}")
     if args.workload == "polytrope":
         x, m, h = workloads.polytrope(args.n, seed=2)
@@ -117,11 +170,12 @@ def main():
     work = {"far": far_flops, "near": near_flops}
     dom = max(("far", "near"), key=lambda k: ph_mean[k])
     achieved = work[dom] / (ph_mean[dom] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": {"far": "k_far (M2L+L2L+L2P)",
-                                           "near": "k_near (P2P)"}[dom],
+    kern = KERNELS[(args.precision, dom)]
+    roofline = {"bound": "alu", "kernel": kern[2],
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                "flops_per_launch": work[dom]}
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+                "traffic": measured_traffic(args, kern),
+                "flops_per_launch": work[dom], "ms_per_launch": round(ph_mean[dom], 4)}
     per_phase = {k: {"ms": round(v, 4)} for k, v in ph_mean.items()}
     for k in ("far", "near"):
         tf = work[k] / (ph_mean[k] * 1e-3) / 1e12
