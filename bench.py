@@ -38,6 +38,8 @@ KERNELS = {
                        "k_far32: per-leaf M2L (FP32 terms, FP64 sums) + L2L + L2P"),
     ("fp32c", "near"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
                         "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
+    ("shared", "far"): ("void k_m2l_nodes<", ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
+                        "k_m2l_nodes + k_far_shared: per-node M2L sums, then per-leaf L2L + L2P"),
 }
 
 
@@ -89,6 +91,9 @@ def main():
     ap.add_argument("--walk", choices=["level", "leaf"], default="level",
                     help="level: each (ancestor, source) test once per level; "
                          "leaf: Algorithm 1 with one stack walk per leaf")
+    ap.add_argument("--far", choices=["leaf", "shared"], default="leaf",
+                    help="leaf: every leaf evaluates its ancestors' M2L lists (the paper's "
+                         "replicated walk); shared: each node's list once, then L2L per leaf")
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -136,7 +141,7 @@ def main():
         x, m, h = workloads.plummer(args.n, seed=1)
         wl = f"Plummer sphere a=1 M=1, N={args.n}, seed 1"
     xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
-    solver = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk)
+    solver = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far=args.far)
     acc = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty((args.n,), dtype=torch.float64, device="cuda")
     log(f"warmup {args.warmup}")
@@ -164,13 +169,15 @@ def main():
 
     # algorithmic work of the arithmetic kernels
     p = args.order
-    far_flops = (st["n_m2l"] * (sfmm.FLOPS["m2l"][p] + 1) + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
+    # M2L evaluations actually made: replicated per leaf, or once per node pair
+    n_m2l = st["n_m2l_unique"] if args.far == "shared" else st["n_m2l"]
+    far_flops = (n_m2l * (sfmm.FLOPS["m2l"][p] + 1) + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
                  + args.n * sfmm.FLOPS["l2p"][p])
     near_flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR
     work = {"far": far_flops, "near": near_flops}
     dom = max(("far", "near"), key=lambda k: ph_mean[k])
     achieved = work[dom] / (ph_mean[dom] * 1e-3) / 1e12
-    kern = KERNELS[(args.precision, dom)]
+    kern = KERNELS[("shared" if args.far == "shared" and dom == "far" else args.precision, dom)]
     roofline = {"bound": "alu", "kernel": kern[2],
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
@@ -188,11 +195,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl,
                    "N": args.n, "theta": args.theta, "order": p, "leaf_size": args.leaf_size,
-                   "precision": args.precision, "G": 1.0, "r_kern": 2.0, "walk": args.walk},
+                   "precision": args.precision, "G": 1.0, "r_kern": 2.0, "walk": args.walk,
+                   "far": args.far},
         "roofline": roofline,
         "phases": per_phase,
-        "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l", "n_l2l",
-                                      "n_p2p_leaf_pairs", "n_p2p_pairs")},
+        "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l",
+                                      "n_m2l_unique", "n_l2l", "n_p2p_leaf_pairs",
+                                      "n_p2p_pairs")},
         "momentum_residual": mom,
     }
 
@@ -254,7 +263,7 @@ def serving(args):
     runs = [("fp64", None), ("fp32c", None), ("fp64", 3_000_000)]
     for prec, small_budget_n in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
-                               leaf_size=args.leaf_size)
+                               leaf_size=args.leaf_size, far=args.far)
         free, _ = torch.cuda.mem_get_info()
         budget = 0.8 * free if small_budget_n is None else ex.footprint(small_budget_n)
         jobs = serve.jobs_from_stream(reqs, steps=4)

@@ -75,6 +75,21 @@ typedef enum { SFMM_FP64 = 0, SFMM_FP32C = 1 } sfmm_precision;
  *                  with its own stack. */
 typedef enum { SFMM_WALK_LEVEL = 0, SFMM_WALK_LEAF = 1 } sfmm_walk_mode;
 
+/* How the far field is evaluated (the same interaction set either way):
+ * SFMM_FAR_LEAF    Sect. 3: every leaf evaluates the M2L lists of all its
+ *                  ancestors itself while it carries the field moments down
+ *                  its branch, so an ancestor's interactions are recomputed
+ *                  once per leaf below it (default);
+ * SFMM_FAR_SHARED  the caching of shared long-range interactions proposed in
+ *                  Sect. 5 (Discussion): each node's M2L list is evaluated
+ *                  once into the node's own field moments, and every leaf
+ *                  then only translates and sums them down its branch
+ *                  (L2L) before L2P.  Results agree with SFMM_FAR_LEAF to
+ *                  rounding (the per-node sums are formed before they are
+ *                  added to the translated parent moments).  Needs
+ *                  SFMM_WALK_LEVEL. */
+typedef enum { SFMM_FAR_LEAF = 0, SFMM_FAR_SHARED = 1 } sfmm_far_mode;
+
 typedef struct {
   double G;                   /* gravitational constant (default 1)                   */
   int leaf_size;              /* a node with <= leaf_size particles is a leaf (10)    */
@@ -83,6 +98,7 @@ typedef struct {
   int check_inputs;           /* validate m, h and positions on the device (1)        */
   int walk_mode;              /* sfmm_walk_mode (SFMM_WALK_LEVEL)                     */
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
+  int far_mode;               /* sfmm_far_mode (SFMM_FAR_LEAF)                        */
 } sfmm_config;
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
@@ -97,6 +113,8 @@ typedef struct {
   int64_t n_p2p_pairs;      /* ordered particle pairs summed directly               */
   double momentum[3];       /* sum_i m_i acc_i (FP64), valid after a stream sync    */
   double momentum_abs;      /* sum_i |m_i acc_i|                                    */
+  int64_t n_m2l_unique;     /* distinct (target node, source node) M2L pairs (level
+                               walk; 0 with SFMM_WALK_LEAF)                         */
 } sfmm_stats;
 
 /* Fill *cfg with the defaults listed above.  Returns SFMM_EINVAL if cfg is NULL. */

@@ -46,17 +46,19 @@ class SfmmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("G", C.c_double), ("leaf_size", C.c_int), ("r_kern", C.c_double),
                 ("include_self_potential", C.c_int), ("check_inputs", C.c_int),
-                ("walk_mode", C.c_int), ("fp64_top_depth", C.c_int)]
+                ("walk_mode", C.c_int), ("fp64_top_depth", C.c_int), ("far_mode", C.c_int)]
 
 
 WALK_MODES = {"level": 0, "leaf": 1}
+FAR_MODES = {"leaf": 0, "shared": 1}
 
 
 class Stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("num_nodes", C.c_int64), ("num_leaves", C.c_int64),
                 ("max_depth", C.c_int32), ("n_m2l", C.c_int64), ("n_l2l", C.c_int64),
                 ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
-                ("momentum", C.c_double * 3), ("momentum_abs", C.c_double)]
+                ("momentum", C.c_double * 3), ("momentum_abs", C.c_double),
+                ("n_m2l_unique", C.c_int64)]
 
 
 _lib = None
@@ -109,7 +111,8 @@ class Solver:
 
     def __init__(self, device: int = 0, G: float = 1.0, leaf_size: int = 10,
                  r_kern: float = 2.0, include_self_potential: bool = True,
-                 check_inputs: bool = True, walk: str = "level", fp64_top_depth: int = 8):
+                 check_inputs: bool = True, walk: str = "level", fp64_top_depth: int = 8,
+                 far: str = "leaf"):
         import torch
 
         if not torch.cuda.is_available():
@@ -117,7 +120,7 @@ class Solver:
         self._torch = torch
         self.device = int(device)
         self.cfg = Config(G, leaf_size, r_kern, int(include_self_potential), int(check_inputs),
-                          WALK_MODES[walk], int(fp64_top_depth))
+                          WALK_MODES[walk], int(fp64_top_depth), FAR_MODES[far])
         self._ctx = C.c_void_p(0)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self._check(lib().sfmm_create(C.byref(self._ctx), self.device, C.c_void_p(stream),
@@ -203,7 +206,8 @@ class Solver:
         return dict(n=st.n, num_nodes=st.num_nodes, num_leaves=st.num_leaves,
                     max_depth=st.max_depth, n_m2l=st.n_m2l, n_l2l=st.n_l2l,
                     n_p2p_leaf_pairs=st.n_p2p_leaf_pairs, n_p2p_pairs=st.n_p2p_pairs,
-                    momentum=list(st.momentum), momentum_abs=st.momentum_abs)
+                    momentum=list(st.momentum), momentum_abs=st.momentum_abs,
+                    n_m2l_unique=st.n_m2l_unique)
 
     def timing_start(self, max_solves: int):
         """Record HIP events around every phase of the next max_solves solves."""

@@ -204,7 +204,9 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-template <int LS, bool NODE, int RS>
+// targets in passes of TG, each pass unrolled (static accumulator indices);
+// the sources are read once per pass
+template <int LS, bool NODE, int RS, int TG>
 __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __restrict__ pf,
                                                    const float2* __restrict__ phh) {
   const int lane = threadIdx.x;
@@ -222,9 +224,6 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
     tg[lane][3] = hh.y; tg[lane][4] = hh.x;
   }
   __syncthreads();
-  double fx[LS], fy[LS], fz[LS], ph[LS];
-#pragma unroll
-  for (int i = 0; i < LS; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
   uint64_t e0, e1;
   const int32_t* list;
   if (NODE) {
@@ -236,82 +235,89 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-    int cnt = 0, lo = 0;
-    float dcx = 0.f, dcy = 0.f, dcz = 0.f;
-    if (c0 + lane < e1) {
-      const int src = list[c0 + lane];
-      const NodeInfo si = a.info[src];
-      cnt = si.cnt;
-      lo = si.lo;
-      const double* rs = a.rec + (int64_t)src * RS;
-      dcx = (float)(ct0 - rs[0]);
-      dcy = (float)(ct1 - rs[1]);
-      dcz = (float)(ct2 - rs[2]);
-    }
-    const int incl = wave_incl_scan32(cnt);
-    const int pre = incl - cnt;
-    const int total = __shfl(incl, 63, 64);
-    for (int f0 = 0; f0 < total; f0 += 64) {
-      const int f = f0 + lane;
-      int k = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int pk = __shfl(pre, k + step, 64);
-        if (pk <= f) k += step;
-      }
-      const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-      const float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
-      if (f >= total) continue;
-      const float4 oj = pf[j];
-      const float2 hj = phh[j];
-      const float hj2inv = hj.y * hj.y;
-#pragma unroll
-      for (int i = 0; i < LS; ++i) {
-        if (i >= nt) break;
-        const float w = (j == ti.lo + i) ? 0.f : oj.w;
-        const float thi = tg[i][3];
-        const float dx = cx + (tg[i][0] - oj.x);
-        const float dy = cy + (tg[i][1] - oj.y);
-        const float dz = cz + (tg[i][2] - oj.z);
-        const float r2 = dx * dx + dy * dy + dz * dz;
-        const float rinv = r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
-        const float rinv3 = rinv * rinv * rinv;
-        float gs = rinv3, ps = rinv;
-        const bool inside = (r2 * (thi * thi) < 4.0f) || (r2 * hj2inv < 4.0f);
-        if (__ballot(inside)) {
-          const float r = r2 * rinv;
-          float g1, p1, g2, p2;
-          soft32(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
-          soft32(r * hj.y, hj.y, hj.x * rinv, rinv, rinv3, g2, p2);
-          if (inside) {
-            gs = 0.5f * (g1 + g2);
-            ps = 0.5f * (p1 + p2);
-          }
-        }
-        const float mg = w * gs;
-        fx[i] += (double)(mg * dx);
-        fy[i] += (double)(mg * dy);
-        fz[i] += (double)(mg * dz);
-        ph[i] += (double)(w * ps);
-      }
-    }
-  }
   const double G = a.G;
+  for (int t0 = 0; t0 < nt; t0 += TG) {
+    double fx[TG], fy[TG], fz[TG], ph[TG];
 #pragma unroll
-  for (int i = 0; i < LS; ++i) {
-    if (i >= nt) break;
-    const double sx = wave_sum64(fx[i]), sy = wave_sum64(fy[i]), sz = wave_sum64(fz[i]);
-    double sp = wave_sum64(ph[i]);
-    if (lane == i) {
-      const int j = ti.lo + i;
-      if (a.include_self) sp = fma(a.ms[j], 1.4 * a.his[j], sp);
-      const double* fr = a.far + 4 * (int64_t)j;
-      const int64_t o = a.perm[j];
-      a.acc[3 * o] = -G * (fr[0] + sx);
-      a.acc[3 * o + 1] = -G * (fr[1] + sy);
-      a.acc[3 * o + 2] = -G * (fr[2] + sz);
-      a.pot[o] = -G * (fr[3] + sp);
+    for (int i = 0; i < TG; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+    for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+      int cnt = 0, lo = 0;
+      float dcx = 0.f, dcy = 0.f, dcz = 0.f;
+      if (c0 + lane < e1) {
+        const int src = list[c0 + lane];
+        const NodeInfo si = a.info[src];
+        cnt = si.cnt;
+        lo = si.lo;
+        const double* rs = a.rec + (int64_t)src * RS;
+        dcx = (float)(ct0 - rs[0]);
+        dcy = (float)(ct1 - rs[1]);
+        dcz = (float)(ct2 - rs[2]);
+      }
+      const int incl = wave_incl_scan32(cnt);
+      const int pre = incl - cnt;
+      const int total = __shfl(incl, 63, 64);
+      for (int f0 = 0; f0 < total; f0 += 64) {
+        const int f = f0 + lane;
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int pk = __shfl(pre, k + step, 64);
+          if (pk <= f) k += step;
+        }
+        const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+        const float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
+        if (f >= total) continue;
+        const float4 oj = pf[j];
+        const float2 hj = phh[j];
+        const float hj2inv = hj.y * hj.y;
+#pragma unroll
+        for (int ii = 0; ii < TG; ++ii) {
+          const int i = t0 + ii;
+          if (i >= nt) continue;
+          const float w = (j == ti.lo + i) ? 0.f : oj.w;
+          const float thi = tg[i][3];
+          const float dx = cx + (tg[i][0] - oj.x);
+          const float dy = cy + (tg[i][1] - oj.y);
+          const float dz = cz + (tg[i][2] - oj.z);
+          const float r2 = dx * dx + dy * dy + dz * dz;
+          const float rinv = r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
+          const float rinv3 = rinv * rinv * rinv;
+          float gs = rinv3, ps = rinv;
+          const bool inside = (r2 * (thi * thi) < 4.0f) || (r2 * hj2inv < 4.0f);
+          if (__ballot(inside)) {
+            const float r = r2 * rinv;
+            float g1, p1, g2, p2;
+            soft32(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
+            soft32(r * hj.y, hj.y, hj.x * rinv, rinv, rinv3, g2, p2);
+            if (inside) {
+              gs = 0.5f * (g1 + g2);
+              ps = 0.5f * (p1 + p2);
+            }
+          }
+          const float mg = w * gs;
+          fx[ii] += (double)(mg * dx);
+          fy[ii] += (double)(mg * dy);
+          fz[ii] += (double)(mg * dz);
+          ph[ii] += (double)(w * ps);
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < TG; ++ii) {
+      const int i = t0 + ii;
+      if (i >= nt) break;
+      const double sx = wave_sum64(fx[ii]), sy = wave_sum64(fy[ii]), sz = wave_sum64(fz[ii]);
+      double sp = wave_sum64(ph[ii]);
+      if (lane == i) {
+        const int j = ti.lo + i;
+        if (a.include_self) sp = fma(a.ms[j], 1.4 * a.his[j], sp);
+        const double* fr = a.far + 4 * (int64_t)j;
+        const int64_t o = a.perm[j];
+        a.acc[3 * o] = -G * (fr[0] + sx);
+        a.acc[3 * o + 1] = -G * (fr[1] + sy);
+        a.acc[3 * o + 2] = -G * (fr[2] + sz);
+        a.pot[o] = -G * (fr[3] + sp);
+      }
     }
   }
 }
@@ -335,8 +341,9 @@ void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
 
 template <int LS, int RS>
 void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, hipStream_t s) {
-  if (node_lists) k_p2p_leaf32<LS, true, RS><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
-  else k_p2p_leaf32<LS, false, RS><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
+  constexpr int TG = LS <= 10 ? 5 : 8;
+  if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
+  else k_p2p_leaf32<LS, false, RS, TG><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
 }
 
 }  // namespace

@@ -128,7 +128,151 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
   }
 }
 
+// ---- shared far field -------------------------------------------------------
+// The caching of shared interactions of Sect. 5: the M2L list of node v (the
+// pairs the level walk accepted with v as target) is evaluated once into
+// LN[v]; a leaf's far field is then the root-to-leaf chain
+//   L <- L2L(L, s_v - s_parent) (when L is non-zero), L <- L + LN[v],
+// and L2P at its particles -- the same terms as the per-leaf form, whose
+// replicated evaluation of every ancestor's list is what this removes.
+//
+// k_m2l_nodes: SPLIT lanes per node, nodes taken in level order (neighbours
+// in a wave have similar list lengths); each lane sums every SPLIT-th entry,
+// the group's partial sums are added with shuffles, and lane q of the group
+// stores the coefficients q, q + SPLIT, ...  With F32 the contraction of a
+// target at depth >= top runs on FP32 terms (FP64 sums), as in the per-leaf
+// FP32C kernel.
+template <int P, int SPLIT, bool F32>
+__global__ __launch_bounds__(64) void k_m2l_nodes(SharedFarArgs a) {
+  using E = Exp<P>;
+  constexpr int NQ = E::NQ;
+  constexpr int NL = E::NL;
+  constexpr int RS = rec_stride(P), RS32 = rec32_stride(P);
+  const int lane = threadIdx.x;
+  const int sub = lane % SPLIT;
+  const int g = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
+  const bool active = g < a.nn;
+  const int v = active ? a.level_nodes[g] : 0;
+  const uint32_t cnt = active ? a.m2l_cnt[v] : 0u;
+  const uint32_t off = active ? a.m2l_off[v] : 0u;
+  const double* __restrict__ rec = a.rec;
+  const double sv[3] = {rec[(int64_t)v * RS], rec[(int64_t)v * RS + 1], rec[(int64_t)v * RS + 2]};
+  const bool f32 = F32 && active && a.depth[v] >= a.top;
+  double L[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) L[q] = 0.0;
+  for (uint32_t e = off + sub; e < off + cnt; e += SPLIT) {
+    const uint32_t src = a.pool[e] & kSrcMask;
+    const double* rs = rec + (int64_t)src * RS;
+    if (F32 && f32) {
+      const float r[3] = {(float)(rs[0] - sv[0]), (float)(rs[1] - sv[1]), (float)(rs[2] - sv[2])};
+      const float* r32 = a.rec32 + (int64_t)src * RS32;
+      float Q[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) Q[q] = r32[q];
+      E::m2l_add_f32(r, Q, L);
+    } else {
+      const double r[3] = {rs[0] - sv[0], rs[1] - sv[1], rs[2] - sv[2]};
+      double Q[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) Q[q] = rs[8 + q];
+      E::m2l_add(r, Q, L);
+    }
+  }
+#pragma unroll
+  for (int o = SPLIT / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] += __shfl_xor(L[q], o, 64);
+  }
+  if (active && cnt > 0) {
+    double* out = a.ln + (int64_t)v * NL;
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+      if (q % SPLIT == sub) out[q] = L[q];
+  }
+}
+
+// k_far_shared: one lane per leaf walks its branch from the root
+template <int P>
+__global__ __launch_bounds__(64) void k_far_shared(FarArgs a, const double* __restrict__ ln) {
+  using E = Exp<P>;
+  constexpr int NL = E::NL;
+  constexpr int RS = rec_stride(P);
+  const int l = blockIdx.x * 64 + threadIdx.x;
+  if (l >= a.nleaves) return;
+  const NodeInfo* __restrict__ info = a.info;
+  const double* __restrict__ rec = a.rec;
+  const int leaf = a.leaf_node[l];
+  const int d = a.leaf_depth[l];
+  const int lo = info[leaf].lo;
+  const int cnt = info[leaf].cnt;
+  double L[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) L[q] = 0.0;
+  bool have = false;
+  int v = 0;
+  double sv[3] = {rec[0], rec[1], rec[2]};
+  auto add_node = [&](int u) {
+    if (a.node_m2l_cnt[u] == 0) return;
+    const double* lu = ln + (int64_t)u * NL;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] += lu[q];
+    have = true;
+  };
+  add_node(0);
+  for (int k = 0; k < d; ++k) {
+    const int c = info[v].child;
+    const int nv = (lo < info[c + 1].lo) ? c : c + 1;
+    const double* rn = rec + (int64_t)nv * RS;
+    const double sn[3] = {rn[0], rn[1], rn[2]};
+    if (have) {
+      const double hv[3] = {sn[0] - sv[0], sn[1] - sv[1], sn[2] - sv[2]};
+      E::l2l(hv, L);
+    }
+    v = nv;
+    sv[0] = sn[0]; sv[1] = sn[1]; sv[2] = sn[2];
+    add_node(v);
+  }
+  for (int j = lo; j < lo + cnt; ++j) {
+    const double off[3] = {a.xs[j] - sv[0], a.ys[j] - sv[1], a.zs[j] - sv[2]};
+    double f[3] = {0.0, 0.0, 0.0}, phi = 0.0;
+    if (have) E::l2p(off, L, f, phi);
+    double* o = a.far + 4 * (int64_t)j;
+    o[0] = f[0]; o[1] = f[1]; o[2] = f[2]; o[3] = phi;
+  }
+}
+
+template <int P, int SPLIT>
+void shared_order(const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_t s) {
+  if (a.nn > 0) {
+    const unsigned nb = (unsigned)((a.nn + 64 / SPLIT - 1) / (64 / SPLIT));
+    if (f32) k_m2l_nodes<P, SPLIT, true><<<nb, 64, 0, s>>>(a);
+    else k_m2l_nodes<P, SPLIT, false><<<nb, 64, 0, s>>>(a);
+  }
+  if (f.nleaves > 0) k_far_shared<P><<<(unsigned)((f.nleaves + 63) / 64), 64, 0, s>>>(f, a.ln);
+}
+
+template <int SPLIT>
+void shared_split(int order, const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_t s) {
+  switch (order) {
+    case 0: shared_order<0, SPLIT>(f, a, f32, s); break;
+    case 1: shared_order<1, SPLIT>(f, a, f32, s); break;
+    case 2: shared_order<2, SPLIT>(f, a, f32, s); break;
+    case 3: shared_order<3, SPLIT>(f, a, f32, s); break;
+    case 4: shared_order<4, SPLIT>(f, a, f32, s); break;
+  }
+}
+
 }  // namespace
+
+void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
+                       hipStream_t s) {
+  switch (variant) {
+    case 1: shared_split<4>(order, f, a, f32, s); break;
+    case 2: shared_split<16>(order, f, a, f32, s); break;
+    default: shared_split<8>(order, f, a, f32, s); break;
+  }
+}
 
 template <bool NODE, int SPLIT, int WAVES>
 void far_dispatch(int order, const FarArgs& a, hipStream_t s) {

@@ -145,8 +145,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int LS, bool NODE>
+// TG == 0: one pass over the sources for all targets, the loop over the
+//          targets stopping at nt (per-target accumulators indexed at run
+//          time);
+// TG > 0:  passes of TG targets each, fully unrolled (static accumulator
+//          indices; nt is the same on every lane, so the guard is a scalar
+//          branch); the sources are read once per pass.
+template <int LS, bool NODE, int TG>
 __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
+  constexpr int NA = TG > 0 ? TG : LS;  // accumulators per pass
   const int lane = threadIdx.x;
   const int l = blockIdx.x;
   const int node = a.leaf_node[l];
@@ -160,9 +167,6 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     tg[lane][3] = a.his[j]; tg[lane][4] = a.hs[j];
   }
   __syncthreads();
-  double fx[LS], fy[LS], fz[LS], ph[LS];
-#pragma unroll
-  for (int i = 0; i < LS; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
   uint64_t e0, e1;
   const int32_t* list;
   if (NODE) {
@@ -174,75 +178,83 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-    // 64 list entries: their particle ranges, flattened by a prefix scan
-    int cnt = 0, lo = 0;
-    if (c0 + lane < e1) {
-      const NodeInfo si = a.info[list[c0 + lane]];
-      cnt = si.cnt;
-      lo = si.lo;
-    }
-    const int incl = wave_incl_scan(cnt);
-    const int pre = incl - cnt;
-    const int total = __shfl(incl, 63, 64);
-    for (int f0 = 0; f0 < total; f0 += 64) {
-      const int f = f0 + lane;
-      // owner lane k: the last lane with pre <= f (binary search over lanes)
-      int k = 0;
-#pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int pk = __shfl(pre, k + step, 64);
-        if (pk <= f) k += step;
-      }
-      const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-      if (f >= total) continue;
-      const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j], mj = a.ms[j];
-      const double hj = a.hs[j], hjinv = a.his[j];
-      const double hj2inv = hjinv * hjinv;
-#pragma unroll
-      for (int i = 0; i < LS; ++i) {
-        if (i >= nt) break;
-        const double w = (j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
-        const double thi = tg[i][3];
-        const double dx = tg[i][0] - xj, dy = tg[i][1] - yj, dz = tg[i][2] - zj;
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
-        const double rinv3 = rinv * rinv * rinv;
-        double gs = rinv3, ps = rinv;  // both kernels at q >= 2
-        const bool inside = (r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0);
-        if (__ballot(inside)) {
-          const double r = r2 * rinv;
-          double g1, p1, g2, p2;
-          soft_sel(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
-          soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
-          if (inside) {
-            gs = 0.5 * (g1 + g2);
-            ps = 0.5 * (p1 + p2);
-          }
-        }
-        const double mg = w * gs;
-        fx[i] = fma(mg, dx, fx[i]);
-        fy[i] = fma(mg, dy, fy[i]);
-        fz[i] = fma(mg, dz, fz[i]);
-        ph[i] = fma(w, ps, ph[i]);
-      }
-    }
-  }
   const double G = a.G;
+  for (int t0 = 0; t0 < nt; t0 += NA) {
+    double fx[NA], fy[NA], fz[NA], ph[NA];
 #pragma unroll
-  for (int i = 0; i < LS; ++i) {
-    if (i >= nt) break;
-    const double sx = wave_sum(fx[i]), sy = wave_sum(fy[i]), sz = wave_sum(fz[i]);
-    double sp = wave_sum(ph[i]);
-    if (lane == i) {
-      const int j = ti.lo + i;
-      if (a.include_self) sp = fma(a.ms[j], 1.4 * tg[i][3], sp);
-      const double* fr = a.far + 4 * (int64_t)j;
-      const int64_t o = a.perm[j];
-      a.acc[3 * o] = -G * (fr[0] + sx);
-      a.acc[3 * o + 1] = -G * (fr[1] + sy);
-      a.acc[3 * o + 2] = -G * (fr[2] + sz);
-      a.pot[o] = -G * (fr[3] + sp);
+    for (int i = 0; i < NA; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+    for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+      // 64 list entries: their particle ranges, flattened by a prefix scan
+      int cnt = 0, lo = 0;
+      if (c0 + lane < e1) {
+        const NodeInfo si = a.info[list[c0 + lane]];
+        cnt = si.cnt;
+        lo = si.lo;
+      }
+      const int incl = wave_incl_scan(cnt);
+      const int pre = incl - cnt;
+      const int total = __shfl(incl, 63, 64);
+      for (int f0 = 0; f0 < total; f0 += 64) {
+        const int f = f0 + lane;
+        // owner lane k: the last lane with pre <= f (binary search over lanes)
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int pk = __shfl(pre, k + step, 64);
+          if (pk <= f) k += step;
+        }
+        const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+        if (f >= total) continue;
+        const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j], mj = a.ms[j];
+        const double hj = a.hs[j], hjinv = a.his[j];
+        const double hj2inv = hjinv * hjinv;
+#pragma unroll
+        for (int ii = 0; ii < NA; ++ii) {
+          const int i = t0 + ii;
+          if (TG > 0) { if (i >= nt) continue; }
+          else if (i >= nt) break;
+          const double w = (j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
+          const double thi = tg[i][3];
+          const double dx = tg[i][0] - xj, dy = tg[i][1] - yj, dz = tg[i][2] - zj;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+          const double rinv3 = rinv * rinv * rinv;
+          double gs = rinv3, ps = rinv;  // both kernels at q >= 2
+          const bool inside = (r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0);
+          if (__ballot(inside)) {
+            const double r = r2 * rinv;
+            double g1, p1, g2, p2;
+            soft_sel(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
+            soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
+            if (inside) {
+              gs = 0.5 * (g1 + g2);
+              ps = 0.5 * (p1 + p2);
+            }
+          }
+          const double mg = w * gs;
+          fx[ii] = fma(mg, dx, fx[ii]);
+          fy[ii] = fma(mg, dy, fy[ii]);
+          fz[ii] = fma(mg, dz, fz[ii]);
+          ph[ii] = fma(w, ps, ph[ii]);
+        }
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < NA; ++ii) {
+      const int i = t0 + ii;
+      if (i >= nt) break;
+      const double sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+      double sp = wave_sum(ph[ii]);
+      if (lane == i) {
+        const int j = ti.lo + i;
+        if (a.include_self) sp = fma(a.ms[j], 1.4 * tg[i][3], sp);
+        const double* fr = a.far + 4 * (int64_t)j;
+        const int64_t o = a.perm[j];
+        a.acc[3 * o] = -G * (fr[0] + sx);
+        a.acc[3 * o + 1] = -G * (fr[1] + sy);
+        a.acc[3 * o + 2] = -G * (fr[2] + sz);
+        a.pot[o] = -G * (fr[3] + sp);
+      }
     }
   }
 }
@@ -289,16 +301,27 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
+#define NEAR_LAUNCH(LS, TG)                                           \
+  do {                                                                \
+    if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);   \
+    else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);             \
+  } while (0)
+
 void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s) {
   if (a.n <= 0) return;
   const unsigned nbl = (unsigned)a.nleaves;
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
+  // variant: targets per pass 5 (default), 10 (2), 4 (4), a run-time loop
+  // over all targets (3)
   if (leaf_size <= 10) {
-    if (node_lists) k_p2p_leaf<10, true><<<nbl, 64, 0, s>>>(a);
-    else k_p2p_leaf<10, false><<<nbl, 64, 0, s>>>(a);
+    switch (variant) {
+      case 2: NEAR_LAUNCH(10, 10); break;
+      case 3: NEAR_LAUNCH(10, 0); break;
+      case 4: NEAR_LAUNCH(10, 4); break;
+      default: NEAR_LAUNCH(10, 5); break;
+    }
   } else if (leaf_size <= 16) {
-    if (node_lists) k_p2p_leaf<16, true><<<nbl, 64, 0, s>>>(a);
-    else k_p2p_leaf<16, false><<<nbl, 64, 0, s>>>(a);
+    NEAR_LAUNCH(16, 8);
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);

@@ -84,6 +84,10 @@ struct Emit {
   // reserved bases (uniform) and running offsets
   uint32_t m2l_base, open_base, p2p_base;
   uint32_t m2l_run, open_run, p2p_run;
+  // leaf P2P lists: pairs that may fall inside a kernel from the front,
+  // pairs beyond both kernels (plain_run of them so far) from the back of
+  // the leaf's p2p_total entries
+  uint32_t plain_run, p2p_total;
 };
 
 template <bool WRITE>
@@ -113,11 +117,64 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
   if (to_p2p) e.p2p_run += to; else e.open_run += to;
 }
 
+// a leaf's lists: nm M2L entries (sel_m), np P2P entries that may need
+// softening (sel_p) and nq P2P entries beyond both kernels (sel_q); the
+// latter are written from the end of the leaf's range, so the P2P kernel
+// meets the softened pairs first and the rest in whole chunks without them
+template <bool WRITE>
+__device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, uint32_t s0,
+                                                uint32_t s1, uint32_t nm, uint32_t sel_m,
+                                                uint32_t np, uint32_t sel_p, uint32_t nq,
+                                                uint32_t sel_q) {
+  uint32_t tm, tp, tq;
+  const uint32_t pm = wave_prefix(nm, tm);
+  const uint32_t pp = wave_prefix(np, tp);
+  const uint32_t pq = wave_prefix(nq, tq);
+  if (WRITE) {
+    uint32_t k = e.m2l_base + e.m2l_run + pm;
+    if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
+    if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
+    uint32_t q = e.p2p_base + e.p2p_run + pp;
+    if (sel_p & 1u) { if (q < a.p2p_cap) a.p2p_pool[q] = s0; ++q; }
+    if (sel_p & 2u) { if (q < a.p2p_cap) a.p2p_pool[q] = s1; }
+    uint32_t r = e.plain_run + pq;  // rank from the back
+    for (int b = 0; b < 2; ++b) {
+      if (!(sel_q & (1u << b))) continue;
+      if (r < e.p2p_total) {
+        const uint32_t t = e.p2p_base + (e.p2p_total - 1u - r);
+        if (t < a.p2p_cap) a.p2p_pool[t] = b ? s1 : s0;
+      }
+      ++r;
+    }
+  }
+  e.m2l_run += tm;
+  e.p2p_run += tp;
+  e.plain_run += tq;
+}
+
 // classification of one tested source against target v
 // returns 0 = M2L, 1 = opened
 __device__ __forceinline__ int classify(const NodeWalkArgs& a, int v, const double* rv, uint32_t s) {
   if ((int)s == v) return 1;
   return accept(rv, a.rec + (int64_t)s * a.stride, a.theta2, a.r_kern) ? 0 : 1;
+}
+
+// the same test for a leaf target, from one evaluation of d^2: 0 = M2L,
+// 1 = opened (or P2P that may need softening), 2 = opened although beyond
+// both kernels (only the opening angle failed; a P2P pair of leaves then
+// needs no softening)
+__device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const double* rv,
+                                         uint32_t s) {
+  if ((int)s == v) return 1;
+  const double* rs = a.rec + (int64_t)s * a.stride;
+  const double dx = rs[0] - rv[0];
+  const double dy = rs[1] - rv[1];
+  const double dz = rs[2] - rv[2];
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  const double lsum = rv[3] + rs[3];
+  const double rsum = lsum + a.r_kern * fmax(rv[4], rs[4]);
+  if (!(d2 >= rsum * rsum)) return 1;
+  return (lsum * lsum < a.theta2 * d2) ? 0 : 2;
 }
 
 template <bool WRITE>
@@ -147,16 +204,21 @@ template <bool WRITE>
 __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv, uint32_t t0,
                                           uint32_t t1, int nt, Emit& e, uint32_t* stk,
                                           uint32_t& sp) {
-  uint32_t selm = 0, selp = 0, nm = 0, np = 0, npush = 0;
+  uint32_t selm = 0, selp = 0, selq = 0, nm = 0, np = 0, nq = 0, npush = 0;
   uint32_t push[4];
   for (int q = 0; q < nt; ++q) {
     const uint32_t t = q ? t1 : t0;
-    if (classify(a, v, rv, t) == 0) { selm |= 1u << q; ++nm; continue; }
+    const int k = classify3(a, v, rv, t);
+    if (k == 0) { selm |= 1u << q; ++nm; continue; }
     const int c = a.info[t].child;
-    if (c < 0) { selp |= 1u << q; ++np; }
-    else { push[npush++] = (uint32_t)c; push[npush++] = (uint32_t)c + 1u; }
+    if (c < 0) {
+      if (k == 2) { selq |= 1u << q; ++nq; }
+      else { selp |= 1u << q; ++np; }
+    } else {
+      push[npush++] = (uint32_t)c; push[npush++] = (uint32_t)c + 1u;
+    }
   }
-  emit_lists<WRITE>(a, e, t0, t1, nm, selm, np, selp, true);
+  emit_leaf_lists<WRITE>(a, e, t0, t1, nm, selm, np, selp, nq, selq);
   uint32_t tpush;
   const uint32_t pp = wave_prefix(npush, tpush);
   if (sp + tpush > a.stack_cap) return false;
@@ -253,6 +315,7 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
       if (lane == 0) a.open_off[v] = e.open_base;
     } else {
       e.p2p_base = hi;
+      e.p2p_total = a.p2p_cnt[v];  // from the count pass
       if (lane == 0) { a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
     }
   }
@@ -274,10 +337,11 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
   } else {
     walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
     if (!FILL && lane == 0) {
+      const uint32_t np = e.p2p_run + e.plain_run;
       a.m2l_cnt[v] = e.m2l_run;
-      a.p2p_cnt[v] = e.p2p_run;
+      a.p2p_cnt[v] = np;
       a.open_cnt[v] = 0;
-      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)e.p2p_run << 32) | (1ull << 63);
+      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)np << 32) | (1ull << 63);
     }
   }
 }

@@ -36,6 +36,7 @@ enum BufId {
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
+  B_LN,
   B_COUNT
 };
 
@@ -57,6 +58,7 @@ struct sfmm_ctx {
   int64_t nn = 0, nleaves = 0;
   int maxdepth = 0;
   uint64_t m2l_total = 0, p2p_total = 0, pair_total = 0, l2l_total = 0;
+  uint64_t m2l_unique = 0;  // level walk: entries of all per-node M2L lists
   // phase timing: SFMM_NUM_PHASES event pairs per timed solve
   std::vector<hipEvent_t> events;
   int timing_cap = 0, timing_used = 0;
@@ -273,6 +275,9 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     ctx->nn = 1 + 2 * (int64_t)nkept;
     ctx->nleaves = (int64_t)(hsmall[S_NLEAVES] & 0xffffffffu);
   }
+  // interaction-list entries carry a node index in kSrcBits bits
+  if (ctx->nn > (int64_t)kSrcMask + 1)
+    return fail(ctx, SFMM_EUNSUPPORTED, "tree has more than 2^25 nodes");
   const int nn = (int)ctx->nn, nl = (int)ctx->nleaves;
   // node depths and nodes grouped by depth (level walk): one stable radix
   // pass on the depth
@@ -465,6 +470,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
       ctx->p2p_total = htot[2];
+      ctx->m2l_unique = htot[0];
       return SFMM_OK;
     }
     if (attempt >= 8) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
@@ -504,6 +510,11 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   const bool level = ctx->cfg.walk_mode == SFMM_WALK_LEVEL;
   if (!level && ctx->nsys > 1)
     return fail(ctx, SFMM_EUNSUPPORTED, "several systems need SFMM_WALK_LEVEL");
+  const bool shared = ctx->cfg.far_mode == SFMM_FAR_SHARED;
+  if (shared && !level) return fail(ctx, SFMM_EUNSUPPORTED, "SFMM_FAR_SHARED needs SFMM_WALK_LEVEL");
+  if (shared && (rc = ensure(ctx, B_LN, sizeof(double) * local_count(ctx->order) * (size_t)ctx->nn)))
+    return rc;
+  if (!level) ctx->m2l_unique = 0;
   phase_mark(ctx, 1, 0);
   if (level) {
     if ((rc = walk_levels(ctx, theta))) return rc;
@@ -547,6 +558,21 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     launch_prep32(ctx->order, (int)ctx->nn, nl, f.leaf_node, f.info, f.rec, P<int32_t>(ctx, B_NDEPTH),
                   f.xs, f.ys, f.zs, P<double>(ctx, B_MS), P<double>(ctx, B_HS),
                   P<float>(ctx, B_REC32), P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), s);
+  }
+  if (shared) {
+    SharedFarArgs sa{};
+    sa.nn = (int)ctx->nn;
+    sa.level_nodes = reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES));
+    sa.depth = P<int32_t>(ctx, B_NDEPTH);
+    sa.m2l_off = f.node_m2l_off;
+    sa.m2l_cnt = f.node_m2l_cnt;
+    sa.pool = f.node_m2l_pool;
+    sa.rec = f.rec;
+    sa.rec32 = f32 ? P<float>(ctx, B_REC32) : nullptr;
+    sa.top = ctx->cfg.fp64_top_depth;
+    sa.ln = P<double>(ctx, B_LN);
+    launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
+  } else if (f32) {
     launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
   } else {
     launch_far(ctx->order, level, ctx->far_variant, f, s);
@@ -607,6 +633,7 @@ int sfmm_config_default(sfmm_config* cfg) {
   cfg->check_inputs = 1;
   cfg->walk_mode = SFMM_WALK_LEVEL;
   cfg->fp64_top_depth = 8;
+  cfg->far_mode = SFMM_FAR_LEAF;
   return SFMM_OK;
 }
 
@@ -618,7 +645,8 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   if (cfg) c = *cfg;
   if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
-      c.fp64_top_depth < 0 || c.fp64_top_depth > 128)
+      c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
+      (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED))
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -753,6 +781,7 @@ int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
     out->n_l2l = (int64_t)ctx->l2l_total;
     out->n_p2p_leaf_pairs = (int64_t)ctx->p2p_total;
     out->n_p2p_pairs = (int64_t)ctx->pair_total;
+    out->n_m2l_unique = (int64_t)ctx->m2l_unique;
   }
   if (ctx->have_mom && ctx->n > 0) {
     double mom[4];

@@ -33,6 +33,8 @@ constexpr int kMaxOrder = 4;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
+// local (field) coefficients: H_g for 1 <= |g| <= p+1, then P_b for |b| <= p
+__host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 + ncoef(p); }
 // FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
 __host__ __device__ constexpr int rec32_stride(int p) { return ((ncoef(p) + 1 + 7) / 8) * 8; }
 
@@ -184,6 +186,21 @@ struct FarArgs {
 // variant: 0 = 4 lanes per leaf (default), 1 = idem with a two-wave register
 // budget, 2 = 2 lanes per leaf, 3 = one lane per leaf
 void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipStream_t s);
+
+// shared far field: per-node M2L sums, then the per-leaf L2L chain and L2P
+struct SharedFarArgs {
+  int nn;
+  const int32_t* level_nodes;  // nodes in level order
+  const int32_t* depth;        // node depth
+  const uint32_t *m2l_off, *m2l_cnt, *pool;  // per-node M2L lists
+  const double* rec;
+  const float* rec32;  // FP32 moments (FP32C)
+  int top;             // FP32C: targets at depth < top in FP64
+  double* ln;          // [nn][NL] per-node local expansions (written where cnt > 0)
+};
+// variant: lanes per node 8 (default), 4 (1), 16 (2)
+void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
+                       hipStream_t s);
 
 // ---- near field (P2P) + output in the caller's order ----------------------
 struct NearArgs {

@@ -46,7 +46,7 @@ def test_null_arguments(L):
     c = P.Config()
     assert L.sfmm_config_default(C.byref(c)) == 0
     assert (c.G, c.leaf_size, c.r_kern, c.include_self_potential, c.check_inputs,
-            c.walk_mode, c.fp64_top_depth) == (1.0, 10, 2.0, 1, 1, 0, 8)
+            c.walk_mode, c.fp64_top_depth, c.far_mode) == (1.0, 10, 2.0, 1, 1, 0, 8, 0)
     assert L.sfmm_create(None, 0, None, None) == -1
     assert L.sfmm_solve(None, 10, None, None, None, 0.5, 3, 0, None, None) == -1
     assert L.sfmm_build(None, 10, None, None, None, 3) == -1
@@ -59,11 +59,13 @@ def test_bad_config_rejected(L):
     import paper_2602_05804_amd as P
 
     ctx = C.c_void_p(0)
-    bad = P.Config(1.0, 0, 2.0, 1, 1, 0, 8)  # leaf_size 0
+    bad = P.Config(1.0, 0, 2.0, 1, 1, 0, 8, 0)  # leaf_size 0
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
-    bad = P.Config(1.0, 10, -1.0, 1, 1, 0, 8)  # negative kernel radius
+    bad = P.Config(1.0, 10, -1.0, 1, 1, 0, 8, 0)  # negative kernel radius
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
-    bad = P.Config(1.0, 10, 2.0, 1, 1, 7, 8)  # unknown walk mode
+    bad = P.Config(1.0, 10, 2.0, 1, 1, 7, 8, 0)  # unknown walk mode
+    assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
+    bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 5)  # unknown far mode
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
 
 

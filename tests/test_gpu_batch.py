@@ -52,14 +52,14 @@ def _systems():
             far]
 
 
-@pytest.mark.parametrize("order", [3, 1])
-def test_batch_equals_alone_fp64(torch, P, order):
-    print(f"case: batch vs alone fp64 order {order}", flush=True)
+@pytest.mark.parametrize("order,far", [(3, "leaf"), (1, "leaf"), (3, "shared")])
+def test_batch_equals_alone_fp64(torch, P, order, far):
+    print(f"case: batch vs alone fp64 order {order} far {far}", flush=True)
     systems = _systems()
     dsys = [tuple(dev(torch, *s)) for s in systems]
-    s = P.Solver()
+    s = P.Solver(far=far)
     res = s.solve_batch(dsys, theta=0.5, order=order)
-    alone = P.Solver()
+    alone = P.Solver(far=far)
     for i, (xd, md, hd) in enumerate(dsys):
         a, p = alone.solve(xd, md, hd, theta=0.5, order=order)
         assert torch.equal(res[i][0], a), f"system {i}: acc differs from the solo solve"

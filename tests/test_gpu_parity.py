@@ -110,6 +110,22 @@ def _lists_equal(s, t, g, leaf_nodes, theta, same_order):
             assert sorted(g2o[p2p].tolist()) == sorted(op2p.tolist())
 
 
+def _p2p_partitioned(s, g, leaf_nodes, r_kern=2.0):
+    """Level walk: each leaf's P2P list holds the source leaves that may
+    have a pair inside a kernel first and those entirely beyond both kernels
+    last (the same test as the walk, in the same FP64 operation order)."""
+    c = g["s"]; lsz = g["l"]; hm = g["hmax"]
+    for li, node in enumerate(leaf_nodes):
+        _, _, p2p = s.leaf_lists(li)
+        d = c[p2p] - c[node]
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        rsum = (lsz[node] + lsz[p2p]) + r_kern * np.maximum(hm[node], hm[p2p])
+        beyond = (d2 >= rsum * rsum) & (p2p != node)
+        if beyond.any():
+            first = int(np.argmax(beyond))
+            assert beyond[first:].all(), f"leaf {li}: plain entries not at the end"
+
+
 @pytest.mark.parametrize("walk", ["level", "leaf"])
 def test_lists_parity(torch, P, orc, walk):
     print(f"case: list parity, plummer N=4096 seed 1, walk={walk}", flush=True)
@@ -120,6 +136,8 @@ def test_lists_parity(torch, P, orc, walk):
     t = orc.Tree(x, m, h, leaf_size=10, order=3)
     assert len(leaf_nodes) == t.num_leaves
     _lists_equal(s, t, g, leaf_nodes, 0.5, same_order=(walk == "leaf"))
+    if walk == "level":
+        _p2p_partitioned(s, g, leaf_nodes)
     st = s.stats()
     ost = t.solve(0.5)[2]
     assert st["n_m2l"] == ost["n_m2l"]
@@ -317,5 +335,73 @@ def test_fp32c_binary_polytrope(torch, P, orc):
     t = orc.Tree(x, m, h, leaf_size=10, order=3)
     oa, op, _ = t.solve(0.5, targets=tg)
     assert _rms_rel(acc[tg], oa) <= 1e-6
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+
+
+# ---- shared far field (each node's M2L list evaluated once) ------------------
+@pytest.mark.parametrize("theta,order", [(0.3, 3), (0.5, 3), (0.7, 3), (0.6, 0), (0.6, 2),
+                                         (0.6, 4)])
+def test_far_shared_parity(torch, P, orc, theta, order):
+    print(f"case: far shared theta={theta} order={order}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta, order=order, far="shared")
+    oa, op = orc.sfmm_solve(x, m, h, theta=theta, order=order)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+    # one evaluation per distinct (target node, source node) pair of the
+    # interaction set
+    t = orc.Tree(x, m, h, leaf_size=10, order=order)
+    mt, _, _, _ = t.mutual_pairs(theta)
+    assert st["n_m2l_unique"] == len(mt)
+    assert st["n_m2l"] > st["n_m2l_unique"]
+
+
+@pytest.mark.parametrize("n,leaf_size", [(10, 10), (4097, 10), (5000, 1), (5000, 16)])
+def test_far_shared_sizes(torch, P, orc, n, leaf_size):
+    print(f"case: far shared n={n} leaf_size={leaf_size}", flush=True)
+    x, m, h = workloads.polytrope(n, seed=3) if n > 100 else workloads.plummer(n, seed=5)
+    acc, pot, _ = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=leaf_size, far="shared")
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=leaf_size)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+
+
+def test_far_shared_needs_level_walk(torch, P):
+    print("case: far shared + leaf walk", flush=True)
+    x, m, h = dev(torch, *workloads.plummer(500, seed=2))
+    with pytest.raises(P.SfmmError, match="SFMM_WALK_LEVEL"):
+        P.Solver(walk="leaf", far="shared").solve(x, m, h)
+
+
+def test_far_shared_full_size_sampled(torch, P, orc):
+    print("case: far shared N=1e6 polytrope sampled", flush=True)
+    x, m, h = workloads.polytrope(1_000_000, seed=2)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far="shared")
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+    rng = np.random.default_rng(3)
+    tg = rng.choice(len(m), 256, replace=False)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    oa, op, _ = t.solve(0.5, targets=tg)
+    nb = np.linalg.norm(oa, axis=1)
+    assert (np.linalg.norm(acc[tg] - oa, axis=1) / nb).max() < TOL
+    assert (np.abs(pot[tg] - op) / np.abs(op)).max() < TOL
+
+
+@pytest.mark.parametrize("top", [8, 0])
+def test_far_shared_fp32c(torch, P, orc, top):
+    print(f"case: far shared fp32c top={top}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    s = P.Solver(fp64_top_depth=top, far="shared")
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    assert _rms_rel(acc, oa) <= 1e-6
+    assert np.sqrt((((pot - op) / op) ** 2).mean()) <= 1e-6
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
