@@ -91,9 +91,10 @@ def main():
     ap.add_argument("--walk", choices=["level", "leaf"], default="level",
                     help="level: each (ancestor, source) test once per level; "
                          "leaf: Algorithm 1 with one stack walk per leaf")
-    ap.add_argument("--far", choices=["leaf", "shared"], default="leaf",
-                    help="leaf: every leaf evaluates its ancestors' M2L lists (the paper's "
-                         "replicated walk); shared: each node's list once, then L2L per leaf")
+    ap.add_argument("--far", choices=["leaf", "shared"], default="shared",
+                    help="shared: each node's M2L list once, then L2L per leaf (the caching "
+                         "the paper proposes); leaf: every leaf evaluates its ancestors' "
+                         "lists (the paper's replicated walk), also timed beside shared")
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -196,7 +197,7 @@ def main():
         "config": {"workload": wl,
                    "N": args.n, "theta": args.theta, "order": p, "leaf_size": args.leaf_size,
                    "precision": args.precision, "G": 1.0, "r_kern": 2.0, "walk": args.walk,
-                   "far": args.far},
+                   "far": args.far, "h_min": float(h.min()), "h_max": float(h.max())},
         "roofline": roofline,
         "phases": per_phase,
         "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l",
@@ -204,6 +205,35 @@ def main():
                                       "n_p2p_pairs")},
         "momentum_residual": mom,
     }
+
+    if args.far == "shared":
+        # the paper's replicated far field on the same input, for comparison
+        rep = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far="leaf")
+        for _ in range(args.warmup):
+            rep.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot,
+                      precision=args.precision)
+        rep.timing_start(args.steps)
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot,
+                      precision=args.precision)
+        torch.cuda.synchronize()
+        r1 = time.perf_counter()
+        rph = rep.timing_stop()
+        rst = rep.stats()
+        rdt = (r1 - r0) / args.steps
+        result["far_leaf_mode"] = {
+            "value": args.n / rdt, "ms_per_step": rdt * 1e3,
+            "far_ms": float(np.mean([q["far"] for q in rph])),
+            "n_m2l": rst["n_m2l"],
+            "note": "every leaf evaluates all of its ancestors' M2L lists (replicated)"}
+        log(f"replicated far field: {args.n / rdt:.4g} particles/s")
+        rep.close()
+        # the headline solve's outputs again (the comparison run overwrote them)
+        solver.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot,
+                     precision=args.precision)
+        torch.cuda.synchronize()
 
     if not args.no_cpu:
         import oracle

@@ -79,7 +79,7 @@ typedef enum { SFMM_WALK_LEVEL = 0, SFMM_WALK_LEAF = 1 } sfmm_walk_mode;
  * SFMM_FAR_LEAF    Sect. 3: every leaf evaluates the M2L lists of all its
  *                  ancestors itself while it carries the field moments down
  *                  its branch, so an ancestor's interactions are recomputed
- *                  once per leaf below it (default);
+ *                  once per leaf below it;
  * SFMM_FAR_SHARED  the caching of shared long-range interactions proposed in
  *                  Sect. 5 (Discussion): each node's M2L list is evaluated
  *                  once into the node's own field moments, and every leaf
@@ -87,7 +87,8 @@ typedef enum { SFMM_WALK_LEVEL = 0, SFMM_WALK_LEAF = 1 } sfmm_walk_mode;
  *                  (L2L) before L2P.  Results agree with SFMM_FAR_LEAF to
  *                  rounding (the per-node sums are formed before they are
  *                  added to the translated parent moments).  Needs
- *                  SFMM_WALK_LEVEL. */
+ *                  SFMM_WALK_LEVEL.  Default; with SFMM_WALK_LEAF the
+ *                  context falls back to SFMM_FAR_LEAF. */
 typedef enum { SFMM_FAR_LEAF = 0, SFMM_FAR_SHARED = 1 } sfmm_far_mode;
 
 typedef struct {
@@ -98,7 +99,7 @@ typedef struct {
   int check_inputs;           /* validate m, h and positions on the device (1)        */
   int walk_mode;              /* sfmm_walk_mode (SFMM_WALK_LEVEL)                     */
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
-  int far_mode;               /* sfmm_far_mode (SFMM_FAR_LEAF)                        */
+  int far_mode;               /* sfmm_far_mode (SFMM_FAR_SHARED)                      */
 } sfmm_config;
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */

@@ -112,7 +112,7 @@ class Solver:
     def __init__(self, device: int = 0, G: float = 1.0, leaf_size: int = 10,
                  r_kern: float = 2.0, include_self_potential: bool = True,
                  check_inputs: bool = True, walk: str = "level", fp64_top_depth: int = 8,
-                 far: str = "leaf"):
+                 far: str = "shared"):
         import torch
 
         if not torch.cuda.is_available():

@@ -142,8 +142,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
 // stores the coefficients q, q + SPLIT, ...  With F32 the contraction of a
 // target at depth >= top runs on FP32 terms (FP64 sums), as in the per-leaf
 // FP32C kernel.
-template <int P, int SPLIT, bool F32>
-__global__ __launch_bounds__(64) void k_m2l_nodes(SharedFarArgs a) {
+template <int P, int SPLIT, bool F32, int WAVES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_m2l_nodes(
+    SharedFarArgs a) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int NL = E::NL;
@@ -242,24 +243,24 @@ __global__ __launch_bounds__(64) void k_far_shared(FarArgs a, const double* __re
   }
 }
 
-template <int P, int SPLIT>
+template <int P, int SPLIT, int WAVES>
 void shared_order(const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_t s) {
   if (a.nn > 0) {
     const unsigned nb = (unsigned)((a.nn + 64 / SPLIT - 1) / (64 / SPLIT));
-    if (f32) k_m2l_nodes<P, SPLIT, true><<<nb, 64, 0, s>>>(a);
-    else k_m2l_nodes<P, SPLIT, false><<<nb, 64, 0, s>>>(a);
+    if (f32) k_m2l_nodes<P, SPLIT, true, WAVES><<<nb, 64, 0, s>>>(a);
+    else k_m2l_nodes<P, SPLIT, false, WAVES><<<nb, 64, 0, s>>>(a);
   }
   if (f.nleaves > 0) k_far_shared<P><<<(unsigned)((f.nleaves + 63) / 64), 64, 0, s>>>(f, a.ln);
 }
 
-template <int SPLIT>
+template <int SPLIT, int WAVES>
 void shared_split(int order, const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_t s) {
   switch (order) {
-    case 0: shared_order<0, SPLIT>(f, a, f32, s); break;
-    case 1: shared_order<1, SPLIT>(f, a, f32, s); break;
-    case 2: shared_order<2, SPLIT>(f, a, f32, s); break;
-    case 3: shared_order<3, SPLIT>(f, a, f32, s); break;
-    case 4: shared_order<4, SPLIT>(f, a, f32, s); break;
+    case 0: shared_order<0, SPLIT, WAVES>(f, a, f32, s); break;
+    case 1: shared_order<1, SPLIT, WAVES>(f, a, f32, s); break;
+    case 2: shared_order<2, SPLIT, WAVES>(f, a, f32, s); break;
+    case 3: shared_order<3, SPLIT, WAVES>(f, a, f32, s); break;
+    case 4: shared_order<4, SPLIT, WAVES>(f, a, f32, s); break;
   }
 }
 
@@ -267,10 +268,17 @@ void shared_split(int order, const FarArgs& f, const SharedFarArgs& a, bool f32,
 
 void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s) {
+  // the FP64 contraction fits a two-wave register budget without spilling;
+  // the FP32 one does not
   switch (variant) {
-    case 1: shared_split<4>(order, f, a, f32, s); break;
-    case 2: shared_split<16>(order, f, a, f32, s); break;
-    default: shared_split<8>(order, f, a, f32, s); break;
+    case 1: shared_split<4, 1>(order, f, a, f32, s); break;
+    case 2: shared_split<16, 1>(order, f, a, f32, s); break;
+    case 3: shared_split<8, 1>(order, f, a, f32, s); break;
+    case 4: shared_split<8, 2>(order, f, a, f32, s); break;
+    default:
+      if (f32) shared_split<8, 1>(order, f, a, f32, s);
+      else shared_split<8, 2>(order, f, a, f32, s);
+      break;
   }
 }
 

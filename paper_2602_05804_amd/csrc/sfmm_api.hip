@@ -510,8 +510,9 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   const bool level = ctx->cfg.walk_mode == SFMM_WALK_LEVEL;
   if (!level && ctx->nsys > 1)
     return fail(ctx, SFMM_EUNSUPPORTED, "several systems need SFMM_WALK_LEVEL");
-  const bool shared = ctx->cfg.far_mode == SFMM_FAR_SHARED;
-  if (shared && !level) return fail(ctx, SFMM_EUNSUPPORTED, "SFMM_FAR_SHARED needs SFMM_WALK_LEVEL");
+  // per-node lists exist only with the level walk; the per-leaf walk keeps
+  // the per-leaf far field
+  const bool shared = ctx->cfg.far_mode == SFMM_FAR_SHARED && level;
   if (shared && (rc = ensure(ctx, B_LN, sizeof(double) * local_count(ctx->order) * (size_t)ctx->nn)))
     return rc;
   if (!level) ctx->m2l_unique = 0;
@@ -633,7 +634,7 @@ int sfmm_config_default(sfmm_config* cfg) {
   cfg->check_inputs = 1;
   cfg->walk_mode = SFMM_WALK_LEVEL;
   cfg->fp64_top_depth = 8;
-  cfg->far_mode = SFMM_FAR_LEAF;
+  cfg->far_mode = SFMM_FAR_SHARED;
   return SFMM_OK;
 }
 

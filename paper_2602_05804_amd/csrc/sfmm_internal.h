@@ -198,7 +198,8 @@ struct SharedFarArgs {
   int top;             // FP32C: targets at depth < top in FP64
   double* ln;          // [nn][NL] per-node local expansions (written where cnt > 0)
 };
-// variant: lanes per node 8 (default), 4 (1), 16 (2)
+// variant: lanes per node 8 with a two-wave register budget for FP64 and
+// one wave for FP32C (default), 4 (1), 16 (2), 8 one wave (3), 8 two waves (4)
 void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s);
 

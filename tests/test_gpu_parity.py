@@ -149,7 +149,8 @@ def test_lists_parity(torch, P, orc, walk):
 def test_solve_parity_plummer(torch, P, orc, theta, walk):
     print(f"case: solve parity plummer N=4096 theta={theta} walk={walk}", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta, walk=walk)
+    # the paper's per-leaf (replicated) far field; the shared one is below
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta, walk=walk, far="leaf")
     oa, op = orc.sfmm_solve(x, m, h, theta=theta)
     assert rel_err(acc, oa).max() < TOL
     assert pot_err(pot, op) < TOL
@@ -283,7 +284,7 @@ def test_full_size_sampled(torch, P, orc):
     momentum bound."""
     print("case: full-size polytrope N=1e6 sampled", flush=True)
     x, m, h = workloads.polytrope(1_000_000, seed=2)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far="leaf")
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
     rng = np.random.default_rng(0)
@@ -308,7 +309,7 @@ def test_fp32c_plummer(torch, P, orc, top):
     oracle of the same method, momentum residual <= 1e-7."""
     print(f"case: fp32c plummer N=4096 top={top}", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
-    s = P.Solver(fp64_top_depth=top)
+    s = P.Solver(fp64_top_depth=top, far="leaf")
     xd, md, hd = dev(torch, x, m, h)
     acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
     torch.cuda.synchronize()
@@ -369,11 +370,15 @@ def test_far_shared_sizes(torch, P, orc, n, leaf_size):
     assert pot_err(pot, op) < TOL
 
 
-def test_far_shared_needs_level_walk(torch, P):
+def test_leaf_walk_keeps_per_leaf_far(torch, P, orc):
+    """The per-leaf walk has no per-node lists: the shared far-field mode
+    falls back to the per-leaf far field (no unique count), same results."""
     print("case: far shared + leaf walk", flush=True)
-    x, m, h = dev(torch, *workloads.plummer(500, seed=2))
-    with pytest.raises(P.SfmmError, match="SFMM_WALK_LEVEL"):
-        P.Solver(walk="leaf", far="shared").solve(x, m, h)
+    x, m, h = workloads.plummer(2000, seed=2)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, walk="leaf", far="shared")
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    assert rel_err(acc, oa).max() < TOL
+    assert s.stats()["n_m2l_unique"] == 0
 
 
 def test_far_shared_full_size_sampled(torch, P, orc):
