@@ -177,86 +177,140 @@ __device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const dou
   return (lsum * lsum < a.theta2 * d2) ? 0 : 2;
 }
 
+// internal target: the tested sources, 64 * kWalkBatch at a time; every
+// load of a batch (list entries, then children, then records) is issued
+// before the classification, so a node waits for one chain of dependent
+// loads per batch instead of one per 64 sources; entries are emitted in
+// the order of the tested list
+constexpr int kWalkBatch = 4;
+
 template <bool WRITE>
 __device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
                               uint32_t nsrc, Emit& e) {
-  for (uint32_t base = 0; base < nsrc; base += 64) {
-    const uint32_t i = base + (threadIdx.x & 63);
-    uint32_t t0 = 0, t1 = 0;
-    int nt = 0;
-    if (i < nsrc) {
-      const uint32_t s = src[i];
-      const int c = a.info[s].child;
-      if (c < 0) { t0 = s; nt = 1; }
-      else { t0 = (uint32_t)c; t1 = (uint32_t)c + 1u; nt = 2; }
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint32_t base = 0; base < nsrc; base += 64 * kWalkBatch) {
+    uint32_t sb[kWalkBatch];
+#pragma unroll
+    for (int u = 0; u < kWalkBatch; ++u) {
+      const uint32_t i = base + 64u * u + lane;
+      sb[u] = i < nsrc ? src[i] : 0xffffffffu;
     }
-    uint32_t selm = 0, selo = 0, nm = 0, no = 0;
-    if (nt >= 1) { if (classify(a, v, rv, t0) == 0) { selm |= 1u; ++nm; } else { selo |= 1u; ++no; } }
-    if (nt >= 2) { if (classify(a, v, rv, t1) == 0) { selm |= 2u; ++nm; } else { selo |= 2u; ++no; } }
-    emit_lists<WRITE>(a, e, t0, t1, nm, selm, no, selo, false);
+    int cb[kWalkBatch];
+#pragma unroll
+    for (int u = 0; u < kWalkBatch; ++u) cb[u] = sb[u] != 0xffffffffu ? a.info[sb[u]].child : 0;
+    uint32_t selm[kWalkBatch], selo[kWalkBatch], nm[kWalkBatch], no[kWalkBatch];
+    uint32_t t0[kWalkBatch], t1[kWalkBatch];
+#pragma unroll
+    for (int u = 0; u < kWalkBatch; ++u) {
+      selm[u] = selo[u] = nm[u] = no[u] = 0;
+      t0[u] = t1[u] = 0;
+      if (sb[u] == 0xffffffffu) continue;
+      int nt;
+      if (cb[u] < 0) { t0[u] = sb[u]; nt = 1; }
+      else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt = 2; }
+      if (classify(a, v, rv, t0[u]) == 0) { selm[u] |= 1u; ++nm[u]; } else { selo[u] |= 1u; ++no[u]; }
+      if (nt >= 2) {
+        if (classify(a, v, rv, t1[u]) == 0) { selm[u] |= 2u; ++nm[u]; } else { selo[u] |= 2u; ++no[u]; }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kWalkBatch; ++u) {
+      if (base + 64u * u >= nsrc) break;  // uniform
+      emit_lists<WRITE>(a, e, t0[u], t1[u], nm[u], selm[u], no[u], selo[u], false);
+    }
   }
 }
 
-// leaf target: tested sources from the parent's opened list, 64 at a time;
-// after each chunk the lowering stack (in LDS) is drained, 64 entries per
-// step, so the stack stays within a few chunks per tree level
-template <bool WRITE>
-__device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv, uint32_t t0,
-                                          uint32_t t1, int nt, Emit& e, uint32_t* stk,
+// leaf target: U groups of 64 tested sources per step (all their loads
+// issued before the classification); opened internal sources are pushed on
+// the lowering stack (in LDS), which is drained 64 entries per step after
+// each batch of the tested list, so the stack stays within a few chunks per
+// tree level.  Returns false when the stack would overflow (the walk is then
+// rerun with a larger stack).
+template <bool WRITE, int U>
+__device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv,
+                                          const uint32_t (&t0)[U], const uint32_t (&t1)[U],
+                                          const int (&nt)[U], Emit& e, uint32_t* stk,
                                           uint32_t& sp) {
-  uint32_t selm = 0, selp = 0, selq = 0, nm = 0, np = 0, nq = 0, npush = 0;
-  uint32_t push[4];
-  for (int q = 0; q < nt; ++q) {
-    const uint32_t t = q ? t1 : t0;
-    const int k = classify3(a, v, rv, t);
-    if (k == 0) { selm |= 1u << q; ++nm; continue; }
-    const int c = a.info[t].child;
-    if (c < 0) {
-      if (k == 2) { selq |= 1u << q; ++nq; }
-      else { selp |= 1u << q; ++np; }
-    } else {
-      push[npush++] = (uint32_t)c; push[npush++] = (uint32_t)c + 1u;
+  int kk[U][2], cc[U][2];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t t = q ? t1[u] : t0[u];
+      const bool valid = q < nt[u];
+      kk[u][q] = valid ? classify3(a, v, rv, t) : -1;
+      cc[u][q] = valid ? a.info[t].child : 0;
     }
   }
-  emit_leaf_lists<WRITE>(a, e, t0, t1, nm, selm, np, selp, nq, selq);
-  uint32_t tpush;
-  const uint32_t pp = wave_prefix(npush, tpush);
-  if (sp + tpush > a.stack_cap) return false;
-  for (uint32_t q = 0; q < npush; ++q) stk[sp + pp + q] = push[q];
+  bool ok = true;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    uint32_t selm = 0, selp = 0, selq = 0, nm = 0, np = 0, nq = 0;
+    bool open0 = false, open1 = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = kk[u][q];
+      if (k < 0) continue;
+      if (k == 0) { selm |= 1u << q; ++nm; continue; }
+      if (cc[u][q] < 0) {
+        if (k == 2) { selq |= 1u << q; ++nq; }
+        else { selp |= 1u << q; ++np; }
+      } else {
+        if (q) open1 = true; else open0 = true;
+      }
+    }
+    emit_leaf_lists<WRITE>(a, e, t0[u], t1[u], nm, selm, np, selp, nq, selq);
+    const uint32_t npush = (open0 ? 2u : 0u) + (open1 ? 2u : 0u);
+    uint32_t tpush;
+    const uint32_t pp = wave_prefix(npush, tpush);
+    if (!ok || sp + tpush > a.stack_cap) { ok = false; continue; }  // uniform
+    uint32_t w = sp + pp;
+    if (open0) { stk[w] = (uint32_t)cc[u][0]; stk[w + 1] = (uint32_t)cc[u][0] + 1u; w += 2; }
+    if (open1) { stk[w] = (uint32_t)cc[u][1]; stk[w + 1] = (uint32_t)cc[u][1] + 1u; }
+    sp += tpush;
+  }
   __syncthreads();
-  sp += tpush;
-  return true;
+  return ok;
 }
 
 template <bool WRITE>
 __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
                           uint32_t nsrc, bool root, Emit& e, uint32_t* stk, int* status) {
+  constexpr int U = kWalkBatch;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t n0 = root ? 1u : nsrc;
   uint32_t sp = 0;
   bool ok = true;
-  for (uint32_t base = 0; base < n0 && ok; base += 64) {
-    uint32_t t0 = 0, t1 = 0;
-    int nt = 0;
-    const uint32_t i = base + lane;
-    if (i < n0) {
-      if (root) { t0 = (uint32_t)v; nt = 1; }
-      else {
-        const uint32_t s = src[i];
-        const int c = a.info[s].child;
-        if (c < 0) { t0 = s; nt = 1; }
-        else { t0 = (uint32_t)c; t1 = (uint32_t)c + 1u; nt = 2; }
-      }
+  for (uint32_t base = 0; base < n0 && ok; base += 64 * U) {
+    uint32_t sb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t i = base + 64u * u + lane;
+      sb[u] = i < n0 ? (root ? (uint32_t)v : src[i]) : 0xffffffffu;
     }
-    ok = leaf_step<WRITE>(a, v, rv, t0, t1, nt, e, stk, sp);
+    int cb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cb[u] = (sb[u] != 0xffffffffu && !root) ? a.info[sb[u]].child : -1;
+    uint32_t t0[U], t1[U];
+    int nt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      t0[u] = t1[u] = 0;
+      nt[u] = 0;
+      if (sb[u] == 0xffffffffu) continue;
+      if (cb[u] < 0) { t0[u] = sb[u]; nt[u] = 1; }
+      else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt[u] = 2; }
+    }
+    ok = leaf_step<WRITE, U>(a, v, rv, t0, t1, nt, e, stk, sp);
     while (ok && sp > 0) {
       const uint32_t k = sp < 64u ? sp : 64u;
-      uint32_t t = 0;
-      const int n1 = lane < k ? 1 : 0;
-      if (n1) t = stk[sp - k + lane];
+      uint32_t d0[1] = {0}, d1[1] = {0};
+      int dn[1] = {lane < k ? 1 : 0};
+      if (dn[0]) d0[0] = stk[sp - k + lane];
       __syncthreads();
       sp -= k;
-      ok = leaf_step<WRITE>(a, v, rv, t, 0u, n1, e, stk, sp);
+      ok = leaf_step<WRITE, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
     }
   }
   if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
