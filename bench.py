@@ -38,7 +38,8 @@ KERNELS = {
                        "k_far32: per-leaf M2L (FP32 terms, FP64 sums) + L2L + L2P"),
     ("fp32c", "near"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
                         "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
-    ("shared", "far"): ("void k_m2l_nodes<", ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
+    ("shared", "far"): (("void k_m2l_nodes<", "void k_far_shared<"),
+                        ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
                         "k_m2l_nodes + k_far_shared: per-node M2L sums, then per-leaf L2L + L2P"),
 }
 
@@ -58,16 +59,19 @@ def measured_traffic(args, kern):
     entry = json.load(open(path)).get(tag)
     if entry is None:
         return None
-    for name, rec in entry["kernels"].items():
-        if not name.startswith(kern[0]) or rec.get("sources") != kern[1]:
-            continue
-        h = hashlib.sha256()
-        for fn in kern[1]:
-            with open(os.path.join(ROOT, "paper_2602_05804_amd", "csrc", fn), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest() == rec["sources_sha256"]:
-            return round(rec["bytes_per_dispatch"])
-    return None
+    prefixes = kern[0] if isinstance(kern[0], tuple) else (kern[0],)
+    h = hashlib.sha256()
+    for fn in kern[1]:
+        with open(os.path.join(ROOT, "paper_2602_05804_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    total = 0.0
+    for pre in prefixes:  # every kernel of the phase, each profiled on these sources
+        recs = [r for name, r in entry["kernels"].items() if name.startswith(pre)]
+        if len(recs) != 1 or recs[0].get("sources") != kern[1] \
+                or recs[0].get("sources_sha256") != h.hexdigest():
+            return None
+        total += recs[0]["bytes_per_dispatch"]
+    return round(total)
 
 
 def log(msg):
@@ -104,6 +108,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving run (Poisson arrivals at 200/s, N log-uniform "
                          "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
+    ap.add_argument("--serve-pack", type=float, default=16e6,
+                    help="particles per packed solve in the serving run")
+    ap.add_argument("--serve-inflight", type=float, default=24e6,
+                    help="particles admitted at once in the serving run (bounds a step)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -288,18 +296,21 @@ def serving(args):
                                     nmin=1e3, nmax=1e6)
     ntot = sum(len(q.m) for q in reqs)
     out = {"requests": len(reqs), "particles": ntot, "rate_per_s": 200.0, "steps_per_request": 4,
+           "pack_particles": args.serve_pack, "max_particles_in_flight": args.serve_inflight,
            "trace": "Poisson arrivals at 200/s, N = 10^U(3,6), Plummer/polytrope alternating, "
                     "seed 7"}
     runs = [("fp64", None), ("fp32c", None), ("fp64", 3_000_000)]
     for prec, small_budget_n in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
-                               leaf_size=args.leaf_size, far=args.far)
+                               leaf_size=args.leaf_size, far=args.far,
+                               pack_particles=args.serve_pack)
         free, _ = torch.cuda.mem_get_info()
         budget = 0.8 * free if small_budget_n is None else ex.footprint(small_budget_n)
         jobs = serve.jobs_from_stream(reqs, steps=4)
         log(f"serving: {prec}, budget {budget / 2**30:.1f} GiB "
             f"({ex.bytes_per_particle} B/particle)")
-        rep = serve.Server(ex, hbm_budget=budget).run(jobs)
+        rep = serve.Server(ex, hbm_budget=budget,
+                           max_particles=args.serve_inflight).run(jobs)
         summ = rep.summary()
         summ["hbm_budget_gib"] = budget / 2 ** 30
         summ["bytes_per_particle"] = ex.bytes_per_particle

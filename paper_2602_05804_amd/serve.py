@@ -8,11 +8,10 @@ Requests arrive over time; the loop
   * admits the head of the queue while its device footprint fits the HBM
     budget and a slot is free (a request larger than the whole budget fails
     at once instead of blocking the queue);
-  * at every tick advances every admitted request by one step: all "small"
-    systems are packed into one forest solve (``Solver.solve_batch``: one
-    pass of every kernel for all of them), each large system runs on a
-    context and HIP stream of its own, in its own host thread, so their work
-    overlaps on the device;
+  * at every tick advances every admitted request by one step: the active
+    systems are packed into forest solves of a bounded number of particles
+    (``Solver.solve_batch``: one pass of every kernel for all systems of a
+    pack);
   * frees a request's slot when its last step is done, so waiting requests
     join at the next tick (the set of systems in a packed solve changes from
     tick to tick);
@@ -24,7 +23,6 @@ failure handling can be exercised without a GPU (``FakeExecutor``).
 from __future__ import annotations
 
 import math
-import threading
 import time
 from dataclasses import dataclass, field
 from typing import Callable, List, Optional
@@ -81,10 +79,15 @@ class FakeExecutor:
 
 
 class GpuExecutor:
-    """Runs steps on the GPU through libsfmm.  Systems with N <= small_n share
-    one packed solve per tick; larger ones get a Solver and a stream each."""
+    """Runs steps on the GPU through libsfmm.  At every tick the active
+    systems are grouped, in admission order, into packs of at most
+    `pack_particles` particles, and each pack is one packed solve
+    (``Solver.solve_batch``): one pass of every kernel for all of its systems.
+    A system larger than the cap is a pack of its own.  When a packed solve
+    fails, its systems are solved one by one so that only the failing
+    requests fail."""
 
-    def __init__(self, precision="fp64", theta=0.5, order=3, small_n=200_000, big_slots=4,
+    def __init__(self, precision="fp64", theta=0.5, order=3, pack_particles=16_000_000,
                  bytes_per_particle=None, **solver_cfg):
         import torch
 
@@ -95,11 +98,10 @@ class GpuExecutor:
         self.precision = precision
         self.theta = theta
         self.order = order
-        self.small_n = small_n
+        self.pack_particles = int(pack_particles)
         self.solver_cfg = solver_cfg
-        self.packed = sfmm.Solver(**solver_cfg)
-        self.packed_stream = torch.cuda.Stream()
-        self.big = [(sfmm.Solver(**solver_cfg), torch.cuda.Stream()) for _ in range(big_slots)]
+        self.solver = sfmm.Solver(**solver_cfg)
+        self.stream = torch.cuda.Stream()
         # per-particle device bytes: the context's workspace plus the request's
         # own buffers (x, v, m, h, acc, pot); measured once if not given
         self.bytes_per_particle = bytes_per_particle or self._measure_bytes()
@@ -129,8 +131,7 @@ class GpuExecutor:
               "h": torch.from_numpy(np.ascontiguousarray(h)).to(dev)}
         st["v"] = torch.zeros_like(st["x"])
         st["acc"] = torch.empty_like(st["x"])
-        st["pot"] = torch.empty_like(st["m"])
-        torch.cuda.current_stream().synchronize()  # the step runs on other streams
+        torch.cuda.current_stream().synchronize()  # the steps run on another stream
         job.state = st
         job.payload = None
 
@@ -153,58 +154,41 @@ class GpuExecutor:
             kick = 0.5 * job.dt if k == 1 else job.dt
             self.sfmm.leapfrog(job.state["x"], job.state["v"], job.state["acc"], kick, job.dt)
 
+    def packs(self, jobs: List[Job]) -> List[List[Job]]:
+        out, cur, n = [], [], 0
+        for j in jobs:
+            if cur and n + j.n > self.pack_particles:
+                out.append(cur)
+                cur, n = [], 0
+            cur.append(j)
+            n += j.n
+        if cur:
+            out.append(cur)
+        return out
+
     def step(self, jobs: List[Job]):
         torch = self.torch
-        small = [j for j in jobs if j.n <= self.small_n]
-        large = [j for j in jobs if j.n > self.small_n]
-        errors = {}
-        # accelerations of the previous step are read by this step's kicks on
-        # other streams than the one they were allocated on: hold them until
-        # every stream of the step has finished
-        keep = [j.state.get("acc") for j in jobs]
-
-        def run_small():
-            try:
-                with torch.cuda.stream(self.packed_stream):
-                    for j in small:
-                        self._pre(j)
-                    res = self.packed.solve_batch([(j.state["x"], j.state["m"], j.state["h"])
-                                                   for j in small], theta=self.theta,
-                                                  order=self.order, precision=self.precision)
-                    for j, (a, p) in zip(small, res):
-                        self._advance(j, a.clone())
-                self.packed_stream.synchronize()
-            except Exception as e:  # isolate: only these requests fail
-                for j in small:
-                    errors[j.rid] = str(e)
-
-        def run_large(j, solver, stream):
-            try:
-                with torch.cuda.stream(stream):
+        with torch.cuda.stream(self.stream):
+            for pack in self.packs(jobs):
+                for j in pack:
                     self._pre(j)
-                    a, p = solver.solve(j.state["x"], j.state["m"], j.state["h"], theta=self.theta,
-                                        order=self.order, precision=self.precision)
-                    self._advance(j, a)
-                stream.synchronize()
-            except Exception as e:
-                errors[j.rid] = str(e)
-
-        # the packed solve runs beside the first wave of large systems; large
-        # systems beyond the number of streams run in further waves
-        waves = [large[i:i + len(self.big)] for i in range(0, len(large), len(self.big))] or [[]]
-        for w, wave in enumerate(waves):
-            ts = [threading.Thread(target=run_large, args=(j, *self.big[s]))
-                  for s, j in enumerate(wave)]
-            if w == 0 and small:
-                ts.append(threading.Thread(target=run_small))
-            for t in ts:
-                t.start()
-            for t in ts:
-                t.join()
-        for j in jobs:
-            if j.rid in errors:
-                j.error = errors[j.rid]
-        del keep
+                try:
+                    res = self.solver.solve_batch(
+                        [(j.state["x"], j.state["m"], j.state["h"]) for j in pack],
+                        theta=self.theta, order=self.order, precision=self.precision)
+                    for j, (a, _) in zip(pack, res):
+                        self._advance(j, a.clone())
+                except Exception:
+                    # isolate: solve the pack's systems one by one
+                    for j in pack:
+                        try:
+                            a, _ = self.solver.solve(j.state["x"], j.state["m"], j.state["h"],
+                                                     theta=self.theta, order=self.order,
+                                                     precision=self.precision)
+                            self._advance(j, a)
+                        except Exception as e:
+                            j.error = str(e)
+        self.stream.synchronize()
 
 
 @dataclass
@@ -236,11 +220,15 @@ class Report:
 
 
 class Server:
-    def __init__(self, executor, hbm_budget: float, max_active: int = 256,
+    def __init__(self, executor, hbm_budget: float, max_active: int = 1024,
+                 max_particles: float = math.inf,
                  clock: Callable[[], float] = time.perf_counter):
+        """hbm_budget: bytes of device memory for admitted requests;
+        max_particles: particles in flight (bounds the time of one step)."""
         self.ex = executor
         self.budget = float(hbm_budget)
         self.max_active = max_active
+        self.max_particles = float(max_particles)
         self.clock = clock
 
     def run(self, jobs: List[Job], realtime: bool = True) -> Report:
@@ -251,6 +239,7 @@ class Server:
         active: List[Job] = []
         done: List[Job] = []
         used = 0.0
+        inflight = 0
         t0 = self.clock()
         solves = psolves = ticks = max_act = rejected = 0
         tick_s: List[float] = []
@@ -269,7 +258,7 @@ class Server:
                     rejected += 1
                     done.append(j)
                     continue
-                if used + fp > self.budget:
+                if used + fp > self.budget or (active and inflight + j.n > self.max_particles):
                     break
                 queue.pop(0)
                 try:
@@ -282,6 +271,7 @@ class Server:
                 j.admitted_at = self.clock() - t0
                 j.state["_fp"] = fp
                 used += fp
+                inflight += j.n
                 active.append(j)
             if not active:
                 if pending and realtime:
@@ -299,6 +289,7 @@ class Server:
                 if j.error is not None or j.done:
                     j.finished_at = self.clock() - t0
                     used -= j.state.get("_fp", 0)
+                    inflight -= j.n
                     self.ex.release(j)
                     done.append(j)
                 else:

@@ -138,7 +138,8 @@ def test_serving_loop(torch, P):
     reqs = workloads.serving_stream(count=24, seed=9, rate=400.0, nmin=50, nmax=30000)
     jobs = serve.jobs_from_stream(reqs, steps=3)
     ref = {j.rid: (j.payload, j.dt) for j in jobs}
-    ex = serve.GpuExecutor(small_n=8000, big_slots=2)
+    # several packs per tick; systems above the cap are packs of their own
+    ex = serve.GpuExecutor(pack_particles=20000)
     finals = {}
     orig_release = ex.release
 
@@ -183,3 +184,21 @@ def test_context_reuse_small_then_large(torch, P):
     for (xd, md, hd), (ab, pb) in zip(sysl, res):
         aa, pa = P.Solver().solve(xd, md, hd)
         assert torch.equal(ab, aa) and torch.equal(pb, pa)
+
+
+def test_serving_failure_isolated(torch, P):
+    """A request with a non-finite position fails alone; the other systems of
+    its pack complete."""
+    print("case: serving failure isolation", flush=True)
+    from paper_2602_05804_amd import serve
+
+    reqs = workloads.serving_stream(count=6, seed=4, rate=1e6, nmin=200, nmax=3000)
+    jobs = serve.jobs_from_stream(reqs, steps=2)
+    x, m, h = jobs[2].payload
+    x = x.copy()
+    x[5, 0] = np.nan
+    jobs[2].payload = (x, m, h)
+    ex = serve.GpuExecutor(pack_particles=10**7)
+    rep = serve.Server(ex, hbm_budget=ex.footprint(10**6)).run(jobs, realtime=False)
+    assert rep.completed == 5 and rep.failed == 1
+    assert jobs[2].error is not None and "non-finite" in jobs[2].error

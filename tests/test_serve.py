@@ -80,3 +80,18 @@ def test_jobs_from_stream():
     assert [j.rid for j in jobs] == [q.rid for q in reqs]
     assert all(j.dt > 0 and j.n == len(q.m) for j, q in zip(jobs, reqs))
     assert all(a.arrival <= b.arrival for a, b in zip(jobs, jobs[1:]))
+
+
+def test_max_particles_in_flight():
+    ex = serve.FakeExecutor(sec_per_particle=0.0, bytes_per_particle=1)
+    ns = [400, 300, 500, 200, 600, 100]
+    rep = serve.Server(ex, hbm_budget=1e12, max_particles=1000).run(_jobs(ns, steps=1),
+                                                                    realtime=False)
+    assert rep.completed == len(ns)
+    sizes = dict(enumerate(ns))
+    assert all(sum(sizes[r] for r in t) <= 1000 for t in ex.ticks)
+    # a request larger than the cap still runs (alone)
+    ex = serve.FakeExecutor(sec_per_particle=0.0, bytes_per_particle=1)
+    rep = serve.Server(ex, hbm_budget=1e12, max_particles=1000).run(_jobs([5000, 10]),
+                                                                    realtime=False)
+    assert rep.completed == 2 and ex.ticks[0] == [0]
