@@ -221,6 +221,16 @@ int sfmm_workspace_bytes(const sfmm_ctx* ctx, uint64_t* out);
 int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const double* acc,
                   double kick, double drift);
 
+/* The softened direct sum of Sect. 2, Eq. softdirectsum, over all n sources
+ * (x, m, h as in sfmm_solve; the context's G, include_self_potential and
+ * stream), for nt targets: targets is a DEVICE array of nt particle indices
+ * in [0, n), or NULL for 0..nt-1.  acc [nt][3] and pot [nt] are written in
+ * target order.  O(n nt) work: the reference the SFMM approximates, for
+ * accuracy studies.  Errors: SFMM_EINVAL (sizes, NULL arrays, a target index
+ * outside [0, n), found on the device; the call then synchronises). */
+int sfmm_direct(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+                int64_t nt, const int64_t* targets, double* acc, double* pot);
+
 /* Human-readable text of a status code (static storage). */
 const char* sfmm_strerror(int status);
 

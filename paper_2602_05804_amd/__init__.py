@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libsfmm.so")
 EXPORTED = ("sfmm_config_default", "sfmm_create", "sfmm_destroy", "sfmm_set_stream",
             "sfmm_build", "sfmm_solve", "sfmm_solve_batch", "sfmm_get_stats", "sfmm_get_tree", "sfmm_get_leaves",
             "sfmm_get_leaf_lists", "sfmm_timing_start", "sfmm_timing_stop", "sfmm_phase_name",
-            "sfmm_workspace_bytes", "sfmm_leapfrog",
+            "sfmm_workspace_bytes", "sfmm_leapfrog", "sfmm_direct",
             "sfmm_strerror", "sfmm_last_error")
 PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum")
 
@@ -90,6 +90,7 @@ def lib():
         L.sfmm_phase_name.argtypes = [C.c_int]
         L.sfmm_workspace_bytes.argtypes = [vp, vp]
         L.sfmm_leapfrog.argtypes = [vp, i64, vp, vp, vp, d, d]
+        L.sfmm_direct.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sfmm_strerror.restype = C.c_char_p
         L.sfmm_strerror.argtypes = [C.c_int]
         L.sfmm_last_error.restype = C.c_char_p
@@ -199,6 +200,22 @@ class Solver:
                                            _PRECISION[precision], _ptr(acc), _ptr(pot)),
                     "sfmm_solve_batch")
         return [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(systems))]
+
+    def direct(self, x, m, h, targets=None):
+        """Softened direct sum over all particles for `targets` (a device int64
+        tensor of indices, or None for every particle): (acc [nt, 3], pot [nt])."""
+        torch = self._torch
+        n = self._inputs(x, m, h)
+        if targets is None:
+            nt, tp = n, C.c_void_p(0)
+        else:
+            targets = targets.to(device=x.device, dtype=torch.int64).contiguous()
+            nt, tp = int(targets.shape[0]), _ptr(targets)
+        acc = torch.empty((nt, 3), dtype=torch.float64, device=x.device)
+        pot = torch.empty((nt,), dtype=torch.float64, device=x.device)
+        self._check(lib().sfmm_direct(self._ctx, n, _ptr(x), _ptr(m), _ptr(h), nt, tp,
+                                      _ptr(acc), _ptr(pot)), "sfmm_direct")
+        return acc, pot
 
     def stats(self) -> dict:
         st = Stats()

@@ -210,7 +210,10 @@ template <int LS, bool NODE, int RS, int TG>
 __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __restrict__ pf,
                                                    const float2* __restrict__ phh) {
   const int lane = threadIdx.x;
-  const int l = blockIdx.x;
+  const uint32_t item = blockIdx.x;
+  if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
+  const int l = a.item_leaf[item];
+  const uint32_t kitem = a.item_k[item];
   const int node = a.leaf_node[l];
   const NodeInfo ti = a.info[node];
   const int nt = ti.cnt;
@@ -235,7 +238,11 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  const double G = a.G;
+  {
+    const uint64_t b = e0 + (uint64_t)kitem * kP2PItem;
+    e1 = b + kP2PItem < e1 ? b + kP2PItem : e1;
+    e0 = b;
+  }
   for (int t0 = 0; t0 < nt; t0 += TG) {
     double fx[TG], fy[TG], fz[TG], ph[TG];
 #pragma unroll
@@ -307,16 +314,10 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
       const int i = t0 + ii;
       if (i >= nt) break;
       const double sx = wave_sum64(fx[ii]), sy = wave_sum64(fy[ii]), sz = wave_sum64(fz[ii]);
-      double sp = wave_sum64(ph[ii]);
+      const double sp = wave_sum64(ph[ii]);
       if (lane == i) {
-        const int j = ti.lo + i;
-        if (a.include_self) sp = fma(a.ms[j], 1.4 * a.his[j], sp);
-        const double* fr = a.far + 4 * (int64_t)j;
-        const int64_t o = a.perm[j];
-        a.acc[3 * o] = -G * (fr[0] + sx);
-        a.acc[3 * o + 1] = -G * (fr[1] + sy);
-        a.acc[3 * o + 2] = -G * (fr[2] + sz);
-        a.pot[o] = -G * (fr[3] + sp);
+        double* o = a.part + ((int64_t)item * LS + i) * 4;
+        o[0] = sx; o[1] = sy; o[2] = sz; o[3] = sp;
       }
     }
   }
@@ -340,10 +341,12 @@ void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
 }
 
 template <int LS, int RS>
-void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, hipStream_t s) {
+void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, int64_t items,
+           hipStream_t s) {
   constexpr int TG = LS <= 10 ? 5 : 8;
-  if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
-  else k_p2p_leaf32<LS, false, RS, TG><<<a.nleaves, 64, 0, s>>>(a, pf, ph);
+  if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
+  else k_p2p_leaf32<LS, false, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
+  launch_p2p_reduce(a, LS, s);
 }
 
 }  // namespace
@@ -381,16 +384,16 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
 }
 
 bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, hipStream_t s) {
+                   const float2* ph, int64_t items, hipStream_t s) {
   if (a.n <= 0) return true;
   const int RS = rec_stride(order);
   if (leaf_size > 16) return false;
-#define SFMM_P2P32(LS)                                                  \
-  switch (RS) {                                                         \
-    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, s); break;            \
-    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, s); break;            \
-    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, s); break;            \
-    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, s); break;            \
+#define SFMM_P2P32(LS)                                                   \
+  switch (RS) {                                                          \
+    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, items, s); break;      \
+    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, items, s); break;      \
+    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, items, s); break;      \
+    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, items, s); break;      \
   }
   if (leaf_size <= 10) { SFMM_P2P32(10) } else { SFMM_P2P32(16) }
 #undef SFMM_P2P32

@@ -14,45 +14,10 @@
 //                   1/q                                            (q >= 2)
 // (force per unit separation = shape / h^3, potential = shape / h).
 #include "sfmm_internal.h"
+#include "softening.h"
 
 namespace sfmm {
 namespace {
-
-__device__ __forceinline__ void soft(double r, double hinv, double& g, double& psi) {
-  const double q = r * hinv;
-  const double h3 = hinv * hinv * hinv;
-  if (q < 1.0) {
-    const double q2 = q * q;
-    g = h3 * fma(q2, fma(0.5, q, -1.2), 4.0 / 3.0);
-    psi = hinv * fma(q2, fma(q2, fma(-0.1, q, 0.3), -2.0 / 3.0), 1.4);
-  } else {
-    const double q2 = q * q;
-    const double qi = 1.0 / q;
-    const double qi3 = qi * qi * qi;
-    // 8/3 - 3q + 6/5 q^2 - 1/6 q^3 - 1/(15 q^3)
-    g = h3 * (fma(q, fma(q, fma(q, -1.0 / 6.0, 1.2), -3.0), 8.0 / 3.0) - qi3 * (1.0 / 15.0));
-    // 8/5 - 4/3 q^2 + q^3 - 3/10 q^4 + 1/30 q^5 - 1/(15 q)
-    psi = hinv * (fma(q2, fma(q, fma(q, fma(q, 1.0 / 30.0, -0.3), 1.0), -4.0 / 3.0), 1.6) -
-                  qi * (1.0 / 15.0));
-  }
-}
-
-// g = f(q)/(q h^3) and psi = psi(q)/h for one particle's kernel at q = r/h,
-// without branches; qi = 1/q (= h/r), rinv = 1/r, rinv3 = 1/r^3
-__device__ __forceinline__ void soft_sel(double q, double hinv, double qi, double rinv,
-                                         double rinv3, double& g, double& psi) {
-  const double q2 = q * q;
-  const double h3 = hinv * hinv * hinv;
-  const double gA = h3 * fma(q2, fma(0.5, q, -1.2), 4.0 / 3.0);
-  const double pA = hinv * fma(q2, fma(q2, fma(-0.1, q, 0.3), -2.0 / 3.0), 1.4);
-  const double qi3 = qi * qi * qi;
-  const double gB = h3 * (fma(q, fma(q, fma(q, -1.0 / 6.0, 1.2), -3.0), 8.0 / 3.0) -
-                          qi3 * (1.0 / 15.0));
-  const double pB = hinv * (fma(q2, fma(q, fma(q, fma(q, 1.0 / 30.0, -0.3), 1.0), -4.0 / 3.0), 1.6) -
-                            qi * (1.0 / 15.0));
-  g = q >= 2.0 ? rinv3 : (q < 1.0 ? gA : gB);
-  psi = q >= 2.0 ? rinv : (q < 1.0 ? pA : pB);
-}
 
 template <bool NODE>
 __global__ __launch_bounds__(256) void k_near(NearArgs a) {
@@ -155,7 +120,10 @@ template <int LS, bool NODE, int TG>
 __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   constexpr int NA = TG > 0 ? TG : LS;  // accumulators per pass
   const int lane = threadIdx.x;
-  const int l = blockIdx.x;
+  const uint32_t item = blockIdx.x;
+  if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
+  const int l = a.item_leaf[item];
+  const uint32_t kitem = a.item_k[item];
   const int node = a.leaf_node[l];
   const NodeInfo ti = a.info[node];
   const int nt = ti.cnt;
@@ -178,7 +146,12 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  const double G = a.G;
+  // this item's run of the leaf's list
+  {
+    const uint64_t b = e0 + (uint64_t)kitem * kP2PItem;
+    e1 = b + kP2PItem < e1 ? b + kP2PItem : e1;
+    e0 = b;
+  }
   for (int t0 = 0; t0 < nt; t0 += NA) {
     double fx[NA], fy[NA], fz[NA], ph[NA];
 #pragma unroll
@@ -244,19 +217,56 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
       const int i = t0 + ii;
       if (i >= nt) break;
       const double sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
-      double sp = wave_sum(ph[ii]);
+      const double sp = wave_sum(ph[ii]);
       if (lane == i) {
-        const int j = ti.lo + i;
-        if (a.include_self) sp = fma(a.ms[j], 1.4 * tg[i][3], sp);
-        const double* fr = a.far + 4 * (int64_t)j;
-        const int64_t o = a.perm[j];
-        a.acc[3 * o] = -G * (fr[0] + sx);
-        a.acc[3 * o + 1] = -G * (fr[1] + sy);
-        a.acc[3 * o + 2] = -G * (fr[2] + sz);
-        a.pot[o] = -G * (fr[3] + sp);
+        double* o = a.part + ((int64_t)item * LS + i) * 4;
+        o[0] = sx; o[1] = sy; o[2] = sz; o[3] = sp;
       }
     }
   }
+}
+
+// items per leaf: max(1, ceil(list entries / kP2PItem))
+template <bool NODE>
+__global__ void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ cnt) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.nleaves) return;
+  const uint64_t c = NODE ? (uint64_t)a.node_p2p_cnt[a.leaf_node[l]] : a.p2p_off[l + 1] - a.p2p_off[l];
+  const uint64_t k = (c + kP2PItem - 1) / kP2PItem;
+  cnt[l] = k > 0 ? (uint32_t)k : 1u;
+}
+
+__global__ void k_p2p_items_fill(NearArgs a, int32_t* __restrict__ item_leaf,
+                                 uint32_t* __restrict__ item_k) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= a.nleaves) return;
+  const uint32_t b = a.item_off[l], e = a.item_off[l + 1];
+  for (uint32_t t = b; t < e; ++t) {
+    item_leaf[t] = l;
+    item_k[t] = t - b;
+  }
+}
+
+// one thread per sorted particle: its items' partial sums in item order,
+// the far field and the self term, in the caller's order
+__global__ void k_p2p_reduce(NearArgs a, int ls) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.n) return;
+  const int l = a.p_leaf[j];
+  const int i = j - a.info[a.leaf_node[l]].lo;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
+  for (uint32_t t = a.item_off[l]; t < a.item_off[l + 1]; ++t) {
+    const double* q = a.part + ((int64_t)t * ls + i) * 4;
+    sx += q[0]; sy += q[1]; sz += q[2]; sp += q[3];
+  }
+  if (a.include_self) sp = fma(a.ms[j], 1.4 * a.his[j], sp);
+  const double* fr = a.far + 4 * (int64_t)j;
+  const int64_t o = a.perm[j];
+  const double G = a.G;
+  a.acc[3 * o] = -G * (fr[0] + sx);
+  a.acc[3 * o + 1] = -G * (fr[1] + sy);
+  a.acc[3 * o + 2] = -G * (fr[2] + sz);
+  a.pot[o] = -G * (fr[3] + sp);
 }
 
 constexpr int MOM_THREADS = 256;
@@ -305,11 +315,31 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
   do {                                                                \
     if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);   \
     else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);             \
+    launch_p2p_reduce(a, LS, s);                                      \
   } while (0)
 
-void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s) {
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* item_cnt,
+                            hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  if (node_lists) k_p2p_items_count<true><<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_cnt);
+  else k_p2p_items_count<false><<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_cnt);
+}
+
+void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k,
+                           hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  k_p2p_items_fill<<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_leaf, item_k);
+}
+
+void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s) {
   if (a.n <= 0) return;
-  const unsigned nbl = (unsigned)a.nleaves;
+  k_p2p_reduce<<<blocks_for(a.n, 256), 256, 0, s>>>(a, ls);
+}
+
+void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, int64_t items,
+                 hipStream_t s) {
+  if (a.n <= 0) return;
+  const unsigned nbl = (unsigned)items;
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
   // variant: targets per pass 5 (default), 10 (2), 4 (4), a run-time loop
   // over all targets (3)

@@ -558,7 +558,6 @@ __global__ void k_extent_final(int nn, const NodeInfo* __restrict__ info,
   rec[(int64_t)v * RS + 3] = sqrt(__longlong_as_double((long long)l2bits[v]));
 }
 
-inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 

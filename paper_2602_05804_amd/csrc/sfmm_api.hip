@@ -36,7 +36,7 @@ enum BufId {
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
-  B_LN,
+  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART,
   B_COUNT
 };
 
@@ -601,10 +601,34 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.include_self = ctx->cfg.include_self_potential;
   a.acc = acc;
   a.pot = pot;
+  // P2P work items: runs of at most kP2PItem list entries of one leaf
+  int64_t items = 0;
+  if (ctx->cfg.leaf_size <= 16) {
+    items = p2p_item_bound(nl, ctx->p2p_total);
+    const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
+    struct { int id; size_t bytes; } need4[] = {
+        {B_ITEMCNT, sizeof(uint32_t) * (size_t)nl}, {B_ITEMOFF, sizeof(uint32_t) * (size_t)(nl + 1)},
+        {B_ITEMLEAF, sizeof(int32_t) * (size_t)items}, {B_ITEMK, sizeof(uint32_t) * (size_t)items},
+        {B_PART, sizeof(double) * 4 * (size_t)ls * (size_t)items}};
+    for (auto& q : need4)
+      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+    uint32_t* item_off = P<uint32_t>(ctx, B_ITEMOFF);
+    a.item_off = item_off;
+    a.item_leaf = P<int32_t>(ctx, B_ITEMLEAF);
+    a.item_k = P<uint32_t>(ctx, B_ITEMK);
+    a.part = P<double>(ctx, B_PART);
+  }
   phase_mark(ctx, 4, 0);
+  if (items > 0) {
+    uint32_t* cnt = P<uint32_t>(ctx, B_ITEMCNT);
+    launch_p2p_items_count(level, a, cnt, s);
+    scan_u32(cnt, P<uint32_t>(ctx, B_ITEMOFF), nl, P<uint32_t>(ctx, B_ITEMOFF) + nl,
+             P<uint32_t>(ctx, B_SCANTMP), s);
+    launch_p2p_items_fill(a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK), s);
+  }
   if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, a, P<float4>(ctx, B_PF32),
-                        P<float2>(ctx, B_PH32), s);
-  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, s);
+                        P<float2>(ctx, B_PH32), items, s);
+  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, s);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
@@ -982,6 +1006,32 @@ int sfmm_workspace_bytes(const sfmm_ctx* ctx, uint64_t* out) {
   uint64_t b = 0;
   for (const auto& q : ctx->buf) b += q.cap;
   *out = b;
+  return SFMM_OK;
+}
+
+int sfmm_direct(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+                int64_t nt, const int64_t* targets, double* acc, double* pot) {
+  if (!ctx) return SFMM_EINVAL;
+  ctx->err.clear();
+  if (n < 0 || nt < 0 || n >= (int64_t(1) << 30))
+    return fail(ctx, SFMM_EINVAL, "n or target count out of range");
+  if (nt == 0) return SFMM_OK;
+  if (n == 0) return fail(ctx, SFMM_EINVAL, "targets given for an empty system");
+  if (!x || !m || !h || !acc || !pot) return fail(ctx, SFMM_EINVAL, "NULL array");
+  if (!targets && nt > n) return fail(ctx, SFMM_EINVAL, "more targets than particles");
+  int rc;
+  if ((rc = set_device(ctx))) return rc;
+  if ((rc = ensure(ctx, B_STATUS, sizeof(int) * 4))) return rc;
+  const hipStream_t s = ctx->stream;
+  int* status = P<int>(ctx, B_STATUS);
+  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+  launch_direct(n, x, m, h, nt, targets, ctx->cfg.G, ctx->cfg.include_self_potential, acc, pot,
+                status, s);
+  HIPCHK(hipGetLastError());
+  int hs = 0;
+  HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hs & ST_OVERFLOW) return fail(ctx, SFMM_EINVAL, "target index out of range");
   return SFMM_OK;
 }
 

@@ -33,6 +33,8 @@ constexpr int kMaxOrder = 4;
 
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
 // local (field) coefficients: H_g for 1 <= |g| <= p+1, then P_b for |b| <= p
 __host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 + ncoef(p); }
 // FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
@@ -221,9 +223,30 @@ struct NearArgs {
   int include_self;
   double* acc;  // caller order [n][3]
   double* pot;  // caller order [n]
+  // work items (leaf_size <= 16): one wave per run of at most kP2PItem list
+  // entries of one leaf; each item writes partial sums for the leaf's
+  // targets, which a second kernel adds in item order
+  const uint32_t* item_off;  // [nleaves + 1] first item of each leaf; [nleaves] = total
+  const int32_t* item_leaf;  // [items] leaf of each item
+  const uint32_t* item_k;    // [items] index of the item within its leaf
+  double* part;              // [items][LS][4] partial field (x, y, z) and potential
 };
-// wave-per-leaf kernel for leaf_size <= 16, particle-per-thread otherwise
-void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, hipStream_t s);
+constexpr int kP2PItem = 128;
+// upper bound on the number of work items
+inline int64_t p2p_item_bound(int64_t nleaves, uint64_t p2p_entries) {
+  return nleaves + (int64_t)(p2p_entries / kP2PItem) + 1;
+}
+// items of each leaf into item_cnt (nleaves entries)
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* item_cnt, hipStream_t s);
+// item_leaf / item_k from the scanned item offsets
+void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k, hipStream_t s);
+// wave-per-item kernel for leaf_size <= 16 (then the reduction in item
+// order), particle-per-thread otherwise; items: the bound on the item count
+void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, int64_t items,
+                 hipStream_t s);
+// sum of the item partials per target, plus the far field and the self term,
+// written in the caller's order (LS = the P2P kernel's target count)
+void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s);
 
 // ---- FP32-compensated form ------------------------------------------------------
 // FP32 moments per node and FP32 leaf-relative particle offsets (+ mass, h, 1/h)
@@ -235,10 +258,16 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
                   hipStream_t s);
 // false when leaf_size > 16 (not built)
 bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, hipStream_t s);
+                   const float2* ph, int64_t items, hipStream_t s);
 
 void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double kick, double drift,
                      hipStream_t s);
+
+// softened direct sum over all n sources for nt targets (targets == nullptr:
+// 0..nt-1); an out-of-range target index sets ST_OVERFLOW in *status
+void launch_direct(int64_t n, const double* x, const double* m, const double* h, int64_t nt,
+                   const int64_t* targets, double G, int include_self, double* acc, double* pot,
+                   int* status, hipStream_t s);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);

@@ -410,3 +410,29 @@ def test_far_shared_fp32c(torch, P, orc, top):
     assert np.sqrt((((pot - op) / op) ** 2).mean()) <= 1e-6
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+
+
+# ---- softened direct sum (accuracy reference) --------------------------------
+def test_direct_sum_parity(torch, P, orc):
+    print("case: direct sum vs oracle", flush=True)
+    x, m, h = workloads.plummer(3000, seed=8)
+    s = P.Solver()
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.direct(xd, md, hd)
+    torch.cuda.synchronize()
+    da, dp = orc.direct(x, m, h)
+    assert rel_err(acc.cpu().numpy(), da).max() < TOL
+    assert pot_err(pot.cpu().numpy(), dp) < TOL
+    # a subset of targets, in the order given
+    x, m, h = workloads.polytrope(20000, seed=9)
+    xd, md, hd = dev(torch, x, m, h)
+    tg = np.array([19999, 0, 7, 12345, 7], dtype=np.int64)
+    acc, pot = s.direct(xd, md, hd, targets=torch.from_numpy(tg).cuda())
+    ta, tp = orc.direct(x, m, h, targets=tg)
+    assert rel_err(acc.cpu().numpy(), ta).max() < TOL
+    assert np.abs(pot.cpu().numpy() - tp).max() / np.abs(tp).max() < TOL
+    # an index outside [0, n) is an error, not a read
+    with pytest.raises(P.SfmmError, match="out of range"):
+        s.direct(xd, md, hd, targets=torch.tensor([3, 20000], device="cuda"))
+    with pytest.raises(P.SfmmError, match="out of range"):
+        s.direct(xd, md, hd, targets=torch.tensor([-1], device="cuda"))
