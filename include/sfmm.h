@@ -32,9 +32,9 @@
  *     workspace only grows, is reused by later solves and is released by
  *     sfmm_destroy.
  *   - Work is enqueued on the context's HIP stream.  sfmm_solve synchronises
- *     that stream at two points (to size the tree and the interaction lists)
- *     and returns once the results are enqueued; they are valid after the
- *     next synchronisation of the stream.
+ *     that stream at a few points (to size the tree, the interaction lists
+ *     and the P2P work items) and returns once the results are enqueued; they
+ *     are valid after the next synchronisation of the stream.
  *   - Errors are returned as negative sfmm_status values; no C++ exception
  *     crosses this boundary.  After an error the outputs are undefined.
  *   - A context may be used by one host thread at a time.
@@ -110,7 +110,9 @@ typedef struct {
   int32_t max_depth;        /* depth of the deepest leaf (root = 0)                 */
   int64_t n_m2l;            /* M2L evaluations, replication over leaves included    */
   int64_t n_l2l;            /* L2L translations carried out down the branches       */
-  int64_t n_p2p_leaf_pairs; /* (target leaf, source leaf) P2P list entries          */
+  int64_t n_p2p_leaf_pairs; /* P2P list entries: (target leaf, source) with the source
+                               a leaf, or (level walk) a whole subtree that lies
+                               inside the target's kernel reach                     */
   int64_t n_p2p_pairs;      /* ordered particle pairs summed directly               */
   double momentum[3];       /* sum_i m_i acc_i (FP64), valid after a stream sync    */
   double momentum_abs;      /* sum_i |m_i acc_i|                                    */

@@ -238,28 +238,43 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
+  // this item's run [f_lo, f_hi) of the leaf's flattened sources
+  const uint32_t f_lo = kitem * kP2PItem;
+  const uint32_t ftot = a.flat[e1 - 1];
+  const uint32_t f_hi = f_lo + kP2PItem < ftot ? f_lo + kP2PItem : ftot;
   {
-    const uint64_t b = e0 + (uint64_t)kitem * kP2PItem;
-    e1 = b + kP2PItem < e1 ? b + kP2PItem : e1;
-    e0 = b;
+    uint64_t lo_e = e0, hi_e = e1 - 1;
+    while (lo_e < hi_e) {
+      const uint64_t mid = (lo_e + hi_e) >> 1;
+      if (a.flat[mid] > f_lo) hi_e = mid; else lo_e = mid + 1;
+    }
+    e0 = lo_e;
   }
   for (int t0 = 0; t0 < nt; t0 += TG) {
     double fx[TG], fy[TG], fz[TG], ph[TG];
 #pragma unroll
     for (int i = 0; i < TG; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
     for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-      int cnt = 0, lo = 0;
+      int cnt = 0, lo = 0, sub = 0;
+      uint32_t fb = 0xffffffffu;
       float dcx = 0.f, dcy = 0.f, dcz = 0.f;
       if (c0 + lane < e1) {
         const int src = list[c0 + lane];
         const NodeInfo si = a.info[src];
-        cnt = si.cnt;
-        lo = si.lo;
+        const uint32_t fe = a.flat[c0 + lane];
+        fb = fe - (uint32_t)si.cnt;
+        const uint32_t b = fb > f_lo ? fb : f_lo;
+        const uint32_t en = fe < f_hi ? fe : f_hi;
+        if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
+        // a whole subtree: its particles' offsets are relative to their own
+        // leaves, whose centres are looked up per particle
+        sub = si.child >= 0 ? 1 : 0;
         const double* rs = a.rec + (int64_t)src * RS;
         dcx = (float)(ct0 - rs[0]);
         dcy = (float)(ct1 - rs[1]);
         dcz = (float)(ct2 - rs[2]);
       }
+      if (__shfl((int)fb, 0, 64) >= (int)f_hi) break;  // the run is done (uniform)
       const int incl = wave_incl_scan32(cnt);
       const int pre = incl - cnt;
       const int total = __shfl(incl, 63, 64);
@@ -272,8 +287,15 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
           if (pk <= f) k += step;
         }
         const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-        const float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
+        float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
+        const int jsub = __shfl(sub, k, 64);
         if (f >= total) continue;
+        if (jsub) {
+          const double* rl = a.rec + (int64_t)a.leaf_node[a.p_leaf[j]] * RS;
+          cx = (float)(ct0 - rl[0]);
+          cy = (float)(ct1 - rl[1]);
+          cz = (float)(ct2 - rl[2]);
+        }
         const float4 oj = pf[j];
         const float2 hj = phh[j];
         const float hj2inv = hj.y * hj.y;

@@ -146,24 +146,37 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  // this item's run of the leaf's list
+  // this item's run [f_lo, f_hi) of the leaf's flattened sources, and the
+  // first list entry that reaches into it
+  const uint32_t f_lo = kitem * kP2PItem;
+  const uint32_t ftot = a.flat[e1 - 1];
+  const uint32_t f_hi = f_lo + kP2PItem < ftot ? f_lo + kP2PItem : ftot;
   {
-    const uint64_t b = e0 + (uint64_t)kitem * kP2PItem;
-    e1 = b + kP2PItem < e1 ? b + kP2PItem : e1;
-    e0 = b;
+    uint64_t lo_e = e0, hi_e = e1 - 1;  // flat[e1 - 1] = ftot > f_lo
+    while (lo_e < hi_e) {
+      const uint64_t mid = (lo_e + hi_e) >> 1;
+      if (a.flat[mid] > f_lo) hi_e = mid; else lo_e = mid + 1;
+    }
+    e0 = lo_e;
   }
   for (int t0 = 0; t0 < nt; t0 += NA) {
     double fx[NA], fy[NA], fz[NA], ph[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
     for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-      // 64 list entries: their particle ranges, flattened by a prefix scan
+      // 64 list entries: their particle ranges clipped to the run, flattened
+      // by a prefix scan
       int cnt = 0, lo = 0;
+      uint32_t fb = 0xffffffffu;
       if (c0 + lane < e1) {
         const NodeInfo si = a.info[list[c0 + lane]];
-        cnt = si.cnt;
-        lo = si.lo;
+        const uint32_t fe = a.flat[c0 + lane];
+        fb = fe - (uint32_t)si.cnt;
+        const uint32_t b = fb > f_lo ? fb : f_lo;
+        const uint32_t en = fe < f_hi ? fe : f_hi;
+        if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
       }
+      if (__shfl((int)fb, 0, 64) >= (int)f_hi) break;  // the run is done (uniform)
       const int incl = wave_incl_scan(cnt);
       const int pre = incl - cnt;
       const int total = __shfl(incl, 63, 64);
@@ -226,14 +239,37 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   }
 }
 
-// items per leaf: max(1, ceil(list entries / kP2PItem))
+// per list entry, the end of its particles in the leaf's flattened sources;
+// items per leaf: max(1, ceil(sources / kP2PItem)).  One wave per leaf.
 template <bool NODE>
-__global__ void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ cnt) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= a.nleaves) return;
-  const uint64_t c = NODE ? (uint64_t)a.node_p2p_cnt[a.leaf_node[l]] : a.p2p_off[l + 1] - a.p2p_off[l];
-  const uint64_t k = (c + kP2PItem - 1) / kP2PItem;
-  cnt[l] = k > 0 ? (uint32_t)k : 1u;
+__global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ flat,
+                                                        uint32_t* __restrict__ cnt) {
+  const int l = blockIdx.x;
+  const int lane = threadIdx.x;
+  uint64_t e0, e1;
+  const int32_t* list;
+  if (NODE) {
+    const int node = a.leaf_node[l];
+    e0 = a.node_p2p_off[node];
+    e1 = e0 + a.node_p2p_cnt[node];
+    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    e0 = a.p2p_off[l];
+    e1 = a.p2p_off[l + 1];
+    list = a.p2p_list;
+  }
+  uint32_t carry = 0;
+  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+    const bool in = c0 + lane < e1;
+    const int c = in ? a.info[list[c0 + lane]].cnt : 0;
+    const int incl = wave_incl_scan(c);
+    if (in) flat[c0 + lane] = carry + (uint32_t)incl;
+    carry += (uint32_t)__shfl(incl, 63, 64);
+  }
+  if (lane == 0) {
+    const uint32_t k = (carry + kP2PItem - 1) / kP2PItem;
+    cnt[l] = k > 0 ? k : 1u;
+  }
 }
 
 __global__ void k_p2p_items_fill(NearArgs a, int32_t* __restrict__ item_leaf,
@@ -318,11 +354,11 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
     launch_p2p_reduce(a, LS, s);                                      \
   } while (0)
 
-void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* item_cnt,
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, uint32_t* item_cnt,
                             hipStream_t s) {
   if (a.nleaves <= 0) return;
-  if (node_lists) k_p2p_items_count<true><<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_cnt);
-  else k_p2p_items_count<false><<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_cnt);
+  if (node_lists) k_p2p_items_count<true><<<a.nleaves, 64, 0, s>>>(a, flat, item_cnt);
+  else k_p2p_items_count<false><<<a.nleaves, 64, 0, s>>>(a, flat, item_cnt);
 }
 
 void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k,

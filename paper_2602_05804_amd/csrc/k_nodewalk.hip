@@ -162,7 +162,12 @@ __device__ __forceinline__ int classify(const NodeWalkArgs& a, int v, const doub
 // the same test for a leaf target, from one evaluation of d^2: 0 = M2L,
 // 1 = opened (or P2P that may need softening), 2 = opened although beyond
 // both kernels (only the opening angle failed; a P2P pair of leaves then
-// needs no softening)
+// needs no softening), 3 = opened, and every node below s would fail the
+// softening test against v too: s lies inside v's own kernel reach,
+// d + l_s < l_v + R_kern h_max(v) (any node below s has its centre within
+// l_s of s's and h_max >= 0), so the lowering would end with all of s's
+// leaves as P2P sources; the margin keeps rounding in the tests the
+// lowering would make from deciding otherwise
 __device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const double* rv,
                                          uint32_t s) {
   if ((int)s == v) return 1;
@@ -173,7 +178,10 @@ __device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const dou
   const double d2 = dx * dx + dy * dy + dz * dz;
   const double lsum = rv[3] + rs[3];
   const double rsum = lsum + a.r_kern * fmax(rv[4], rs[4]);
-  if (!(d2 >= rsum * rsum)) return 1;
+  if (!(d2 >= rsum * rsum)) {
+    const double reach = rv[3] + a.r_kern * rv[4] - rs[3];
+    return (reach > 0.0 && d2 < reach * reach * (1.0 - 1e-9)) ? 3 : 1;
+  }
   return (lsum * lsum < a.theta2 * d2) ? 0 : 2;
 }
 
@@ -253,7 +261,8 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
       const int k = kk[u][q];
       if (k < 0) continue;
       if (k == 0) { selm |= 1u << q; ++nm; continue; }
-      if (cc[u][q] < 0) {
+      if (cc[u][q] < 0 || k == 3) {
+        // a leaf, or a whole subtree of P2P sources kept as one entry
         if (k == 2) { selq |= 1u << q; ++nq; }
         else { selp |= 1u << q; ++np; }
       } else {

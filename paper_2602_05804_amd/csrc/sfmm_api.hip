@@ -36,7 +36,7 @@ enum BufId {
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
-  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART,
+  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT,
   B_COUNT
 };
 
@@ -601,29 +601,34 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.include_self = ctx->cfg.include_self_potential;
   a.acc = acc;
   a.pot = pot;
-  // P2P work items: runs of at most kP2PItem list entries of one leaf
+  phase_mark(ctx, 4, 0);
+  // P2P work items: runs of at most kP2PItem flattened source particles of
+  // one leaf; their number is read back to size the partial sums
   int64_t items = 0;
   if (ctx->cfg.leaf_size <= 16) {
-    items = p2p_item_bound(nl, ctx->p2p_total);
-    const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
     struct { int id; size_t bytes; } need4[] = {
-        {B_ITEMCNT, sizeof(uint32_t) * (size_t)nl}, {B_ITEMOFF, sizeof(uint32_t) * (size_t)(nl + 1)},
-        {B_ITEMLEAF, sizeof(int32_t) * (size_t)items}, {B_ITEMK, sizeof(uint32_t) * (size_t)items},
-        {B_PART, sizeof(double) * 4 * (size_t)ls * (size_t)items}};
+        {B_P2PFLAT, sizeof(uint32_t) * (size_t)std::max<uint64_t>(ctx->p2p_total, 1)},
+        {B_ITEMCNT, sizeof(uint32_t) * (size_t)nl}, {B_ITEMOFF, sizeof(uint32_t) * (size_t)(nl + 1)}};
     for (auto& q : need4)
       if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
     uint32_t* item_off = P<uint32_t>(ctx, B_ITEMOFF);
+    a.flat = P<uint32_t>(ctx, B_P2PFLAT);
     a.item_off = item_off;
+    launch_p2p_items_count(level, a, P<uint32_t>(ctx, B_P2PFLAT), P<uint32_t>(ctx, B_ITEMCNT), s);
+    scan_u32(P<uint32_t>(ctx, B_ITEMCNT), item_off, nl, item_off + nl, P<uint32_t>(ctx, B_SCANTMP), s);
+    uint32_t htot = 0;
+    HIPCHK(hipMemcpyAsync(&htot, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    items = htot;
+    const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
+    struct { int id; size_t bytes; } need5[] = {
+        {B_ITEMLEAF, sizeof(int32_t) * (size_t)items}, {B_ITEMK, sizeof(uint32_t) * (size_t)items},
+        {B_PART, sizeof(double) * 4 * (size_t)ls * (size_t)items}};
+    for (auto& q : need5)
+      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
     a.item_leaf = P<int32_t>(ctx, B_ITEMLEAF);
     a.item_k = P<uint32_t>(ctx, B_ITEMK);
     a.part = P<double>(ctx, B_PART);
-  }
-  phase_mark(ctx, 4, 0);
-  if (items > 0) {
-    uint32_t* cnt = P<uint32_t>(ctx, B_ITEMCNT);
-    launch_p2p_items_count(level, a, cnt, s);
-    scan_u32(cnt, P<uint32_t>(ctx, B_ITEMOFF), nl, P<uint32_t>(ctx, B_ITEMOFF) + nl,
-             P<uint32_t>(ctx, B_SCANTMP), s);
     launch_p2p_items_fill(a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK), s);
   }
   if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, a, P<float4>(ctx, B_PF32),

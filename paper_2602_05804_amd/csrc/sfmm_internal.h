@@ -223,21 +223,21 @@ struct NearArgs {
   int include_self;
   double* acc;  // caller order [n][3]
   double* pot;  // caller order [n]
-  // work items (leaf_size <= 16): one wave per run of at most kP2PItem list
-  // entries of one leaf; each item writes partial sums for the leaf's
-  // targets, which a second kernel adds in item order
+  // work items (leaf_size <= 16): a leaf's P2P sources, flattened over its
+  // list entries (leaves, or whole subtrees), are cut into runs of at most
+  // kP2PItem source particles, one wave per run; each item writes partial
+  // sums for the leaf's targets, which a second kernel adds in item order
+  const uint32_t* flat;      // per list entry: end of its particles in the leaf's flattened sources
   const uint32_t* item_off;  // [nleaves + 1] first item of each leaf; [nleaves] = total
   const int32_t* item_leaf;  // [items] leaf of each item
   const uint32_t* item_k;    // [items] index of the item within its leaf
   double* part;              // [items][LS][4] partial field (x, y, z) and potential
 };
-constexpr int kP2PItem = 128;
-// upper bound on the number of work items
-inline int64_t p2p_item_bound(int64_t nleaves, uint64_t p2p_entries) {
-  return nleaves + (int64_t)(p2p_entries / kP2PItem) + 1;
-}
-// items of each leaf into item_cnt (nleaves entries)
-void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* item_cnt, hipStream_t s);
+constexpr uint32_t kP2PItem = 2048;
+// per-entry flattened ends (flat) and the number of items of each leaf
+// (item_cnt, nleaves entries); one wave per leaf
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, uint32_t* item_cnt,
+                            hipStream_t s);
 // item_leaf / item_k from the scanned item offsets
 void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k, hipStream_t s);
 // wave-per-item kernel for leaf_size <= 16 (then the reduction in item

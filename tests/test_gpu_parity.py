@@ -89,12 +89,28 @@ def test_tree_parity(torch, P, orc):
     s.close()
 
 
+def _expand_p2p(g, leaf_nodes, p2p):
+    """P2P entries as source leaves: a subtree entry stands for all its leaves."""
+    llo = g["lo"][leaf_nodes]
+    out = []
+    for e in p2p.tolist():
+        if g["child"][e] < 0:
+            out.append(e)
+        else:
+            lo, hi = g["lo"][e], g["lo"][e] + g["cnt"][e]
+            out += leaf_nodes[(llo >= lo) & (llo < hi)].tolist()
+    return np.array(out, dtype=np.int64)
+
+
 def _lists_equal(s, t, g, leaf_nodes, theta, same_order):
     nd = t.nodes()
     omap = {(int(a), int(b)): i for i, (a, b) in enumerate(zip(nd["lo"], nd["hi"]))}
     g2o = np.array([omap[(int(a), int(a + c))] for a, c in zip(g["lo"], g["cnt"])])
+    leaf_nodes = np.asarray(leaf_nodes)
     for li, node in enumerate(leaf_nodes):
         dep, src, p2p = s.leaf_lists(li)
+        if not same_order:
+            p2p = _expand_p2p(g, leaf_nodes, p2p)
         odep, osrc, op2p = t.leaf_lists(g2o[node], theta)
         if same_order:
             # Algorithm 1 per leaf: the oracle's entries grouped by depth, in
@@ -187,7 +203,13 @@ def test_large_softening_all_pairs(torch, P, orc):
     acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.9)
     da, dp = orc.direct(x, m, h)
     st = s.stats()
-    assert st["n_m2l"] == 0 and st["n_p2p_leaf_pairs"] == st["num_leaves"] ** 2
+    # every ordered particle pair once (i != j); with the level walk a leaf
+    # keeps the subtrees inside its kernel reach as single P2P entries
+    assert st["n_m2l"] == 0 and st["n_p2p_pairs"] == 2000 * 1999
+    assert st["n_p2p_leaf_pairs"] < st["num_leaves"] ** 2
+    assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.9, walk="leaf")
+    assert s.stats()["n_p2p_leaf_pairs"] == st["num_leaves"] ** 2
     assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
 
 
