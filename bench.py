@@ -99,6 +99,10 @@ def main():
                     help="shared: each node's M2L list once, then L2L per leaf (the caching "
                          "the paper proposes); leaf: every leaf evaluates its ancestors' "
                          "lists (the paper's replicated walk), also timed beside shared")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the kernel shapes (and with --autotune-leaf the leaf size) by a "
+                         "timed search on this input before the timed run")
+    ap.add_argument("--autotune-leaf", action="store_true")
     ap.add_argument("--cpu-leaves", type=int, default=1500,
                     help="leaves the CPU oracle walks for the baseline and the parity sample")
     ap.add_argument("--no-cpu", action="store_true")
@@ -150,7 +154,19 @@ def main():
         x, m, h = workloads.plummer(args.n, seed=1)
         wl = f"Plummer sphere a=1 M=1, N={args.n}, seed 1"
     xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
-    solver = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far=args.far)
+    cfg = {"leaf_size": args.leaf_size, "walk": args.walk, "far": args.far}
+    if args.autotune:
+        from paper_2602_05804_amd import autotune
+
+        log("autotune")
+        res = autotune.search(xd, md, hd, theta=args.theta, order=args.order,
+                              precision=args.precision, log=log,
+                              leaf_sizes=autotune.LEAF_SIZES if args.autotune_leaf
+                              else (args.leaf_size,),
+                              base={"walk": args.walk, "far": args.far})
+        cfg = res["config"]
+        args.leaf_size = cfg["leaf_size"]
+    solver = sfmm.Solver(**cfg)
     acc = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty((args.n,), dtype=torch.float64, device="cuda")
     log(f"warmup {args.warmup}")
@@ -205,7 +221,9 @@ def main():
         "config": {"workload": wl,
                    "N": args.n, "theta": args.theta, "order": p, "leaf_size": args.leaf_size,
                    "precision": args.precision, "G": 1.0, "r_kern": 2.0, "walk": args.walk,
-                   "far": args.far, "h_min": float(h.min()), "h_max": float(h.max())},
+                   "far": args.far, "h_min": float(h.min()), "h_max": float(h.max()),
+                   "kernels": {k: cfg.get(k, 0) for k in ("near_kernel", "far_kernel")},
+                   "autotuned": bool(args.autotune)},
         "roofline": roofline,
         "phases": per_phase,
         "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l",

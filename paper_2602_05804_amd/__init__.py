@@ -46,7 +46,8 @@ class SfmmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("G", C.c_double), ("leaf_size", C.c_int), ("r_kern", C.c_double),
                 ("include_self_potential", C.c_int), ("check_inputs", C.c_int),
-                ("walk_mode", C.c_int), ("fp64_top_depth", C.c_int), ("far_mode", C.c_int)]
+                ("walk_mode", C.c_int), ("fp64_top_depth", C.c_int), ("far_mode", C.c_int),
+                ("far_kernel", C.c_int), ("near_kernel", C.c_int)]
 
 
 WALK_MODES = {"level": 0, "leaf": 1}
@@ -113,7 +114,7 @@ class Solver:
     def __init__(self, device: int = 0, G: float = 1.0, leaf_size: int = 10,
                  r_kern: float = 2.0, include_self_potential: bool = True,
                  check_inputs: bool = True, walk: str = "level", fp64_top_depth: int = 8,
-                 far: str = "shared"):
+                 far: str = "shared", far_kernel: int = 0, near_kernel: int = 0):
         import torch
 
         if not torch.cuda.is_available():
@@ -121,7 +122,8 @@ class Solver:
         self._torch = torch
         self.device = int(device)
         self.cfg = Config(G, leaf_size, r_kern, int(include_self_potential), int(check_inputs),
-                          WALK_MODES[walk], int(fp64_top_depth), FAR_MODES[far])
+                          WALK_MODES[walk], int(fp64_top_depth), FAR_MODES[far],
+                          int(far_kernel), int(near_kernel))
         self._ctx = C.c_void_p(0)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         self._check(lib().sfmm_create(C.byref(self._ctx), self.device, C.c_void_p(stream),

@@ -664,6 +664,8 @@ int sfmm_config_default(sfmm_config* cfg) {
   cfg->walk_mode = SFMM_WALK_LEVEL;
   cfg->fp64_top_depth = 8;
   cfg->far_mode = SFMM_FAR_SHARED;
+  cfg->far_kernel = 0;
+  cfg->near_kernel = 0;
   return SFMM_OK;
 }
 
@@ -676,7 +678,8 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
-      (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED))
+      (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED) || c.far_kernel < 0 ||
+      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 4)
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -688,6 +691,9 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->cfg = c;
+  ctx->far_variant = c.far_kernel;
+  ctx->near_variant = c.near_kernel;
+  // measurement overrides
   if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
   if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
   *out = ctx;

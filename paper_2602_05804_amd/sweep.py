@@ -8,6 +8,10 @@ paper's Plummer / homogeneous-sphere tests, Sect. 4.1).
       sphere and a homogeneous sphere, and the time of one solve
   python -m paper_2602_05804_amd.sweep scaling   [--theta 0.5]
       time of one solve of a Plummer sphere for N = 1e4 ... 3e6
+  python -m paper_2602_05804_amd.sweep binary    [--n-each 100000 --steps 200]
+      gravity-only leapfrog evolution of the binary polytrope (Sect. 4.2's
+      binary without the gas dynamics): drift of the linear momentum, angular
+      momentum and energy
 
 Prints one JSON object per line.  Inputs are the seeded generators of the
 `workloads` module (Plummer a = 1, M = 1, seed 1; homogeneous sphere R = 1,
@@ -90,9 +94,55 @@ def scaling(theta: float, precision: str, far: str, sizes):
     s.close()
 
 
+def binary(n_each: int, steps: int, precision: str, far: str, orbit_fraction: float,
+           every: int = 0):
+    """Gravity-only kick-drift-kick evolution of the binary polytrope (two
+    n = 1.5 stars of M = 1 at separation 3R on a circular orbit): linear
+    momentum P = sum m v, angular momentum L = sum m x cross v and energy
+    E = sum m v^2 / 2 + sum m phi / 2 (no self term), relative to their
+    initial values, every `every` steps (default: ten records); yields dicts."""
+    import torch
+
+    import paper_2602_05804_amd as sfmm
+    import workloads
+
+    x, m, h, v = workloads.binary_polytrope(n_each)
+    xd, md, hd, vd = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (x, m, h, v))
+    s = sfmm.Solver(far=far, include_self_potential=False)
+    period = 2.0 * np.pi * np.sqrt(27.0 / 2.0)
+    dt = orbit_fraction * period / steps
+    mcol = md[:, None]
+
+    def invariants(acc, pot):
+        p = (mcol * vd).sum(0)
+        lv = (mcol * torch.cross(xd, vd, dim=1)).sum(0)
+        e = 0.5 * (md * (vd * vd).sum(1)).sum() + 0.5 * (md * pot).sum()
+        pabs = (md * vd.norm(dim=1)).sum()
+        return p.cpu().numpy(), lv.cpu().numpy(), float(e), float(pabs)
+
+    acc, pot = s.solve(xd, md, hd, precision=precision)
+    p0, l0, e0, pabs = invariants(acc, pot)
+    t0 = time.perf_counter()
+    for k in range(1, steps + 1):
+        sfmm.leapfrog(xd, vd, acc, 0.5 * dt, dt)
+        acc, pot = s.solve(xd, md, hd, precision=precision)
+        sfmm.leapfrog(xd, vd, acc, 0.5 * dt, 0.0)
+        if k % (every or max(1, steps // 10)) == 0 or k == steps:
+            p, lv, e, _ = invariants(acc, pot)
+            yield {"sweep": "binary", "N": 2 * n_each, "step": k, "dt": dt,
+                   "precision": precision, "far": far,
+                   "dP_rel": float(np.linalg.norm(p - p0) / pabs),
+                   "dL_rel": float(np.linalg.norm(lv - l0) / np.linalg.norm(l0)),
+                   "dE_rel": abs(e - e0) / abs(e0), "seconds": time.perf_counter() - t0}
+    s.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["accuracy", "scaling"])
+    ap.add_argument("what", choices=["accuracy", "scaling", "binary"])
+    ap.add_argument("--n-each", type=int, default=100_000)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--orbit-fraction", type=float, default=0.25)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
@@ -104,6 +154,9 @@ def main(argv=None):
         sys.path.insert(0, root)
     if args.what == "accuracy":
         accuracy(args.n, args.precision, args.far)
+    elif args.what == "binary":
+        for rec in binary(args.n_each, args.steps, args.precision, args.far, args.orbit_fraction):
+            print(json.dumps(rec), flush=True)
     else:
         scaling(args.theta, args.precision, args.far, [int(v) for v in args.sizes.split(",")])
 

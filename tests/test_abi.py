@@ -46,7 +46,8 @@ def test_null_arguments(L):
     c = P.Config()
     assert L.sfmm_config_default(C.byref(c)) == 0
     assert (c.G, c.leaf_size, c.r_kern, c.include_self_potential, c.check_inputs,
-            c.walk_mode, c.fp64_top_depth, c.far_mode) == (1.0, 10, 2.0, 1, 1, 0, 8, 1)
+            c.walk_mode, c.fp64_top_depth, c.far_mode, c.far_kernel,
+            c.near_kernel) == (1.0, 10, 2.0, 1, 1, 0, 8, 1, 0, 0)
     assert L.sfmm_create(None, 0, None, None) == -1
     assert L.sfmm_solve(None, 10, None, None, None, 0.5, 3, 0, None, None) == -1
     assert L.sfmm_build(None, 10, None, None, None, 3) == -1
@@ -66,6 +67,8 @@ def test_bad_config_rejected(L):
     bad = P.Config(1.0, 10, 2.0, 1, 1, 7, 8, 0)  # unknown walk mode
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
     bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 5)  # unknown far mode
+    assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
+    bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 1, 9, 0)  # unknown far kernel shape
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
 
 

@@ -1,0 +1,80 @@
+"""Autotuner search and cache on the CPU, with a stand-in for the timing."""
+import json
+
+import pytest
+
+from paper_2602_05804_amd import autotune
+
+
+class _T:
+    """Tensor stand-in: shape and device only."""
+
+    def __init__(self, n):
+        self.shape = (n,)
+        self.device = "cpu"
+
+
+def _cost(cfg):
+    # separable bowl: best at leaf 12, near kernel 4, far kernel 2, top depth 12
+    c = abs(cfg["leaf_size"] - 12) + abs(cfg["near_kernel"] - 4) * 0.5
+    c += 0.0 if cfg["far_kernel"] == 2 else 1.0
+    c += abs(cfg.get("fp64_top_depth", 12) - 12) * 0.1
+    return 1.0 + c
+
+
+def test_search_finds_separable_minimum(monkeypatch):
+    calls = []
+    monkeypatch.setattr(autotune, "time_config",
+                        lambda x, m, h, cfg, *a, **k: calls.append(dict(cfg)) or _cost(cfg))
+    res = autotune.search(None, _T(1000), None, precision="fp32c")
+    assert res["config"] == {"leaf_size": 12, "near_kernel": 4, "far_kernel": 2,
+                             "fp64_top_depth": 12}
+    assert res["seconds"] == 1.0
+    # a coordinate search: one run per value per axis, not the full product
+    assert len(calls) == 1 + 4 + 3 + 3 + 2
+
+
+def test_cache_roundtrip(monkeypatch, tmp_path):
+    import torch
+
+    monkeypatch.setattr(torch.cuda, "get_device_name", lambda d=None: "TestGPU")
+    n_search = []
+
+    def fake_search(x, m, h, theta, order, precision, log=None):
+        n_search.append(1)
+        return {"config": {"leaf_size": 8, "near_kernel": 0, "far_kernel": 1}, "seconds": 0.1}
+
+    monkeypatch.setattr(autotune, "search", fake_search)
+    path = str(tmp_path / "cache.json")
+    c1 = autotune.tuned_config(_T(1000), _T(1000), _T(1000), label="plummer", cache_path=path)
+    c2 = autotune.tuned_config(_T(1100), _T(1100), _T(1100), label="plummer", cache_path=path)
+    assert c1 == c2 == {"leaf_size": 8, "near_kernel": 0, "far_kernel": 1}
+    assert len(n_search) == 1  # same power-of-two bucket: cached
+    autotune.tuned_config(_T(5000), _T(5000), _T(5000), label="plummer", cache_path=path)
+    assert len(n_search) == 2  # another bucket
+    keys = sorted(json.load(open(path)))
+    assert len(keys) == 2 and all(k.startswith("TestGPU|N~") for k in keys)
+
+
+@pytest.mark.gpu
+def test_autotuned_solver_parity(orc):
+    import numpy as np
+    import torch
+
+    import paper_2602_05804_amd as P
+    import workloads
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    print("case: autotuned config parity", flush=True)
+    x, m, h = workloads.plummer(20000, seed=3)
+    xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
+    res = autotune.search(xd, md, hd, reps=2)
+    cfg = res["config"]
+    assert cfg["leaf_size"] in autotune.LEAF_SIZES
+    acc, pot = P.Solver(**cfg).solve(xd, md, hd)
+    torch.cuda.synchronize()
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=cfg["leaf_size"])
+    acc = acc.cpu().numpy()
+    nb = np.linalg.norm(oa, axis=1)
+    assert (np.linalg.norm(acc - oa, axis=1) / np.maximum(nb, 1e-6 * np.sqrt((nb ** 2).mean()))).max() < 1e-12

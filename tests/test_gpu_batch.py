@@ -202,3 +202,16 @@ def test_serving_failure_isolated(torch, P):
     rep = serve.Server(ex, hbm_budget=ex.footprint(10**6)).run(jobs, realtime=False)
     assert rep.completed == 5 and rep.failed == 1
     assert jobs[2].error is not None and "non-finite" in jobs[2].error
+
+
+@pytest.mark.parametrize("precision,bound", [("fp64", 1e-13), ("fp32c", 1e-6)])
+def test_binary_momentum_drift(torch, P, precision, bound):
+    """Gravity-only leapfrog of the binary polytrope: the pairwise forces
+    keep the total momentum to rounding over many steps (without pressure the
+    cold stars collapse, so energy is not a useful check here)."""
+    print(f"case: binary leapfrog drift {precision}", flush=True)
+    from paper_2602_05804_amd import sweep
+
+    recs = list(sweep.binary(3000, 20, precision, "shared", 0.05, every=5))
+    assert len(recs) == 4
+    assert max(r["dP_rel"] for r in recs) < bound
