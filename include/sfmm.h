@@ -101,15 +101,16 @@ typedef struct {
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
   int far_mode;               /* sfmm_far_mode (SFMM_FAR_SHARED)                      */
   int far_kernel;             /* far-field kernel shape, 0..4 (0)                    */
-  int near_kernel;            /* P2P kernel shape, 0..4 (0)                          */
+  int near_kernel;            /* P2P kernel shape, 0..5 (0)                          */
 } sfmm_config;
 /* Kernel shapes (same results up to summation order; picked by the autotuner):
  * far_kernel, SFMM_FAR_SHARED: lanes per node 8 (0; a two-wave register budget
  *   in FP64), 4 (1), 16 (2), 8 with one wave (3), 8 with two waves (4);
  *   SFMM_FAR_LEAF: lanes per leaf 4 (0), 4 with two waves (1), 2 (2), 1 (3).
- * near_kernel (leaf_size <= 16): targets of a leaf in unrolled passes of 5 (0),
- *   one thread per particle (1), passes of 10 (2), one pass with a run-time
- *   target loop (3), passes of 4 (4). */
+ * near_kernel (leaf_size <= 16): targets of a leaf in unrolled passes of 5
+ *   with the pairs inside a kernel queued and evaluated 64 at a time (0), one
+ *   thread per particle (1), passes of 10 (2), one pass with a run-time
+ *   target loop (3), passes of 4 (4), passes of 5 without the queue (5). */
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
 typedef struct {

@@ -116,7 +116,11 @@ __device__ __forceinline__ double wave_sum(double v) {
 // TG > 0:  passes of TG targets each, fully unrolled (static accumulator
 //          indices; nt is the same on every lane, so the guard is a scalar
 //          branch); the sources are read once per pass.
-template <int LS, bool NODE, int TG>
+// Q: pairs inside a kernel are not evaluated in the wave's pass over the
+// sources (where most lanes would idle through the softening branch) but
+// queued in LDS as (target, source); every 64 queued pairs are evaluated
+// together, one per lane, and added to the same per-target accumulators.
+template <int LS, bool NODE, int TG, bool Q = false>
 __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   constexpr int NA = TG > 0 ? TG : LS;  // accumulators per pass
   const int lane = threadIdx.x;
@@ -159,10 +163,47 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     }
     e0 = lo_e;
   }
+  __shared__ int qj[Q ? 128 : 1];
+  __shared__ int qi[Q ? 128 : 1];
+  uint32_t qn = 0;  // queued softened pairs (the same on every lane)
   for (int t0 = 0; t0 < nt; t0 += NA) {
     double fx[NA], fy[NA], fz[NA], ph[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+    // the softened pairs of queue slots [0, count), one per lane, into the
+    // accumulators of their targets; the rest of the queue moves to the front
+    auto flush = [&](uint32_t count) {
+      __syncthreads();
+      const bool act = (uint32_t)lane < count;
+      const int j2 = act ? qj[lane] : ti.lo;
+      const int i2 = act ? qi[lane] : 0;
+      const double thi = tg[i2][3];
+      const double dx = tg[i2][0] - a.xs[j2], dy = tg[i2][1] - a.ys[j2], dz = tg[i2][2] - a.zs[j2];
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double rinv = rsqrt_pair(r2);
+      const double rinv3 = rinv * rinv * rinv;
+      const double r = r2 * rinv;
+      const double hj = a.hs[j2], hjinv = a.his[j2];
+      double g1, p1, g2, p2;
+      soft_sel(r * thi, thi, tg[i2][4] * rinv, rinv, rinv3, g1, p1);
+      soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
+      const double w = act ? a.ms[j2] : 0.0;
+      const double mg = w * (0.5 * (g1 + g2));
+      const double cx = mg * dx, cy = mg * dy, cz = mg * dz, cp = w * (0.5 * (p1 + p2));
+#pragma unroll
+      for (int ii = 0; ii < NA; ++ii) {
+        if (act && i2 == t0 + ii) {
+          fx[ii] += cx; fy[ii] += cy; fz[ii] += cz; ph[ii] += cp;
+        }
+      }
+      const uint32_t rem = qn - count;
+      int tj = 0, tq = 0;
+      if ((uint32_t)lane < rem) { tj = qj[count + lane]; tq = qi[count + lane]; }
+      __syncthreads();
+      if ((uint32_t)lane < rem) { qj[lane] = tj; qi[lane] = tq; }
+      qn = rem;
+      __syncthreads();
+    };
     for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
       // 64 list entries: their particle ranges clipped to the run, flattened
       // by a prefix scan
@@ -189,8 +230,11 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
           const int pk = __shfl(pre, k + step, 64);
           if (pk <= f) k += step;
         }
-        const int j = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-        if (f >= total) continue;
+        const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+        // lanes past the window's end stay in step with the others (the queue
+        // count and its barriers are per wave) and contribute nothing
+        const bool fv = f < total;
+        const int j = fv ? jj : ti.lo;
         const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j], mj = a.ms[j];
         const double hj = a.hs[j], hjinv = a.his[j];
         const double hj2inv = hjinv * hjinv;
@@ -199,15 +243,26 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
           const int i = t0 + ii;
           if (TG > 0) { if (i >= nt) continue; }
           else if (i >= nt) break;
-          const double w = (j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
+          const double w = (!fv || j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
           const double thi = tg[i][3];
           const double dx = tg[i][0] - xj, dy = tg[i][1] - yj, dz = tg[i][2] - zj;
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          const double rinv = r2 > 0.0 ? rsqrt(r2) : 0.0;
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const double rinv = rsqrt_pair(r2);
           const double rinv3 = rinv * rinv * rinv;
           double gs = rinv3, ps = rinv;  // both kernels at q >= 2
-          const bool inside = (r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0);
-          if (__ballot(inside)) {
+          const bool inside = fv && ((r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0));
+          double wq = w;
+          if (Q) {
+            const bool push = inside && w != 0.0;
+            const uint64_t bal = __ballot(push);
+            if (bal) {
+              const uint32_t below =
+                  __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+              if (push) { qj[qn + below] = j; qi[qn + below] = i; }
+              qn += (uint32_t)__popcll(bal);
+            }
+            if (inside) wq = 0.0;
+          } else if (__ballot(inside)) {
             const double r = r2 * rinv;
             double g1, p1, g2, p2;
             soft_sel(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
@@ -217,14 +272,16 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
               ps = 0.5 * (p1 + p2);
             }
           }
-          const double mg = w * gs;
+          const double mg = wq * gs;
           fx[ii] = fma(mg, dx, fx[ii]);
           fy[ii] = fma(mg, dy, fy[ii]);
           fz[ii] = fma(mg, dz, fz[ii]);
-          ph[ii] = fma(w, ps, ph[ii]);
+          ph[ii] = fma(wq, ps, ph[ii]);
+          if (Q && qn >= 64) flush(64);
         }
       }
     }
+    if (Q && qn > 0) flush(qn);
 #pragma unroll
     for (int ii = 0; ii < NA; ++ii) {
       const int i = t0 + ii;
@@ -347,11 +404,11 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
-#define NEAR_LAUNCH(LS, TG)                                           \
-  do {                                                                \
-    if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);   \
-    else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);             \
-    launch_p2p_reduce(a, LS, s);                                      \
+#define NEAR_LAUNCH(LS, TG, QU)                                            \
+  do {                                                                    \
+    if (node_lists) k_p2p_leaf<LS, true, TG, QU><<<nbl, 64, 0, s>>>(a);   \
+    else k_p2p_leaf<LS, false, TG, QU><<<nbl, 64, 0, s>>>(a);             \
+    launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 
 void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, uint32_t* item_cnt,
@@ -377,17 +434,19 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   if (a.n <= 0) return;
   const unsigned nbl = (unsigned)items;
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
-  // variant: targets per pass 5 (default), 10 (2), 4 (4), a run-time loop
-  // over all targets (3)
+  // variant: targets per pass 5 with the softened pairs queued (default),
+  // 10 (2), 4 (4), a run-time loop over all targets (3), 5 without the queue (5)
   if (leaf_size <= 10) {
     switch (variant) {
-      case 2: NEAR_LAUNCH(10, 10); break;
-      case 3: NEAR_LAUNCH(10, 0); break;
-      case 4: NEAR_LAUNCH(10, 4); break;
-      default: NEAR_LAUNCH(10, 5); break;
+      case 2: NEAR_LAUNCH(10, 10, false); break;
+      case 3: NEAR_LAUNCH(10, 0, false); break;
+      case 4: NEAR_LAUNCH(10, 4, false); break;
+      case 5: NEAR_LAUNCH(10, 5, false); break;
+      default: NEAR_LAUNCH(10, 5, true); break;
     }
   } else if (leaf_size <= 16) {
-    NEAR_LAUNCH(16, 8);
+    if (variant == 5) NEAR_LAUNCH(16, 8, false);
+    else NEAR_LAUNCH(16, 8, true);
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);

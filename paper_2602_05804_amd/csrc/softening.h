@@ -13,6 +13,16 @@
 
 namespace sfmm {
 
+// 1/sqrt(r2) for r2 > 0, 0 for r2 == 0: the hardware estimate refined once
+// with the third-order step y' = y (1 + e/2 + 3e^2/8), e = 1 - r2 y^2 (the
+// series of (1 - e)^(-1/2)); no branch
+__device__ __forceinline__ double rsqrt_pair(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2 * y, y, 1.0);
+  const double r = fma(y * e, fma(e, 0.375, 0.5), y);
+  return r2 > 0.0 ? r : 0.0;
+}
+
 __device__ __forceinline__ void soft(double r, double hinv, double& g, double& psi) {
   const double q = r * hinv;
   const double h3 = hinv * hinv * hinv;

@@ -31,7 +31,7 @@ def test_search_finds_separable_minimum(monkeypatch):
                              "fp64_top_depth": 12}
     assert res["seconds"] == 1.0
     # a coordinate search: one run per value per axis, not the full product
-    assert len(calls) == 1 + 4 + 3 + 3 + 2
+    assert len(calls) == 1 + 4 + 4 + 3 + 2
 
 
 def test_cache_roundtrip(monkeypatch, tmp_path):

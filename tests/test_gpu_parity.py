@@ -458,3 +458,18 @@ def test_direct_sum_parity(torch, P, orc):
         s.direct(xd, md, hd, targets=torch.tensor([3, 20000], device="cuda"))
     with pytest.raises(P.SfmmError, match="out of range"):
         s.direct(xd, md, hd, targets=torch.tensor([-1], device="cuda"))
+
+
+@pytest.mark.parametrize("near_kernel", [1, 2, 3, 4, 5])
+def test_p2p_kernel_shapes(torch, P, orc, near_kernel):
+    """Every P2P kernel shape gives the oracle's result (halo leaves with
+    large softening lengths, coincident particles)."""
+    print(f"case: P2P kernel shape {near_kernel}", flush=True)
+    x, m, h = workloads.plummer(6000, seed=4)
+    x[100:140] = x[99]  # a clump of coincident particles
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, near_kernel=near_kernel)
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
