@@ -24,7 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle gravity evals/sec (SFMM, N=1e6, theta=0.5); serving p50/p99 latency"
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CUs x 128 flop/clk x 2.4 GHz)
-P2P_FLOPS_PER_PAIR = 22      # far-pair branch of the P2P kernel (FMA = 2, rsqrt = 1)
+P2P_FLOPS_PER_PAIR = 22      # a pair outside both kernels (FMA = 2, rsqrt = 1)
+P2P_FLOPS_SOFT = 40          # more for a pair inside a kernel: one branch of each of
+                             # the two cubic-spline kernels (force and potential)
 
 
 # dominant kernel of each phase: name prefix in the profiler's output and the
@@ -198,7 +200,7 @@ def main():
     n_m2l = st["n_m2l_unique"] if args.far == "shared" else st["n_m2l"]
     far_flops = (n_m2l * (sfmm.FLOPS["m2l"][p] + 1) + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
                  + args.n * sfmm.FLOPS["l2p"][p])
-    near_flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR
+    near_flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR + st["n_p2p_soft_pairs"] * P2P_FLOPS_SOFT
     work = {"far": far_flops, "near": near_flops}
     dom = max(("far", "near"), key=lambda k: ph_mean[k])
     achieved = work[dom] / (ph_mean[dom] * 1e-3) / 1e12
@@ -228,7 +230,7 @@ def main():
         "phases": per_phase,
         "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l",
                                       "n_m2l_unique", "n_l2l", "n_p2p_leaf_pairs",
-                                      "n_p2p_pairs")},
+                                      "n_p2p_pairs", "n_p2p_soft_pairs")},
         "momentum_residual": mom,
     }
 

@@ -128,6 +128,9 @@ typedef struct {
   double momentum_abs;      /* sum_i |m_i acc_i|                                    */
   int64_t n_m2l_unique;     /* distinct (target node, source node) M2L pairs (level
                                walk; 0 with SFMM_WALK_LEAF)                         */
+  int64_t n_p2p_soft_pairs; /* ordered particle pairs inside a softening kernel
+                               (counted by the default P2P kernel shape of either
+                               precision; 0 for the other shapes)                  */
 } sfmm_stats;
 
 /* Fill *cfg with the defaults listed above.  Returns SFMM_EINVAL if cfg is NULL. */

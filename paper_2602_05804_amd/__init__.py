@@ -59,7 +59,7 @@ class Stats(C.Structure):
                 ("max_depth", C.c_int32), ("n_m2l", C.c_int64), ("n_l2l", C.c_int64),
                 ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("momentum", C.c_double * 3), ("momentum_abs", C.c_double),
-                ("n_m2l_unique", C.c_int64)]
+                ("n_m2l_unique", C.c_int64), ("n_p2p_soft_pairs", C.c_int64)]
 
 
 _lib = None
@@ -226,7 +226,7 @@ class Solver:
                     max_depth=st.max_depth, n_m2l=st.n_m2l, n_l2l=st.n_l2l,
                     n_p2p_leaf_pairs=st.n_p2p_leaf_pairs, n_p2p_pairs=st.n_p2p_pairs,
                     momentum=list(st.momentum), momentum_abs=st.momentum_abs,
-                    n_m2l_unique=st.n_m2l_unique)
+                    n_m2l_unique=st.n_m2l_unique, n_p2p_soft_pairs=st.n_p2p_soft_pairs)
 
     def timing_start(self, max_solves: int):
         """Record HIP events around every phase of the next max_solves solves."""

@@ -250,6 +250,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
     }
     e0 = lo_e;
   }
+  uint32_t nsoft = 0;  // pairs inside a kernel (complete on lane 0)
   for (int t0 = 0; t0 < nt; t0 += TG) {
     double fx[TG], fy[TG], fz[TG], ph[TG];
 #pragma unroll
@@ -313,6 +314,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
           const float rinv3 = rinv * rinv * rinv;
           float gs = rinv3, ps = rinv;
           const bool inside = (r2 * (thi * thi) < 4.0f) || (r2 * hj2inv < 4.0f);
+          nsoft += (uint32_t)__popcll(__ballot(inside && w != 0.f));  // lane 0 is always active
           if (__ballot(inside)) {
             const float r = r2 * rinv;
             float g1, p1, g2, p2;
@@ -343,6 +345,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
       }
     }
   }
+  if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
 constexpr int kFarSplit32 = 2;

@@ -165,7 +165,8 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   }
   __shared__ int qj[Q ? 128 : 1];
   __shared__ int qi[Q ? 128 : 1];
-  uint32_t qn = 0;  // queued softened pairs (the same on every lane)
+  uint32_t qn = 0;     // queued softened pairs (the same on every lane)
+  uint32_t nsoft = 0;  // softened pairs of this item
   for (int t0 = 0; t0 < nt; t0 += NA) {
     double fx[NA], fy[NA], fz[NA], ph[NA];
 #pragma unroll
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
                   __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
               if (push) { qj[qn + below] = j; qi[qn + below] = i; }
               qn += (uint32_t)__popcll(bal);
+              nsoft += (uint32_t)__popcll(bal);
             }
             if (inside) wq = 0.0;
           } else if (__ballot(inside)) {
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
       }
     }
   }
+  if (Q && lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
 // per list entry, the end of its particles in the leaf's flattened sources;

@@ -36,7 +36,7 @@ enum BufId {
   B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
-  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT,
+  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT, B_SOFTCNT,
   B_COUNT
 };
 
@@ -601,7 +601,10 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.include_self = ctx->cfg.include_self_potential;
   a.acc = acc;
   a.pot = pot;
+  if ((rc = ensure(ctx, B_SOFTCNT, sizeof(unsigned long long)))) return rc;
+  a.soft_pairs = P<unsigned long long>(ctx, B_SOFTCNT);
   phase_mark(ctx, 4, 0);
+  HIPCHK(hipMemsetAsync(a.soft_pairs, 0, sizeof(unsigned long long), s));
   // P2P work items: runs of at most kP2PItem flattened source particles of
   // one leaf; their number is read back to size the partial sums
   int64_t items = 0;
@@ -818,6 +821,13 @@ int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
     out->n_p2p_leaf_pairs = (int64_t)ctx->p2p_total;
     out->n_p2p_pairs = (int64_t)ctx->pair_total;
     out->n_m2l_unique = (int64_t)ctx->m2l_unique;
+    unsigned long long soft = 0;
+    if (ctx->buf[B_SOFTCNT].p &&
+        (hipMemcpyAsync(&soft, ctx->buf[B_SOFTCNT].p, sizeof(soft), hipMemcpyDeviceToHost,
+                        ctx->stream) != hipSuccess ||
+         hipStreamSynchronize(ctx->stream) != hipSuccess))
+      return fail(ctx, SFMM_EDEVICE, "statistics copy failed");
+    out->n_p2p_soft_pairs = (int64_t)soft;
   }
   if (ctx->have_mom && ctx->n > 0) {
     double mom[4];

@@ -232,6 +232,7 @@ struct NearArgs {
   const int32_t* item_leaf;  // [items] leaf of each item
   const uint32_t* item_k;    // [items] index of the item within its leaf
   double* part;              // [items][LS][4] partial field (x, y, z) and potential
+  unsigned long long* soft_pairs;  // count of pairs inside a kernel (queueing shape)
 };
 constexpr uint32_t kP2PItem = 2048;
 // per-entry flattened ends (flat) and the number of items of each leaf

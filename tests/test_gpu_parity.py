@@ -473,3 +473,23 @@ def test_p2p_kernel_shapes(torch, P, orc, near_kernel):
     assert pot_err(pot, op) < TOL
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_soft_pair_count(torch, P, precision):
+    """The P2P kernels count the ordered pairs inside a softening kernel; every
+    such pair is a P2P pair (accepted node pairs keep all pairs outside both
+    kernels), so the count is the brute-force one (up to pairs that sit on a
+    kernel edge to rounding)."""
+    print(f"case: softened pair count {precision}", flush=True)
+    x, m, h = workloads.plummer(3000, seed=12)
+    s = P.Solver()
+    xd, md, hd = dev(torch, x, m, h)
+    s.solve(xd, md, hd, precision=precision)
+    torch.cuda.synchronize()
+    got = s.stats()["n_p2p_soft_pairs"]
+    d = x[:, None, :] - x[None, :, :]
+    r2 = (d * d).sum(-1)
+    hm = np.maximum(h[:, None], h[None, :])
+    want = int(((r2 < 4.0 * hm * hm) & ~np.eye(len(m), dtype=bool)).sum())
+    assert abs(got - want) <= max(2, 1e-4 * want), (got, want)
