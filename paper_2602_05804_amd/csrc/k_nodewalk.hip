@@ -49,13 +49,14 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // exclusive prefix over the wave of a small non-negative count (< 8) and the
 // wave total
 __device__ __forceinline__ uint32_t wave_prefix(uint32_t c, uint32_t& total) {
-  const uint64_t lt = lanemask_lt();
   uint32_t pre = 0;
   total = 0;
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     const uint64_t m = __ballot((c >> b) & 1u);
-    pre += (uint32_t)__popcll(m & lt) << b;
+    // set bits of m below this lane
+    pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))
+           << b;
     total += (uint32_t)__popcll(m) << b;
   }
   return pre;
@@ -153,10 +154,10 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
 }
 
 // classification of one tested source against target v
-// returns 0 = M2L, 1 = opened
+// returns 0 = M2L, 1 = opened (no branches: the self pair is selected out)
 __device__ __forceinline__ int classify(const NodeWalkArgs& a, int v, const double* rv, uint32_t s) {
-  if ((int)s == v) return 1;
-  return accept(rv, a.rec + (int64_t)s * a.stride, a.theta2, a.r_kern) ? 0 : 1;
+  const bool acc = accept(rv, a.rec + (int64_t)s * a.stride, a.theta2, a.r_kern);
+  return ((int)s != v && acc) ? 0 : 1;
 }
 
 // the same test for a leaf target, from one evaluation of d^2: 0 = M2L,
@@ -170,7 +171,6 @@ __device__ __forceinline__ int classify(const NodeWalkArgs& a, int v, const doub
 // lowering would make from deciding otherwise
 __device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const double* rv,
                                          uint32_t s) {
-  if ((int)s == v) return 1;
   const double* rs = a.rec + (int64_t)s * a.stride;
   const double dx = rs[0] - rv[0];
   const double dy = rs[1] - rv[1];
@@ -178,11 +178,12 @@ __device__ __forceinline__ int classify3(const NodeWalkArgs& a, int v, const dou
   const double d2 = dx * dx + dy * dy + dz * dz;
   const double lsum = rv[3] + rs[3];
   const double rsum = lsum + a.r_kern * fmax(rv[4], rs[4]);
-  if (!(d2 >= rsum * rsum)) {
-    const double reach = rv[3] + a.r_kern * rv[4] - rs[3];
-    return (reach > 0.0 && d2 < reach * reach * (1.0 - 1e-9)) ? 3 : 1;
-  }
-  return (lsum * lsum < a.theta2 * d2) ? 0 : 2;
+  const double reach = rv[3] + a.r_kern * rv[4] - rs[3];
+  const bool beyond = d2 >= rsum * rsum;
+  const bool whole = reach > 0.0 && d2 < reach * reach * (1.0 - 1e-9);
+  const bool mac = lsum * lsum < a.theta2 * d2;
+  const int k = beyond ? (mac ? 0 : 2) : (whole ? 3 : 1);
+  return (int)s == v ? 1 : k;  // selects, no branches
 }
 
 // internal target: the tested sources, 64 * kWalkBatch at a time; every
@@ -203,23 +204,30 @@ __device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, co
       const uint32_t i = base + 64u * u + lane;
       sb[u] = i < nsrc ? src[i] : 0xffffffffu;
     }
+    // invalid slots read node v (a valid index) and are masked afterwards,
+    // so the loads and tests need no branches
     int cb[kWalkBatch];
 #pragma unroll
-    for (int u = 0; u < kWalkBatch; ++u) cb[u] = sb[u] != 0xffffffffu ? a.info[sb[u]].child : 0;
+    for (int u = 0; u < kWalkBatch; ++u) {
+      const bool ok = sb[u] != 0xffffffffu;
+      cb[u] = a.info[ok ? sb[u] : (uint32_t)v].child;
+      if (!ok) cb[u] = -2;
+    }
     uint32_t selm[kWalkBatch], selo[kWalkBatch], nm[kWalkBatch], no[kWalkBatch];
     uint32_t t0[kWalkBatch], t1[kWalkBatch];
 #pragma unroll
     for (int u = 0; u < kWalkBatch; ++u) {
-      selm[u] = selo[u] = nm[u] = no[u] = 0;
-      t0[u] = t1[u] = 0;
-      if (sb[u] == 0xffffffffu) continue;
-      int nt;
-      if (cb[u] < 0) { t0[u] = sb[u]; nt = 1; }
-      else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt = 2; }
-      if (classify(a, v, rv, t0[u]) == 0) { selm[u] |= 1u; ++nm[u]; } else { selo[u] |= 1u; ++no[u]; }
-      if (nt >= 2) {
-        if (classify(a, v, rv, t1[u]) == 0) { selm[u] |= 2u; ++nm[u]; } else { selo[u] |= 2u; ++no[u]; }
-      }
+      const bool ok = cb[u] != -2;
+      const bool two = cb[u] >= 0;
+      t0[u] = two ? (uint32_t)cb[u] : (ok ? sb[u] : (uint32_t)v);
+      t1[u] = two ? (uint32_t)cb[u] + 1u : (uint32_t)v;
+      const bool m0 = classify(a, v, rv, t0[u]) == 0;
+      const bool m1 = classify(a, v, rv, t1[u]) == 0;
+      const uint32_t v0 = ok ? 1u : 0u, v1 = two ? 1u : 0u;
+      selm[u] = (m0 ? v0 : 0u) | ((m1 ? v1 : 0u) << 1);
+      selo[u] = (m0 ? 0u : v0) | ((m1 ? 0u : v1) << 1);
+      nm[u] = (m0 ? v0 : 0u) + (m1 ? v1 : 0u);
+      no[u] = (m0 ? 0u : v0) + (m1 ? 0u : v1);
     }
 #pragma unroll
     for (int u = 0; u < kWalkBatch; ++u) {
@@ -245,10 +253,12 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
   for (int u = 0; u < U; ++u) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const uint32_t t = q ? t1[u] : t0[u];
       const bool valid = q < nt[u];
-      kk[u][q] = valid ? classify3(a, v, rv, t) : -1;
-      cc[u][q] = valid ? a.info[t].child : 0;
+      const uint32_t t = valid ? (q ? t1[u] : t0[u]) : (uint32_t)v;  // a valid index
+      const int k = classify3(a, v, rv, t);
+      const int c = a.info[t].child;
+      kk[u][q] = valid ? k : -1;
+      cc[u][q] = valid ? c : 0;
     }
   }
   bool ok = true;
