@@ -426,10 +426,24 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
 // One block.
 constexpr int SCAN_T = 1024;
 constexpr int SCAN_I = 4;
+constexpr int SCAN_W = SCAN_T / 64;
+
+__device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// in-wave shuffle scans, then one step across the block's 16 waves
 __global__ __launch_bounds__(SCAN_T) void k_nodewalk_scan(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
-  __shared__ uint32_t sm[SCAN_T], so[SCAN_T], sp[SCAN_T];
+  __shared__ uint32_t wt[3][SCAN_W];
   __shared__ uint32_t carry[3];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x < 3) carry[threadIdx.x] = a.run[threadIdx.x];
   __syncthreads();
   for (uint32_t base = beg; base < end; base += SCAN_T * SCAN_I) {
@@ -443,20 +457,11 @@ __global__ __launch_bounds__(SCAN_T) void k_nodewalk_scan(NodeWalkArgs a, int le
       cm += (uint32_t)v[q];
       if (v[q] >> 63) cp += b; else co += b;
     }
-    sm[threadIdx.x] = cm; so[threadIdx.x] = co; sp[threadIdx.x] = cp;
+    const uint32_t im = wave_incl_u32(cm), io = wave_incl_u32(co), ip = wave_incl_u32(cp);
+    if (lane == 63) { wt[0][w] = im; wt[1][w] = io; wt[2][w] = ip; }
     __syncthreads();
-    for (int off = 1; off < SCAN_T; off <<= 1) {
-      uint32_t xm = 0, xo = 0, xp = 0;
-      if ((int)threadIdx.x >= off) {
-        xm = sm[threadIdx.x - off]; xo = so[threadIdx.x - off]; xp = sp[threadIdx.x - off];
-      }
-      __syncthreads();
-      sm[threadIdx.x] += xm; so[threadIdx.x] += xo; sp[threadIdx.x] += xp;
-      __syncthreads();
-    }
-    uint32_t rm = carry[0] + sm[threadIdx.x] - cm;
-    uint32_t ro = carry[1] + so[threadIdx.x] - co;
-    uint32_t rp = carry[2] + sp[threadIdx.x] - cp;
+    uint32_t rm = carry[0] + im - cm, ro = carry[1] + io - co, rp = carry[2] + ip - cp;
+    for (int k = 0; k < w; ++k) { rm += wt[0][k]; ro += wt[1][k]; rp += wt[2][k]; }
 #pragma unroll
     for (int q = 0; q < SCAN_I; ++q) {
       const uint32_t i = base + threadIdx.x * SCAN_I + q;
@@ -467,10 +472,10 @@ __global__ __launch_bounds__(SCAN_T) void k_nodewalk_scan(NodeWalkArgs a, int le
       if (leaf) rp += b; else ro += b;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      carry[0] += sm[SCAN_T - 1];
-      carry[1] += so[SCAN_T - 1];
-      carry[2] += sp[SCAN_T - 1];
+    if (threadIdx.x < 3) {
+      uint32_t t = 0;
+      for (int k = 0; k < SCAN_W; ++k) t += wt[threadIdx.x][k];
+      carry[threadIdx.x] += t;
     }
     __syncthreads();
   }
