@@ -23,7 +23,11 @@
 // one-block scan that places every node's lists after those of the nodes
 // before it (running pool totals stay on the device), and a fill pass that
 // repeats the tests and writes in lane order.  The layout of the pools is
-// therefore the same on every run.
+// therefore the same on every run.  An internal node's M2L and opened lists
+// together are its tested list, whose size its parent records while walking
+// (opened leaves once, opened internal nodes twice), so internal nodes skip
+// the count pass: one region of the M2L pool holds both lists, M2L entries
+// from the front and opened entries from the back.
 #include "sfmm_internal.h"
 
 namespace sfmm {
@@ -89,6 +93,10 @@ struct Emit {
   // pairs beyond both kernels (plain_run of them so far) from the back of
   // the leaf's p2p_total entries
   uint32_t plain_run, p2p_total;
+  // internal node: opened entries go backwards from open_base - 1 (the end
+  // of its region); exp_lane sums this lane's opened entries, an internal
+  // one counted twice
+  uint32_t exp_lane;
 };
 
 template <bool WRITE>
@@ -109,9 +117,17 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
       if (sel_o & 1u) { if (q < a.p2p_cap) a.p2p_pool[q] = s0; ++q; }
       if (sel_o & 2u) { if (q < a.p2p_cap) a.p2p_pool[q] = s1; }
     } else {
-      uint32_t q = e.open_base + e.open_run + po;
-      if (sel_o & 1u) { if (q < a.open_cap) a.open_pool[q] = s0; ++q; }
-      if (sel_o & 2u) { if (q < a.open_cap) a.open_pool[q] = s1; }
+      // rank from the end of the node's region
+      uint32_t r = e.open_run + po;
+      if (sel_o & 1u) {
+        const uint32_t q = e.open_base - 1u - r;
+        if (q < a.open_cap) a.open_pool[q] = s0;
+        ++r;
+      }
+      if (sel_o & 2u) {
+        const uint32_t q = e.open_base - 1u - r;
+        if (q < a.open_cap) a.open_pool[q] = s1;
+      }
     }
   }
   e.m2l_run += tm;
@@ -228,6 +244,10 @@ __device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, co
       selo[u] = (m0 ? 0u : v0) | ((m1 ? 0u : v1) << 1);
       nm[u] = (m0 ? v0 : 0u) + (m1 ? v1 : 0u);
       no[u] = (m0 ? 0u : v0) + (m1 ? 0u : v1);
+      // the children's tested list: an opened leaf once, an internal node twice
+      const uint32_t x0 = a.info[t0[u]].child >= 0 ? 2u : 1u;
+      const uint32_t x1 = a.info[t1[u]].child >= 0 ? 2u : 1u;
+      e.exp_lane += ((selo[u] & 1u) ? x0 : 0u) + ((selo[u] & 2u) ? x1 : 0u);
     }
 #pragma unroll
     for (int u = 0; u < kWalkBatch; ++u) {
@@ -367,6 +387,16 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
     }
     return;
   }
+  // internal node: its region (M2L + opened = its tested list) has a size
+  // known without walking it, so it has no count pass
+  const uint32_t region = root ? 1u : (vi.child >= 0 ? a.exp[vi.parent] : 0u);
+  if (!FILL && vi.child >= 0) {
+    if (lane == 0) {
+      a.lvl_cnt[idx] = (uint64_t)region;  // bit 63 clear: internal
+      a.p2p_cnt[v] = 0;
+    }
+    return;
+  }
   const uint32_t* src = nullptr;
   uint32_t nsrc = 0;
   if (!root) {
@@ -377,15 +407,14 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
   }
   Emit e{};
   if (FILL) {
-    // absolute pool offsets from the level scan: low word M2L, high word
-    // the opened (internal node) or P2P (leaf) list
+    // absolute pool offsets from the level scan: low word M2L (for an
+    // internal node its whole region), high word the P2P list of a leaf
     const uint64_t off = a.lvl_off[idx];
     e.m2l_base = (uint32_t)off;
     const uint32_t hi = (uint32_t)(off >> 32);
     if (lane == 0) a.m2l_off[v] = e.m2l_base;
     if (vi.child >= 0) {
-      e.open_base = hi;
-      if (lane == 0) a.open_off[v] = e.open_base;
+      e.open_base = e.m2l_base + region;
     } else {
       e.p2p_base = hi;
       e.p2p_total = a.p2p_cnt[v];  // from the count pass
@@ -396,16 +425,23 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
     if (root) {
       // (root, root) is opened: both root children meet both root children
       if (lane == 0) {
-        if (FILL) { if (e.open_base < a.open_cap) a.open_pool[e.open_base] = (uint32_t)v; }
-        else { a.m2l_cnt[v] = 0; a.open_cnt[v] = 1; a.lvl_cnt[idx] = 1ull << 32; }
+        if (e.m2l_base < a.open_cap) a.open_pool[e.m2l_base] = (uint32_t)v;
+        a.m2l_cnt[v] = 0;
+        a.open_cnt[v] = 1;
+        a.open_off[v] = e.m2l_base;
+        a.exp[v] = 2;
       }
       return;
     }
-    walk_internal<FILL>(a, v, rv, src, nsrc, e);
-    if (!FILL && lane == 0) {
+    walk_internal<true>(a, v, rv, src, nsrc, e);
+    uint32_t ex = e.exp_lane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ex += (uint32_t)__shfl_xor((int)ex, o, 64);
+    if (lane == 0) {
       a.m2l_cnt[v] = e.m2l_run;
       a.open_cnt[v] = e.open_run;
-      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)e.open_run << 32);  // bit 63 clear: internal
+      a.open_off[v] = e.open_base - e.open_run;
+      a.exp[v] = ex;
     }
   } else {
     walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
@@ -420,8 +456,9 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
 }
 
 // Places one level's lists: a scan, in level order, of the packed counts
-// (bits 0-31 M2L, 32-62 the opened list of an internal node or the P2P
-// list of a leaf, bit 63 set for a leaf) into absolute pool offsets, after
+// (bits 0-31 the M2L pool region: a leaf's M2L list, an internal node's
+// M2L + opened lists; bits 32-62 the P2P list of a leaf, 0 for an internal
+// node; bit 63 set for a leaf) into absolute pool offsets, after
 // everything placed by earlier levels; then the running pool sizes advance.
 // One block.
 constexpr int SCAN_T = 1024;
@@ -506,7 +543,25 @@ __global__ void k_leaf_stats(LeafStatArgs a) {
   a.pairs[l] = src * (uint64_t)li.cnt - (uint64_t)li.cnt;
 }
 
+// out[0] += sum of x[0..n)
+__global__ __launch_bounds__(256) void k_sum_u32(int n, const uint32_t* __restrict__ x,
+                                                 uint32_t* out) {
+  __shared__ uint32_t ws[4];
+  uint32_t t = 0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) t += x[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) t += (uint32_t)__shfl_xor((int)t, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, ws[0] + ws[1] + ws[2] + ws[3]);
+}
+
 }  // namespace
+
+void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  k_sum_u32<<<std::min(512, (n + 255) / 256), 256, 0, s>>>(n, x, out);
+}
 
 void launch_leaf_stats(const LeafStatArgs& a, hipStream_t s) {
   if (a.nleaves <= 0) return;

@@ -33,7 +33,7 @@ enum BufId {
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
   B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
-  B_M2LPOOL, B_OPENPOOL, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
+  B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT, B_SOFTCNT,
@@ -66,7 +66,7 @@ struct sfmm_ctx {
   hipEvent_t order_ev = nullptr;  // orders work across a stream change
   // level walk: nodes per depth (host copy) and pool capacities
   std::vector<uint32_t> level_off;
-  uint64_t m2l_cap = 0, open_cap = 0, p2p_cap = 0;
+  uint64_t m2l_cap = 0, p2p_cap = 0;
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
@@ -408,7 +408,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   const int nn = (int)ctx->nn, nl = (int)ctx->nleaves;
   uint64_t* small = P<uint64_t>(ctx, B_SMALL);
   int* status = P<int>(ctx, B_STATUS);
-  const int node_arrays[] = {B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT};
+  const int node_arrays[] = {B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
+                             B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
@@ -417,17 +418,16 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
-  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 48ull * nn + 1024);
-  ctx->open_cap = std::max<uint64_t>(ctx->open_cap, 48ull * nn + 1024);
+  // (the M2L pool also holds the opened lists of internal nodes)
+  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + 2048);
   ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + 1024);
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
   const uint64_t kPoolMax = 0xF0000000ull;
   for (int attempt = 0;; ++attempt) {
-    if (ctx->m2l_cap > kPoolMax || ctx->open_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
+    if (ctx->m2l_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
       return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed 2^32 entries");
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
-    if ((rc = ensure(ctx, B_OPENPOOL, sizeof(uint32_t) * ctx->open_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint32_t* tot = P<uint32_t>(ctx, B_WALKTOT);
     HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 4, s));
@@ -448,10 +448,11 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.p2p_off = P<uint32_t>(ctx, B_NP2POFF);
     a.p2p_cnt = P<uint32_t>(ctx, B_NP2PCNT);
     a.m2l_pool = P<uint32_t>(ctx, B_M2LPOOL);
-    a.open_pool = P<uint32_t>(ctx, B_OPENPOOL);
+    a.open_pool = a.m2l_pool;
+    a.exp = P<uint32_t>(ctx, B_NEXP);
     a.p2p_pool = P<uint32_t>(ctx, B_P2PPOOL);
     a.m2l_cap = (uint32_t)ctx->m2l_cap;
-    a.open_cap = (uint32_t)ctx->open_cap;
+    a.open_cap = a.m2l_cap;
     a.p2p_cap = (uint32_t)ctx->p2p_cap;
     a.lvl_cnt = P<uint64_t>(ctx, B_LVLCNT);
     a.lvl_off = P<uint64_t>(ctx, B_LVLOFF);
@@ -460,17 +461,18 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.status = status;
     for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_off[k + 1] - ctx->level_off[k]), s);
+    // M2L entries proper (the pool also holds the opened lists)
+    launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
     uint32_t htot[4];
     int hstatus[4];
     HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const bool pool_over = htot[0] > ctx->m2l_cap || htot[1] > ctx->open_cap ||
-                           htot[2] > ctx->p2p_cap;
+    const bool pool_over = htot[0] > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
       ctx->p2p_total = htot[2];
-      ctx->m2l_unique = htot[0];
+      ctx->m2l_unique = htot[1];
       return SFMM_OK;
     }
     if (attempt >= 8) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
@@ -481,7 +483,6 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
       ctx->m2l_cap = grow(ctx->m2l_cap, htot[0]);
-      ctx->open_cap = grow(ctx->open_cap, htot[1]);
       ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
     }
     if (stack_over) {

@@ -140,13 +140,18 @@ struct NodeWalkArgs {
   const int32_t* level_nodes;  // nodes grouped by depth
   const uint8_t* node_flag;    // 0 spans systems (skipped), 1 walk root, 2 other
   const uint32_t* level_off;   // [levels + 1]
-  // per node (node-indexed): M2L list, opened list (internal), P2P list (leaf)
+  // per node (node-indexed): M2L list, opened list (internal), P2P list (leaf).
+  // An internal node's M2L and opened lists share one region of the M2L pool
+  // (M2L from the front, opened from the back); its size, the node's tested
+  // list, is known before the node is walked: exp[parent], the parent's
+  // opened sources with internal ones counted twice (their two children).
   uint32_t *m2l_off, *m2l_cnt, *open_off, *open_cnt, *p2p_off, *p2p_cnt;
-  uint32_t *m2l_pool, *open_pool, *p2p_pool;
+  uint32_t *m2l_pool, *open_pool, *p2p_pool;  // open_pool: the M2L pool
   uint32_t m2l_cap, open_cap, p2p_cap;
-  uint64_t* lvl_cnt;  // [nn] packed counts in level order (low: M2L, high: opened/P2P)
+  uint32_t* exp;  // per internal node: tested-list size of each of its children
+  uint64_t* lvl_cnt;  // [nn] packed counts in level order (low: M2L pool region, high: P2P)
   uint64_t* lvl_off;  // [nn] their exclusive scan within the level
-  uint32_t* run;      // [3] running pool sizes: M2L, opened, P2P
+  uint32_t* run;      // [3] running pool sizes: M2L (with opened lists), unused, P2P
   uint32_t stack_cap;  // LDS lowering stack, entries
   int* status;
 };
@@ -157,6 +162,8 @@ void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* k
 // read from the scanned radix histogram (digit-major, nb blocks)
 void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
                           uint32_t* level_off, hipStream_t s);
+// out[0] += sum of x[0..n) (out on the device)
+void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
 
 // per-leaf statistics of node lists: replicated M2L count, L2L count, pairs
