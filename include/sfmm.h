@@ -101,16 +101,23 @@ typedef struct {
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
   int far_mode;               /* sfmm_far_mode (SFMM_FAR_SHARED)                      */
   int far_kernel;             /* far-field kernel shape, 0..4 (0)                    */
-  int near_kernel;            /* P2P kernel shape, 0..5 (0)                          */
+  int near_kernel;            /* P2P kernel shape, 0..11 (0)                         */
 } sfmm_config;
 /* Kernel shapes (same results up to summation order; picked by the autotuner):
  * far_kernel, SFMM_FAR_SHARED: lanes per node 8 (0; a two-wave register budget
  *   in FP64), 4 (1), 16 (2), 8 with one wave (3), 8 with two waves (4);
  *   SFMM_FAR_LEAF: lanes per leaf 4 (0), 4 with two waves (1), 2 (2), 1 (3).
- * near_kernel (leaf_size <= 16): targets of a leaf in unrolled passes of 5
- *   with the pairs inside a kernel queued and evaluated 64 at a time (0), one
- *   thread per particle (1), passes of 10 (2), one pass with a run-time
- *   target loop (3), passes of 4 (4), passes of 5 without the queue (5). */
+ * near_kernel, leaf_size <= 10: a wave per work item with the targets in
+ *   scalar registers, wave-uniform loop control and the pairs inside a kernel
+ *   queued and evaluated 64 at a time, in passes of 5 targets at four waves
+ *   per SIMD (0), 8 at three (7), 10 at two (8), 5 at three (9), 5 at five
+ *   (10), 8 at four (11); one thread per particle (1); the earlier
+ *   wave-per-item kernel with targets in LDS: passes of 10 (2), one pass with
+ *   a run-time target loop (3), passes of 4 (4), passes of 5 without the
+ *   queue (5), passes of 5 with the queue (6).
+ * near_kernel, leaf_size <= 16: scalar-register targets in passes of 8 (0),
+ *   6 (7), 16 (8); one thread per particle (1); targets in LDS, passes of 8
+ *   without (5) and with (6) the queue. */
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
 typedef struct {

@@ -16,6 +16,9 @@
 #include "sfmm_internal.h"
 #include "softening.h"
 
+#include <type_traits>
+#include <utility>
+
 namespace sfmm {
 namespace {
 
@@ -108,6 +111,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{})
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
 // TG == 0: one pass over the sources for all targets, the loop over the
@@ -299,6 +312,212 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   if (Q && lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
+// Wave per item, targets held in scalar registers.  The same sums as
+// k_p2p_leaf with less work per pair: the loop control is wave-uniform
+// (scalar), the targets of a pass are wave-uniform values, a pair is inside
+// a kernel when r^2 < max(4 h_i^2, 4 h_j^2), and the field of a pair beyond
+// both kernels is m/r^3 (dx, dy, dz) and m/r, with the refined 1/r replaced
+// by 0 for pairs inside a kernel (the self pair and coincident particles
+// included: r^2 = 0 is always inside).  Pairs inside a kernel, other than
+// the self pair, go to a queue per target in LDS and are evaluated 64 at a
+// time, each batch for one target (so its data stay wave-uniform), after
+// each group of 64 sources has met the pass's targets.  A leaf's targets
+// are taken in passes of TG and one pass of the remainder, each with a fixed
+// target count (no per-target exits inside the unrolled loop).
+struct WaveItem {
+  int tlo, nt;
+  uint64_t e0, e1;
+  const int32_t* list;
+  uint32_t f_lo, f_hi;
+  int64_t item;
+};
+
+constexpr uint32_t kTQ = 128;  // queue slots per target
+
+template <int K, int LS>
+__device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem& w, int t0,
+                                              int* q, uint32_t& nsoft) {
+  const int lane = threadIdx.x;
+  const int tlo = w.tlo;
+  double tx[K], ty[K], tz[K], t4[K];
+  double fx[K], fy[K], fz[K], ph[K];
+  uint32_t qh[K], qn[K];  // per-target ring queue head and length (wave-uniform)
+#pragma unroll
+  for (int ii = 0; ii < K; ++ii) {
+    const int it = tlo + t0 + ii;
+    tx[ii] = wave_uniform(a.xs[it]);
+    ty[ii] = wave_uniform(a.ys[it]);
+    tz[ii] = wave_uniform(a.zs[it]);
+    const double hu = wave_uniform(a.hs[it]);
+    t4[ii] = 4.0 * hu * hu;
+    fx[ii] = 0.0; fy[ii] = 0.0; fz[ii] = 0.0; ph[ii] = 0.0;
+    qh[ii] = 0; qn[ii] = 0;
+  }
+  // the first `count` queued sources of target ii, one per lane
+  auto flush = [&](auto iic, uint32_t count) {
+    constexpr int ii = decltype(iic)::value;
+    __syncthreads();
+    const bool act = (uint32_t)lane < count;
+    uint32_t slot = qh[ii] + (uint32_t)lane;
+    if (slot >= kTQ) slot -= kTQ;
+    const int j2 = act ? q[ii * kTQ + slot] : tlo;
+    const int it = tlo + t0 + ii;  // wave-uniform
+    const double hi = wave_uniform(a.hs[it]), hiinv = wave_uniform(a.his[it]);
+    const double dx = tx[ii] - a.xs[j2], dy = ty[ii] - a.ys[j2], dz = tz[ii] - a.zs[j2];
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double rinv = rsqrt_pair(r2);
+    const double rinv3 = rinv * rinv * rinv;
+    const double r = r2 * rinv;
+    const double hj = a.hs[j2], hjinv = a.his[j2];
+    double g1, p1, g2, p2;
+    soft_sel(r * hiinv, hiinv, hi * rinv, rinv, rinv3, g1, p1);
+    soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
+    const double wm = act ? a.ms[j2] : 0.0;
+    const double mg = wm * (0.5 * (g1 + g2));
+    fx[ii] = fma(mg, dx, fx[ii]);
+    fy[ii] = fma(mg, dy, fy[ii]);
+    fz[ii] = fma(mg, dz, fz[ii]);
+    ph[ii] = fma(wm, 0.5 * (p1 + p2), ph[ii]);
+    qh[ii] += count;
+    if (qh[ii] >= kTQ) qh[ii] -= kTQ;
+    qn[ii] -= count;
+  };
+  for (uint64_t c0 = w.e0; c0 < w.e1; c0 += 64) {
+    // 64 list entries: their particle ranges clipped to the run, flattened
+    // by a prefix scan
+    int cnt = 0, lo = 0;
+    uint32_t fb = 0xffffffffu;
+    if (c0 + lane < w.e1) {
+      const NodeInfo si = a.info[w.list[c0 + lane]];
+      const uint32_t fe = a.flat[c0 + lane];
+      fb = fe - (uint32_t)si.cnt;
+      const uint32_t b = fb > w.f_lo ? fb : w.f_lo;
+      const uint32_t en = fe < w.f_hi ? fe : w.f_hi;
+      if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
+    }
+    // lane 0 always holds an entry (c0 < e1)
+    if ((uint32_t)__builtin_amdgcn_readfirstlane(fb) >= w.f_hi) break;  // the run is done
+    const int incl = wave_incl_scan(cnt);
+    const int pre = incl - cnt;
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    for (int f0 = 0; f0 < total; f0 += 64) {
+      const int f = f0 + lane;
+      // owner lane k: the last lane with pre <= f (binary search over lanes)
+      int k = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int pk = __shfl(pre, k + step, 64);
+        if (pk <= f) k += step;
+      }
+      const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+      const bool fv = f < total;
+      const int j = fv ? jj : tlo;  // a valid index; contributes nothing
+      const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j];
+      const double mj = fv ? a.ms[j] : 0.0;
+      const double hj = a.hs[j];
+      const double h4j = 4.0 * hj * hj;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        const double dx = tx[ii] - xj, dy = ty[ii] - yj, dz = tz[ii] - zj;
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const bool inside = r2 < fmax(t4[ii], h4j);
+        const double rinv = inside ? 0.0 : rsqrt_refined(r2);
+        const double mr = mj * rinv;
+        const double mg = mr * (rinv * rinv);
+        fx[ii] = fma(mg, dx, fx[ii]);
+        fy[ii] = fma(mg, dy, fy[ii]);
+        fz[ii] = fma(mg, dz, fz[ii]);
+        ph[ii] += mr;
+        // (an empty statement that reads the sums: keeps this target's
+        // arithmetic ahead of the queue branch below, so that the compiler
+        // does not move it past the branches of the later targets and hold
+        // every target's separation vector at once)
+        asm volatile("" ::"v"(fx[ii]), "v"(fy[ii]), "v"(fz[ii]), "v"(ph[ii]));
+        const bool push = inside && fv && j != tlo + t0 + ii;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
+        if (bal) {
+          if (push) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            uint32_t sl = qh[ii] + qn[ii] + below;
+            if (sl >= kTQ) sl -= kTQ;
+            q[ii * kTQ + sl] = j;
+          }
+          const uint32_t c = (uint32_t)__popcll(bal);
+          qn[ii] += c;
+          nsoft += c;
+        }
+      }
+      // a queue holds at most 63 + 64 entries here
+      static_for<K>([&](auto iic) {
+        constexpr int ii = decltype(iic)::value;
+        if (qn[ii] >= 64) flush(iic, 64);
+      });
+    }
+  }
+  static_for<K>([&](auto iic) {
+    constexpr int ii = decltype(iic)::value;
+    if (qn[ii] > 0) flush(iic, qn[ii]);
+  });
+#pragma unroll
+  for (int ii = 0; ii < K; ++ii) {
+    const double sx = wave_sum(fx[ii]), sy = wave_sum(fy[ii]), sz = wave_sum(fz[ii]);
+    const double sp = wave_sum(ph[ii]);
+    if (lane == t0 + ii) {
+      double* o = a.part + (w.item * LS + t0 + ii) * 4;
+      o[0] = sx; o[1] = sy; o[2] = sz; o[3] = sp;
+    }
+  }
+}
+
+template <int LS, bool NODE, int TG, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_p2p_wave(
+    NearArgs a) {
+  const int lane = threadIdx.x;
+  const uint32_t item = blockIdx.x;
+  if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
+  const int l = a.item_leaf[item];
+  const uint32_t kitem = a.item_k[item];
+  const int node = a.leaf_node[l];
+  const NodeInfo ti = a.info[node];
+  WaveItem w;
+  w.tlo = ti.lo;
+  w.nt = ti.cnt;
+  w.item = item;
+  if (NODE) {
+    w.e0 = a.node_p2p_off[node];
+    w.e1 = w.e0 + a.node_p2p_cnt[node];
+    w.list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    w.e0 = a.p2p_off[l];
+    w.e1 = a.p2p_off[l + 1];
+    w.list = a.p2p_list;
+  }
+  // this item's run [f_lo, f_hi) of the leaf's flattened sources, and the
+  // first list entry that reaches into it
+  w.f_lo = kitem * kP2PItem;
+  const uint32_t ftot = a.flat[w.e1 - 1];
+  w.f_hi = w.f_lo + kP2PItem < ftot ? w.f_lo + kP2PItem : ftot;
+  if (kitem > 0) {
+    uint64_t lo_e = w.e0, hi_e = w.e1 - 1;  // flat[e1 - 1] = ftot > f_lo
+    while (lo_e < hi_e) {
+      const uint64_t mid = (lo_e + hi_e) >> 1;
+      if (a.flat[mid] > w.f_lo) hi_e = mid; else lo_e = mid + 1;
+    }
+    w.e0 = lo_e;
+  }
+  __shared__ int q[TG * kTQ];
+  uint32_t nsoft = 0;
+  int t0 = 0;
+  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave_pass<TG, LS>(a, w, t0, q, nsoft);
+  // the remainder, a pass with a fixed target count (uniform branches)
+  static_for<TG>([&](auto rc) {
+    constexpr int r = decltype(rc)::value;
+    if (r > 0 && w.nt - t0 == r) p2p_wave_pass<(r > 0 ? r : 1), LS>(a, w, t0, q, nsoft);
+  });
+  if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
+}
+
 // per list entry, the end of its particles in the leaf's flattened sources;
 // items per leaf: max(1, ceil(sources / kP2PItem)).  One wave per leaf.
 template <bool NODE>
@@ -349,9 +568,10 @@ __global__ void k_p2p_reduce(NearArgs a, int ls) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= a.n) return;
   const int l = a.p_leaf[j];
+  const uint32_t t0 = a.item_off[l], t1 = a.item_off[l + 1];
   const int i = j - a.info[a.leaf_node[l]].lo;
   double sx = 0.0, sy = 0.0, sz = 0.0, sp = 0.0;
-  for (uint32_t t = a.item_off[l]; t < a.item_off[l + 1]; ++t) {
+  for (uint32_t t = t0; t < t1; ++t) {
     const double* q = a.part + ((int64_t)t * ls + i) * 4;
     sx += q[0]; sy += q[1]; sz += q[2]; sp += q[3];
   }
@@ -407,6 +627,13 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
+#define WAVE_LAUNCH(LS, TG, WPE)                                          \
+  do {                                                                    \
+    if (node_lists) k_p2p_wave<LS, true, TG, WPE><<<nbl, 64, 0, s>>>(a);  \
+    else k_p2p_wave<LS, false, TG, WPE><<<nbl, 64, 0, s>>>(a);            \
+    launch_p2p_reduce(a, LS, s);                                    \
+  } while (0)
+
 #define NEAR_LAUNCH(LS, TG, QU)                                            \
   do {                                                                    \
     if (node_lists) k_p2p_leaf<LS, true, TG, QU><<<nbl, 64, 0, s>>>(a);   \
@@ -437,19 +664,29 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   if (a.n <= 0) return;
   const unsigned nbl = (unsigned)items;
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
-  // variant: targets per pass 5 with the softened pairs queued (default),
-  // 10 (2), 4 (4), a run-time loop over all targets (3), 5 without the queue (5)
+  // variant (the shapes are listed with sfmm_config.near_kernel)
   if (leaf_size <= 10) {
     switch (variant) {
       case 2: NEAR_LAUNCH(10, 10, false); break;
       case 3: NEAR_LAUNCH(10, 0, false); break;
       case 4: NEAR_LAUNCH(10, 4, false); break;
       case 5: NEAR_LAUNCH(10, 5, false); break;
-      default: NEAR_LAUNCH(10, 5, true); break;
+      case 6: NEAR_LAUNCH(10, 5, true); break;
+      case 7: WAVE_LAUNCH(10, 8, 3); break;
+      case 8: WAVE_LAUNCH(10, 10, 2); break;
+      case 9: WAVE_LAUNCH(10, 5, 3); break;
+      case 10: WAVE_LAUNCH(10, 5, 5); break;
+      case 11: WAVE_LAUNCH(10, 8, 4); break;
+      default: WAVE_LAUNCH(10, 5, 4); break;
     }
   } else if (leaf_size <= 16) {
-    if (variant == 5) NEAR_LAUNCH(16, 8, false);
-    else NEAR_LAUNCH(16, 8, true);
+    switch (variant) {
+      case 5: NEAR_LAUNCH(16, 8, false); break;
+      case 6: NEAR_LAUNCH(16, 8, true); break;
+      case 7: WAVE_LAUNCH(16, 6, 4); break;
+      case 8: WAVE_LAUNCH(16, 16, 2); break;
+      default: WAVE_LAUNCH(16, 8, 3); break;
+    }
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);

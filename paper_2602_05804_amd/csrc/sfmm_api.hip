@@ -683,7 +683,7 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
       (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED) || c.far_kernel < 0 ||
-      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 5)
+      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 11)
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {

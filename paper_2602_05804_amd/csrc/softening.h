@@ -23,6 +23,23 @@ __device__ __forceinline__ double rsqrt_pair(double r2) {
   return r2 > 0.0 ? r : 0.0;
 }
 
+// the same refined 1/sqrt(r2) for r2 > 0 only (r2 == 0 gives NaN): for a
+// caller that replaces the value of every pair inside a kernel anyway
+__device__ __forceinline__ double rsqrt_refined(double r2) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double e = fma(-r2 * y, y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+// a wave-uniform double read from the first active lane (kept in scalar
+// registers by the compiler)
+__device__ __forceinline__ double wave_uniform(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __device__ __forceinline__ void soft(double r, double hinv, double& g, double& psi) {
   const double q = r * hinv;
   const double h3 = hinv * hinv * hinv;

@@ -15,8 +15,8 @@ class _T:
 
 
 def _cost(cfg):
-    # separable bowl: best at leaf 12, near kernel 4, far kernel 2, top depth 12
-    c = abs(cfg["leaf_size"] - 12) + abs(cfg["near_kernel"] - 4) * 0.5
+    # separable bowl: best at leaf 12, near kernel 7, far kernel 2, top depth 12
+    c = abs(cfg["leaf_size"] - 12) + abs(cfg["near_kernel"] - 7) * 0.5
     c += 0.0 if cfg["far_kernel"] == 2 else 1.0
     c += abs(cfg.get("fp64_top_depth", 12) - 12) * 0.1
     return 1.0 + c
@@ -27,11 +27,12 @@ def test_search_finds_separable_minimum(monkeypatch):
     monkeypatch.setattr(autotune, "time_config",
                         lambda x, m, h, cfg, *a, **k: calls.append(dict(cfg)) or _cost(cfg))
     res = autotune.search(None, _T(1000), None, precision="fp32c")
-    assert res["config"] == {"leaf_size": 12, "near_kernel": 4, "far_kernel": 2,
+    assert res["config"] == {"leaf_size": 12, "near_kernel": 7, "far_kernel": 2,
                              "fp64_top_depth": 12}
     assert res["seconds"] == 1.0
     # a coordinate search: one run per value per axis, not the full product
-    assert len(calls) == 1 + 4 + 4 + 3 + 2
+    assert len(calls) == (1 + (len(autotune.LEAF_SIZES) - 1) + (len(autotune.NEAR_KERNELS) - 1)
+                          + (len(autotune.FAR_KERNELS_SHARED) - 1) + (len(autotune.TOP_DEPTHS) - 1))
 
 
 def test_cache_roundtrip(monkeypatch, tmp_path):

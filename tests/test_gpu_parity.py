@@ -460,30 +460,32 @@ def test_direct_sum_parity(torch, P, orc):
         s.direct(xd, md, hd, targets=torch.tensor([-1], device="cuda"))
 
 
-@pytest.mark.parametrize("near_kernel", [1, 2, 3, 4, 5])
-def test_p2p_kernel_shapes(torch, P, orc, near_kernel):
+@pytest.mark.parametrize("leaf_size,near_kernel",
+                         [(10, k) for k in range(1, 12)] + [(16, k) for k in (0, 5, 6, 7, 8)])
+def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     """Every P2P kernel shape gives the oracle's result (halo leaves with
     large softening lengths, coincident particles)."""
-    print(f"case: P2P kernel shape {near_kernel}", flush=True)
+    print(f"case: P2P kernel shape {near_kernel}, leaf size {leaf_size}", flush=True)
     x, m, h = workloads.plummer(6000, seed=4)
     x[100:140] = x[99]  # a clump of coincident particles
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, near_kernel=near_kernel)
-    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, near_kernel=near_kernel,
+                            leaf_size=leaf_size)
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=leaf_size)
     assert rel_err(acc, oa).max() < TOL
     assert pot_err(pot, op) < TOL
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
-def test_soft_pair_count(torch, P, precision):
+@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp32c", 0)])
+def test_soft_pair_count(torch, P, precision, near_kernel):
     """The P2P kernels count the ordered pairs inside a softening kernel; every
     such pair is a P2P pair (accepted node pairs keep all pairs outside both
     kernels), so the count is the brute-force one (up to pairs that sit on a
     kernel edge to rounding)."""
-    print(f"case: softened pair count {precision}", flush=True)
+    print(f"case: softened pair count {precision}, P2P shape {near_kernel}", flush=True)
     x, m, h = workloads.plummer(3000, seed=12)
-    s = P.Solver()
+    s = P.Solver(near_kernel=near_kernel)
     xd, md, hd = dev(torch, x, m, h)
     s.solve(xd, md, hd, precision=precision)
     torch.cuda.synchronize()
