@@ -151,6 +151,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
   constexpr int RS = rec_stride(P), RS32 = rec32_stride(P);
   const int lane = threadIdx.x;
   const int sub = lane % SPLIT;
+  // (no XCD-contiguous mapping here: the cost per node varies with the
+  // level, and the hardware's round-robin keeps the XCDs balanced)
   const int g = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
   const bool active = g < a.nn;
   const int v = active ? a.level_nodes[g] : 0;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(64) void k_far_shared(FarArgs a, const double* __re
   using E = Exp<P>;
   constexpr int NL = E::NL;
   constexpr int RS = rec_stride(P);
-  const int l = blockIdx.x * 64 + threadIdx.x;
+  const int l = xcd_block(blockIdx.x, gridDim.x) * 64 + threadIdx.x;
   if (l >= a.nleaves) return;
   const NodeInfo* __restrict__ info = a.info;
   const double* __restrict__ rec = a.rec;

@@ -332,9 +332,11 @@ struct WaveItem {
   int64_t item;
 };
 
-constexpr uint32_t kTQ = 128;  // queue slots per target
+constexpr uint32_t kTQ = 192;  // queue slots per target (63 + 64 U, U <= 2)
 
-template <int K, int LS>
+// U groups of 64 sources per step: their index searches and loads are
+// independent, so a wave keeps U chains of latency in flight
+template <int K, int LS, int U>
 __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem& w, int t0,
                                               int* q, uint32_t& nsoft) {
   const int lane = threadIdx.x;
@@ -363,7 +365,9 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
     const int j2 = act ? q[ii * kTQ + slot] : tlo;
     const int it = tlo + t0 + ii;  // wave-uniform
     const double hi = wave_uniform(a.hs[it]), hiinv = wave_uniform(a.his[it]);
-    const double dx = tx[ii] - a.xs[j2], dy = ty[ii] - a.ys[j2], dz = tz[ii] - a.zs[j2];
+    const double2* rj = reinterpret_cast<const double2*>(a.p4 + 4 * (int64_t)j2);
+    const double2 sxy = rj[0], szm = rj[1];
+    const double dx = tx[ii] - sxy.x, dy = ty[ii] - sxy.y, dz = tz[ii] - szm.x;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const double rinv = rsqrt_pair(r2);
     const double rinv3 = rinv * rinv * rinv;
@@ -372,7 +376,7 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
     double g1, p1, g2, p2;
     soft_sel(r * hiinv, hiinv, hi * rinv, rinv, rinv3, g1, p1);
     soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
-    const double wm = act ? a.ms[j2] : 0.0;
+    const double wm = act ? szm.y : 0.0;
     const double mg = wm * (0.5 * (g1 + g2));
     fx[ii] = fma(mg, dx, fx[ii]);
     fy[ii] = fma(mg, dy, fy[ii]);
@@ -400,58 +404,74 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
     const int incl = wave_incl_scan(cnt);
     const int pre = incl - cnt;
     const int total = __builtin_amdgcn_readlane(incl, 63);
-    for (int f0 = 0; f0 < total; f0 += 64) {
-      const int f = f0 + lane;
-      // owner lane k: the last lane with pre <= f (binary search over lanes)
-      int k = 0;
+    for (int f0 = 0; f0 < total; f0 += 64 * U) {
+      int j[U];
+      bool fv[U];
+      double xj[U], yj[U], zj[U], mj[U], h4j[U];
 #pragma unroll
-      for (int step = 32; step > 0; step >>= 1) {
-        const int pk = __shfl(pre, k + step, 64);
-        if (pk <= f) k += step;
+      for (int u = 0; u < U; ++u) {
+        const int f = f0 + 64 * u + lane;
+        // owner lane k: the last lane with pre <= f (binary search over lanes)
+        int k = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int pk = __shfl(pre, k + step, 64);
+          if (pk <= f) k += step;
+        }
+        const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+        fv[u] = f < total;
+        j[u] = fv[u] ? jj : tlo;  // a valid index; contributes nothing
       }
-      const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-      const bool fv = f < total;
-      const int j = fv ? jj : tlo;  // a valid index; contributes nothing
-      const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j];
-      const double mj = fv ? a.ms[j] : 0.0;
-      const double hj = a.hs[j];
-      const double h4j = 4.0 * hj * hj;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double2* rj = reinterpret_cast<const double2*>(a.p4 + 4 * (int64_t)j[u]);
+        const double2 sxy = rj[0], szm = rj[1];
+        const double hj = a.hs[j[u]];
+        xj[u] = sxy.x;
+        yj[u] = sxy.y;
+        zj[u] = szm.x;
+        mj[u] = fv[u] ? szm.y : 0.0;
+        h4j[u] = 4.0 * hj * hj;
+      }
 #pragma unroll
       for (int ii = 0; ii < K; ++ii) {
-        const double dx = tx[ii] - xj, dy = ty[ii] - yj, dz = tz[ii] - zj;
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const bool inside = r2 < fmax(t4[ii], h4j);
-        const double rinv = inside ? 0.0 : rsqrt_refined(r2);
-        const double mr = mj * rinv;
-        const double mg = mr * (rinv * rinv);
-        fx[ii] = fma(mg, dx, fx[ii]);
-        fy[ii] = fma(mg, dy, fy[ii]);
-        fz[ii] = fma(mg, dz, fz[ii]);
-        ph[ii] += mr;
-        // (an empty statement that reads the sums: keeps this target's
-        // arithmetic ahead of the queue branch below, so that the compiler
-        // does not move it past the branches of the later targets and hold
-        // every target's separation vector at once)
-        asm volatile("" ::"v"(fx[ii]), "v"(fy[ii]), "v"(fz[ii]), "v"(ph[ii]));
-        const bool push = inside && fv && j != tlo + t0 + ii;
-        const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
-        if (bal) {
-          if (push) {
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            uint32_t sl = qh[ii] + qn[ii] + below;
-            if (sl >= kTQ) sl -= kTQ;
-            q[ii * kTQ + sl] = j;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double dx = tx[ii] - xj[u], dy = ty[ii] - yj[u], dz = tz[ii] - zj[u];
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const bool inside = r2 < fmax(t4[ii], h4j[u]);
+          const double rinv = inside ? 0.0 : rsqrt_refined(r2);
+          const double mr = mj[u] * rinv;
+          const double mg = mr * (rinv * rinv);
+          fx[ii] = fma(mg, dx, fx[ii]);
+          fy[ii] = fma(mg, dy, fy[ii]);
+          fz[ii] = fma(mg, dz, fz[ii]);
+          ph[ii] += mr;
+          // (an empty statement that reads the sums: keeps this target's
+          // arithmetic ahead of the queue branch below, so that the compiler
+          // does not move it past the branches of the later targets and hold
+          // every target's separation vector at once)
+          asm volatile("" ::"v"(fx[ii]), "v"(fy[ii]), "v"(fz[ii]), "v"(ph[ii]));
+          const bool push = inside && fv[u] && j[u] != tlo + t0 + ii;
+          const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
+          if (bal) {
+            if (push) {
+              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                  (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+              uint32_t sl = qh[ii] + qn[ii] + below;
+              if (sl >= kTQ) sl -= kTQ;
+              q[ii * kTQ + sl] = j[u];
+            }
+            const uint32_t c = (uint32_t)__popcll(bal);
+            qn[ii] += c;
+            nsoft += c;
           }
-          const uint32_t c = (uint32_t)__popcll(bal);
-          qn[ii] += c;
-          nsoft += c;
         }
       }
-      // a queue holds at most 63 + 64 entries here
+      // a queue holds at most 63 + 64 U entries here
       static_for<K>([&](auto iic) {
         constexpr int ii = decltype(iic)::value;
-        if (qn[ii] >= 64) flush(iic, 64);
+        while (qn[ii] >= 64) flush(iic, 64);
       });
     }
   }
@@ -470,11 +490,11 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
   }
 }
 
-template <int LS, bool NODE, int TG, int WPE>
+template <int LS, bool NODE, int TG, int WPE, int U>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_p2p_wave(
     NearArgs a) {
   const int lane = threadIdx.x;
-  const uint32_t item = blockIdx.x;
+  const uint32_t item = xcd_block(blockIdx.x, gridDim.x);
   if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
   const int l = a.item_leaf[item];
   const uint32_t kitem = a.item_k[item];
@@ -509,11 +529,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ int q[TG * kTQ];
   uint32_t nsoft = 0;
   int t0 = 0;
-  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave_pass<TG, LS>(a, w, t0, q, nsoft);
+  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave_pass<TG, LS, U>(a, w, t0, q, nsoft);
   // the remainder, a pass with a fixed target count (uniform branches)
   static_for<TG>([&](auto rc) {
     constexpr int r = decltype(rc)::value;
-    if (r > 0 && w.nt - t0 == r) p2p_wave_pass<(r > 0 ? r : 1), LS>(a, w, t0, q, nsoft);
+    if (r > 0 && w.nt - t0 == r) p2p_wave_pass<(r > 0 ? r : 1), LS, U>(a, w, t0, q, nsoft);
   });
   if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
@@ -627,10 +647,16 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
+#define WAVE_LAUNCH_U(LS, TG, WPE, U)                                     \
+  do {                                                                    \
+    if (node_lists) k_p2p_wave<LS, true, TG, WPE, U><<<nbl, 64, 0, s>>>(a); \
+    else k_p2p_wave<LS, false, TG, WPE, U><<<nbl, 64, 0, s>>>(a);         \
+    launch_p2p_reduce(a, LS, s);                                          \
+  } while (0)
 #define WAVE_LAUNCH(LS, TG, WPE)                                          \
   do {                                                                    \
-    if (node_lists) k_p2p_wave<LS, true, TG, WPE><<<nbl, 64, 0, s>>>(a);  \
-    else k_p2p_wave<LS, false, TG, WPE><<<nbl, 64, 0, s>>>(a);            \
+    if (node_lists) k_p2p_wave<LS, true, TG, WPE, 1><<<nbl, 64, 0, s>>>(a); \
+    else k_p2p_wave<LS, false, TG, WPE, 1><<<nbl, 64, 0, s>>>(a);         \
     launch_p2p_reduce(a, LS, s);                                    \
   } while (0)
 
@@ -675,8 +701,9 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
       case 7: WAVE_LAUNCH(10, 8, 3); break;
       case 8: WAVE_LAUNCH(10, 10, 2); break;
       case 9: WAVE_LAUNCH(10, 5, 3); break;
-      case 10: WAVE_LAUNCH(10, 5, 5); break;
+      case 10: WAVE_LAUNCH(10, 6, 4); break;
       case 11: WAVE_LAUNCH(10, 8, 4); break;
+      case 12: WAVE_LAUNCH_U(10, 5, 4, 2); break;
       default: WAVE_LAUNCH(10, 5, 4); break;
     }
   } else if (leaf_size <= 16) {

@@ -360,7 +360,7 @@ template <bool FILL>
 __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level) {
   extern __shared__ uint32_t stk[];
   const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
-  const uint32_t idx = beg + blockIdx.x;
+  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
   if (idx >= end) return;
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];

@@ -300,16 +300,22 @@ __global__ void k_gather(int n, const uint32_t* __restrict__ perm, const double*
                          const double* __restrict__ m, const double* __restrict__ h,
                          double* __restrict__ xs, double* __restrict__ ys,
                          double* __restrict__ zs, double* __restrict__ ms,
-                         double* __restrict__ hs, double* __restrict__ his) {
+                         double* __restrict__ hs, double* __restrict__ his,
+                         double* __restrict__ p4) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t j = perm[i];
-  xs[i] = x[3 * j];
-  ys[i] = x[3 * j + 1];
-  zs[i] = x[3 * j + 2];
-  ms[i] = m[j];
-  hs[i] = h[j];
-  his[i] = 1.0 / h[j];
+  const double px = x[3 * j], py = x[3 * j + 1], pz = x[3 * j + 2], pm = m[j], ph = h[j];
+  const double phi = 1.0 / ph;
+  xs[i] = px;
+  ys[i] = py;
+  zs[i] = pz;
+  ms[i] = pm;
+  hs[i] = ph;
+  his[i] = phi;
+  double2* r = reinterpret_cast<double2*>(p4 + 4 * (int64_t)i);
+  r[0] = make_double2(px, py);
+  r[1] = make_double2(pz, pm);
 }
 
 // ---- binary radix tree (Karras 2012) ----------------------------------------
@@ -631,8 +637,8 @@ void launch_node_flags(int nn, const NodeInfo* info, const uint32_t* sys, uint8_
 
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
-                   double* hs, double* his, hipStream_t s) {
-  k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs, his);
+                   double* hs, double* his, double* p4, hipStream_t s) {
+  k_gather<<<blocks_for(n, 256), 256, 0, s>>>(n, perm, x, m, h, xs, ys, zs, ms, hs, his, p4);
 }
 
 void launch_karras(int n, const uint64_t* key, const uint32_t* sys, const int32_t* sys_start,

@@ -25,7 +25,7 @@ struct DevBuf {
 enum BufId {
   B_BOXPART, B_BOX, B_STATUS, B_SMALL,
   B_KEY0, B_KEY1, B_VAL0, B_VAL1, B_HIST, B_SCANTMP,
-  B_XS, B_YS, B_ZS, B_MS, B_HS, B_HIS,
+  B_XS, B_YS, B_ZS, B_MS, B_HS, B_HIS, B_P4,
   B_KFIRST, B_KLAST, B_KLEFT, B_KRIGHT, B_KPAR, B_KSIDE, B_KEPT,
   B_LFLAG, B_LAT, B_INFO, B_REC, B_L2BITS, B_CHUNK,
   B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
@@ -166,6 +166,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
       {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(n), 2 * (int64_t)n + 2))},
       {B_XS, sizeof(double) * n}, {B_YS, sizeof(double) * n}, {B_ZS, sizeof(double) * n},
       {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n}, {B_HIS, sizeof(double) * n},
+      {B_P4, sizeof(double) * 4 * n},
       {B_KFIRST, sizeof(int32_t) * n}, {B_KLAST, sizeof(int32_t) * n},
       {B_KLEFT, sizeof(int32_t) * n}, {B_KRIGHT, sizeof(int32_t) * n},
       {B_KPAR, sizeof(int32_t) * n}, {B_KSIDE, sizeof(int32_t) * n},
@@ -235,7 +236,8 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   const uint64_t* key = P<uint64_t>(ctx, B_KEY0);
   const uint32_t* perm = P<uint32_t>(ctx, B_VAL0);
   launch_gather(n, perm, x, m, h, P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
-                P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_HIS), s);
+                P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_HIS),
+                P<double>(ctx, B_P4), s);
   NodeInfo* info = P<NodeInfo>(ctx, B_INFO);
   int32_t* leaf_node = P<int32_t>(ctx, B_LEAFNODE);
   // ---- topology
@@ -595,6 +597,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.ms = P<double>(ctx, B_MS);
   a.hs = P<double>(ctx, B_HS);
   a.his = P<double>(ctx, B_HIS);
+  a.p4 = P<double>(ctx, B_P4);
   a.far = f.far;
   a.rec = f.rec;
   a.perm = P<uint32_t>(ctx, B_VAL0);
@@ -683,7 +686,7 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
       (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED) || c.far_kernel < 0 ||
-      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 11)
+      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 12)
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {

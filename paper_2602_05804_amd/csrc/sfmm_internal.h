@@ -35,6 +35,17 @@ __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p +
 __host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Workgroups of a launch are dealt to the chip's 8 XCDs (each with its own
+// L2) in turn.  Work whose neighbours share data (leaves in Morton order,
+// nodes of one level) is better kept together in one L2: this maps block b
+// of nb so that each XCD's blocks cover one contiguous range.
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned per = nb / kXcds, rem = nb % kXcds;
+  const unsigned x = b % kXcds, k = b / kXcds;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
 // local (field) coefficients: H_g for 1 <= |g| <= p+1, then P_b for |b| <= p
 __host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 + ncoef(p); }
 // FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
@@ -67,9 +78,11 @@ void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t*
 void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                 int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
                 hipStream_t s);
+// sorted particle data: separate arrays and one 32-byte record per particle
+// (p4: x, y, z, m)
 void launch_gather(int n, const uint32_t* perm, const double* x, const double* m,
                    const double* h, double* xs, double* ys, double* zs, double* ms,
-                   double* hs, double* his, hipStream_t s);
+                   double* hs, double* his, double* p4, hipStream_t s);
 // sys / sys_start: system of each sorted position and first position of each
 // system (nullptr for a single system)
 void launch_karras(int n, const uint64_t* key, const uint32_t* sys, const int32_t* sys_start,
@@ -223,6 +236,7 @@ struct NearArgs {
   const int32_t* leaf_node;  // (node lists)
   const uint32_t *node_p2p_off, *node_p2p_cnt, *node_p2p_pool;
   const double *xs, *ys, *zs, *ms, *hs, *his;  // his = 1/h
+  const double* p4;  // [n][4] x, y, z, m (one record per particle)
   const double* far;
   const double* rec;  // node records (leaf centres, FP32C)
   const uint32_t* perm;

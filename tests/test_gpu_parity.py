@@ -461,7 +461,7 @@ def test_direct_sum_parity(torch, P, orc):
 
 
 @pytest.mark.parametrize("leaf_size,near_kernel",
-                         [(10, k) for k in range(1, 12)] + [(16, k) for k in (0, 5, 6, 7, 8)])
+                         [(10, k) for k in range(1, 13)] + [(16, k) for k in (0, 5, 6, 7, 8)])
 def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     """Every P2P kernel shape gives the oracle's result (halo leaves with
     large softening lengths, coincident particles)."""
