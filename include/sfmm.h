@@ -221,14 +221,16 @@ int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t
 /* ---- phase timing --------------------------------------------------------
  * Phases of one solve, in order: 0 tree (keys, sort, tree, geometry,
  * moments), 1 walk count pass, 2 walk fill pass, 3 far field (M2L + L2L +
- * L2P), 4 near field (P2P + output), 5 momentum reduction.  Between
+ * L2P), 4 near field (P2P + output), 5 momentum reduction; 6 is the main
+ * P2P kernel alone (inside phase 4, without the work-item set-up and the
+ * reduction of the partial sums).  Between
  * sfmm_timing_start and sfmm_timing_stop each solve records a pair of HIP
  * events around every phase on the context's stream (no extra
  * synchronisation).  sfmm_timing_stop synchronises, writes the durations in
  * milliseconds to ms[k * SFMM_NUM_PHASES + phase] for the first
  * min(recorded, cap) solves, stores the number recorded in *nsolves and
  * frees the events.  Solves beyond max_solves are not timed. */
-#define SFMM_NUM_PHASES 6
+#define SFMM_NUM_PHASES 7
 int sfmm_timing_start(sfmm_ctx* ctx, int max_solves);
 int sfmm_timing_stop(sfmm_ctx* ctx, double* ms, int cap, int* nsolves);
 const char* sfmm_phase_name(int phase);

@@ -25,7 +25,7 @@ EXPORTED = ("sfmm_config_default", "sfmm_create", "sfmm_destroy", "sfmm_set_stre
             "sfmm_get_leaf_lists", "sfmm_timing_start", "sfmm_timing_stop", "sfmm_phase_name",
             "sfmm_workspace_bytes", "sfmm_leapfrog", "sfmm_direct",
             "sfmm_strerror", "sfmm_last_error")
-PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum")
+PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum", "near_kernel")
 
 # floating-point operations per unit of work at each expansion order, counted
 # from the generated kernels (FMA = 2); see csrc/expansions_gen.h

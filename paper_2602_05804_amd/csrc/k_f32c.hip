@@ -367,10 +367,12 @@ void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
 
 template <int LS, int RS>
 void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, int64_t items,
-           hipStream_t s) {
+           hipStream_t s, KernelMarks km) {
   constexpr int TG = LS <= 10 ? 5 : 8;
+  record_mark(km.begin, s);
   if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
   else k_p2p_leaf32<LS, false, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
+  record_mark(km.end, s);
   launch_p2p_reduce(a, LS, s);
 }
 
@@ -409,16 +411,16 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
 }
 
 bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, int64_t items, hipStream_t s) {
+                   const float2* ph, int64_t items, hipStream_t s, KernelMarks km) {
   if (a.n <= 0) return true;
   const int RS = rec_stride(order);
   if (leaf_size > 16) return false;
 #define SFMM_P2P32(LS)                                                   \
   switch (RS) {                                                          \
-    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, items, s); break;      \
-    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, items, s); break;      \
-    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, items, s); break;      \
-    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, items, s); break;      \
+    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, items, s, km); break;      \
+    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, items, s, km); break;      \
+    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, items, s, km); break;      \
+    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, items, s, km); break;      \
   }
   if (leaf_size <= 10) { SFMM_P2P32(10) } else { SFMM_P2P32(16) }
 #undef SFMM_P2P32

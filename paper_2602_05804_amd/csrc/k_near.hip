@@ -651,19 +651,22 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
   do {                                                                    \
     if (node_lists) k_p2p_wave<LS, true, TG, WPE, U><<<nbl, 64, 0, s>>>(a); \
     else k_p2p_wave<LS, false, TG, WPE, U><<<nbl, 64, 0, s>>>(a);         \
+    record_mark(km.end, s);                                               \
     launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 #define WAVE_LAUNCH(LS, TG, WPE)                                          \
   do {                                                                    \
     if (node_lists) k_p2p_wave<LS, true, TG, WPE, 1><<<nbl, 64, 0, s>>>(a); \
     else k_p2p_wave<LS, false, TG, WPE, 1><<<nbl, 64, 0, s>>>(a);         \
-    launch_p2p_reduce(a, LS, s);                                    \
+    record_mark(km.end, s);                                               \
+    launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 
 #define NEAR_LAUNCH(LS, TG, QU)                                            \
   do {                                                                    \
     if (node_lists) k_p2p_leaf<LS, true, TG, QU><<<nbl, 64, 0, s>>>(a);   \
     else k_p2p_leaf<LS, false, TG, QU><<<nbl, 64, 0, s>>>(a);             \
+    record_mark(km.end, s);                                               \
     launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 
@@ -686,9 +689,10 @@ void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s) {
 }
 
 void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, int64_t items,
-                 hipStream_t s) {
+                 hipStream_t s, KernelMarks km) {
   if (a.n <= 0) return;
   const unsigned nbl = (unsigned)items;
+  record_mark(km.begin, s);
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
   // variant (the shapes are listed with sfmm_config.near_kernel)
   if (leaf_size <= 10) {
@@ -717,6 +721,7 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);
+    record_mark(km.end, s);
   }
 }
 

@@ -123,10 +123,15 @@ void free_events(sfmm_ctx* ctx) {
   ctx->timing_cap = ctx->timing_used = 0;
 }
 
+// the event of a phase's start (end = 0) or end of this solve, null when
+// the solve is not timed
+hipEvent_t phase_event(sfmm_ctx* ctx, int phase, int end) {
+  if (!ctx->timing || ctx->timing_used >= ctx->timing_cap) return nullptr;
+  return ctx->events[(size_t)ctx->timing_used * 2 * SFMM_NUM_PHASES + 2 * phase + end];
+}
+
 void phase_mark(sfmm_ctx* ctx, int phase, int end) {
-  if (!ctx->timing || ctx->timing_used >= ctx->timing_cap) return;
-  hipEvent_t e = ctx->events[(size_t)ctx->timing_used * 2 * SFMM_NUM_PHASES + 2 * phase + end];
-  (void)hipEventRecord(e, ctx->stream);
+  if (hipEvent_t e = phase_event(ctx, phase, end)) (void)hipEventRecord(e, ctx->stream);
 }
 
 int set_device(sfmm_ctx* ctx) {
@@ -638,9 +643,12 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     a.part = P<double>(ctx, B_PART);
     launch_p2p_items_fill(a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK), s);
   }
+  KernelMarks km;
+  km.begin = phase_event(ctx, 6, 0);
+  km.end = phase_event(ctx, 6, 1);
   if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, a, P<float4>(ctx, B_PF32),
-                        P<float2>(ctx, B_PH32), items, s);
-  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, s);
+                        P<float2>(ctx, B_PH32), items, s, km);
+  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, s, km);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
@@ -1021,8 +1029,8 @@ int sfmm_timing_stop(sfmm_ctx* ctx, double* ms, int cap, int* nsolves) {
 }
 
 const char* sfmm_phase_name(int phase) {
-  static const char* names[SFMM_NUM_PHASES] = {"tree", "walk_count", "walk_fill",
-                                               "far", "near", "momentum"};
+  static const char* names[SFMM_NUM_PHASES] = {"tree",     "walk_count", "walk_fill",  "far",
+                                               "near",     "momentum",   "near_kernel"};
   return (phase >= 0 && phase < SFMM_NUM_PHASES) ? names[phase] : "unknown";
 }
 

@@ -264,8 +264,16 @@ void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, 
 void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k, hipStream_t s);
 // wave-per-item kernel for leaf_size <= 16 (then the reduction in item
 // order), particle-per-thread otherwise; items: the bound on the item count
+// HIP events recorded on the stream around the main P2P kernel alone (null:
+// none), for the timing of that kernel
+struct KernelMarks {
+  hipEvent_t begin = nullptr, end = nullptr;
+};
+inline void record_mark(hipEvent_t e, hipStream_t s) {
+  if (e) (void)hipEventRecord(e, s);
+}
 void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, int64_t items,
-                 hipStream_t s);
+                 hipStream_t s, KernelMarks km = {});
 // sum of the item partials per target, plus the far field and the self term,
 // written in the caller's order (LS = the P2P kernel's target count)
 void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s);
@@ -280,7 +288,7 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
                   hipStream_t s);
 // false when leaf_size > 16 (not built)
 bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, int64_t items, hipStream_t s);
+                   const float2* ph, int64_t items, hipStream_t s, KernelMarks km = {});
 
 void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double kick, double drift,
                      hipStream_t s);
