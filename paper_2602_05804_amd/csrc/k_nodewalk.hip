@@ -355,48 +355,104 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
   if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
 }
 
-// count (FILL = false) or fill (FILL = true) pass of one level
-template <bool FILL>
-__global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level) {
-  extern __shared__ uint32_t stk[];
+// ---- internal nodes, level by level ---------------------------------------
+// Region sizes of one level (thread per node): an internal node's region in
+// the M2L pool is its tested list (1 for a root, else exp[parent]); leaves
+// take no room here (they are walked after all levels); a node over two
+// systems gets empty lists.
+__global__ void k_region_count(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  const int v = a.level_nodes[idx];
+  const NodeInfo vi = a.info[v];
+  const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
+  uint64_t c = 0;
+  if (flag == 0) {
+    a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+    a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
+  } else if (vi.child >= 0) {
+    c = flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
+    a.p2p_cnt[v] = 0;
+    a.p2p_off[v] = 0;
+  }
+  a.lvl_cnt[idx] = c;
+}
+
+// fill pass of one level's internal nodes (one wave per node; the level
+// scan has placed their regions)
+__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
   const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
   if (idx >= end) return;
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
-  const double* rv = a.rec + (int64_t)v * a.stride;
   // a node over two systems (several systems solved together) is never
   // walked; the walk of each system starts at its own root
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
+  if (flag == 0 || vi.child < 0) return;
   const bool root = flag == 1;
   const uint32_t lane = threadIdx.x & 63;
-  // (the top node of several systems has no parent: nothing below may read
-  // a parent's lists before this branch returns)
-  if (flag == 0) {
+  const double* rv = a.rec + (int64_t)v * a.stride;
+  const uint32_t region = root ? 1u : a.exp[vi.parent];
+  Emit e{};
+  e.m2l_base = (uint32_t)a.lvl_off[idx];
+  e.open_base = e.m2l_base + region;
+  if (lane == 0) a.m2l_off[v] = e.m2l_base;
+  if (root) {
+    // (root, root) is opened: both root children meet both root children
+    if (lane == 0) {
+      if (e.m2l_base < a.open_cap) a.open_pool[e.m2l_base] = (uint32_t)v;
+      a.m2l_cnt[v] = 0;
+      a.open_cnt[v] = 1;
+      a.open_off[v] = e.m2l_base;
+      a.exp[v] = 2;
+    }
+    return;
+  }
+  const uint32_t po = a.open_off[vi.parent];
+  uint32_t nsrc = a.open_cnt[vi.parent];
+  if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
+  walk_internal<true>(a, v, rv, a.open_pool + po, nsrc, e);
+  uint32_t ex = e.exp_lane;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ex += (uint32_t)__shfl_xor((int)ex, o, 64);
+  if (lane == 0) {
+    a.m2l_cnt[v] = e.m2l_run;
+    a.open_cnt[v] = e.open_run;
+    a.open_off[v] = e.open_base - e.open_run;
+    a.exp[v] = ex;
+  }
+}
+
+// ---- leaves, all levels at once ---------------------------------------------
+// A leaf's lists depend only on its parent's opened list, so the leaves are
+// walked after every level's internal nodes, in leaf order (one wave per
+// leaf): a count pass, a scan over the leaves, and a fill pass that repeats
+// the walk and writes.  Leaf M2L lists follow the internal nodes' regions in
+// the M2L pool; the P2P pool holds only leaf lists.
+template <bool FILL>
+__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
+  extern __shared__ uint32_t stk[];
+  const int l = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (l >= a.nleaves) return;
+  const int v = a.leaf_node[l];
+  const NodeInfo vi = a.info[v];
+  const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
+  const uint32_t lane = threadIdx.x & 63;
+  if (flag == 0) {  // (a leaf never spans two systems; kept for safety)
     if (lane == 0) {
       if (FILL) {
-        a.m2l_off[v] = (uint32_t)a.lvl_off[idx];
-        a.open_off[v] = (uint32_t)(a.lvl_off[idx] >> 32);
-        a.p2p_off[v] = 0;
+        a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
       } else {
-        a.m2l_cnt[v] = 0;
-        a.open_cnt[v] = 0;
-        a.p2p_cnt[v] = 0;
-        a.lvl_cnt[idx] = vi.child >= 0 ? 0ull : (1ull << 63);
+        a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+        a.leaf_m2l_cnt[l] = 0; a.leaf_p2p_cnt[l] = 0;
       }
     }
     return;
   }
-  // internal node: its region (M2L + opened = its tested list) has a size
-  // known without walking it, so it has no count pass
-  const uint32_t region = root ? 1u : (vi.child >= 0 ? a.exp[vi.parent] : 0u);
-  if (!FILL && vi.child >= 0) {
-    if (lane == 0) {
-      a.lvl_cnt[idx] = (uint64_t)region;  // bit 63 clear: internal
-      a.p2p_cnt[v] = 0;
-    }
-    return;
-  }
+  const bool root = flag == 1;
+  const double* rv = a.rec + (int64_t)v * a.stride;
   const uint32_t* src = nullptr;
   uint32_t nsrc = 0;
   if (!root) {
@@ -407,51 +463,19 @@ __global__ __launch_bounds__(64) void k_nodewalk_pass(NodeWalkArgs a, int level)
   }
   Emit e{};
   if (FILL) {
-    // absolute pool offsets from the level scan: low word M2L (for an
-    // internal node its whole region), high word the P2P list of a leaf
-    const uint64_t off = a.lvl_off[idx];
-    e.m2l_base = (uint32_t)off;
-    const uint32_t hi = (uint32_t)(off >> 32);
-    if (lane == 0) a.m2l_off[v] = e.m2l_base;
-    if (vi.child >= 0) {
-      e.open_base = e.m2l_base + region;
-    } else {
-      e.p2p_base = hi;
-      e.p2p_total = a.p2p_cnt[v];  // from the count pass
-      if (lane == 0) { a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
-    }
+    e.m2l_base = a.run[0] + a.leaf_m2l_off[l];
+    e.p2p_base = a.leaf_p2p_off[l];
+    e.p2p_total = a.p2p_cnt[v];  // from the count pass
+    if (lane == 0) { a.m2l_off[v] = e.m2l_base; a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
   }
-  if (vi.child >= 0) {
-    if (root) {
-      // (root, root) is opened: both root children meet both root children
-      if (lane == 0) {
-        if (e.m2l_base < a.open_cap) a.open_pool[e.m2l_base] = (uint32_t)v;
-        a.m2l_cnt[v] = 0;
-        a.open_cnt[v] = 1;
-        a.open_off[v] = e.m2l_base;
-        a.exp[v] = 2;
-      }
-      return;
-    }
-    walk_internal<true>(a, v, rv, src, nsrc, e);
-    uint32_t ex = e.exp_lane;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ex += (uint32_t)__shfl_xor((int)ex, o, 64);
-    if (lane == 0) {
-      a.m2l_cnt[v] = e.m2l_run;
-      a.open_cnt[v] = e.open_run;
-      a.open_off[v] = e.open_base - e.open_run;
-      a.exp[v] = ex;
-    }
-  } else {
-    walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
-    if (!FILL && lane == 0) {
-      const uint32_t np = e.p2p_run + e.plain_run;
-      a.m2l_cnt[v] = e.m2l_run;
-      a.p2p_cnt[v] = np;
-      a.open_cnt[v] = 0;
-      a.lvl_cnt[idx] = (uint64_t)e.m2l_run | ((uint64_t)np << 32) | (1ull << 63);
-    }
+  walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
+  if (!FILL && lane == 0) {
+    const uint32_t np = e.p2p_run + e.plain_run;
+    a.m2l_cnt[v] = e.m2l_run;
+    a.p2p_cnt[v] = np;
+    a.open_cnt[v] = 0;
+    a.leaf_m2l_cnt[l] = e.m2l_run;
+    a.leaf_p2p_cnt[l] = np;
   }
 }
 
@@ -580,10 +604,18 @@ void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned
 
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s) {
   if (nodes_in_level <= 0) return;
-  const size_t lds = a.stack_cap * sizeof(uint32_t);
-  k_nodewalk_pass<false><<<nodes_in_level, 64, lds, s>>>(a, level);
+  k_region_count<<<blocks_for(nodes_in_level, 256), 256, 0, s>>>(a, level);
   k_nodewalk_scan<<<1, SCAN_T, 0, s>>>(a, level);
-  k_nodewalk_pass<true><<<nodes_in_level, 64, lds, s>>>(a, level);
+  k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level);
+}
+
+void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s) {
+  if (a.nleaves <= 0) return;
+  const size_t lds = a.stack_cap * sizeof(uint32_t);
+  k_nodewalk_leaves<false><<<a.nleaves, 64, lds, s>>>(a);
+  scan_u32(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3, scan_tmp, s);
+  scan_u32(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2, scan_tmp, s);
+  k_nodewalk_leaves<true><<<a.nleaves, 64, lds, s>>>(a);
 }
 
 }  // namespace sfmm

@@ -37,6 +37,7 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT, B_SOFTCNT,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
   B_COUNT
 };
 
@@ -420,6 +421,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
+  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
+    if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint64_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
@@ -466,8 +469,16 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.run = tot;
     a.stack_cap = ctx->stack_cap;
     a.status = status;
+    a.nleaves = nl;
+    a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+    a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
+    a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
+    a.leaf_m2l_off = P<uint32_t>(ctx, B_LWM2LOFF);
+    a.leaf_p2p_off = P<uint32_t>(ctx, B_LWP2POFF);
+    // internal nodes level by level, then every leaf
     for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_off[k + 1] - ctx->level_off[k]), s);
+    launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
     // M2L entries proper (the pool also holds the opened lists)
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
     uint32_t htot[4];
@@ -475,7 +486,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const bool pool_over = htot[0] > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
+    const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
+    const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
       ctx->p2p_total = htot[2];
@@ -489,7 +501,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       auto grow = [](uint64_t cap, uint64_t need) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
-      ctx->m2l_cap = grow(ctx->m2l_cap, htot[0]);
+      ctx->m2l_cap = grow(ctx->m2l_cap, m2l_used);
       ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
     }
     if (stack_over) {

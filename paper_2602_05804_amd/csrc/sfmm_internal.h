@@ -164,7 +164,12 @@ struct NodeWalkArgs {
   uint32_t* exp;  // per internal node: tested-list size of each of its children
   uint64_t* lvl_cnt;  // [nn] packed counts in level order (low: M2L pool region, high: P2P)
   uint64_t* lvl_off;  // [nn] their exclusive scan within the level
-  uint32_t* run;      // [3] running pool sizes: M2L (with opened lists), unused, P2P
+  uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
+                      // walk's sum), P2P pool, M2L pool used by leaves
+  // leaves (walked after all levels, in leaf order)
+  int nleaves;
+  const int32_t* leaf_node;
+  uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt, *leaf_m2l_off, *leaf_p2p_off;
   uint32_t stack_cap;  // LDS lowering stack, entries
   int* status;
 };
@@ -175,6 +180,9 @@ void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* k
 // read from the scanned radix histogram (digit-major, nb blocks)
 void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
                           uint32_t* level_off, hipStream_t s);
+// every leaf's lists (count, scans over the leaves, fill); scan_tmp holds
+// scan_tmp_elems(nleaves) words
+void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s);
 // out[0] += sum of x[0..n) (out on the device)
 void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
