@@ -356,27 +356,23 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
 }
 
 // ---- internal nodes, level by level ---------------------------------------
-// Region sizes of one level (thread per node): an internal node's region in
-// the M2L pool is its tested list (1 for a root, else exp[parent]); leaves
-// take no room here (they are walked after all levels); a node over two
-// systems gets empty lists.
-__global__ void k_region_count(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
-  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= end) return;
+// The M2L pool region of an internal node is its tested list (1 for a root,
+// else exp[parent]); leaves take no room at their level (they are walked
+// after all levels); a node over two systems gets empty lists.  This is the
+// region of level node idx (and it clears the lists of a node it owns).
+__device__ __forceinline__ uint32_t node_region(const NodeWalkArgs& a, uint32_t idx) {
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  uint64_t c = 0;
   if (flag == 0) {
     a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
     a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
-  } else if (vi.child >= 0) {
-    c = flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
-    a.p2p_cnt[v] = 0;
-    a.p2p_off[v] = 0;
+    return 0;
   }
-  a.lvl_cnt[idx] = c;
+  if (vi.child < 0) return 0;
+  a.p2p_cnt[v] = 0;
+  a.p2p_off[v] = 0;
+  return flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
 }
 
 // fill pass of one level's internal nodes (one wave per node; the level
@@ -396,7 +392,7 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
   const double* rv = a.rec + (int64_t)v * a.stride;
   const uint32_t region = root ? 1u : a.exp[vi.parent];
   Emit e{};
-  e.m2l_base = (uint32_t)a.lvl_off[idx];
+  e.m2l_base = a.lvl_off[idx];
   e.open_base = e.m2l_base + region;
   if (lane == 0) a.m2l_off[v] = e.m2l_base;
   if (root) {
@@ -479,15 +475,15 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
   }
 }
 
-// Places one level's lists: a scan, in level order, of the packed counts
-// (bits 0-31 the M2L pool region: a leaf's M2L list, an internal node's
-// M2L + opened lists; bits 32-62 the P2P list of a leaf, 0 for an internal
-// node; bit 63 set for a leaf) into absolute pool offsets, after
-// everything placed by earlier levels; then the running pool sizes advance.
-// One block.
+// Places one level's internal nodes: an exclusive scan, in level order, of
+// their region sizes into absolute M2L pool offsets after everything the
+// levels above placed (levbase[level]); levbase[level + 1] and run[0] get
+// the new pool size.  A level of at most one tile (SCAN_T * SCAN_I nodes)
+// is one block; a larger one a pass of tile sums and a pass of tile scans.
 constexpr int SCAN_T = 1024;
 constexpr int SCAN_I = 4;
 constexpr int SCAN_W = SCAN_T / 64;
+constexpr uint32_t kScanTile = SCAN_T * SCAN_I;
 
 __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   const int lane = threadIdx.x & 63;
@@ -499,48 +495,83 @@ __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   return x;
 }
 
-// in-wave shuffle scans, then one step across the block's 16 waves
-__global__ __launch_bounds__(SCAN_T) void k_nodewalk_scan(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
-  __shared__ uint32_t wt[3][SCAN_W];
-  __shared__ uint32_t carry[3];
+// exclusive scan of c (per thread, SCAN_I consecutive items summed) over the
+// block; returns the exclusive prefix of this thread and the block total
+__device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) {
+  __shared__ uint32_t wt[SCAN_W];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x < 3) carry[threadIdx.x] = a.run[threadIdx.x];
+  const uint32_t inc = wave_incl_u32(c);
+  if (lane == 63) wt[w] = inc;
   __syncthreads();
-  for (uint32_t base = beg; base < end; base += SCAN_T * SCAN_I) {
-    uint64_t v[SCAN_I];
-    uint32_t cm = 0, co = 0, cp = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_I; ++q) {
-      const uint32_t i = base + threadIdx.x * SCAN_I + q;
-      v[q] = i < end ? a.lvl_cnt[i] : 0ull;
-      const uint32_t b = (uint32_t)(v[q] >> 32) & 0x7fffffffu;
-      cm += (uint32_t)v[q];
-      if (v[q] >> 63) cp += b; else co += b;
-    }
-    const uint32_t im = wave_incl_u32(cm), io = wave_incl_u32(co), ip = wave_incl_u32(cp);
-    if (lane == 63) { wt[0][w] = im; wt[1][w] = io; wt[2][w] = ip; }
-    __syncthreads();
-    uint32_t rm = carry[0] + im - cm, ro = carry[1] + io - co, rp = carry[2] + ip - cp;
-    for (int k = 0; k < w; ++k) { rm += wt[0][k]; ro += wt[1][k]; rp += wt[2][k]; }
-#pragma unroll
-    for (int q = 0; q < SCAN_I; ++q) {
-      const uint32_t i = base + threadIdx.x * SCAN_I + q;
-      const uint32_t b = (uint32_t)(v[q] >> 32) & 0x7fffffffu;
-      const bool leaf = (v[q] >> 63) != 0;
-      if (i < end) a.lvl_off[i] = (uint64_t)rm | ((uint64_t)(leaf ? rp : ro) << 32);
-      rm += (uint32_t)v[q];
-      if (leaf) rp += b; else ro += b;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-      uint32_t t = 0;
-      for (int k = 0; k < SCAN_W; ++k) t += wt[threadIdx.x][k];
-      carry[threadIdx.x] += t;
-    }
-    __syncthreads();
+  uint32_t pre = inc - c;
+  total = 0;
+  for (int k = 0; k < SCAN_W; ++k) {
+    const uint32_t t = wt[k];
+    if (k < w) pre += t;
+    total += t;
   }
-  if (threadIdx.x < 3) a.run[threadIdx.x] = carry[threadIdx.x];
+  __syncthreads();
+  return pre;
+}
+
+// one tile: regions of tile t of the level, scanned, written at base
+__device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
+                                              uint32_t t, uint32_t base, bool recompute) {
+  const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
+  uint32_t r[SCAN_I], c = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_I; ++q) {
+    const uint32_t i = i0 + q;
+    r[q] = i < end ? (recompute ? node_region(a, i) : a.lvl_cnt32[i]) : 0u;
+    c += r[q];
+  }
+  uint32_t total;
+  uint32_t o = base + block_excl_u32(c, total);
+#pragma unroll
+  for (int q = 0; q < SCAN_I; ++q) {
+    const uint32_t i = i0 + q;
+    if (i < end) a.lvl_off[i] = o;
+    o += r[q];
+  }
+  return total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t base = a.levbase[level];
+  const uint32_t total = scan_tile(a, beg, end, 0, base, true);
+  if (threadIdx.x == 0) {
+    a.levbase[level + 1] = base + total;
+    a.run[0] = base + total;
+  }
+}
+
+// tile sums (and the regions, kept for the second pass)
+__global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
+  uint32_t c = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_I; ++q) {
+    const uint32_t i = i0 + q;
+    const uint32_t r = i < end ? node_region(a, i) : 0u;
+    if (i < end) a.lvl_cnt32[i] = r;
+    c += r;
+  }
+  uint32_t total;
+  (void)block_excl_u32(c, total);
+  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  uint32_t base = a.levbase[level];
+  for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
+  const uint32_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
+  if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
+    a.levbase[level + 1] = base + total;
+    a.run[0] = base + total;
+  }
 }
 
 __global__ void k_leaf_stats(LeafStatArgs a) {
@@ -603,9 +634,18 @@ void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned
 }
 
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s) {
-  if (nodes_in_level <= 0) return;
-  k_region_count<<<blocks_for(nodes_in_level, 256), 256, 0, s>>>(a, level);
-  k_nodewalk_scan<<<1, SCAN_T, 0, s>>>(a, level);
+  if (nodes_in_level <= 0) {
+    // an empty level still carries the pool size to the next one
+    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
+    return;
+  }
+  const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
+  if (tiles == 1) {
+    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
+  } else {
+    k_level_tile_sums<<<tiles, SCAN_T, 0, s>>>(a, level);
+    k_level_tile_scan<<<tiles, SCAN_T, 0, s>>>(a, level);
+  }
   k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level);
 }
 

@@ -33,7 +33,7 @@ enum BufId {
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
   B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
-  B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF,
+  B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT, B_SOFTCNT,
@@ -423,8 +423,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
   for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
-  if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint64_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint32_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 4096 + 2)))) return rc;
+  if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint32_t) * (kMaxDepthCap + 2)))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
@@ -464,8 +466,11 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.m2l_cap = (uint32_t)ctx->m2l_cap;
     a.open_cap = a.m2l_cap;
     a.p2p_cap = (uint32_t)ctx->p2p_cap;
-    a.lvl_cnt = P<uint64_t>(ctx, B_LVLCNT);
-    a.lvl_off = P<uint64_t>(ctx, B_LVLOFF);
+    a.lvl_cnt32 = P<uint32_t>(ctx, B_LVLCNT);
+    a.lvl_off = P<uint32_t>(ctx, B_LVLOFF);
+    a.tile_sum = P<uint32_t>(ctx, B_TILESUM);
+    a.levbase = P<uint32_t>(ctx, B_LEVBASE);
+    HIPCHK(hipMemsetAsync(a.levbase, 0, sizeof(uint32_t), s));
     a.run = tot;
     a.stack_cap = ctx->stack_cap;
     a.status = status;

@@ -162,8 +162,10 @@ struct NodeWalkArgs {
   uint32_t *m2l_pool, *open_pool, *p2p_pool;  // open_pool: the M2L pool
   uint32_t m2l_cap, open_cap, p2p_cap;
   uint32_t* exp;  // per internal node: tested-list size of each of its children
-  uint64_t* lvl_cnt;  // [nn] packed counts in level order (low: M2L pool region, high: P2P)
-  uint64_t* lvl_off;  // [nn] their exclusive scan within the level
+  uint32_t* lvl_cnt32;  // [nn] M2L pool region of each internal node, in level order
+  uint32_t* lvl_off;    // [nn] its absolute offset in the M2L pool
+  uint32_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
+  uint32_t* levbase;    // [levels + 1] M2L pool size before each level
   uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
                       // walk's sum), P2P pool, M2L pool used by leaves
   // leaves (walked after all levels, in leaf order)
