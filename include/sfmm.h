@@ -220,7 +220,8 @@ int sfmm_get_leaf_lists(sfmm_ctx* ctx, int64_t leaf, int32_t* m2l_depth, int32_t
 
 /* ---- phase timing --------------------------------------------------------
  * Phases of one solve, in order: 0 tree (keys, sort, tree, geometry,
- * moments), 1 walk count pass, 2 walk fill pass, 3 far field (M2L + L2L +
+ * moments), 1 walk (SFMM_WALK_LEVEL: all of it; SFMM_WALK_LEAF: the count
+ * pass), 2 walk fill pass (SFMM_WALK_LEAF only), 3 far field (M2L + L2L +
  * L2P), 4 near field (P2P + output), 5 momentum reduction; 6 is the main
  * P2P kernel alone (inside phase 4, without the work-item set-up and the
  * reduction of the partial sums).  Between
