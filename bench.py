@@ -77,6 +77,27 @@ def measured_traffic(args, kern):
     return round(total)
 
 
+# algorithmic HBM bytes per particle of the tree phase: keys (24 B read,
+# 12 B written), 8 radix passes over (key, index) (12 B read + 12 B written
+# each), the gather (40 B read + 4 B index, 80 B written: arrays + records)
+TREE_BYTES_PER_PARTICLE = 36 + 8 * 24 + 124
+PEAK_HBM_GBS = 8000.0
+
+
+def solve_fraction(args, work, total_ms):
+    """Whole-solve fraction: the sum over phases of the time each would take at
+    its own bound (far and near at the FP64 peak, the tree at the HBM peak)
+    over the measured time of a solve.  The walk has no arithmetic or
+    bandwidth roof of its own (dependent gathers and branches); it counts as
+    measured time only."""
+    ideal = {"far": work["far"] / (PEAK_FP64_TFLOPS * 1e12) * 1e3,
+             "near": work["near"] / (PEAK_FP64_TFLOPS * 1e12) * 1e3,
+             "tree": args.n * TREE_BYTES_PER_PARTICLE / (PEAK_HBM_GBS * 1e9) * 1e3}
+    tot = sum(ideal.values())
+    return {"ideal_ms": {k: round(v, 4) for k, v in ideal.items()}, "ideal_total_ms": round(tot, 4),
+            "measured_ms": round(total_ms, 4), "frac": round(tot / total_ms, 4)}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -238,6 +259,7 @@ def main():
                                       "n_m2l_unique", "n_l2l", "n_p2p_leaf_pairs",
                                       "n_p2p_pairs", "n_p2p_soft_pairs")},
         "momentum_residual": mom,
+        "solve_fraction": solve_fraction(args, work, dt * 1e3),
     }
 
     if args.far == "shared":
