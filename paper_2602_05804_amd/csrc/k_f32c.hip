@@ -240,29 +240,27 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
   }
   // this item's run [f_lo, f_hi) of the leaf's flattened sources
   const uint32_t f_lo = kitem * kP2PItem;
-  const uint32_t ftot = a.flat[e1 - 1];
+  const uint32_t ftot = a.src_total[l];
   const uint32_t f_hi = f_lo + kP2PItem < ftot ? f_lo + kP2PItem : ftot;
-  {
-    uint64_t lo_e = e0, hi_e = e1 - 1;
-    while (lo_e < hi_e) {
-      const uint64_t mid = (lo_e + hi_e) >> 1;
-      if (a.flat[mid] > f_lo) hi_e = mid; else lo_e = mid + 1;
-    }
-    e0 = lo_e;
-  }
+  uint32_t carry0 = 0;  // from the list entry that holds the run's first source
+  if (kitem > 0) { e0 = a.item_e0[item]; carry0 = a.item_c0[item]; }
   uint32_t nsoft = 0;  // pairs inside a kernel (complete on lane 0)
   for (int t0 = 0; t0 < nt; t0 += TG) {
     double fx[TG], fy[TG], fz[TG], ph[TG];
 #pragma unroll
     for (int i = 0; i < TG; ++i) { fx[i] = 0.0; fy[i] = 0.0; fz[i] = 0.0; ph[i] = 0.0; }
+    uint32_t carry = carry0;  // sources of the list entries before c0
     for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
       int cnt = 0, lo = 0, sub = 0;
       uint32_t fb = 0xffffffffu;
       float dcx = 0.f, dcy = 0.f, dcz = 0.f;
-      if (c0 + lane < e1) {
-        const int src = list[c0 + lane];
-        const NodeInfo si = a.info[src];
-        const uint32_t fe = a.flat[c0 + lane];
+      const bool in = c0 + lane < e1;
+      const int src = in ? list[c0 + lane] : 0;
+      NodeInfo si{};
+      if (in) si = a.info[src];
+      const int sincl = wave_incl_scan32(in ? si.cnt : 0);
+      if (in) {
+        const uint32_t fe = carry + (uint32_t)sincl;
         fb = fe - (uint32_t)si.cnt;
         const uint32_t b = fb > f_lo ? fb : f_lo;
         const uint32_t en = fe < f_hi ? fe : f_hi;
@@ -275,6 +273,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
         dcy = (float)(ct1 - rs[1]);
         dcz = (float)(ct2 - rs[2]);
       }
+      carry += (uint32_t)__shfl(sincl, 63, 64);
       if (__shfl((int)fb, 0, 64) >= (int)f_hi) break;  // the run is done (uniform)
       const int incl = wave_incl_scan32(cnt);
       const int pre = incl - cnt;

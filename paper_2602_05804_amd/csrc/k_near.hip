@@ -163,19 +163,13 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
     e1 = a.p2p_off[l + 1];
     list = a.p2p_list;
   }
-  // this item's run [f_lo, f_hi) of the leaf's flattened sources, and the
-  // first list entry that reaches into it
+  // this item's run [f_lo, f_hi) of the leaf's flattened sources, from the
+  // list entry that holds its first source
   const uint32_t f_lo = kitem * kP2PItem;
-  const uint32_t ftot = a.flat[e1 - 1];
+  const uint32_t ftot = a.src_total[l];
   const uint32_t f_hi = f_lo + kP2PItem < ftot ? f_lo + kP2PItem : ftot;
-  {
-    uint64_t lo_e = e0, hi_e = e1 - 1;  // flat[e1 - 1] = ftot > f_lo
-    while (lo_e < hi_e) {
-      const uint64_t mid = (lo_e + hi_e) >> 1;
-      if (a.flat[mid] > f_lo) hi_e = mid; else lo_e = mid + 1;
-    }
-    e0 = lo_e;
-  }
+  uint32_t carry0 = 0;
+  if (kitem > 0) { e0 = a.item_e0[item]; carry0 = a.item_c0[item]; }
   __shared__ int qj[Q ? 128 : 1];
   __shared__ int qi[Q ? 128 : 1];
   uint32_t qn = 0;     // queued softened pairs (the same on every lane)
@@ -218,19 +212,23 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
       qn = rem;
       __syncthreads();
     };
+    uint32_t carry = carry0;  // sources of the list entries before c0
     for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-      // 64 list entries: their particle ranges clipped to the run, flattened
-      // by a prefix scan
+      // 64 list entries: their particle ranges [fb, fe) in the flattened
+      // order, then clipped to the run
       int cnt = 0, lo = 0;
       uint32_t fb = 0xffffffffu;
+      NodeInfo si{};
+      if (c0 + lane < e1) si = a.info[list[c0 + lane]];
+      const int sincl = wave_incl_scan(c0 + lane < e1 ? si.cnt : 0);
       if (c0 + lane < e1) {
-        const NodeInfo si = a.info[list[c0 + lane]];
-        const uint32_t fe = a.flat[c0 + lane];
+        const uint32_t fe = carry + (uint32_t)sincl;
         fb = fe - (uint32_t)si.cnt;
         const uint32_t b = fb > f_lo ? fb : f_lo;
         const uint32_t en = fe < f_hi ? fe : f_hi;
         if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
       }
+      carry += (uint32_t)__shfl(sincl, 63, 64);
       if (__shfl((int)fb, 0, 64) >= (int)f_hi) break;  // the run is done (uniform)
       const int incl = wave_incl_scan(cnt);
       const int pre = incl - cnt;
@@ -329,6 +327,7 @@ struct WaveItem {
   uint64_t e0, e1;
   const int32_t* list;
   uint32_t f_lo, f_hi;
+  uint32_t carry0;  // the flattened start of entry e0
   int64_t item;
 };
 
@@ -386,19 +385,24 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
     if (qh[ii] >= kTQ) qh[ii] -= kTQ;
     qn[ii] -= count;
   };
+  uint32_t carry = w.carry0;  // sources of the list entries before c0 (wave-uniform)
   for (uint64_t c0 = w.e0; c0 < w.e1; c0 += 64) {
-    // 64 list entries: their particle ranges clipped to the run, flattened
-    // by a prefix scan
+    // 64 list entries: their particle ranges [fb, fe) in the flattened
+    // order, then clipped to the run
     int cnt = 0, lo = 0;
     uint32_t fb = 0xffffffffu;
-    if (c0 + lane < w.e1) {
-      const NodeInfo si = a.info[w.list[c0 + lane]];
-      const uint32_t fe = a.flat[c0 + lane];
+    NodeInfo si{};
+    const bool in = c0 + lane < w.e1;
+    if (in) si = a.info[w.list[c0 + lane]];
+    const int sincl = wave_incl_scan(in ? si.cnt : 0);
+    if (in) {
+      const uint32_t fe = carry + (uint32_t)sincl;
       fb = fe - (uint32_t)si.cnt;
       const uint32_t b = fb > w.f_lo ? fb : w.f_lo;
       const uint32_t en = fe < w.f_hi ? fe : w.f_hi;
       if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
     }
+    carry += (uint32_t)__builtin_amdgcn_readlane(sincl, 63);
     // lane 0 always holds an entry (c0 < e1)
     if ((uint32_t)__builtin_amdgcn_readfirstlane(fb) >= w.f_hi) break;  // the run is done
     const int incl = wave_incl_scan(cnt);
@@ -513,19 +517,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     w.e1 = a.p2p_off[l + 1];
     w.list = a.p2p_list;
   }
-  // this item's run [f_lo, f_hi) of the leaf's flattened sources, and the
-  // first list entry that reaches into it
+  // this item's run [f_lo, f_hi) of the leaf's flattened sources, from the
+  // list entry that holds its first source
   w.f_lo = kitem * kP2PItem;
-  const uint32_t ftot = a.flat[w.e1 - 1];
+  const uint32_t ftot = a.src_total[l];
   w.f_hi = w.f_lo + kP2PItem < ftot ? w.f_lo + kP2PItem : ftot;
-  if (kitem > 0) {
-    uint64_t lo_e = w.e0, hi_e = w.e1 - 1;  // flat[e1 - 1] = ftot > f_lo
-    while (lo_e < hi_e) {
-      const uint64_t mid = (lo_e + hi_e) >> 1;
-      if (a.flat[mid] > w.f_lo) hi_e = mid; else lo_e = mid + 1;
-    }
-    w.e0 = lo_e;
-  }
+  w.carry0 = 0;
+  if (kitem > 0) { w.e0 = a.item_e0[item]; w.carry0 = a.item_c0[item]; }
   __shared__ int q[TG * kTQ];
   uint32_t nsoft = 0;
   int t0 = 0;
@@ -538,10 +536,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
-// per list entry, the end of its particles in the leaf's flattened sources;
-// items per leaf: max(1, ceil(sources / kP2PItem)).  One wave per leaf.
+// per leaf, the particles over its P2P list entries and its work items:
+// max(1, ceil(sources / kP2PItem)).  One wave per leaf.  (The level walk
+// computes both in its leaf count pass.)
 template <bool NODE>
-__global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ flat,
+__global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ src_total,
                                                         uint32_t* __restrict__ cnt) {
   const int l = blockIdx.x;
   const int lane = threadIdx.x;
@@ -562,23 +561,58 @@ __global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __
     const bool in = c0 + lane < e1;
     const int c = in ? a.info[list[c0 + lane]].cnt : 0;
     const int incl = wave_incl_scan(c);
-    if (in) flat[c0 + lane] = carry + (uint32_t)incl;
     carry += (uint32_t)__shfl(incl, 63, 64);
   }
   if (lane == 0) {
+    src_total[l] = carry;
     const uint32_t k = (carry + kP2PItem - 1) / kP2PItem;
     cnt[l] = k > 0 ? k : 1u;
   }
 }
 
-__global__ void k_p2p_items_fill(NearArgs a, int32_t* __restrict__ item_leaf,
-                                 uint32_t* __restrict__ item_k) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= a.nleaves) return;
+// item_leaf / item_k of every item, and for each item after a leaf's first
+// the list entry holding its first source and that entry's start in the
+// flattened order (item k starts at source k * kP2PItem).  One wave per leaf.
+template <bool NODE>
+__global__ __launch_bounds__(64) void k_p2p_items_fill(NearArgs a, int32_t* __restrict__ item_leaf,
+                                                       uint32_t* __restrict__ item_k,
+                                                       uint32_t* __restrict__ item_e0,
+                                                       uint32_t* __restrict__ item_c0) {
+  const int l = blockIdx.x;
+  const int lane = threadIdx.x;
   const uint32_t b = a.item_off[l], e = a.item_off[l + 1];
-  for (uint32_t t = b; t < e; ++t) {
+  for (uint32_t t = b + lane; t < e; t += 64) {
     item_leaf[t] = l;
     item_k[t] = t - b;
+  }
+  if (e - b <= 1) return;  // (uniform)
+  uint64_t e0, e1;
+  const int32_t* list;
+  if (NODE) {
+    const int node = a.leaf_node[l];
+    e0 = a.node_p2p_off[node];
+    e1 = e0 + a.node_p2p_cnt[node];
+    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    e0 = a.p2p_off[l];
+    e1 = a.p2p_off[l + 1];
+    list = a.p2p_list;
+  }
+  uint32_t carry = 0;
+  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
+    const bool in = c0 + lane < e1;
+    const uint32_t c = in ? (uint32_t)a.info[list[c0 + lane]].cnt : 0u;
+    const int incl = wave_incl_scan((int)c);
+    const uint32_t fe = carry + (uint32_t)incl, fb = fe - c;
+    if (in && c > 0) {
+      uint32_t k = (fb + kP2PItem - 1) / kP2PItem;
+      if (k == 0) k = 1;
+      for (; k * kP2PItem < fe && b + k < e; ++k) {
+        item_e0[b + k] = (uint32_t)(c0 + lane);
+        item_c0[b + k] = fb;
+      }
+    }
+    carry += (uint32_t)__shfl(incl, 63, 64);
   }
 }
 
@@ -670,17 +704,20 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
     launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 
-void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, uint32_t* item_cnt,
-                            hipStream_t s) {
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* src_total,
+                            uint32_t* item_cnt, hipStream_t s) {
   if (a.nleaves <= 0) return;
-  if (node_lists) k_p2p_items_count<true><<<a.nleaves, 64, 0, s>>>(a, flat, item_cnt);
-  else k_p2p_items_count<false><<<a.nleaves, 64, 0, s>>>(a, flat, item_cnt);
+  if (node_lists) k_p2p_items_count<true><<<a.nleaves, 64, 0, s>>>(a, src_total, item_cnt);
+  else k_p2p_items_count<false><<<a.nleaves, 64, 0, s>>>(a, src_total, item_cnt);
 }
 
-void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k,
-                           hipStream_t s) {
+void launch_p2p_items_fill(bool node_lists, const NearArgs& a, int32_t* item_leaf,
+                           uint32_t* item_k, uint32_t* item_e0, uint32_t* item_c0, hipStream_t s) {
   if (a.nleaves <= 0) return;
-  k_p2p_items_fill<<<blocks_for(a.nleaves, 256), 256, 0, s>>>(a, item_leaf, item_k);
+  if (node_lists)
+    k_p2p_items_fill<true><<<a.nleaves, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
+  else
+    k_p2p_items_fill<false><<<a.nleaves, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
 }
 
 void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s) {

@@ -97,6 +97,8 @@ struct Emit {
   // of its region); exp_lane sums this lane's opened entries, an internal
   // one counted twice
   uint32_t exp_lane;
+  // leaf: this lane's share of the particles of the P2P entries
+  uint32_t src_lane;
 };
 
 template <bool WRITE>
@@ -268,7 +270,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
                                           const uint32_t (&t0)[U], const uint32_t (&t1)[U],
                                           const int (&nt)[U], Emit& e, uint32_t* stk,
                                           uint32_t& sp) {
-  int kk[U][2], cc[U][2];
+  int kk[U][2], cc[U][2], pc[U][2];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -276,9 +278,10 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
       const bool valid = q < nt[u];
       const uint32_t t = valid ? (q ? t1[u] : t0[u]) : (uint32_t)v;  // a valid index
       const int k = classify3(a, v, rv, t);
-      const int c = a.info[t].child;
+      const NodeInfo ti = a.info[t];
       kk[u][q] = valid ? k : -1;
-      cc[u][q] = valid ? c : 0;
+      cc[u][q] = valid ? ti.child : 0;
+      pc[u][q] = ti.cnt;
     }
   }
   bool ok = true;
@@ -295,6 +298,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
         // a leaf, or a whole subtree of P2P sources kept as one entry
         if (k == 2) { selq |= 1u << q; ++nq; }
         else { selp |= 1u << q; ++np; }
+        e.src_lane += (uint32_t)pc[u][q];
       } else {
         if (q) open1 = true; else open0 = true;
       }
@@ -465,13 +469,22 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
     if (lane == 0) { a.m2l_off[v] = e.m2l_base; a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
   }
   walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
-  if (!FILL && lane == 0) {
-    const uint32_t np = e.p2p_run + e.plain_run;
-    a.m2l_cnt[v] = e.m2l_run;
-    a.p2p_cnt[v] = np;
-    a.open_cnt[v] = 0;
-    a.leaf_m2l_cnt[l] = e.m2l_run;
-    a.leaf_p2p_cnt[l] = np;
+  if (!FILL) {
+    uint32_t ns = e.src_lane;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
+    if (lane == 0) {
+      const uint32_t np = e.p2p_run + e.plain_run;
+      a.m2l_cnt[v] = e.m2l_run;
+      a.p2p_cnt[v] = np;
+      a.open_cnt[v] = 0;
+      a.leaf_m2l_cnt[l] = e.m2l_run;
+      a.leaf_p2p_cnt[l] = np;
+      // P2P work items of the leaf: runs of at most kP2PItem source particles
+      a.src_total[l] = ns;
+      const uint32_t k = (ns + kP2PItem - 1) / kP2PItem;
+      a.item_cnt[l] = k > 0 ? k : 1u;
+    }
   }
 }
 
@@ -655,6 +668,8 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
   k_nodewalk_leaves<false><<<a.nleaves, 64, lds, s>>>(a);
   scan_u32(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3, scan_tmp, s);
   scan_u32(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2, scan_tmp, s);
+  // P2P work items: item_off[nleaves] = their total (read back with the walk's)
+  scan_u32(a.item_cnt, a.item_off, a.nleaves, a.item_off + a.nleaves, scan_tmp, s);
   k_nodewalk_leaves<true><<<a.nleaves, 64, lds, s>>>(a);
 }
 

@@ -36,7 +36,7 @@ enum BufId {
   B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
-  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_P2PFLAT, B_SOFTCNT,
+  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0,
   B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
   B_COUNT
 };
@@ -68,6 +68,7 @@ struct sfmm_ctx {
   // level walk: nodes per depth (host copy) and pool capacities
   std::vector<uint32_t> level_off;
   uint64_t m2l_cap = 0, p2p_cap = 0;
+  int64_t items_from_walk = 0;  // P2P work items counted by the level walk
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
@@ -408,6 +409,16 @@ int walk_per_leaf(sfmm_ctx* ctx, double theta) {
   return SFMM_OK;
 }
 
+// per-leaf P2P item buffers (source totals, item counts, item offsets)
+int ensure_item_buffers(sfmm_ctx* ctx) {
+  int rc;
+  const size_t nl = (size_t)std::max<int64_t>(ctx->nleaves, 1);
+  if ((rc = ensure(ctx, B_SRCTOT, sizeof(uint32_t) * nl))) return rc;
+  if ((rc = ensure(ctx, B_ITEMCNT, sizeof(uint32_t) * nl))) return rc;
+  if ((rc = ensure(ctx, B_ITEMOFF, sizeof(uint32_t) * (nl + 1)))) return rc;
+  return SFMM_OK;
+}
+
 // level-synchronous walk: one launch per depth; pools grow and the walk is
 // repeated if a list pool or a lowering stack was too small
 int walk_levels(sfmm_ctx* ctx, double theta) {
@@ -421,6 +432,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
+  if ((rc = ensure_item_buffers(ctx))) return rc;
   for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
@@ -480,6 +492,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
     a.leaf_m2l_off = P<uint32_t>(ctx, B_LWM2LOFF);
     a.leaf_p2p_off = P<uint32_t>(ctx, B_LWP2POFF);
+    a.src_total = P<uint32_t>(ctx, B_SRCTOT);
+    a.item_cnt = P<uint32_t>(ctx, B_ITEMCNT);
+    a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
     // internal nodes level by level, then every leaf
     for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_off[k + 1] - ctx->level_off[k]), s);
@@ -488,9 +503,13 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
     uint32_t htot[4];
     int hstatus[4];
+    uint32_t hitems = 0;
     HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+    if (nl > 0)
+      HIPCHK(hipMemcpyAsync(&hitems, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    ctx->items_from_walk = hitems;
     const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
     const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
@@ -635,30 +654,37 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   // one leaf; their number is read back to size the partial sums
   int64_t items = 0;
   if (ctx->cfg.leaf_size <= 16) {
-    struct { int id; size_t bytes; } need4[] = {
-        {B_P2PFLAT, sizeof(uint32_t) * (size_t)std::max<uint64_t>(ctx->p2p_total, 1)},
-        {B_ITEMCNT, sizeof(uint32_t) * (size_t)nl}, {B_ITEMOFF, sizeof(uint32_t) * (size_t)(nl + 1)}};
-    for (auto& q : need4)
-      if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
+    // P2P work items: the level walk has counted them (and read their total
+    // back with its own totals); the per-leaf walk's lists are counted here
+    if ((rc = ensure_item_buffers(ctx))) return rc;
     uint32_t* item_off = P<uint32_t>(ctx, B_ITEMOFF);
-    a.flat = P<uint32_t>(ctx, B_P2PFLAT);
+    a.src_total = P<uint32_t>(ctx, B_SRCTOT);
     a.item_off = item_off;
-    launch_p2p_items_count(level, a, P<uint32_t>(ctx, B_P2PFLAT), P<uint32_t>(ctx, B_ITEMCNT), s);
-    scan_u32(P<uint32_t>(ctx, B_ITEMCNT), item_off, nl, item_off + nl, P<uint32_t>(ctx, B_SCANTMP), s);
-    uint32_t htot = 0;
-    HIPCHK(hipMemcpyAsync(&htot, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    items = htot;
+    if (level) {
+      items = ctx->items_from_walk;
+    } else {
+      launch_p2p_items_count(level, a, P<uint32_t>(ctx, B_SRCTOT), P<uint32_t>(ctx, B_ITEMCNT), s);
+      scan_u32(P<uint32_t>(ctx, B_ITEMCNT), item_off, nl, item_off + nl, P<uint32_t>(ctx, B_SCANTMP),
+               s);
+      uint32_t htot = 0;
+      HIPCHK(hipMemcpyAsync(&htot, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      items = htot;
+    }
     const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
     struct { int id; size_t bytes; } need5[] = {
         {B_ITEMLEAF, sizeof(int32_t) * (size_t)items}, {B_ITEMK, sizeof(uint32_t) * (size_t)items},
+        {B_ITEME0, sizeof(uint32_t) * (size_t)items}, {B_ITEMC0, sizeof(uint32_t) * (size_t)items},
         {B_PART, sizeof(double) * 4 * (size_t)ls * (size_t)items}};
     for (auto& q : need5)
       if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
     a.item_leaf = P<int32_t>(ctx, B_ITEMLEAF);
     a.item_k = P<uint32_t>(ctx, B_ITEMK);
     a.part = P<double>(ctx, B_PART);
-    launch_p2p_items_fill(a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK), s);
+    a.item_e0 = P<uint32_t>(ctx, B_ITEME0);
+    a.item_c0 = P<uint32_t>(ctx, B_ITEMC0);
+    launch_p2p_items_fill(level, a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK),
+                          P<uint32_t>(ctx, B_ITEME0), P<uint32_t>(ctx, B_ITEMC0), s);
   }
   KernelMarks km;
   km.begin = phase_event(ctx, 6, 0);

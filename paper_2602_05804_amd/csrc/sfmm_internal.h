@@ -172,6 +172,9 @@ struct NodeWalkArgs {
   int nleaves;
   const int32_t* leaf_node;
   uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt, *leaf_m2l_off, *leaf_p2p_off;
+  // per leaf: particles over its P2P entries, P2P work items and their offsets
+  // ([nleaves + 1], the last entry the total)
+  uint32_t *src_total, *item_cnt, *item_off;
   uint32_t stack_cap;  // LDS lowering stack, entries
   int* status;
 };
@@ -258,20 +261,25 @@ struct NearArgs {
   // list entries (leaves, or whole subtrees), are cut into runs of at most
   // kP2PItem source particles, one wave per run; each item writes partial
   // sums for the leaf's targets, which a second kernel adds in item order
-  const uint32_t* flat;      // per list entry: end of its particles in the leaf's flattened sources
+  const uint32_t* src_total;  // per leaf: particles over its P2P list entries
   const uint32_t* item_off;  // [nleaves + 1] first item of each leaf; [nleaves] = total
   const int32_t* item_leaf;  // [items] leaf of each item
   const uint32_t* item_k;    // [items] index of the item within its leaf
+  const uint32_t* item_e0;   // [items] (k > 0) list entry holding the item's first source
+  const uint32_t* item_c0;   // [items] (k > 0) that entry's start in the flattened order
   double* part;              // [items][LS][4] partial field (x, y, z) and potential
   unsigned long long* soft_pairs;  // count of pairs inside a kernel (queueing shape)
 };
 constexpr uint32_t kP2PItem = 2048;
-// per-entry flattened ends (flat) and the number of items of each leaf
-// (item_cnt, nleaves entries); one wave per leaf
-void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* flat, uint32_t* item_cnt,
-                            hipStream_t s);
+// particles over each leaf's P2P entries (src_total) and the number of
+// items of each leaf (item_cnt), nleaves entries each; one wave per leaf
+void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* src_total,
+                            uint32_t* item_cnt, hipStream_t s);
 // item_leaf / item_k from the scanned item offsets
-void launch_p2p_items_fill(const NearArgs& a, int32_t* item_leaf, uint32_t* item_k, hipStream_t s);
+// item_leaf / item_k of every item; item_e0 / item_c0 of the items after a
+// leaf's first (one wave per leaf)
+void launch_p2p_items_fill(bool node_lists, const NearArgs& a, int32_t* item_leaf,
+                           uint32_t* item_k, uint32_t* item_e0, uint32_t* item_c0, hipStream_t s);
 // wave-per-item kernel for leaf_size <= 16 (then the reduction in item
 // order), particle-per-thread otherwise; items: the bound on the item count
 // HIP events recorded on the stream around the main P2P kernel alone (null:
