@@ -118,7 +118,10 @@ typedef struct {
  *   queue (5), passes of 5 with the queue (6).
  * near_kernel, leaf_size <= 16: scalar-register targets in passes of 8 (0),
  *   6 (7), 16 (8); one thread per particle (1); targets in LDS, passes of 8
- *   without (5) and with (6) the queue. */
+ *   without (5) and with (6) the queue.
+ * near_kernel with SFMM_FP32C: the wave kernel with scalar-register targets
+ *   and a queue per target (every value but 6), the earlier shape with the
+ *   targets in LDS and the softened branch taken in the pass (6). */
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
 typedef struct {

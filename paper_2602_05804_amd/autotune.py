@@ -26,7 +26,7 @@ from typing import Dict, Optional
 LEAF_SIZES = (6, 8, 10, 12, 16)
 NEAR_KERNELS = (0, 10, 7, 11, 12, 6)
 FAR_KERNELS_SHARED = (0, 1, 2, 3)
-TOP_DEPTHS = (4, 8, 12)
+TOP_DEPTHS = (4, 8, 12, 128)  # 128: every M2L in FP64
 
 
 def default_cache_path() -> str:

@@ -347,6 +347,242 @@ __global__ __launch_bounds__(64) void k_p2p_leaf32(NearArgs a, const float4* __r
   if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
+// ---- P2P, wave per item with the targets in scalar registers -------------------
+// The FP32 form of k_p2p_wave (k_near.hip): wave-uniform loop control, the
+// targets of a pass (FP32 offsets and 4 h^2) as wave-uniform values, the
+// field of a pair beyond both kernels as m/r^3 (dx, dy, dz) and m/r with 1/r
+// replaced by 0 inside a kernel, and the pairs inside a kernel queued per
+// target (with the pair's FP32 centre difference) and evaluated 64 at a
+// time.  Every term is added into FP64 sums.
+__device__ __forceinline__ float wave_uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+struct Wave32Item {
+  int tlo, nt;
+  uint64_t e0, e1;
+  const int32_t* list;
+  uint32_t f_lo, f_hi, carry0;
+  int64_t item;
+  double ct0, ct1, ct2;  // the target leaf's centre
+};
+
+constexpr uint32_t kTQ32 = 128;  // queue slots per target (63 + 64)
+
+template <int K, int LS, int RS>
+__device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4* __restrict__ pf,
+                                                const float2* __restrict__ phh, const Wave32Item& w,
+                                                int t0, int* qj, float* qc, uint32_t& nsoft) {
+  const int lane = threadIdx.x;
+  const int tlo = w.tlo;
+  float tx[K], ty[K], tz[K], t4[K];
+  double fx[K], fy[K], fz[K], ph[K];
+  uint32_t qn[K];
+#pragma unroll
+  for (int ii = 0; ii < K; ++ii) {
+    const float4 o = pf[tlo + t0 + ii];
+    tx[ii] = wave_uniform_f(o.x);
+    ty[ii] = wave_uniform_f(o.y);
+    tz[ii] = wave_uniform_f(o.z);
+    const float hu = wave_uniform_f(phh[tlo + t0 + ii].x);
+    t4[ii] = 4.0f * hu * hu;
+    fx[ii] = 0.0; fy[ii] = 0.0; fz[ii] = 0.0; ph[ii] = 0.0;
+    qn[ii] = 0;
+  }
+  // the first `count` queued pairs of target ii (the rest moves down)
+  auto flush = [&](auto iic, uint32_t count) {
+    constexpr int ii = decltype(iic)::value;
+    __syncthreads();
+    const bool act = (uint32_t)lane < count;
+    int* qjt = qj + ii * kTQ32;
+    float* qct = qc + ii * kTQ32 * 3;
+    const int j2 = act ? qjt[lane] : tlo;
+    const float cx = act ? qct[3 * lane] : 0.f, cy = act ? qct[3 * lane + 1] : 0.f,
+                cz = act ? qct[3 * lane + 2] : 0.f;
+    const float2 th = phh[tlo + t0 + ii];
+    const float hi = wave_uniform_f(th.x), hiinv = wave_uniform_f(th.y);
+    const float4 oj = pf[j2];
+    const float2 hj = phh[j2];
+    const float dx = cx + (tx[ii] - oj.x), dy = cy + (ty[ii] - oj.y), dz = cz + (tz[ii] - oj.z);
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float rinv = r2 > 0.f ? __frsqrt_rn(r2) : 0.f;
+    const float rinv3 = rinv * rinv * rinv;
+    const float r = r2 * rinv;
+    float g1, p1, g2, p2;
+    soft32(r * hiinv, hiinv, hi * rinv, rinv, rinv3, g1, p1);
+    soft32(r * hj.y, hj.y, hj.x * rinv, rinv, rinv3, g2, p2);
+    const float wm = act ? oj.w : 0.f;
+    const float mg = wm * (0.5f * (g1 + g2));
+    fx[ii] += (double)(mg * dx);
+    fy[ii] += (double)(mg * dy);
+    fz[ii] += (double)(mg * dz);
+    ph[ii] += (double)(wm * (0.5f * (p1 + p2)));
+    // the remainder moves to the front of the queue
+    const uint32_t rem = qn[ii] - count;
+    int tj = 0;
+    float ta = 0.f, tb = 0.f, tc = 0.f;
+    if ((uint32_t)lane < rem) {
+      tj = qjt[count + lane];
+      ta = qct[3 * (count + lane)]; tb = qct[3 * (count + lane) + 1]; tc = qct[3 * (count + lane) + 2];
+    }
+    __syncthreads();
+    if ((uint32_t)lane < rem) {
+      qjt[lane] = tj;
+      qct[3 * lane] = ta; qct[3 * lane + 1] = tb; qct[3 * lane + 2] = tc;
+    }
+    qn[ii] = rem;
+  };
+  uint32_t carry = w.carry0;  // sources of the list entries before c0 (wave-uniform)
+  for (uint64_t c0 = w.e0; c0 < w.e1; c0 += 64) {
+    // 64 list entries: their particle ranges [fb, fe) in the flattened
+    // order, clipped to the run; a leaf entry's FP32 centre difference
+    int cnt = 0, lo = 0, sub = 0;
+    uint32_t fb = 0xffffffffu;
+    float dcx = 0.f, dcy = 0.f, dcz = 0.f;
+    const bool in = c0 + lane < w.e1;
+    const int src = in ? w.list[c0 + lane] : 0;
+    NodeInfo si{};
+    if (in) si = a.info[src];
+    const int sincl = wave_incl_scan32(in ? si.cnt : 0);
+    if (in) {
+      const uint32_t fe = carry + (uint32_t)sincl;
+      fb = fe - (uint32_t)si.cnt;
+      const uint32_t b = fb > w.f_lo ? fb : w.f_lo;
+      const uint32_t en = fe < w.f_hi ? fe : w.f_hi;
+      if (en > b) { cnt = (int)(en - b); lo = si.lo + (int)(b - fb); }
+      // a whole subtree: its particles' offsets are relative to their own
+      // leaves, whose centres are looked up per particle
+      sub = si.child >= 0 ? 1 : 0;
+      const double* rs = a.rec + (int64_t)src * RS;
+      dcx = (float)(w.ct0 - rs[0]);
+      dcy = (float)(w.ct1 - rs[1]);
+      dcz = (float)(w.ct2 - rs[2]);
+    }
+    carry += (uint32_t)__builtin_amdgcn_readlane(sincl, 63);
+    // lane 0 always holds an entry (c0 < e1)
+    if ((uint32_t)__builtin_amdgcn_readfirstlane(fb) >= w.f_hi) break;  // the run is done
+    const int incl = wave_incl_scan32(cnt);
+    const int pre = incl - cnt;
+    const int total = __builtin_amdgcn_readlane(incl, 63);
+    for (int f0 = 0; f0 < total; f0 += 64) {
+      const int f = f0 + lane;
+      int k = 0;
+#pragma unroll
+      for (int step = 32; step > 0; step >>= 1) {
+        const int pk = __shfl(pre, k + step, 64);
+        if (pk <= f) k += step;
+      }
+      const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+      float cx = __shfl(dcx, k, 64), cy = __shfl(dcy, k, 64), cz = __shfl(dcz, k, 64);
+      const int jsub = __shfl(sub, k, 64);
+      const bool fv = f < total;
+      const int j = fv ? jj : tlo;  // a valid index; contributes nothing
+      if (fv && jsub) {
+        const double* rl = a.rec + (int64_t)a.leaf_node[a.p_leaf[j]] * RS;
+        cx = (float)(w.ct0 - rl[0]);
+        cy = (float)(w.ct1 - rl[1]);
+        cz = (float)(w.ct2 - rl[2]);
+      }
+      const float4 oj = pf[j];
+      const float hj = phh[j].x;
+      const float mj = fv ? oj.w : 0.f;
+      const float h4j = 4.0f * hj * hj;
+#pragma unroll
+      for (int ii = 0; ii < K; ++ii) {
+        const float dx = cx + (tx[ii] - oj.x), dy = cy + (ty[ii] - oj.y), dz = cz + (tz[ii] - oj.z);
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        const bool inside = r2 < fmaxf(t4[ii], h4j);
+        const float rinv = inside ? 0.f : __builtin_amdgcn_rsqf(r2);
+        const float mr = mj * rinv;
+        const float mg = mr * (rinv * rinv);
+        fx[ii] += (double)(mg * dx);
+        fy[ii] += (double)(mg * dy);
+        fz[ii] += (double)(mg * dz);
+        ph[ii] += (double)mr;
+        // (keeps this target's arithmetic ahead of the queue branch)
+        asm volatile("" ::"v"(fx[ii]), "v"(fy[ii]), "v"(fz[ii]), "v"(ph[ii]));
+        const bool push = inside && fv && j != tlo + t0 + ii;
+        const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
+        if (bal) {
+          if (push) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            const uint32_t sl = qn[ii] + below;
+            qj[ii * kTQ32 + sl] = j;
+            float* qq = qc + (ii * kTQ32 + sl) * 3;
+            qq[0] = cx; qq[1] = cy; qq[2] = cz;
+          }
+          const uint32_t c = (uint32_t)__popcll(bal);
+          qn[ii] += c;
+          nsoft += c;
+        }
+      }
+      // a queue holds at most 63 + 64 entries here
+      static_for<K>([&](auto iic) {
+        constexpr int ii = decltype(iic)::value;
+        if (qn[ii] >= 64) flush(iic, 64);
+      });
+    }
+  }
+  static_for<K>([&](auto iic) {
+    constexpr int ii = decltype(iic)::value;
+    if (qn[ii] > 0) flush(iic, qn[ii]);
+  });
+#pragma unroll
+  for (int ii = 0; ii < K; ++ii) {
+    const double sx = wave_sum64(fx[ii]), sy = wave_sum64(fy[ii]), sz = wave_sum64(fz[ii]);
+    const double sp = wave_sum64(ph[ii]);
+    if (lane == t0 + ii) {
+      double* o = a.part + (w.item * LS + t0 + ii) * 4;
+      o[0] = sx; o[1] = sy; o[2] = sz; o[3] = sp;
+    }
+  }
+}
+
+template <int LS, bool NODE, int RS, int TG, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_p2p_wave32(
+    NearArgs a, const float4* __restrict__ pf, const float2* __restrict__ phh) {
+  const int lane = threadIdx.x;
+  const uint32_t item = xcd_block(blockIdx.x, gridDim.x);
+  if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
+  const int l = a.item_leaf[item];
+  const uint32_t kitem = a.item_k[item];
+  const int node = a.leaf_node[l];
+  const NodeInfo ti = a.info[node];
+  Wave32Item w;
+  w.tlo = ti.lo;
+  w.nt = ti.cnt;
+  w.item = item;
+  const double* rt = a.rec + (int64_t)node * RS;
+  w.ct0 = rt[0]; w.ct1 = rt[1]; w.ct2 = rt[2];
+  if (NODE) {
+    w.e0 = a.node_p2p_off[node];
+    w.e1 = w.e0 + a.node_p2p_cnt[node];
+    w.list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+  } else {
+    w.e0 = a.p2p_off[l];
+    w.e1 = a.p2p_off[l + 1];
+    w.list = a.p2p_list;
+  }
+  w.f_lo = kitem * kP2PItem;
+  const uint32_t ftot = a.src_total[l];
+  w.f_hi = w.f_lo + kP2PItem < ftot ? w.f_lo + kP2PItem : ftot;
+  w.carry0 = 0;
+  if (kitem > 0) { w.e0 = a.item_e0[item]; w.carry0 = a.item_c0[item]; }
+  __shared__ int qj[TG * kTQ32];
+  __shared__ float qc[TG * kTQ32 * 3];
+  uint32_t nsoft = 0;
+  int t0 = 0;
+  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave32_pass<TG, LS, RS>(a, pf, phh, w, t0, qj, qc, nsoft);
+  // the remainder, a pass with a fixed target count (uniform branches)
+  static_for<TG>([&](auto rc) {
+    constexpr int r = decltype(rc)::value;
+    if (r > 0 && w.nt - t0 == r)
+      p2p_wave32_pass<(r > 0 ? r : 1), LS, RS>(a, pf, phh, w, t0, qj, qc, nsoft);
+  });
+  if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
+}
+
 constexpr int kFarSplit32 = 2;
 
 template <int P>
@@ -364,13 +600,21 @@ void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                                                                zs, ms, hs, pf, ph);
 }
 
+// variant 0: the wave kernel with scalar-register targets; 6: the earlier
+// shape (targets in LDS, the softened branch taken in the pass)
 template <int LS, int RS>
-void p2p32(bool node_lists, const NearArgs& a, const float4* pf, const float2* ph, int64_t items,
-           hipStream_t s, KernelMarks km) {
+void p2p32(bool node_lists, int variant, const NearArgs& a, const float4* pf, const float2* ph,
+           int64_t items, hipStream_t s, KernelMarks km) {
   constexpr int TG = LS <= 10 ? 5 : 8;
+  const unsigned nb = (unsigned)items;
   record_mark(km.begin, s);
-  if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
-  else k_p2p_leaf32<LS, false, RS, TG><<<(unsigned)items, 64, 0, s>>>(a, pf, ph);
+  if (variant == 6) {
+    if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<nb, 64, 0, s>>>(a, pf, ph);
+    else k_p2p_leaf32<LS, false, RS, TG><<<nb, 64, 0, s>>>(a, pf, ph);
+  } else {
+    if (node_lists) k_p2p_wave32<LS, true, RS, TG, 4><<<nb, 64, 0, s>>>(a, pf, ph);
+    else k_p2p_wave32<LS, false, RS, TG, 4><<<nb, 64, 0, s>>>(a, pf, ph);
+  }
   record_mark(km.end, s);
   launch_p2p_reduce(a, LS, s);
 }
@@ -409,17 +653,18 @@ void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec
   }
 }
 
-bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, int64_t items, hipStream_t s, KernelMarks km) {
+bool launch_near32(int order, bool node_lists, int leaf_size, int variant, const NearArgs& a,
+                   const float4* pf, const float2* ph, int64_t items, hipStream_t s,
+                   KernelMarks km) {
   if (a.n <= 0) return true;
   const int RS = rec_stride(order);
   if (leaf_size > 16) return false;
 #define SFMM_P2P32(LS)                                                   \
   switch (RS) {                                                          \
-    case 16: p2p32<LS, 16>(node_lists, a, pf, ph, items, s, km); break;      \
-    case 24: p2p32<LS, 24>(node_lists, a, pf, ph, items, s, km); break;      \
-    case 32: p2p32<LS, 32>(node_lists, a, pf, ph, items, s, km); break;      \
-    case 48: p2p32<LS, 48>(node_lists, a, pf, ph, items, s, km); break;      \
+    case 16: p2p32<LS, 16>(node_lists, variant, a, pf, ph, items, s, km); break;      \
+    case 24: p2p32<LS, 24>(node_lists, variant, a, pf, ph, items, s, km); break;      \
+    case 32: p2p32<LS, 32>(node_lists, variant, a, pf, ph, items, s, km); break;      \
+    case 48: p2p32<LS, 48>(node_lists, variant, a, pf, ph, items, s, km); break;      \
   }
   if (leaf_size <= 10) { SFMM_P2P32(10) } else { SFMM_P2P32(16) }
 #undef SFMM_P2P32

@@ -16,9 +16,6 @@
 #include "sfmm_internal.h"
 #include "softening.h"
 
-#include <type_traits>
-#include <utility>
-
 namespace sfmm {
 namespace {
 
@@ -111,16 +108,6 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{})
-template <int N, typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-  (f(std::integral_constant<int, I>{}), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
 }
 
 // TG == 0: one pass over the sources for all targets, the loop over the

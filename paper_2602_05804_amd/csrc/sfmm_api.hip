@@ -689,8 +689,8 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   KernelMarks km;
   km.begin = phase_event(ctx, 6, 0);
   km.end = phase_event(ctx, 6, 1);
-  if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, a, P<float4>(ctx, B_PF32),
-                        P<float2>(ctx, B_PH32), items, s, km);
+  if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, ctx->near_variant, a,
+                        P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), items, s, km);
   else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, s, km);
   phase_mark(ctx, 4, 1);
   phase_mark(ctx, 5, 0);

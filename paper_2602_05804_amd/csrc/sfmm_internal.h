@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
+#include <utility>
 
 #include "expansions_gen.h"
 
@@ -34,6 +36,16 @@ constexpr int kMaxOrder = 4;
 __host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
 __host__ __device__ constexpr int rec_stride(int p) { return ((8 + ncoef(p) + 7) / 8) * 8; }
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// f(std::integral_constant<int, 0>{}), ..., f(std::integral_constant<int, N - 1>{})
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
 
 // Workgroups of a launch are dealt to the chip's 8 XCDs (each with its own
 // L2) in turn.  Work whose neighbours share data (leaves in Morton order,
@@ -305,8 +317,11 @@ void launch_prep32(int order, int nn, int nleaves, const int32_t* leaf_node, con
 void launch_far32(int order, bool node_lists, const FarArgs& a, const float* rec32, int top,
                   hipStream_t s);
 // false when leaf_size > 16 (not built)
-bool launch_near32(int order, bool node_lists, int leaf_size, const NearArgs& a, const float4* pf,
-                   const float2* ph, int64_t items, hipStream_t s, KernelMarks km = {});
+// variant: the P2P shape (0 the wave kernel with scalar-register targets,
+// 6 the earlier one with targets in LDS; others as 0)
+bool launch_near32(int order, bool node_lists, int leaf_size, int variant, const NearArgs& a,
+                   const float4* pf, const float2* ph, int64_t items, hipStream_t s,
+                   KernelMarks km = {});
 
 void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double kick, double drift,
                      hipStream_t s);

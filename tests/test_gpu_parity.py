@@ -344,6 +344,25 @@ def test_fp32c_plummer(torch, P, orc, top):
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
 
 
+@pytest.mark.parametrize("leaf_size,near_kernel", [(10, 6), (16, 0), (16, 6)])
+def test_fp32c_p2p_shapes(torch, P, orc, leaf_size, near_kernel):
+    """The FP32C P2P shapes (the default wave kernel is covered above) within
+    the FP32C bound against the oracle, with coincident particles."""
+    print(f"case: fp32c P2P shape {near_kernel}, leaf size {leaf_size}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=5)
+    x[100:130] = x[99]
+    s = P.Solver(near_kernel=near_kernel, leaf_size=leaf_size)
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5, leaf_size=leaf_size)
+    assert _rms_rel(acc, oa) <= 1e-6
+    assert np.sqrt((((pot - op) / op) ** 2).mean()) <= 1e-6
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+
+
 def test_fp32c_binary_polytrope(torch, P, orc):
     """Two n=1.5 stars (the binary-polytrope shape at reduced N), sampled."""
     print("case: fp32c binary polytrope 2x30000", flush=True)
