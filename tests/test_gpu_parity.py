@@ -213,6 +213,32 @@ def test_large_softening_all_pairs(torch, P, orc):
     assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
 
 
+@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp64", 3),
+                                                   ("fp32c", 0), ("fp32c", 6)])
+def test_p2p_many_work_items(torch, P, orc, precision, near_kernel):
+    """Every leaf's sources split into several P2P work items (more than 2048
+    source particles per leaf): 7000 particles all inside each other's kernel,
+    so the solve is the softened direct sum; both walks."""
+    print(f"case: P2P work items, {precision} shape {near_kernel}", flush=True)
+    n = 7000
+    x, m, h = workloads.plummer(n, seed=13)
+    h = np.full(n, 1e3)
+    da, dp = orc.direct(x, m, h)
+    tol = TOL if precision == "fp64" else 1e-6
+    for walk in ("level", "leaf"):
+        s = P.Solver(near_kernel=near_kernel, walk=walk)
+        xd, md, hd = dev(torch, x, m, h)
+        acc, pot = s.solve(xd, md, hd, theta=0.9, precision=precision)
+        torch.cuda.synchronize()
+        acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+        assert s.stats()["n_p2p_pairs"] == n * (n - 1)
+        if precision == "fp64":
+            assert rel_err(acc, da).max() < tol and pot_err(pot, dp) < tol
+        else:
+            assert _rms_rel(acc, da) <= tol
+            assert np.sqrt((((pot - dp) / dp) ** 2).mean()) <= tol
+
+
 def test_theta_to_zero_equals_direct(torch, P, orc):
     print("case: theta->0 direct", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
