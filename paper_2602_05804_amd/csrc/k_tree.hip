@@ -432,14 +432,15 @@ __global__ void k_single_leaf(int n, NodeInfo* info, int32_t* leaf_node) {
   leaf_node[0] = 0;
 }
 
+// (node_depth: every node's depth, from the level grouping)
 __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
-                             const NodeInfo* __restrict__ info, int32_t* __restrict__ leaf_depth,
+                             const NodeInfo* __restrict__ info,
+                             const int32_t* __restrict__ node_depth, int32_t* __restrict__ leaf_depth,
                              int32_t* __restrict__ p_leaf, int* maxdepth) {
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nleaves) return;
   const int node = leaf_node[l];
-  int d = 0;
-  for (int v = info[node].parent; v >= 0; v = info[v].parent) ++d;
+  const int d = node_depth[node];
   leaf_depth[l] = d;
   atomicMax(maxdepth, d);
   const NodeInfo ni = info[node];
@@ -523,9 +524,19 @@ __global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
 // one wave per chunk of an internal node: largest squared distance to the
 // node's centre of mass, folded in with an integer max on the FP64 bits
 // (non-negative doubles order like their bit patterns)
+// the node of each chunk (thread per node)
+__global__ void k_extent_map(int nn, int nitems, const uint32_t* __restrict__ chunk_off,
+                             uint32_t* __restrict__ item_node) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  const uint32_t b = chunk_off[v], e = v + 1 < nn ? chunk_off[v + 1] : (uint32_t)nitems;
+  for (uint32_t t = b; t < e; ++t) item_node[t] = (uint32_t)v;
+}
+
 template <int RS>
 __global__ __launch_bounds__(256) void k_extent(int nn, int nitems, const NodeInfo* __restrict__ info,
                                                 const uint32_t* __restrict__ chunk_off,
+                                                const uint32_t* __restrict__ item_node,
                                                 const double* __restrict__ xs,
                                                 const double* __restrict__ ys,
                                                 const double* __restrict__ zs,
@@ -534,13 +545,7 @@ __global__ __launch_bounds__(256) void k_extent(int nn, int nitems, const NodeIn
   const int item = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (item >= nitems) return;
-  // node = last v with chunk_off[v] <= item
-  int lo = 0, hi = nn - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (chunk_off[mid] <= (uint32_t)item) lo = mid; else hi = mid - 1;
-  }
-  const int v = lo;
+  const int v = (int)item_node[item];
   const NodeInfo ni = info[v];
   const int c = item - (int)chunk_off[v];
   const int beg = ni.lo + c * kExtentChunk;
@@ -666,9 +671,10 @@ void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s
 }
 
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
-                       int32_t* leaf_depth, int32_t* p_leaf, int* maxdepth, hipStream_t s) {
-  k_leaf_depth<<<blocks_for(nleaves, 256), 256, 0, s>>>(nleaves, leaf_node, info, leaf_depth,
-                                                        p_leaf, maxdepth);
+                       const int32_t* node_depth, int32_t* leaf_depth, int32_t* p_leaf,
+                       int* maxdepth, hipStream_t s) {
+  k_leaf_depth<<<blocks_for(nleaves, 256), 256, 0, s>>>(nleaves, leaf_node, info, node_depth,
+                                                        leaf_depth, p_leaf, maxdepth);
 }
 
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
@@ -694,16 +700,21 @@ void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStre
 }
 
 void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
-                   const uint32_t* chunk_off, const double* xs, const double* ys,
-                   const double* zs, double* rec, unsigned long long* l2bits, hipStream_t s) {
+                   const uint32_t* chunk_off, uint32_t* item_node, const double* xs,
+                   const double* ys, const double* zs, double* rec, unsigned long long* l2bits,
+                   hipStream_t s) {
   if (nitems <= 0) return;
+  k_extent_map<<<blocks_for(nn, 256), 256, 0, s>>>(nn, nitems, chunk_off, item_node);
   const unsigned nb = blocks_for(nitems, 4);
+#define SFMM_EXTENT(RS) \
+  k_extent<RS><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, item_node, xs, ys, zs, rec, l2bits)
   switch (rec_stride(order)) {
-    case 16: k_extent<16><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
-    case 24: k_extent<24><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
-    case 32: k_extent<32><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
-    case 48: k_extent<48><<<nb, 256, 0, s>>>(nn, nitems, info, chunk_off, xs, ys, zs, rec, l2bits); break;
+    case 16: SFMM_EXTENT(16); break;
+    case 24: SFMM_EXTENT(24); break;
+    case 32: SFMM_EXTENT(32); break;
+    case 48: SFMM_EXTENT(48); break;
   }
+#undef SFMM_EXTENT
 }
 
 void launch_extent_final(int order, int nn, const NodeInfo* info,

@@ -36,7 +36,7 @@ enum BufId {
   B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
-  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0,
+  B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
   B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
   B_COUNT
 };
@@ -313,8 +313,8 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     launch_node_flags(nn, info, sys_sorted, P<uint8_t>(ctx, B_NFLAG), s);
   }
   int* maxd_dev = reinterpret_cast<int*>(small + S_MAXDEPTH);
-  launch_leaf_depth(nl, leaf_node, info, P<int32_t>(ctx, B_LEAFDEPTH), P<int32_t>(ctx, B_PLEAF),
-                    maxd_dev, s);
+  launch_leaf_depth(nl, leaf_node, info, P<int32_t>(ctx, B_NDEPTH), P<int32_t>(ctx, B_LEAFDEPTH),
+                    P<int32_t>(ctx, B_PLEAF), maxd_dev, s);
   if (nn > 1) {
     uint32_t* chunk = P<uint32_t>(ctx, B_CHUNK);
     launch_extent_count(nn, info, chunk, s);
@@ -336,7 +336,9 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                   P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_REC), s);
   if (nn > 1) {
     const int nitems = (int)(hsmall[S_NITEMS] & 0xffffffffu);
-    launch_extent(order, nn, nitems, info, P<uint32_t>(ctx, B_CHUNK), P<double>(ctx, B_XS),
+    if ((rc = ensure(ctx, B_EXTMAP, sizeof(uint32_t) * (size_t)std::max(nitems, 1)))) return rc;
+    launch_extent(order, nn, nitems, info, P<uint32_t>(ctx, B_CHUNK), P<uint32_t>(ctx, B_EXTMAP),
+                  P<double>(ctx, B_XS),
                   P<double>(ctx, B_YS), P<double>(ctx, B_ZS), P<double>(ctx, B_REC),
                   reinterpret_cast<unsigned long long*>(P<uint64_t>(ctx, B_L2BITS)), s);
     launch_extent_final(order, nn, info, reinterpret_cast<unsigned long long*>(P<uint64_t>(ctx, B_L2BITS)),

@@ -120,7 +120,8 @@ void launch_leaf_fill(int n, const uint32_t* leaf_flag, const uint32_t* leaf_sca
                       const int32_t* leaf_at, int32_t* leaf_node, hipStream_t s);
 void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s);
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
-                       int32_t* leaf_depth, int32_t* p_leaf, int* maxdepth, hipStream_t s);
+                       const int32_t* node_depth, int32_t* leaf_depth, int32_t* p_leaf,
+                       int* maxdepth, hipStream_t s);
 // geometry and moments, deepest level first (level_off_host: host copy)
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
@@ -128,8 +129,9 @@ void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
                      double* rec, hipStream_t s);
 void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s);
 void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
-                   const uint32_t* chunk_off, const double* xs, const double* ys,
-                   const double* zs, double* rec, unsigned long long* l2bits, hipStream_t s);
+                   const uint32_t* chunk_off, uint32_t* item_node, const double* xs,
+                   const double* ys, const double* zs, double* rec, unsigned long long* l2bits,
+                   hipStream_t s);
 void launch_extent_final(int order, int nn, const NodeInfo* info,
                          const unsigned long long* l2bits, double* rec, hipStream_t s);
 constexpr int kExtentChunk = 2048;
