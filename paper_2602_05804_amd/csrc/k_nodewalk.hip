@@ -73,15 +73,19 @@ __global__ void k_node_depth(int nn, const NodeInfo* __restrict__ info, int32_t*
   int d = 0;
   for (int u = info[v].parent; u >= 0; u = info[u].parent) ++d;
   depth[v] = d;
-  key[v] = (uint64_t)min(d, 255);
+  // grouped by depth, and within a depth the internal nodes first
+  key[v] = (uint64_t)min(2 * d + (info[v].child < 0 ? 1 : 0), 255);
   ids[v] = (uint32_t)v;
 }
 
+// level k spans [level_off[k], level_off[k + 1]), its internal nodes
+// [level_off[k], level_int[k]) (the scanned histogram of the sort keys)
 __global__ void k_level_offsets(int nlev, int nb, int nn, const uint32_t* __restrict__ hist,
-                                uint32_t* __restrict__ level_off) {
+                                uint32_t* __restrict__ level_off, uint32_t* __restrict__ level_int) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > nlev) return;
-  level_off[k] = k < nlev ? hist[(int64_t)k * nb] : (uint32_t)nn;
+  level_off[k] = k < nlev ? hist[(int64_t)(2 * k) * nb] : (uint32_t)nn;
+  level_int[k] = k < nlev ? hist[(int64_t)(2 * k + 1) * nb] : (uint32_t)nn;
 }
 
 // ---- one level -----------------------------------------------------------------
@@ -382,7 +386,7 @@ __device__ __forceinline__ uint32_t node_region(const NodeWalkArgs& a, uint32_t 
 // fill pass of one level's internal nodes (one wave per node; the level
 // scan has placed their regions)
 __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
   if (idx >= end) return;
   const int v = a.level_nodes[idx];
@@ -550,7 +554,7 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t base = a.levbase[level];
   const uint32_t total = scan_tile(a, beg, end, 0, base, true);
   if (threadIdx.x == 0) {
@@ -561,7 +565,7 @@ __global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int
 
 // tile sums (and the regions, kept for the second pass)
 __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
   uint32_t c = 0;
 #pragma unroll
@@ -577,7 +581,7 @@ __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int 
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_off[level + 1];
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
   uint32_t base = a.levbase[level];
   for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
   const uint32_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
@@ -642,11 +646,13 @@ void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* k
 }
 
 void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
-                          uint32_t* level_off, hipStream_t s) {
-  k_level_offsets<<<(nlev + 1 + 255) / 256, 256, 0, s>>>(nlev, nb, nn, hist_scanned, level_off);
+                          uint32_t* level_off, uint32_t* level_int, hipStream_t s) {
+  k_level_offsets<<<(nlev + 1 + 255) / 256, 256, 0, s>>>(nlev, nb, nn, hist_scanned, level_off,
+                                                          level_int);
 }
 
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s) {
+  // (nodes_in_level: the level's internal nodes)
   if (nodes_in_level <= 0) {
     // an empty level still carries the pool size to the next one
     k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);

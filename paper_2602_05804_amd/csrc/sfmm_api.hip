@@ -31,7 +31,7 @@ enum BufId {
   B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
   B_LDOFF, B_DEPTHCNT, B_M2LCNT, B_P2PCNT, B_PAIRCNT, B_M2L, B_P2P,
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
-  B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES,
+  B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES, B_LEVINT,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
   B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
   B_REC32, B_PF32, B_PH32,
@@ -67,6 +67,7 @@ struct sfmm_ctx {
   hipEvent_t order_ev = nullptr;  // orders work across a stream change
   // level walk: nodes per depth (host copy) and pool capacities
   std::vector<uint32_t> level_off;
+  std::vector<uint32_t> level_int;  // end of each level's internal nodes
   uint64_t m2l_cap = 0, p2p_cap = 0;
   int64_t items_from_walk = 0;  // P2P work items counted by the level walk
   uint32_t stack_cap = 0;
@@ -295,6 +296,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
         {B_NDEPTH, sizeof(int32_t) * nn}, {B_LEVNODES, sizeof(uint32_t) * nn},
         {B_LEVKEY0, sizeof(uint64_t) * nn}, {B_LEVKEY1, sizeof(uint64_t) * nn},
         {B_LEVIDS, sizeof(uint32_t) * nn}, {B_LEVOFF, sizeof(uint32_t) * (kMaxDepthCap + 2)},
+        {B_LEVINT, sizeof(uint32_t) * (kMaxDepthCap + 2)},
         {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(nn)},
         {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(nn), 2 * (int64_t)n + 2))}};
     for (auto& q : need2)
@@ -306,7 +308,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
                reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
     launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn, P<uint32_t>(ctx, B_HIST),
-                         P<uint32_t>(ctx, B_LEVOFF), s);
+                         P<uint32_t>(ctx, B_LEVOFF), P<uint32_t>(ctx, B_LEVINT), s);
   }
   if (nsys > 1) {
     if ((rc = ensure(ctx, B_NFLAG, sizeof(uint8_t) * nn))) return rc;
@@ -324,7 +326,10 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   }
   HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
   ctx->level_off.resize(kMaxDepthCap + 2);
+  ctx->level_int.resize(kMaxDepthCap + 2);
   HIPCHK(hipMemcpyAsync(ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
+                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->level_int.data(), P<uint32_t>(ctx, B_LEVINT),
                         sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
@@ -467,6 +472,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.level_nodes = P<int32_t>(ctx, B_LEVNODES);
     a.node_flag = ctx->nsys > 1 ? P<uint8_t>(ctx, B_NFLAG) : nullptr;
     a.level_off = P<uint32_t>(ctx, B_LEVOFF);
+    a.level_int = P<uint32_t>(ctx, B_LEVINT);
     a.m2l_off = P<uint32_t>(ctx, B_NM2LOFF);
     a.m2l_cnt = P<uint32_t>(ctx, B_NM2LCNT);
     a.open_off = P<uint32_t>(ctx, B_NOPENOFF);
@@ -499,7 +505,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
     // internal nodes level by level, then every leaf
     for (int k = 0; k <= ctx->maxdepth; ++k)
-      launch_nodewalk_level(a, k, (int)(ctx->level_off[k + 1] - ctx->level_off[k]), s);
+      launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
     // M2L entries proper (the pool also holds the opened lists)
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);

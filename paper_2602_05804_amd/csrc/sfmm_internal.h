@@ -167,6 +167,7 @@ struct NodeWalkArgs {
   const int32_t* level_nodes;  // nodes grouped by depth
   const uint8_t* node_flag;    // 0 spans systems (skipped), 1 walk root, 2 other
   const uint32_t* level_off;   // [levels + 1]
+  const uint32_t* level_int;   // [levels] end of each level's internal nodes
   // per node (node-indexed): M2L list, opened list (internal), P2P list (leaf).
   // An internal node's M2L and opened lists share one region of the M2L pool
   // (M2L from the front, opened from the back); its size, the node's tested
@@ -195,10 +196,12 @@ struct NodeWalkArgs {
 // node depth as a sort key (u64) and node ids (u32) for the bucketing by depth
 void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* key,
                        uint32_t* ids, hipStream_t s);
-// level_off[k] = first position of depth k in the depth-sorted node list,
-// read from the scanned radix histogram (digit-major, nb blocks)
+// level_off[k] = first position of depth k in the depth-sorted node list
+// (sort key 2 depth + leaf: a level's internal nodes first), level_int[k] =
+// the end of its internal nodes; read from the scanned radix histogram
+// (digit-major, nb blocks)
 void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
-                          uint32_t* level_off, hipStream_t s);
+                          uint32_t* level_off, uint32_t* level_int, hipStream_t s);
 // every leaf's lists (count, scans over the leaves, fill); scan_tmp holds
 // scan_tmp_elems(nleaves) words
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s);
