@@ -39,12 +39,32 @@ KERNELS = {
                        "registers"),
     ("fp32c", "far"): ("void k_far32<", ["k_f32c.hip", "expansions_gen.h", "sfmm_internal.h"],
                        "k_far32: per-leaf M2L (FP32 terms, FP64 sums) + L2L + L2P"),
-    ("fp32c", "near"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
-                        "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
+    ("fp32c", "near"): ("void k_p2p_wave32<", ["k_f32c.hip", "sfmm_internal.h"],
+                        "k_p2p_wave32: softened P2P, FP32 terms, FP64 sums, one wave per "
+                        "work item"),
+    # the earlier P2P shapes, still selectable (near kernel 1 to 6)
+    ("fp64", "near_leaf"): ("void k_p2p_leaf<", ["k_near.hip", "sfmm_internal.h", "softening.h"],
+                            "k_p2p_leaf: softened P2P, targets of a leaf in LDS"),
+    ("fp64", "near_thread"): ("void k_near<", ["k_near.hip", "sfmm_internal.h", "softening.h"],
+                              "k_near: softened P2P, one target particle per thread"),
+    ("fp32c", "near_leaf"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
+                             "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
     ("shared", "far"): (("void k_m2l_nodes<", "void k_far_shared<"),
                         ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
                         "k_m2l_nodes + k_far_shared: per-node M2L sums, then per-leaf L2L + L2P"),
 }
+
+
+def near_shape(precision, leaf_size, variant):
+    """Which P2P kernel a near-kernel number launches (the shapes that
+    sfmm_config.near_kernel documents)."""
+    if precision == "fp32c":
+        return "near_leaf" if variant == 6 else "near"
+    if leaf_size > 16 or variant == 1:
+        return "near_thread"
+    if variant in ((2, 3, 4, 5, 6) if leaf_size <= 10 else (5, 6)):
+        return "near_leaf"
+    return "near"
 
 
 def measured_traffic(args, kern):
@@ -229,7 +249,9 @@ def main():
     # its own events (phase near_kernel); the far phase is its kernels
     dom_ms = ph_mean["near_kernel"] if dom == "near" and ph_mean["near_kernel"] > 0 else ph_mean[dom]
     achieved = work[dom] / (dom_ms * 1e-3) / 1e12
-    kern = KERNELS[("shared" if args.far == "shared" and dom == "far" else args.precision, dom)]
+    kern = KERNELS[("shared" if args.far == "shared" and dom == "far" else args.precision,
+                    near_shape(args.precision, args.leaf_size, cfg.get("near_kernel", 0))
+                    if dom == "near" else dom)]
     roofline = {"bound": "alu", "kernel": kern[2],
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4),

@@ -1,5 +1,5 @@
-"""bench.py's host-side bookkeeping, on the CPU: the --gpus guard and the
-whole-solve fraction."""
+"""bench.py's host-side bookkeeping, on the CPU: the --gpus guard, the
+whole-solve fraction and the P2P kernel named in the roofline."""
 import os
 import subprocess
 import sys
@@ -27,3 +27,21 @@ def test_solve_fraction_sums_phase_ideals():
     tree = 1e6 * bench.TREE_BYTES_PER_PARTICLE / 8e12 * 1e3
     assert abs(f["ideal_ms"]["tree"] - round(tree, 4)) < 1e-9
     assert abs(f["frac"] - round((3.0 + tree) / 10.0, 4)) < 1e-9
+
+
+def test_near_shape_names_the_launched_kernel():
+    # the roofline's kernel name follows the near-kernel number and leaf size
+    # the same way the C++ dispatch does
+    assert bench.near_shape("fp64", 10, 0) == "near"
+    assert bench.near_shape("fp64", 10, 12) == "near"
+    assert bench.near_shape("fp64", 10, 1) == "near_thread"
+    assert bench.near_shape("fp64", 10, 4) == "near_leaf"
+    assert bench.near_shape("fp64", 16, 4) == "near"
+    assert bench.near_shape("fp64", 16, 6) == "near_leaf"
+    assert bench.near_shape("fp64", 24, 0) == "near_thread"
+    assert bench.near_shape("fp32c", 10, 0) == "near"
+    assert bench.near_shape("fp32c", 10, 6) == "near_leaf"
+    for prec in ("fp64", "fp32c"):
+        for ls in (10, 16, 24):
+            for v in range(13):
+                assert (prec, bench.near_shape(prec, ls, v)) in bench.KERNELS
