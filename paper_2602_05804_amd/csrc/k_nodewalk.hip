@@ -366,37 +366,38 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
 // ---- internal nodes, level by level ---------------------------------------
 // The M2L pool region of an internal node is its tested list (1 for a root,
 // else exp[parent]); leaves take no room at their level (they are walked
-// after all levels); a node over two systems gets empty lists.  This is the
-// region of level node idx (and it clears the lists of a node it owns).
+// after all levels); a node over two systems gets none.  This is the region
+// of level node idx (loads only, so a thread's several nodes overlap their
+// loads).
 __device__ __forceinline__ uint32_t node_region(const NodeWalkArgs& a, uint32_t idx) {
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  if (flag == 0) {
-    a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
-    a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
-    return 0;
-  }
-  if (vi.child < 0) return 0;
-  a.p2p_cnt[v] = 0;
-  a.p2p_off[v] = 0;
+  if (flag == 0 || vi.child < 0) return 0;
   return flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
 }
 
-// fill pass of one level's internal nodes (one wave per node; the level
-// scan has placed their regions)
-__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
-  if (idx >= end) return;
+// fill pass of one internal node, level position idx (one wave; the level
+// scan has placed its region)
+__device__ void internal_node(const NodeWalkArgs& a, uint32_t idx) {
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   // a node over two systems (several systems solved together) is never
-  // walked; the walk of each system starts at its own root
+  // walked and gets empty lists; the walk of each system starts at its own
+  // root
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  if (flag == 0 || vi.child < 0) return;
-  const bool root = flag == 1;
   const uint32_t lane = threadIdx.x & 63;
+  if (vi.child < 0) return;  // (the launch covers the level's internal nodes)
+  if (lane == 0) {
+    a.p2p_cnt[v] = 0;
+    a.p2p_off[v] = 0;
+    if (flag == 0) {
+      a.m2l_cnt[v] = 0; a.open_cnt[v] = 0;
+      a.m2l_off[v] = 0; a.open_off[v] = 0;
+    }
+  }
+  if (flag == 0) return;
+  const bool root = flag == 1;
   const double* rv = a.rec + (int64_t)v * a.stride;
   const uint32_t region = root ? 1u : a.exp[vi.parent];
   Emit e{};
@@ -427,6 +428,12 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
     a.open_off[v] = e.open_base - e.open_run;
     a.exp[v] = ex;
   }
+}
+
+__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
+  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
+  if (idx < end) internal_node(a, idx);
 }
 
 // ---- leaves, all levels at once ---------------------------------------------
@@ -495,12 +502,13 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
 // Places one level's internal nodes: an exclusive scan, in level order, of
 // their region sizes into absolute M2L pool offsets after everything the
 // levels above placed (levbase[level]); levbase[level + 1] and run[0] get
-// the new pool size.  A level of at most one tile (SCAN_T * SCAN_I nodes)
-// is one block; a larger one a pass of tile sums and a pass of tile scans.
-constexpr int SCAN_T = 1024;
+// the new pool size.  A level of at most kSmallLevel nodes is one block of
+// 1024 threads; a larger one a pass of tile sums and a pass of tile scans
+// over tiles of kScanTile nodes (blocks of 256 threads).
 constexpr int SCAN_I = 4;
-constexpr int SCAN_W = SCAN_T / 64;
-constexpr uint32_t kScanTile = SCAN_T * SCAN_I;
+constexpr uint32_t kSmallLevel = 1024 * SCAN_I;
+constexpr int TILE_T = 256;
+constexpr uint32_t kScanTile = TILE_T * SCAN_I;
 
 __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   const int lane = threadIdx.x & 63;
@@ -512,17 +520,20 @@ __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   return x;
 }
 
-// exclusive scan of c (per thread, SCAN_I consecutive items summed) over the
-// block; returns the exclusive prefix of this thread and the block total
+// exclusive scan of c over a block of NT threads; returns the exclusive
+// prefix of this thread and the block total
+template <int NT>
 __device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) {
-  __shared__ uint32_t wt[SCAN_W];
+  constexpr int W = NT / 64;
+  __shared__ uint32_t wt[W];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t inc = wave_incl_u32(c);
   if (lane == 63) wt[w] = inc;
   __syncthreads();
   uint32_t pre = inc - c;
   total = 0;
-  for (int k = 0; k < SCAN_W; ++k) {
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
     const uint32_t t = wt[k];
     if (k < w) pre += t;
     total += t;
@@ -531,10 +542,12 @@ __device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) 
   return pre;
 }
 
-// one tile: regions of tile t of the level, scanned, written at base
+// one tile of NT * SCAN_I nodes: regions of tile t of the level, scanned,
+// written at base
+template <int NT>
 __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
                                               uint32_t t, uint32_t base, bool recompute) {
-  const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
+  const uint32_t i0 = beg + t * (NT * SCAN_I) + threadIdx.x * SCAN_I;
   uint32_t r[SCAN_I], c = 0;
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
@@ -543,7 +556,7 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
     c += r[q];
   }
   uint32_t total;
-  uint32_t o = base + block_excl_u32(c, total);
+  uint32_t o = base + block_excl_u32<NT>(c, total);
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
@@ -553,10 +566,10 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
   return total;
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(1024) void k_level_scan_small(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t base = a.levbase[level];
-  const uint32_t total = scan_tile(a, beg, end, 0, base, true);
+  const uint32_t total = scan_tile<1024>(a, beg, end, 0, base, true);
   if (threadIdx.x == 0) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
@@ -564,7 +577,7 @@ __global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int
 }
 
 // tile sums (and the regions, kept for the second pass)
-__global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(TILE_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
   uint32_t c = 0;
@@ -576,18 +589,43 @@ __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int 
     c += r;
   }
   uint32_t total;
-  (void)block_excl_u32(c, total);
+  (void)block_excl_u32<TILE_T>(c, total);
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(TILE_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  uint32_t base = a.levbase[level];
-  for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
-  const uint32_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
+  // the sums of the tiles before this one, read by the whole block
+  uint32_t c = 0;
+  for (uint32_t t = threadIdx.x; t < blockIdx.x; t += TILE_T) c += a.tile_sum[t];
+  uint32_t before;
+  (void)block_excl_u32<TILE_T>(c, before);
+  const uint32_t base = a.levbase[level] + before;
+  const uint32_t total = scan_tile<TILE_T>(a, beg, end, blockIdx.x, base, false);
   if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
+  }
+}
+
+// levels 0 .. top, each of at most kTopLevelNodes internal nodes, in one
+// block: per level the scan, a barrier, one wave per node, a barrier
+constexpr int kTopWaves = 16;
+constexpr uint32_t kTopLevelNodes = 4 * kTopWaves;
+
+__global__ __launch_bounds__(64 * kTopWaves) void k_nodewalk_top(NodeWalkArgs a, int top) {
+  const uint32_t w = threadIdx.x >> 6;
+  for (int k = 0; k <= top; ++k) {
+    const uint32_t beg = a.level_off[k], end = a.level_int[k];
+    const uint32_t base = a.levbase[k];
+    const uint32_t total = scan_tile<64 * kTopWaves>(a, beg, end, 0, base, true);
+    if (threadIdx.x == 0) {
+      a.levbase[k + 1] = base + total;
+      a.run[0] = base + total;
+    }
+    __syncthreads();
+    for (uint32_t i = beg + w; i < end; i += kTopWaves) internal_node(a, i);
+    __syncthreads();
   }
 }
 
@@ -655,17 +693,28 @@ void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level,
   // (nodes_in_level: the level's internal nodes)
   if (nodes_in_level <= 0) {
     // an empty level still carries the pool size to the next one
-    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
+    k_level_scan_small<<<1, 1024, 0, s>>>(a, level);
     return;
   }
-  const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
-  if (tiles == 1) {
-    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
+  if ((uint32_t)nodes_in_level <= kSmallLevel) {
+    k_level_scan_small<<<1, 1024, 0, s>>>(a, level);
   } else {
-    k_level_tile_sums<<<tiles, SCAN_T, 0, s>>>(a, level);
-    k_level_tile_scan<<<tiles, SCAN_T, 0, s>>>(a, level);
+    const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
+    k_level_tile_sums<<<tiles, TILE_T, 0, s>>>(a, level);
+    k_level_tile_scan<<<tiles, TILE_T, 0, s>>>(a, level);
   }
   k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level);
+}
+
+int nodewalk_top_levels(int maxdepth, const uint32_t* level_off, const uint32_t* level_int) {
+  int top = -1;
+  while (top < maxdepth && level_int[top + 1] - level_off[top + 1] <= kTopLevelNodes) ++top;
+  return top;
+}
+
+void launch_nodewalk_top(const NodeWalkArgs& a, int top, hipStream_t s) {
+  if (top < 0) return;
+  k_nodewalk_top<<<1, 64 * kTopWaves, 0, s>>>(a, top);
 }
 
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s) {

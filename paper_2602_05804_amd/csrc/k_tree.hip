@@ -449,19 +449,21 @@ __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
 
 // ---- geometry, moments (bottom-up, one launch per depth) ------------------
 // A leaf sums its particles in sorted order; an internal node combines its
-// two children (children first: the deepest level is launched first).
+// two children (children first: the deepest level goes first).  The top
+// levels, each of at most kGeomTopNodes nodes, run in one block, a barrier
+// between levels.
+constexpr int kGeomTopNodes = 1024;
+
 template <int P>
-__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
-                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
-                             const double* __restrict__ ys, const double* __restrict__ zs,
-                             const double* __restrict__ ms, const double* __restrict__ hs,
-                             double* __restrict__ rec) {
+__device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ info,
+                                          const double* __restrict__ xs,
+                                          const double* __restrict__ ys,
+                                          const double* __restrict__ zs,
+                                          const double* __restrict__ ms,
+                                          const double* __restrict__ hs, double* rec) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int RS = rec_stride(P);
-  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= end) return;
-  const int v = level_nodes[idx];
   const NodeInfo ni = info[v];
   double* r = rec + (int64_t)v * RS;
   double Q[NQ];
@@ -511,6 +513,40 @@ __global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t b
   }
 #pragma unroll
   for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
+}
+
+template <int P>
+__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
+                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                             const double* __restrict__ ys, const double* __restrict__ zs,
+                             const double* __restrict__ ms, const double* __restrict__ hs,
+                             double* __restrict__ rec) {
+  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
+}
+
+// levels top .. 0 in one block of kGeomTopNodes threads; the records a level
+// reads were written by this block before the barrier
+struct GeomTop {
+  uint32_t off[kMaxDepthCap + 2];
+};
+
+template <int P>
+__global__ __launch_bounds__(kGeomTopNodes) void k_geom_top(const int32_t* __restrict__ level_nodes,
+                                                            GeomTop lv, int top,
+                                                            const NodeInfo* __restrict__ info,
+                                                            const double* __restrict__ xs,
+                                                            const double* __restrict__ ys,
+                                                            const double* __restrict__ zs,
+                                                            const double* __restrict__ ms,
+                                                            const double* __restrict__ hs,
+                                                            double* rec) {
+  for (int k = top; k >= 0; --k) {
+    const uint32_t idx = lv.off[k] + threadIdx.x;
+    if (idx < lv.off[k + 1]) geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
+    __syncthreads();
+  }
 }
 
 __global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
@@ -681,7 +717,12 @@ void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                      const double* ys, const double* zs, const double* ms, const double* hs,
                      double* rec, hipStream_t s) {
-  for (int k = maxdepth; k >= 0; --k) {
+  // the top levels that all fit one block
+  int top = -1;
+  while (top < maxdepth &&
+         level_off_host[top + 2] - level_off_host[top + 1] <= (uint32_t)kGeomTopNodes)
+    ++top;
+  for (int k = maxdepth; k > top; --k) {
     const uint32_t beg = level_off_host[k], end = level_off_host[k + 1];
     if (end <= beg) continue;
     const unsigned nb = blocks_for(end - beg, 128);
@@ -692,6 +733,16 @@ void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
       case 3: k_geom_level<3><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
       case 4: k_geom_level<4><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
     }
+  }
+  if (top < 0) return;
+  GeomTop lv;
+  for (int k = 0; k <= top + 1; ++k) lv.off[k] = level_off_host[k];
+  switch (order) {
+    case 0: k_geom_top<0><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
+    case 1: k_geom_top<1><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
+    case 2: k_geom_top<2><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
+    case 3: k_geom_top<3><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
+    case 4: k_geom_top<4><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
   }
 }
 

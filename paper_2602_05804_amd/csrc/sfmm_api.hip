@@ -45,6 +45,18 @@ enum BufId {
 enum SmallId { S_NKEPT = 0, S_NLEAVES, S_MAXDEPTH, S_NITEMS, S_M2LTOT, S_P2PTOT, S_PAIRTOT,
                S_DOFFTOT, S_SORTTOT, S_L2LTOT, S_COUNT };
 
+// pinned host copies of the sizes read back during a solve: the copies of one
+// synchronisation point are queued together and waited for once
+struct HostStage {
+  uint64_t small[S_COUNT];
+  int status[4];
+  uint32_t level_off[kMaxDepthCap + 2];
+  uint32_t level_int[kMaxDepthCap + 2];
+  uint32_t walk_tot[4];
+  int walk_status[4];
+  uint32_t walk_items;
+};
+
 }  // namespace
 
 struct sfmm_ctx {
@@ -77,6 +89,7 @@ struct sfmm_ctx {
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
   sfmm_stats stats{};
+  HostStage* stage = nullptr;  // pinned (hipHostMalloc), allocated on first use
 };
 
 namespace {
@@ -92,6 +105,18 @@ int fail(sfmm_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess)                                                             \
       return fail(ctx, SFMM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// the pinned staging area for read-backs (device already set)
+int host_stage(sfmm_ctx* ctx) {
+  if (ctx->stage) return SFMM_OK;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sizeof(HostStage), hipHostMallocDefault) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(ctx, SFMM_ENOMEM, "pinned host staging allocation failed");
+  }
+  ctx->stage = static_cast<HostStage*>(p);
+  return SFMM_OK;
+}
 
 // make buffer `id` hold at least `bytes`; contents are not preserved
 int ensure(sfmm_ctx* ctx, int id, size_t bytes) {
@@ -270,10 +295,12 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     launch_leaf_fill(n, P<uint32_t>(ctx, B_LFLAG), lscan, P<int32_t>(ctx, B_LAT), leaf_node, s);
   }
   // ---- sizes to the host (one synchronisation)
-  uint64_t hsmall[S_COUNT];
-  int hstatus[4];
-  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+  if ((rc = host_stage(ctx))) return rc;
+  HostStage* hs = ctx->stage;
+  const uint64_t* hsmall = hs->small;
+  const int* hstatus = hs->status;
+  HIPCHK(hipMemcpyAsync(hs->small, small, sizeof(hs->small), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs->status, status, sizeof(hs->status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (hstatus[0] & ST_NONFINITE)
     return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
@@ -324,14 +351,14 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
              P<uint32_t>(ctx, B_SCANTMP), s);
     HIPCHK(hipMemsetAsync(P<uint64_t>(ctx, B_L2BITS), 0, sizeof(uint64_t) * nn, s));
   }
-  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-  ctx->level_off.resize(kMaxDepthCap + 2);
-  ctx->level_int.resize(kMaxDepthCap + 2);
-  HIPCHK(hipMemcpyAsync(ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
-                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ctx->level_int.data(), P<uint32_t>(ctx, B_LEVINT),
-                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs->small, small, sizeof(hs->small), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs->level_off, P<uint32_t>(ctx, B_LEVOFF), sizeof(hs->level_off),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hs->level_int, P<uint32_t>(ctx, B_LEVINT), sizeof(hs->level_int),
+                        hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  ctx->level_off.assign(hs->level_off, hs->level_off + kMaxDepthCap + 2);
+  ctx->level_int.assign(hs->level_int, hs->level_int + kMaxDepthCap + 2);
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
   if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
   // ---- geometry and moments, level by level from the deepest
@@ -444,7 +471,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 4096 + 2)))) return rc;
+  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 1024 + 2)))) return rc;
   if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint32_t) * (kMaxDepthCap + 2)))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
@@ -503,21 +530,27 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.src_total = P<uint32_t>(ctx, B_SRCTOT);
     a.item_cnt = P<uint32_t>(ctx, B_ITEMCNT);
     a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
-    // internal nodes level by level, then every leaf
-    for (int k = 0; k <= ctx->maxdepth; ++k)
+    // internal nodes level by level (the small top levels in one block),
+    // then every leaf
+    const int top = nodewalk_top_levels(ctx->maxdepth, ctx->level_off.data(), ctx->level_int.data());
+    launch_nodewalk_top(a, top, s);
+    for (int k = top + 1; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
     // M2L entries proper (the pool also holds the opened lists)
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
-    uint32_t htot[4];
-    int hstatus[4];
-    uint32_t hitems = 0;
-    HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+    if ((rc = host_stage(ctx))) return rc;
+    HostStage* hs = ctx->stage;
+    const uint32_t* htot = hs->walk_tot;
+    const int* hstatus = hs->walk_status;
+    hs->walk_items = 0;
+    HIPCHK(hipMemcpyAsync(hs->walk_tot, tot, sizeof(hs->walk_tot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hs->walk_status, status, sizeof(hs->walk_status), hipMemcpyDeviceToHost, s));
     if (nl > 0)
-      HIPCHK(hipMemcpyAsync(&hitems, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hs->walk_items, a.item_off + nl, sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    ctx->items_from_walk = hitems;
+    ctx->items_from_walk = hs->walk_items;
     const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
     const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
@@ -775,6 +808,7 @@ int sfmm_destroy(sfmm_ctx* ctx) {
   if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
   for (auto& b : ctx->buf)
     if (b.p) (void)hipFree(b.p);
+  if (ctx->stage) (void)hipHostFree(ctx->stage);
   delete ctx;
   return SFMM_OK;
 }

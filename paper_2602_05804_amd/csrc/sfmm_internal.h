@@ -179,7 +179,7 @@ struct NodeWalkArgs {
   uint32_t* exp;  // per internal node: tested-list size of each of its children
   uint32_t* lvl_cnt32;  // [nn] M2L pool region of each internal node, in level order
   uint32_t* lvl_off;    // [nn] its absolute offset in the M2L pool
-  uint32_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
+  uint32_t* tile_sum;   // [nn / 1024 + 1] region sums per scan tile of a level
   uint32_t* levbase;    // [levels + 1] M2L pool size before each level
   uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
                       // walk's sum), P2P pool, M2L pool used by leaves
@@ -208,6 +208,10 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
 // out[0] += sum of x[0..n) (out on the device)
 void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
+// the top levels walked in one block: levels 0 .. top (top = -1: none), the
+// deepest prefix of levels whose internal nodes each fit the block's pass
+int nodewalk_top_levels(int maxdepth, const uint32_t* level_off, const uint32_t* level_int);
+void launch_nodewalk_top(const NodeWalkArgs& a, int top, hipStream_t s);
 
 // per-leaf statistics of node lists: replicated M2L count, L2L count, pairs
 struct LeafStatArgs {
