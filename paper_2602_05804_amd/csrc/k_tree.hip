@@ -19,8 +19,8 @@ namespace sfmm {
 namespace {
 
 constexpr int BBOX_THREADS = 256;
-constexpr int RS_THREADS = 256;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_THREADS = 512;
+constexpr int RS_ITEMS = 8;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(int n, const uint64_t
                                                            int shift, uint32_t* __restrict__ hist,
                                                            int nb) {
   __shared__ uint32_t cnt[256];
-  cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
@@ -248,30 +248,68 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(int n, const uint64_t
     if (i < n) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Stable scatter: elements of the tile are ranked in their original order;
-// equal digits inside a wave are found with eight ballots.
+// exclusive scan of one value per thread over the block, and the total
+__device__ __forceinline__ uint32_t rs_block_excl(uint32_t c, uint32_t& total) {
+  constexpr int W = RS_THREADS / 64;
+  __shared__ uint32_t wt[W];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = c;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wt[w] = x;
+  __syncthreads();
+  uint32_t pre = x - c;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < W; ++k) {
+    if (k < w) pre += wt[k];
+    total += wt[k];
+  }
+  __syncthreads();
+  return pre;
+}
+
+// Stable scatter: the tile's elements are ranked in their original order
+// (equal digits inside a wave found with eight ballots) and placed, sorted
+// by digit, in LDS; the tile then writes each digit's run to its global
+// offset in order, so consecutive threads write consecutive addresses.
+// cnt: the tile digit counts, offs: their exclusive scan (digit-major).
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     int n, const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
-    const uint32_t* __restrict__ offs, int nb) {
-  __shared__ uint32_t run[256];
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wc[RS_THREADS / 64][256];
+    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ offs, int nb) {
+  constexpr int W = RS_THREADS / 64;
+  __shared__ uint64_t sk[RS_TILE];
+  __shared__ uint32_t sv[RS_TILE];
+  __shared__ uint32_t start[256], gbase[256], run[256];
+  __shared__ uint32_t wc[W][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  run[t] = 0;
-  base[t] = offs[(int64_t)t * nb + blockIdx.x];
+  {
+    const uint32_t c = t < 256 ? cnt[(int64_t)t * nb + blockIdx.x] : 0u;
+    uint32_t tot;
+    const uint32_t ex = rs_block_excl(c, tot);
+    if (t < 256) {
+      start[t] = ex;
+      gbase[t] = offs[(int64_t)t * nb + blockIdx.x];
+      run[t] = 0;
+    }
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
-    for (int q = 0; q < RS_THREADS / 64; ++q) wc[q][t] = 0;
+    for (int q = t; q < W * 256; q += RS_THREADS) (&wc[0][0])[q] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * RS_TILE + r * RS_THREADS + t;
+    const int64_t i = tile0 + r * RS_THREADS + t;
     const bool valid = i < n;
-    uint64_t k = valid ? kin[i] : 0ull;
-    uint32_t v = valid ? vin[i] : 0u;
-    uint32_t d = (uint32_t)((k >> shift) & 255u);
+    const uint64_t k = valid ? kin[i] : 0ull;
+    const uint32_t v = valid ? vin[i] : 0u;
+    const uint32_t d = (uint32_t)((k >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -283,16 +321,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = base[d] + run[d] + rank;
+      uint32_t pos = start[d] + run[d] + rank;
       for (int q = 0; q < w; ++q) pos += wc[q][d];
-      kout[pos] = k;
-      vout[pos] = v;
+      sk[pos] = k;
+      sv[pos] = v;
     }
     __syncthreads();
-    uint32_t add = 0;
-    for (int q = 0; q < RS_THREADS / 64; ++q) add += wc[q][t];
-    run[t] += add;
-    __syncthreads();
+    if (t < 256) {
+      uint32_t add = 0;
+      for (int q = 0; q < W; ++q) add += wc[q][t];
+      run[t] += add;
+    }
+  }
+  __syncthreads();
+  const int tn = (int)min<int64_t>(RS_TILE, (int64_t)n - tile0);
+  for (int j = t; j < tn; j += RS_THREADS) {
+    const uint64_t k = sk[j];
+    const uint32_t d = (uint32_t)((k >> shift) & 255u);
+    const uint32_t g = gbase[d] + ((uint32_t)j - start[d]);
+    kout[g] = k;
+    vout[g] = sv[j];
   }
 }
 
@@ -633,9 +681,10 @@ void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                 int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
                 hipStream_t s) {
   const int nb = radix_blocks(n);
+  uint32_t* offs = hist + (int64_t)256 * nb;
   k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
-  scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
-  k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
+  scan_u32(hist, offs, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+  k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, offs, nb);
 }
 
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
@@ -643,10 +692,11 @@ void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t*
   const int nb = radix_blocks(n);
   uint64_t *kin = key0, *kout = key1;
   uint32_t *vin = val0, *vout = val1;
+  uint32_t* offs = hist + (int64_t)256 * nb;
   for (int shift = 0; shift < 64; shift += 8) {  // 8 passes: result lands in key0/val0
     k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
-    scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
-    k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
+    scan_u32(hist, offs, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+    k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, offs, nb);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }

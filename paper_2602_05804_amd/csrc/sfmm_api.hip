@@ -195,7 +195,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
       {B_STATUS, sizeof(int) * 4}, {B_SMALL, sizeof(uint64_t) * S_COUNT},
       {B_KEY0, sizeof(uint64_t) * n}, {B_KEY1, sizeof(uint64_t) * n},
       {B_VAL0, sizeof(uint32_t) * n}, {B_VAL1, sizeof(uint32_t) * n},
-      {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(n)},
+      {B_HIST, sizeof(uint32_t) * 2 * 256 * (size_t)radix_blocks(n)},
       {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(n), 2 * (int64_t)n + 2))},
       {B_XS, sizeof(double) * n}, {B_YS, sizeof(double) * n}, {B_ZS, sizeof(double) * n},
       {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n}, {B_HIS, sizeof(double) * n},
@@ -324,7 +324,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
         {B_LEVKEY0, sizeof(uint64_t) * nn}, {B_LEVKEY1, sizeof(uint64_t) * nn},
         {B_LEVIDS, sizeof(uint32_t) * nn}, {B_LEVOFF, sizeof(uint32_t) * (kMaxDepthCap + 2)},
         {B_LEVINT, sizeof(uint32_t) * (kMaxDepthCap + 2)},
-        {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(nn)},
+        {B_HIST, sizeof(uint32_t) * 2 * 256 * (size_t)radix_blocks(nn)},
         {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(nn), 2 * (int64_t)n + 2))}};
     for (auto& q : need2)
       if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
@@ -334,7 +334,9 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                P<uint64_t>(ctx, B_LEVKEY1), P<uint32_t>(ctx, B_LEVNODES), 0,
                P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
                reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
-    launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn, P<uint32_t>(ctx, B_HIST),
+    // (the scanned digit counts of the pass)
+    launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn,
+                         P<uint32_t>(ctx, B_HIST) + 256 * (size_t)radix_blocks(nn),
                          P<uint32_t>(ctx, B_LEVOFF), P<uint32_t>(ctx, B_LEVINT), s);
   }
   if (nsys > 1) {

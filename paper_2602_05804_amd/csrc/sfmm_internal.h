@@ -82,11 +82,13 @@ void launch_bbox(int n, const double* x, const double* m, const double* h, doubl
 void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint32_t* idx,
                  hipStream_t s);
 int radix_blocks(int64_t n);
-// sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1)
+// sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1);
+// hist holds 2 * 256 * radix_blocks(n) counters
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
                 uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s);
-// one stable pass on the 8-bit digit at `shift`; hist holds 256 * radix_blocks(n)
-// counters and, after the pass, their exclusive scan (digit-major)
+// one stable pass on the 8-bit digit at `shift`; hist holds 2 * 256 * radix_blocks(n)
+// counters: the tile digit counts, then (from hist + 256 * radix_blocks(n)) their
+// exclusive scan (digit-major), kept after the pass
 void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                 int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
                 hipStream_t s);

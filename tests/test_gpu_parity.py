@@ -89,6 +89,33 @@ def test_tree_parity(torch, P, orc):
     s.close()
 
 
+@pytest.mark.parametrize("case", ["plummer", "coarse_grid"])
+def test_tree_parity_many_tiles(torch, P, orc, case):
+    # sizes that span many sort tiles with a ragged last tile, and (coarse
+    # grid) long runs of equal keys across tile boundaries: the sort must
+    # stay stable and every scan size class is met
+    print(f"case: tree parity over many sort tiles, {case}", flush=True)
+    if case == "plummer":
+        x, m, h = workloads.plummer(300_007, seed=3)
+    else:
+        rng = np.random.default_rng(12)
+        n = 70_001
+        x = rng.integers(0, 6, size=(n, 3)).astype(np.float64) * 0.25
+        m = rng.uniform(0.5, 1.5, n) / n
+        h = rng.uniform(0.05, 0.2, n)
+    s = P.Solver()
+    s.build(*dev(torch, x, m, h), order=3)
+    g = s.tree(order=3)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    assert np.array_equal(g["perm"].astype(np.int64), t.perm())
+    assert np.array_equal(g["keys"], t.keys())
+    nd = t.nodes()
+    assert len(g["lo"]) == t.num_nodes
+    assert sorted(zip(g["lo"].tolist(), g["cnt"].tolist())) == sorted(
+        zip(nd["lo"].tolist(), (nd["hi"] - nd["lo"]).tolist()))
+    s.close()
+
+
 def _expand_p2p(g, leaf_nodes, p2p):
     """P2P entries as source leaves: a subtree entry stands for all its leaves."""
     llo = g["lo"][leaf_nodes]
