@@ -302,13 +302,24 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+  // every round's element loaded up front (the rounds are separated by
+  // barriers, which would otherwise wait for one load each)
+  uint64_t kr[RS_ITEMS];
+  uint32_t vr[RS_ITEMS];
+#pragma unroll
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const int64_t i = tile0 + r * RS_THREADS + t;
+    kr[r] = i < n ? kin[i] : 0ull;
+    vr[r] = i < n ? vin[i] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
     for (int q = t; q < W * 256; q += RS_THREADS) (&wc[0][0])[q] = 0;
     __syncthreads();
     const int64_t i = tile0 + r * RS_THREADS + t;
     const bool valid = i < n;
-    const uint64_t k = valid ? kin[i] : 0ull;
-    const uint32_t v = valid ? vin[i] : 0u;
+    const uint64_t k = kr[r];
+    const uint32_t v = vr[r];
     const uint32_t d = (uint32_t)((k >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll

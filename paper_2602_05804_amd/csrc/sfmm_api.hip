@@ -37,7 +37,7 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
-  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_OVFLEAF,
   B_COUNT
 };
 
@@ -52,7 +52,7 @@ struct HostStage {
   int status[4];
   uint32_t level_off[kMaxDepthCap + 2];
   uint32_t level_int[kMaxDepthCap + 2];
-  uint32_t walk_tot[4];
+  uint32_t walk_tot[8];
   int walk_status[4];
   uint32_t walk_items;
 };
@@ -82,6 +82,8 @@ struct sfmm_ctx {
   std::vector<uint32_t> level_int;  // end of each level's internal nodes
   uint64_t m2l_cap = 0, p2p_cap = 0;
   int64_t items_from_walk = 0;  // P2P work items counted by the level walk
+  // level walk: entries of a leaf's fixed list slots (M2L, P2P)
+  uint32_t leaf_slot_m = 512, leaf_slot_p = 256;
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
@@ -467,9 +469,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 8))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
-  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
+  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_OVFLEAF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint32_t) * nn))) return rc;
@@ -479,18 +481,25 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
   // (the M2L pool also holds the opened lists of internal nodes)
-  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + 2048);
-  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + 1024);
+  // leaf list slots (entries per leaf), bounded so that the slots of all
+  // leaves stay well inside 32-bit offsets
+  uint32_t slot_m = (uint32_t)std::min<uint64_t>(ctx->leaf_slot_m, (1ull << 30) / std::max(nl, 1));
+  uint32_t slot_p = (uint32_t)std::min<uint64_t>(ctx->leaf_slot_p, (1ull << 28) / std::max(nl, 1));
+  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + (uint64_t)slot_m * nl + 2048);
+  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + (uint64_t)slot_p * nl + 1024);
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
   const uint64_t kPoolMax = 0xF0000000ull;
   for (int attempt = 0;; ++attempt) {
+    // the staging slots share the leaf pass's LDS with the lowering stack
+    // (at most 64 KB in all): without room, every leaf takes the second pass
+    if (ctx->stack_cap + slot_m + 2 * slot_p > 16384) slot_m = slot_p = 0;
     if (ctx->m2l_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
       return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed 2^32 entries");
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint32_t* tot = P<uint32_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 4, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 8, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     NodeWalkArgs a{};
     a.info = P<NodeInfo>(ctx, B_INFO);
@@ -524,6 +533,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.stack_cap = ctx->stack_cap;
     a.status = status;
     a.nleaves = nl;
+    a.slot_m = slot_m;
+    a.slot_p = slot_p;
+    a.ovf_leaf = P<uint32_t>(ctx, B_OVFLEAF);
     a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
     a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
@@ -539,8 +551,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     for (int k = top + 1; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
-    // M2L entries proper (the pool also holds the opened lists)
+    // M2L entries proper (the pool also holds the opened lists), P2P entries
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
+    launch_sum_u32(nn, a.p2p_cnt, tot + 4, s);
     if ((rc = host_stage(ctx))) return rc;
     HostStage* hs = ctx->stage;
     const uint32_t* htot = hs->walk_tot;
@@ -553,11 +566,13 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                             hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->items_from_walk = hs->walk_items;
-    const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
-    const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
+    // internal regions, the leaves' slots, the lists that did not fit
+    const uint64_t m2l_used = (uint64_t)htot[0] + (uint64_t)slot_m * nl + htot[3];
+    const uint64_t p2p_used = (uint64_t)slot_p * nl + htot[2];
+    const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
-      ctx->p2p_total = htot[2];
+      ctx->p2p_total = htot[4];
       ctx->m2l_unique = htot[1];
       return SFMM_OK;
     }
@@ -569,7 +584,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
       ctx->m2l_cap = grow(ctx->m2l_cap, m2l_used);
-      ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
+      ctx->p2p_cap = grow(ctx->p2p_cap, p2p_used);
     }
     if (stack_over) {
       if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
@@ -797,6 +812,14 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   // measurement overrides
   if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
   if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
+  // leaf list slots "M,P" (0,0: every leaf takes the second pass)
+  if (const char* ls = std::getenv("SFMM_LEAF_SLOTS")) {
+    unsigned sm = 0, sp = 0;
+    if (std::sscanf(ls, "%u,%u", &sm, &sp) == 2 && sm <= 4096 && sp <= 4096) {
+      ctx->leaf_slot_m = sm;
+      ctx->leaf_slot_p = sp;
+    }
+  }
   *out = ctx;
   return SFMM_OK;
 }

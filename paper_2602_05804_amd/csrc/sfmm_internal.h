@@ -183,12 +183,19 @@ struct NodeWalkArgs {
   uint32_t* lvl_off;    // [nn] its absolute offset in the M2L pool
   uint32_t* tile_sum;   // [nn / 1024 + 1] region sums per scan tile of a level
   uint32_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
-                      // walk's sum), P2P pool, M2L pool used by leaves
-  // leaves (walked after all levels, in leaf order)
+  uint32_t* run;      // [8] M2L pool used by internal nodes, M2L entries proper (the
+                      // walk's sum), P2P pool after the slots, M2L pool after the
+                      // slots, P2P entries (the walk's sum), leaves left for the
+                      // second pass
+  // leaves (walked after all levels, in leaf order); leaf l's lists go to
+  // fixed slots (M2L: run[0] + l * slot_m, P2P: l * slot_p) when they fit,
+  // else after all slots: leaf_*_cnt are the lists left for the second pass
+  // (0 for a leaf in its slots), leaf_*_off their scan
   int nleaves;
   const int32_t* leaf_node;
+  uint32_t slot_m, slot_p;
   uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt, *leaf_m2l_off, *leaf_p2p_off;
+  uint32_t* ovf_leaf;  // [nleaves] the leaves left for the second pass (run[5] of them)
   // per leaf: particles over its P2P entries, P2P work items and their offsets
   // ([nleaves + 1], the last entry the total)
   uint32_t *src_total, *item_cnt, *item_off;
