@@ -506,11 +506,11 @@ __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
   for (int p = ni.lo; p < ni.lo + ni.cnt; ++p) p_leaf[p] = l;
 }
 
-// ---- geometry, moments (bottom-up, one launch per depth) ------------------
-// A leaf sums its particles in sorted order; an internal node combines its
-// two children (children first: the deepest level goes first).  The top
-// levels, each of at most kGeomTopNodes nodes, run in one block, a barrier
-// between levels.
+// ---- geometry, moments (leaves, then internal nodes bottom-up) -------------
+// A leaf sums its particles in sorted order (every leaf in one launch); an
+// internal node combines its two children (one launch per depth, the
+// deepest first).  The top levels, each of at most kGeomTopNodes internal
+// nodes, run in one block, a barrier between levels.
 constexpr int kGeomTopNodes = 1024;
 
 template <int P>
@@ -530,6 +530,7 @@ __device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ in
   for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
   if (ni.child < 0) {
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
+#pragma unroll 4
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double mj = ms[j];
       M += mj;
@@ -540,6 +541,7 @@ __device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ in
     }
     const double s0 = S0 / M, s1 = S1 / M, s2 = S2 / M;
     double d2max = 0.0;
+#pragma unroll 4
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double b[3] = {xs[j] - s0, ys[j] - s1, zs[j] - s2};
       const double d2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
@@ -585,10 +587,22 @@ __global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t b
   geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
 }
 
-// levels top .. 0 in one block of kGeomTopNodes threads; the records a level
-// reads were written by this block before the barrier
+template <int P>
+__global__ void k_geom_leaves(int nleaves, const int32_t* __restrict__ leaf_node,
+                              const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                              const double* __restrict__ ys, const double* __restrict__ zs,
+                              const double* __restrict__ ms, const double* __restrict__ hs,
+                              double* __restrict__ rec) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < nleaves) geom_node<P>(leaf_node[l], info, xs, ys, zs, ms, hs, rec);
+}
+
+// internal nodes of levels top .. 0 in one block of kGeomTopNodes threads;
+// the records a level reads were written before the barrier (by this block,
+// or by the launches before it)
 struct GeomTop {
-  uint32_t off[kMaxDepthCap + 2];
+  uint32_t off[kMaxDepthCap + 2];  // level k's internal nodes: [off[k], end[k])
+  uint32_t end[kMaxDepthCap + 2];
 };
 
 template <int P>
@@ -603,7 +617,7 @@ __global__ __launch_bounds__(kGeomTopNodes) void k_geom_top(const int32_t* __res
                                                             double* rec) {
   for (int k = top; k >= 0; --k) {
     const uint32_t idx = lv.off[k] + threadIdx.x;
-    if (idx < lv.off[k + 1]) geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
+    if (idx < lv.end[k]) geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
     __syncthreads();
   }
 }
@@ -775,36 +789,47 @@ void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* in
 }
 
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
+                     const uint32_t* level_int_host, int nleaves, const int32_t* leaf_node,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                      const double* ys, const double* zs, const double* ms, const double* hs,
                      double* rec, hipStream_t s) {
-  // the top levels that all fit one block
+#define GEOM_ORDERS(LAUNCH) \
+  switch (order) {          \
+    case 0: LAUNCH(0); break; \
+    case 1: LAUNCH(1); break; \
+    case 2: LAUNCH(2); break; \
+    case 3: LAUNCH(3); break; \
+    case 4: LAUNCH(4); break; \
+  }
+  if (nleaves > 0) {
+    const unsigned nb = blocks_for(nleaves, 128);
+#define LEAVES(P) k_geom_leaves<P><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec)
+    GEOM_ORDERS(LEAVES)
+#undef LEAVES
+  }
+  // the top levels whose internal nodes all fit one block
   int top = -1;
   while (top < maxdepth &&
-         level_off_host[top + 2] - level_off_host[top + 1] <= (uint32_t)kGeomTopNodes)
+         level_int_host[top + 1] - level_off_host[top + 1] <= (uint32_t)kGeomTopNodes)
     ++top;
   for (int k = maxdepth; k > top; --k) {
-    const uint32_t beg = level_off_host[k], end = level_off_host[k + 1];
+    const uint32_t beg = level_off_host[k], end = level_int_host[k];
     if (end <= beg) continue;
     const unsigned nb = blocks_for(end - beg, 128);
-    switch (order) {
-      case 0: k_geom_level<0><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 1: k_geom_level<1><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 2: k_geom_level<2><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 3: k_geom_level<3><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 4: k_geom_level<4><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-    }
+#define LEVEL(P) k_geom_level<P><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec)
+    GEOM_ORDERS(LEVEL)
+#undef LEVEL
   }
   if (top < 0) return;
   GeomTop lv;
-  for (int k = 0; k <= top + 1; ++k) lv.off[k] = level_off_host[k];
-  switch (order) {
-    case 0: k_geom_top<0><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
-    case 1: k_geom_top<1><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
-    case 2: k_geom_top<2><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
-    case 3: k_geom_top<3><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
-    case 4: k_geom_top<4><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec); break;
+  for (int k = 0; k <= top; ++k) {
+    lv.off[k] = level_off_host[k];
+    lv.end[k] = level_int_host[k];
   }
+#define TOP(P) k_geom_top<P><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec)
+  GEOM_ORDERS(TOP)
+#undef TOP
+#undef GEOM_ORDERS
 }
 
 void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s) {

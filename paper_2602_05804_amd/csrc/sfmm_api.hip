@@ -366,8 +366,8 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
   if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
   // ---- geometry and moments, level by level from the deepest
-  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(),
-                  reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
+  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(), ctx->level_int.data(), nl,
+                  leaf_node, reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
                   P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
                   P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_REC), s);
   if (nn > 1) {

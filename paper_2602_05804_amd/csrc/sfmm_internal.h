@@ -124,8 +124,10 @@ void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                        const int32_t* node_depth, int32_t* leaf_depth, int32_t* p_leaf,
                        int* maxdepth, hipStream_t s);
-// geometry and moments, deepest level first (level_off_host: host copy)
+// geometry and moments: every leaf, then the internal nodes deepest level
+// first (level_off_host, level_int_host: host copies of the level ranges)
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
+                     const uint32_t* level_int_host, int nleaves, const int32_t* leaf_node,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                      const double* ys, const double* zs, const double* ms, const double* hs,
                      double* rec, hipStream_t s);
