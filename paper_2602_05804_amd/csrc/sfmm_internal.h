@@ -58,6 +58,18 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// The same idea for work whose cost varies along the range: rounds of
+// kXcds * C blocks, each XCD taking C consecutive blocks of a round, so the
+// XCDs share the range evenly while neighbours stay in one L2 (the blocks of
+// a last, incomplete round keep their order).
+template <unsigned C>
+__device__ __forceinline__ unsigned xcd_chunk_block(unsigned b, unsigned nb) {
+  constexpr unsigned R = kXcds * C;
+  if (b / R == nb / R) return b;
+  const unsigned j = b / kXcds;
+  return (j / C) * R + (b % kXcds) * C + (j % C);
+}
+
 // local (field) coefficients: H_g for 1 <= |g| <= p+1, then P_b for |b| <= p
 __host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 + ncoef(p); }
 // FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
