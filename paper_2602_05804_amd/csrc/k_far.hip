@@ -151,9 +151,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
   constexpr int RS = rec_stride(P), RS32 = rec32_stride(P);
   const int lane = threadIdx.x;
   const int sub = lane % SPLIT;
-  // (chunks of consecutive blocks per XCD rather than one contiguous range
-  // each: the cost per node varies with the level)
-  const int g = xcd_chunk_block<32>(blockIdx.x, gridDim.x) * (64 / SPLIT) + lane / SPLIT;
+  // (no XCD-contiguous mapping here: the cost per node varies with the
+  // level, and the hardware's round-robin keeps the XCDs balanced)
+  const int g = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
   const bool active = g < a.nn;
   const int v = active ? a.level_nodes[g] : 0;
   const uint32_t cnt = active ? a.m2l_cnt[v] : 0u;

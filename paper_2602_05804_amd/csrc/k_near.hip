@@ -319,16 +319,12 @@ struct WaveItem {
 };
 
 constexpr uint32_t kTQ = 192;  // queue slots per target (63 + 64 U, U <= 2)
-// source indices of the first kJC groups of 64 sources, found by the first
-// pass of an item and read back by its later passes (the groups are the
-// same in every pass)
-constexpr int kJC = 16;
 
 // U groups of 64 sources per step: their index searches and loads are
 // independent, so a wave keeps U chains of latency in flight
 template <int K, int LS, int U>
 __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem& w, int t0,
-                                              int* q, int* jc, uint32_t& nsoft) {
+                                              int* q, uint32_t& nsoft) {
   const int lane = threadIdx.x;
   const int tlo = w.tlo;
   double tx[K], ty[K], tz[K], t4[K];
@@ -377,8 +373,6 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
     qn[ii] -= count;
   };
   uint32_t carry = w.carry0;  // sources of the list entries before c0 (wave-uniform)
-  const bool first = t0 == 0;
-  int gi = 0;  // groups of 64 sources met so far (wave-uniform)
   for (uint64_t c0 = w.e0; c0 < w.e1; c0 += 64) {
     // 64 list entries: their particle ranges [fb, fe) in the flattened
     // order, then clipped to the run
@@ -408,24 +402,17 @@ __device__ __forceinline__ void p2p_wave_pass(const NearArgs& a, const WaveItem&
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int f = f0 + 64 * u + lane;
-        const int slot = gi + u;  // wave-uniform
-        fv[u] = f < total;
-        if (!first && slot < kJC) {
-          j[u] = jc[slot * 64 + lane];
-        } else {
-          // owner lane k: the last lane with pre <= f (binary search over lanes)
-          int k = 0;
+        // owner lane k: the last lane with pre <= f (binary search over lanes)
+        int k = 0;
 #pragma unroll
-          for (int step = 32; step > 0; step >>= 1) {
-            const int pk = __shfl(pre, k + step, 64);
-            if (pk <= f) k += step;
-          }
-          const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
-          j[u] = fv[u] ? jj : tlo;  // a valid index; contributes nothing
-          if (first && slot < kJC) jc[slot * 64 + lane] = j[u];
+        for (int step = 32; step > 0; step >>= 1) {
+          const int pk = __shfl(pre, k + step, 64);
+          if (pk <= f) k += step;
         }
+        const int jj = __shfl(lo, k, 64) + (f - __shfl(pre, k, 64));
+        fv[u] = f < total;
+        j[u] = fv[u] ? jj : tlo;  // a valid index; contributes nothing
       }
-      gi += U;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const double2* rj = reinterpret_cast<const double2*>(a.p4 + 4 * (int64_t)j[u]);
@@ -525,14 +512,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   w.carry0 = 0;
   if (kitem > 0) { w.e0 = a.item_e0[item]; w.carry0 = a.item_c0[item]; }
   __shared__ int q[TG * kTQ];
-  __shared__ int jc[kJC * 64];
   uint32_t nsoft = 0;
   int t0 = 0;
-  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave_pass<TG, LS, U>(a, w, t0, q, jc, nsoft);
+  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave_pass<TG, LS, U>(a, w, t0, q, nsoft);
   // the remainder, a pass with a fixed target count (uniform branches)
   static_for<TG>([&](auto rc) {
     constexpr int r = decltype(rc)::value;
-    if (r > 0 && w.nt - t0 == r) p2p_wave_pass<(r > 0 ? r : 1), LS, U>(a, w, t0, q, jc, nsoft);
+    if (r > 0 && w.nt - t0 == r) p2p_wave_pass<(r > 0 ? r : 1), LS, U>(a, w, t0, q, nsoft);
   });
   if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }

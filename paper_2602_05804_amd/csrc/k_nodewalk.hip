@@ -103,10 +103,6 @@ struct Emit {
   uint32_t exp_lane;
   // leaf: this lane's share of the particles of the P2P entries
   uint32_t src_lane;
-  // leaf lists staged in LDS (count pass): M2L entries, P2P entries that may
-  // need softening, P2P entries beyond both kernels (in rank order)
-  uint32_t *stm, *stp, *stq;
-  uint32_t cap_m, cap_p;
 };
 
 template <bool WRITE>
@@ -147,13 +143,8 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
 // a leaf's lists: nm M2L entries (sel_m), np P2P entries that may need
 // softening (sel_p) and nq P2P entries beyond both kernels (sel_q); the
 // latter are written from the end of the leaf's range, so the P2P kernel
-// meets the softened pairs first and the rest in whole chunks without them.
-// W = kEmitGlobal writes the pools at the leaf's offsets, W = kEmitStage
-// stages the three lists in LDS (as far as they fit).
-constexpr int kEmitGlobal = 1;
-constexpr int kEmitStage = 2;
-
-template <int W>
+// meets the softened pairs first and the rest in whole chunks without them
+template <bool WRITE>
 __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, uint32_t s0,
                                                 uint32_t s1, uint32_t nm, uint32_t sel_m,
                                                 uint32_t np, uint32_t sel_p, uint32_t nq,
@@ -162,18 +153,7 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
   const uint32_t pm = wave_prefix(nm, tm);
   const uint32_t pp = wave_prefix(np, tp);
   const uint32_t pq = wave_prefix(nq, tq);
-  if (W == kEmitStage) {
-    uint32_t k = e.m2l_run + pm;
-    if (sel_m & 1u) { if (k < e.cap_m) e.stm[k] = s0; ++k; }
-    if (sel_m & 2u) { if (k < e.cap_m) e.stm[k] = s1; }
-    uint32_t q = e.p2p_run + pp;
-    if (sel_p & 1u) { if (q < e.cap_p) e.stp[q] = s0; ++q; }
-    if (sel_p & 2u) { if (q < e.cap_p) e.stp[q] = s1; }
-    uint32_t r = e.plain_run + pq;
-    if (sel_q & 1u) { if (r < e.cap_p) e.stq[r] = s0; ++r; }
-    if (sel_q & 2u) { if (r < e.cap_p) e.stq[r] = s1; }
-  }
-  if (W == kEmitGlobal) {
+  if (WRITE) {
     uint32_t k = e.m2l_base + e.m2l_run + pm;
     if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
     if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
@@ -289,7 +269,7 @@ __device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, co
 // each batch of the tested list, so the stack stays within a few chunks per
 // tree level.  Returns false when the stack would overflow (the walk is then
 // rerun with a larger stack).
-template <int W, int U>
+template <bool WRITE, int U>
 __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv,
                                           const uint32_t (&t0)[U], const uint32_t (&t1)[U],
                                           const int (&nt)[U], Emit& e, uint32_t* stk,
@@ -327,7 +307,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
         if (q) open1 = true; else open0 = true;
       }
     }
-    emit_leaf_lists<W>(a, e, t0[u], t1[u], nm, selm, np, selp, nq, selq);
+    emit_leaf_lists<WRITE>(a, e, t0[u], t1[u], nm, selm, np, selp, nq, selq);
     const uint32_t npush = (open0 ? 2u : 0u) + (open1 ? 2u : 0u);
     uint32_t tpush;
     const uint32_t pp = wave_prefix(npush, tpush);
@@ -341,7 +321,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
   return ok;
 }
 
-template <int W>
+template <bool WRITE>
 __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
                           uint32_t nsrc, bool root, Emit& e, uint32_t* stk, int* status) {
   constexpr int U = kWalkBatch;
@@ -369,7 +349,7 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
       if (cb[u] < 0) { t0[u] = sb[u]; nt[u] = 1; }
       else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt[u] = 2; }
     }
-    ok = leaf_step<W, U>(a, v, rv, t0, t1, nt, e, stk, sp);
+    ok = leaf_step<WRITE, U>(a, v, rv, t0, t1, nt, e, stk, sp);
     while (ok && sp > 0) {
       const uint32_t k = sp < 64u ? sp : 64u;
       uint32_t d0[1] = {0}, d1[1] = {0};
@@ -377,7 +357,7 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
       if (dn[0]) d0[0] = stk[sp - k + lane];
       __syncthreads();
       sp -= k;
-      ok = leaf_step<W, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
+      ok = leaf_step<WRITE, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
     }
   }
   if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
@@ -386,38 +366,37 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
 // ---- internal nodes, level by level ---------------------------------------
 // The M2L pool region of an internal node is its tested list (1 for a root,
 // else exp[parent]); leaves take no room at their level (they are walked
-// after all levels); a node over two systems gets none.  This is the region
-// of level node idx (loads only, so a thread's several nodes overlap their
-// loads).
+// after all levels); a node over two systems gets empty lists.  This is the
+// region of level node idx (and it clears the lists of a node it owns).
 __device__ __forceinline__ uint32_t node_region(const NodeWalkArgs& a, uint32_t idx) {
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  if (flag == 0 || vi.child < 0) return 0;
+  if (flag == 0) {
+    a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+    a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
+    return 0;
+  }
+  if (vi.child < 0) return 0;
+  a.p2p_cnt[v] = 0;
+  a.p2p_off[v] = 0;
   return flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
 }
 
-// fill pass of one internal node, level position idx (one wave; the level
-// scan has placed its region)
-__device__ void internal_node(const NodeWalkArgs& a, uint32_t idx) {
+// fill pass of one level's internal nodes (one wave per node; the level
+// scan has placed their regions)
+__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
+  const uint32_t beg = a.level_off[level], end = a.level_int[level];
+  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
+  if (idx >= end) return;
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   // a node over two systems (several systems solved together) is never
-  // walked and gets empty lists; the walk of each system starts at its own
-  // root
+  // walked; the walk of each system starts at its own root
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  const uint32_t lane = threadIdx.x & 63;
-  if (vi.child < 0) return;  // (the launch covers the level's internal nodes)
-  if (lane == 0) {
-    a.p2p_cnt[v] = 0;
-    a.p2p_off[v] = 0;
-    if (flag == 0) {
-      a.m2l_cnt[v] = 0; a.open_cnt[v] = 0;
-      a.m2l_off[v] = 0; a.open_off[v] = 0;
-    }
-  }
-  if (flag == 0) return;
+  if (flag == 0 || vi.child < 0) return;
   const bool root = flag == 1;
+  const uint32_t lane = threadIdx.x & 63;
   const double* rv = a.rec + (int64_t)v * a.stride;
   const uint32_t region = root ? 1u : a.exp[vi.parent];
   Emit e{};
@@ -450,33 +429,29 @@ __device__ void internal_node(const NodeWalkArgs& a, uint32_t idx) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
-  if (idx < end) internal_node(a, idx);
-}
-
 // ---- leaves, all levels at once ---------------------------------------------
 // A leaf's lists depend only on its parent's opened list, so the leaves are
 // walked after every level's internal nodes, in leaf order (one wave per
-// leaf).  The first pass stages each leaf's lists in LDS and, when they fit,
-// writes them to the leaf's fixed slots (slot_m M2L entries after the
-// internal nodes' regions, slot_p P2P entries); a leaf whose lists do not
-// fit is appended to a list of such leaves (run[5] of them) and walked again
-// by a second pass, which writes its lists after all slots at offsets from a
-// scan over the leaves.
+// leaf): a count pass, a scan over the leaves, and a fill pass that repeats
+// the walk and writes.  Leaf M2L lists follow the internal nodes' regions in
+// the M2L pool; the P2P pool holds only leaf lists.
 template <bool FILL>
-__device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
+__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
+  extern __shared__ uint32_t stk[];
+  const int l = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (l >= a.nleaves) return;
   const int v = a.leaf_node[l];
   const NodeInfo vi = a.info[v];
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
   const uint32_t lane = threadIdx.x & 63;
   if (flag == 0) {  // (a leaf never spans two systems; kept for safety)
     if (lane == 0) {
-      a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
-      a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
-      a.leaf_m2l_cnt[l] = 0; a.leaf_p2p_cnt[l] = 0;
-      a.src_total[l] = 0; a.item_cnt[l] = 1;
+      if (FILL) {
+        a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
+      } else {
+        a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+        a.leaf_m2l_cnt[l] = 0; a.leaf_p2p_cnt[l] = 0;
+      }
     }
     return;
   }
@@ -492,83 +467,40 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
   }
   Emit e{};
   if (FILL) {
-    e.m2l_base = a.run[0] + a.nleaves * a.slot_m + a.leaf_m2l_off[l];
-    e.p2p_base = a.nleaves * a.slot_p + a.leaf_p2p_off[l];
-    e.p2p_total = a.p2p_cnt[v];  // from the first pass
-    if (lane == 0) { a.m2l_off[v] = e.m2l_base; a.p2p_off[v] = e.p2p_base; }
-    walk_leaf<kEmitGlobal>(a, v, rv, src, nsrc, root, e, stk, a.status);
-    __syncthreads();  // (the stack is reused by the wave's next leaf)
-    return;
+    e.m2l_base = a.run[0] + a.leaf_m2l_off[l];
+    e.p2p_base = a.leaf_p2p_off[l];
+    e.p2p_total = a.p2p_cnt[v];  // from the count pass
+    if (lane == 0) { a.m2l_off[v] = e.m2l_base; a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
   }
-  e.cap_m = a.slot_m;
-  e.cap_p = a.slot_p;
-  e.stm = stk + a.stack_cap;
-  e.stp = e.stm + a.slot_m;
-  e.stq = e.stp + a.slot_p;
-  walk_leaf<kEmitStage>(a, v, rv, src, nsrc, root, e, stk, a.status);
-  uint32_t ns = e.src_lane;
+  walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
+  if (!FILL) {
+    uint32_t ns = e.src_lane;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
-  const uint32_t nm = e.m2l_run, np = e.p2p_run, nq = e.plain_run;
-  const bool fits = nm <= a.slot_m && np + nq <= a.slot_p;  // uniform
-  __syncthreads();  // the staged lists are complete
-  if (fits) {
-    const uint32_t mb = a.run[0] + (uint32_t)l * a.slot_m;
-    const uint32_t pb = (uint32_t)l * a.slot_p;
-    for (uint32_t i = lane; i < nm; i += 64)
-      if (mb + i < a.m2l_cap) a.m2l_pool[mb + i] = e.stm[i];
-    // the entries beyond both kernels follow in reverse rank order, as the
-    // second pass writes them
-    for (uint32_t i = lane; i < np + nq; i += 64) {
-      const uint32_t x = i < np ? e.stp[i] : e.stq[nq - 1u - (i - np)];
-      if (pb + i < a.p2p_cap) a.p2p_pool[pb + i] = x;
+    for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
+    if (lane == 0) {
+      const uint32_t np = e.p2p_run + e.plain_run;
+      a.m2l_cnt[v] = e.m2l_run;
+      a.p2p_cnt[v] = np;
+      a.open_cnt[v] = 0;
+      a.leaf_m2l_cnt[l] = e.m2l_run;
+      a.leaf_p2p_cnt[l] = np;
+      // P2P work items of the leaf: runs of at most kP2PItem source particles
+      a.src_total[l] = ns;
+      const uint32_t k = (ns + kP2PItem - 1) / kP2PItem;
+      a.item_cnt[l] = k > 0 ? k : 1u;
     }
   }
-  if (lane == 0) {
-    a.m2l_cnt[v] = nm;
-    a.p2p_cnt[v] = np + nq;
-    a.open_cnt[v] = 0;
-    a.open_off[v] = 0;
-    if (fits) {
-      a.m2l_off[v] = a.run[0] + (uint32_t)l * a.slot_m;
-      a.p2p_off[v] = (uint32_t)l * a.slot_p;
-    }
-    // lists left for the second pass (none when they fit)
-    a.leaf_m2l_cnt[l] = fits ? 0u : nm;
-    a.leaf_p2p_cnt[l] = fits ? 0u : np + nq;
-    if (!fits) a.ovf_leaf[atomicAdd(a.run + 5, 1u)] = (uint32_t)l;
-    // P2P work items of the leaf: runs of at most kP2PItem source particles
-    a.src_total[l] = ns;
-    const uint32_t k = (ns + kP2PItem - 1) / kP2PItem;
-    a.item_cnt[l] = k > 0 ? k : 1u;
-  }
-}
-
-__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
-  extern __shared__ uint32_t stk[];
-  const int l = (int)xcd_block(blockIdx.x, gridDim.x);
-  if (l < a.nleaves) leaf_lists<false>(a, l, stk);
-}
-
-// the second pass: a fixed grid of waves takes the listed leaves in turn
-constexpr unsigned kFillWaves = 2048;
-
-__global__ __launch_bounds__(64) void k_nodewalk_leaves_fill(NodeWalkArgs a) {
-  extern __shared__ uint32_t stk[];
-  const uint32_t nov = a.run[5];
-  for (uint32_t i = blockIdx.x; i < nov; i += gridDim.x) leaf_lists<true>(a, (int)a.ovf_leaf[i], stk);
 }
 
 // Places one level's internal nodes: an exclusive scan, in level order, of
 // their region sizes into absolute M2L pool offsets after everything the
 // levels above placed (levbase[level]); levbase[level + 1] and run[0] get
-// the new pool size.  A level of at most kSmallLevel nodes is one block of
-// 1024 threads; a larger one a pass of tile sums and a pass of tile scans
-// over tiles of kScanTile nodes (blocks of 256 threads).
+// the new pool size.  A level of at most one tile (SCAN_T * SCAN_I nodes)
+// is one block; a larger one a pass of tile sums and a pass of tile scans.
+constexpr int SCAN_T = 1024;
 constexpr int SCAN_I = 4;
-constexpr uint32_t kSmallLevel = 1024 * SCAN_I;
-constexpr int TILE_T = 256;
-constexpr uint32_t kScanTile = TILE_T * SCAN_I;
+constexpr int SCAN_W = SCAN_T / 64;
+constexpr uint32_t kScanTile = SCAN_T * SCAN_I;
 
 __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   const int lane = threadIdx.x & 63;
@@ -580,20 +512,17 @@ __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
   return x;
 }
 
-// exclusive scan of c over a block of NT threads; returns the exclusive
-// prefix of this thread and the block total
-template <int NT>
+// exclusive scan of c (per thread, SCAN_I consecutive items summed) over the
+// block; returns the exclusive prefix of this thread and the block total
 __device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) {
-  constexpr int W = NT / 64;
-  __shared__ uint32_t wt[W];
+  __shared__ uint32_t wt[SCAN_W];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t inc = wave_incl_u32(c);
   if (lane == 63) wt[w] = inc;
   __syncthreads();
   uint32_t pre = inc - c;
   total = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
+  for (int k = 0; k < SCAN_W; ++k) {
     const uint32_t t = wt[k];
     if (k < w) pre += t;
     total += t;
@@ -602,12 +531,10 @@ __device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) 
   return pre;
 }
 
-// one tile of NT * SCAN_I nodes: regions of tile t of the level, scanned,
-// written at base
-template <int NT>
+// one tile: regions of tile t of the level, scanned, written at base
 __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
                                               uint32_t t, uint32_t base, bool recompute) {
-  const uint32_t i0 = beg + t * (NT * SCAN_I) + threadIdx.x * SCAN_I;
+  const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
   uint32_t r[SCAN_I], c = 0;
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
@@ -616,7 +543,7 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
     c += r[q];
   }
   uint32_t total;
-  uint32_t o = base + block_excl_u32<NT>(c, total);
+  uint32_t o = base + block_excl_u32(c, total);
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
@@ -626,10 +553,10 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
   return total;
 }
 
-__global__ __launch_bounds__(1024) void k_level_scan_small(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t base = a.levbase[level];
-  const uint32_t total = scan_tile<1024>(a, beg, end, 0, base, true);
+  const uint32_t total = scan_tile(a, beg, end, 0, base, true);
   if (threadIdx.x == 0) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
@@ -637,7 +564,7 @@ __global__ __launch_bounds__(1024) void k_level_scan_small(NodeWalkArgs a, int l
 }
 
 // tile sums (and the regions, kept for the second pass)
-__global__ __launch_bounds__(TILE_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
   uint32_t c = 0;
@@ -649,43 +576,18 @@ __global__ __launch_bounds__(TILE_T) void k_level_tile_sums(NodeWalkArgs a, int 
     c += r;
   }
   uint32_t total;
-  (void)block_excl_u32<TILE_T>(c, total);
+  (void)block_excl_u32(c, total);
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(TILE_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
+__global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  // the sums of the tiles before this one, read by the whole block
-  uint32_t c = 0;
-  for (uint32_t t = threadIdx.x; t < blockIdx.x; t += TILE_T) c += a.tile_sum[t];
-  uint32_t before;
-  (void)block_excl_u32<TILE_T>(c, before);
-  const uint32_t base = a.levbase[level] + before;
-  const uint32_t total = scan_tile<TILE_T>(a, beg, end, blockIdx.x, base, false);
+  uint32_t base = a.levbase[level];
+  for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
+  const uint32_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
   if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
-  }
-}
-
-// levels 0 .. top, each of at most kTopLevelNodes internal nodes, in one
-// block: per level the scan, a barrier, one wave per node, a barrier
-constexpr int kTopWaves = 16;
-constexpr uint32_t kTopLevelNodes = 4 * kTopWaves;
-
-__global__ __launch_bounds__(64 * kTopWaves) void k_nodewalk_top(NodeWalkArgs a, int top) {
-  const uint32_t w = threadIdx.x >> 6;
-  for (int k = 0; k <= top; ++k) {
-    const uint32_t beg = a.level_off[k], end = a.level_int[k];
-    const uint32_t base = a.levbase[k];
-    const uint32_t total = scan_tile<64 * kTopWaves>(a, beg, end, 0, base, true);
-    if (threadIdx.x == 0) {
-      a.levbase[k + 1] = base + total;
-      a.run[0] = base + total;
-    }
-    __syncthreads();
-    for (uint32_t i = beg + w; i < end; i += kTopWaves) internal_node(a, i);
-    __syncthreads();
   }
 }
 
@@ -753,40 +655,28 @@ void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level,
   // (nodes_in_level: the level's internal nodes)
   if (nodes_in_level <= 0) {
     // an empty level still carries the pool size to the next one
-    k_level_scan_small<<<1, 1024, 0, s>>>(a, level);
+    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
     return;
   }
-  if ((uint32_t)nodes_in_level <= kSmallLevel) {
-    k_level_scan_small<<<1, 1024, 0, s>>>(a, level);
+  const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
+  if (tiles == 1) {
+    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
   } else {
-    const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
-    k_level_tile_sums<<<tiles, TILE_T, 0, s>>>(a, level);
-    k_level_tile_scan<<<tiles, TILE_T, 0, s>>>(a, level);
+    k_level_tile_sums<<<tiles, SCAN_T, 0, s>>>(a, level);
+    k_level_tile_scan<<<tiles, SCAN_T, 0, s>>>(a, level);
   }
   k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level);
 }
 
-int nodewalk_top_levels(int maxdepth, const uint32_t* level_off, const uint32_t* level_int) {
-  int top = -1;
-  while (top < maxdepth && level_int[top + 1] - level_off[top + 1] <= kTopLevelNodes) ++top;
-  return top;
-}
-
-void launch_nodewalk_top(const NodeWalkArgs& a, int top, hipStream_t s) {
-  if (top < 0) return;
-  k_nodewalk_top<<<1, 64 * kTopWaves, 0, s>>>(a, top);
-}
-
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s) {
   if (a.nleaves <= 0) return;
-  const size_t lds = (a.stack_cap + a.slot_m + 2 * a.slot_p) * sizeof(uint32_t);
-  k_nodewalk_leaves<<<a.nleaves, 64, lds, s>>>(a);
+  const size_t lds = a.stack_cap * sizeof(uint32_t);
+  k_nodewalk_leaves<false><<<a.nleaves, 64, lds, s>>>(a);
   scan_u32(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3, scan_tmp, s);
   scan_u32(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2, scan_tmp, s);
   // P2P work items: item_off[nleaves] = their total (read back with the walk's)
   scan_u32(a.item_cnt, a.item_off, a.nleaves, a.item_off + a.nleaves, scan_tmp, s);
-  k_nodewalk_leaves_fill<<<std::min<unsigned>(kFillWaves, (unsigned)a.nleaves), 64,
-                           a.stack_cap * sizeof(uint32_t), s>>>(a);
+  k_nodewalk_leaves<true><<<a.nleaves, 64, lds, s>>>(a);
 }
 
 }  // namespace sfmm

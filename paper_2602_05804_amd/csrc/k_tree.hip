@@ -19,8 +19,8 @@ namespace sfmm {
 namespace {
 
 constexpr int BBOX_THREADS = 256;
-constexpr int RS_THREADS = 512;
-constexpr int RS_ITEMS = 8;
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 
 __device__ __forceinline__ double wave_min(double v) {
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(int n, const uint64_t
                                                            int shift, uint32_t* __restrict__ hist,
                                                            int nb) {
   __shared__ uint32_t cnt[256];
-  if (threadIdx.x < 256) cnt[threadIdx.x] = 0;
+  cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ITEMS; ++r) {
@@ -248,79 +248,30 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(int n, const uint64_t
     if (i < n) atomicAdd(&cnt[(key[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+  hist[(int64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// exclusive scan of one value per thread over the block, and the total
-__device__ __forceinline__ uint32_t rs_block_excl(uint32_t c, uint32_t& total) {
-  constexpr int W = RS_THREADS / 64;
-  __shared__ uint32_t wt[W];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t x = c;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) wt[w] = x;
-  __syncthreads();
-  uint32_t pre = x - c;
-  total = 0;
-#pragma unroll
-  for (int k = 0; k < W; ++k) {
-    if (k < w) pre += wt[k];
-    total += wt[k];
-  }
-  __syncthreads();
-  return pre;
-}
-
-// Stable scatter: the tile's elements are ranked in their original order
-// (equal digits inside a wave found with eight ballots) and placed, sorted
-// by digit, in LDS; the tile then writes each digit's run to its global
-// offset in order, so consecutive threads write consecutive addresses.
-// cnt: the tile digit counts, offs: their exclusive scan (digit-major).
+// Stable scatter: elements of the tile are ranked in their original order;
+// equal digits inside a wave are found with eight ballots.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     int n, const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
     uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, int shift,
-    const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ offs, int nb) {
-  constexpr int W = RS_THREADS / 64;
-  __shared__ uint64_t sk[RS_TILE];
-  __shared__ uint32_t sv[RS_TILE];
-  __shared__ uint32_t start[256], gbase[256], run[256];
-  __shared__ uint32_t wc[W][256];
+    const uint32_t* __restrict__ offs, int nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wc[RS_THREADS / 64][256];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  {
-    const uint32_t c = t < 256 ? cnt[(int64_t)t * nb + blockIdx.x] : 0u;
-    uint32_t tot;
-    const uint32_t ex = rs_block_excl(c, tot);
-    if (t < 256) {
-      start[t] = ex;
-      gbase[t] = offs[(int64_t)t * nb + blockIdx.x];
-      run[t] = 0;
-    }
-  }
+  run[t] = 0;
+  base[t] = offs[(int64_t)t * nb + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
-  // every round's element loaded up front (the rounds are separated by
-  // barriers, which would otherwise wait for one load each)
-  uint64_t kr[RS_ITEMS];
-  uint32_t vr[RS_ITEMS];
-#pragma unroll
   for (int r = 0; r < RS_ITEMS; ++r) {
-    const int64_t i = tile0 + r * RS_THREADS + t;
-    kr[r] = i < n ? kin[i] : 0ull;
-    vr[r] = i < n ? vin[i] : 0u;
-  }
-#pragma unroll
-  for (int r = 0; r < RS_ITEMS; ++r) {
-    for (int q = t; q < W * 256; q += RS_THREADS) (&wc[0][0])[q] = 0;
+    for (int q = 0; q < RS_THREADS / 64; ++q) wc[q][t] = 0;
     __syncthreads();
-    const int64_t i = tile0 + r * RS_THREADS + t;
+    const int64_t i = (int64_t)blockIdx.x * RS_TILE + r * RS_THREADS + t;
     const bool valid = i < n;
-    const uint64_t k = kr[r];
-    const uint32_t v = vr[r];
-    const uint32_t d = (uint32_t)((k >> shift) & 255u);
+    uint64_t k = valid ? kin[i] : 0ull;
+    uint32_t v = valid ? vin[i] : 0u;
+    uint32_t d = (uint32_t)((k >> shift) & 255u);
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -332,26 +283,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(
     if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = start[d] + run[d] + rank;
+      uint32_t pos = base[d] + run[d] + rank;
       for (int q = 0; q < w; ++q) pos += wc[q][d];
-      sk[pos] = k;
-      sv[pos] = v;
+      kout[pos] = k;
+      vout[pos] = v;
     }
     __syncthreads();
-    if (t < 256) {
-      uint32_t add = 0;
-      for (int q = 0; q < W; ++q) add += wc[q][t];
-      run[t] += add;
-    }
-  }
-  __syncthreads();
-  const int tn = (int)min<int64_t>(RS_TILE, (int64_t)n - tile0);
-  for (int j = t; j < tn; j += RS_THREADS) {
-    const uint64_t k = sk[j];
-    const uint32_t d = (uint32_t)((k >> shift) & 255u);
-    const uint32_t g = gbase[d] + ((uint32_t)j - start[d]);
-    kout[g] = k;
-    vout[g] = sv[j];
+    uint32_t add = 0;
+    for (int q = 0; q < RS_THREADS / 64; ++q) add += wc[q][t];
+    run[t] += add;
+    __syncthreads();
   }
 }
 
@@ -506,23 +447,21 @@ __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
   for (int p = ni.lo; p < ni.lo + ni.cnt; ++p) p_leaf[p] = l;
 }
 
-// ---- geometry, moments (leaves, then internal nodes bottom-up) -------------
-// A leaf sums its particles in sorted order (every leaf in one launch); an
-// internal node combines its two children (one launch per depth, the
-// deepest first).  The top levels, each of at most kGeomTopNodes internal
-// nodes, run in one block, a barrier between levels.
-constexpr int kGeomTopNodes = 1024;
-
+// ---- geometry, moments (bottom-up, one launch per depth) ------------------
+// A leaf sums its particles in sorted order; an internal node combines its
+// two children (children first: the deepest level is launched first).
 template <int P>
-__device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ info,
-                                          const double* __restrict__ xs,
-                                          const double* __restrict__ ys,
-                                          const double* __restrict__ zs,
-                                          const double* __restrict__ ms,
-                                          const double* __restrict__ hs, double* rec) {
+__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
+                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                             const double* __restrict__ ys, const double* __restrict__ zs,
+                             const double* __restrict__ ms, const double* __restrict__ hs,
+                             double* __restrict__ rec) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int RS = rec_stride(P);
+  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  const int v = level_nodes[idx];
   const NodeInfo ni = info[v];
   double* r = rec + (int64_t)v * RS;
   double Q[NQ];
@@ -530,7 +469,6 @@ __device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ in
   for (int k = 0; k < NQ; ++k) Q[k] = 0.0;
   if (ni.child < 0) {
     double M = 0.0, S0 = 0.0, S1 = 0.0, S2 = 0.0, hm = 0.0;
-#pragma unroll 4
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double mj = ms[j];
       M += mj;
@@ -541,7 +479,6 @@ __device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ in
     }
     const double s0 = S0 / M, s1 = S1 / M, s2 = S2 / M;
     double d2max = 0.0;
-#pragma unroll 4
     for (int j = ni.lo; j < ni.lo + ni.cnt; ++j) {
       const double b[3] = {xs[j] - s0, ys[j] - s1, zs[j] - s2};
       const double d2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
@@ -574,52 +511,6 @@ __device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ in
   }
 #pragma unroll
   for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
-}
-
-template <int P>
-__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
-                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
-                             const double* __restrict__ ys, const double* __restrict__ zs,
-                             const double* __restrict__ ms, const double* __restrict__ hs,
-                             double* __restrict__ rec) {
-  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= end) return;
-  geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
-}
-
-template <int P>
-__global__ void k_geom_leaves(int nleaves, const int32_t* __restrict__ leaf_node,
-                              const NodeInfo* __restrict__ info, const double* __restrict__ xs,
-                              const double* __restrict__ ys, const double* __restrict__ zs,
-                              const double* __restrict__ ms, const double* __restrict__ hs,
-                              double* __restrict__ rec) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l < nleaves) geom_node<P>(leaf_node[l], info, xs, ys, zs, ms, hs, rec);
-}
-
-// internal nodes of levels top .. 0 in one block of kGeomTopNodes threads;
-// the records a level reads were written before the barrier (by this block,
-// or by the launches before it)
-struct GeomTop {
-  uint32_t off[kMaxDepthCap + 2];  // level k's internal nodes: [off[k], end[k])
-  uint32_t end[kMaxDepthCap + 2];
-};
-
-template <int P>
-__global__ __launch_bounds__(kGeomTopNodes) void k_geom_top(const int32_t* __restrict__ level_nodes,
-                                                            GeomTop lv, int top,
-                                                            const NodeInfo* __restrict__ info,
-                                                            const double* __restrict__ xs,
-                                                            const double* __restrict__ ys,
-                                                            const double* __restrict__ zs,
-                                                            const double* __restrict__ ms,
-                                                            const double* __restrict__ hs,
-                                                            double* rec) {
-  for (int k = top; k >= 0; --k) {
-    const uint32_t idx = lv.off[k] + threadIdx.x;
-    if (idx < lv.end[k]) geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
-    __syncthreads();
-  }
 }
 
 __global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
@@ -706,10 +597,9 @@ void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
                 int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
                 hipStream_t s) {
   const int nb = radix_blocks(n);
-  uint32_t* offs = hist + (int64_t)256 * nb;
   k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
-  scan_u32(hist, offs, (int64_t)256 * nb, scratch_total, hist_tmp, s);
-  k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, offs, nb);
+  scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+  k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
 }
 
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
@@ -717,11 +607,10 @@ void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t*
   const int nb = radix_blocks(n);
   uint64_t *kin = key0, *kout = key1;
   uint32_t *vin = val0, *vout = val1;
-  uint32_t* offs = hist + (int64_t)256 * nb;
   for (int shift = 0; shift < 64; shift += 8) {  // 8 passes: result lands in key0/val0
     k_radix_hist<<<nb, RS_THREADS, 0, s>>>(n, kin, shift, hist, nb);
-    scan_u32(hist, offs, (int64_t)256 * nb, scratch_total, hist_tmp, s);
-    k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, offs, nb);
+    scan_u32(hist, hist, (int64_t)256 * nb, scratch_total, hist_tmp, s);
+    k_radix_scatter<<<nb, RS_THREADS, 0, s>>>(n, kin, vin, kout, vout, shift, hist, nb);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
@@ -789,47 +678,21 @@ void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* in
 }
 
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
-                     const uint32_t* level_int_host, int nleaves, const int32_t* leaf_node,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                      const double* ys, const double* zs, const double* ms, const double* hs,
                      double* rec, hipStream_t s) {
-#define GEOM_ORDERS(LAUNCH) \
-  switch (order) {          \
-    case 0: LAUNCH(0); break; \
-    case 1: LAUNCH(1); break; \
-    case 2: LAUNCH(2); break; \
-    case 3: LAUNCH(3); break; \
-    case 4: LAUNCH(4); break; \
-  }
-  if (nleaves > 0) {
-    const unsigned nb = blocks_for(nleaves, 128);
-#define LEAVES(P) k_geom_leaves<P><<<nb, 128, 0, s>>>(nleaves, leaf_node, info, xs, ys, zs, ms, hs, rec)
-    GEOM_ORDERS(LEAVES)
-#undef LEAVES
-  }
-  // the top levels whose internal nodes all fit one block
-  int top = -1;
-  while (top < maxdepth &&
-         level_int_host[top + 1] - level_off_host[top + 1] <= (uint32_t)kGeomTopNodes)
-    ++top;
-  for (int k = maxdepth; k > top; --k) {
-    const uint32_t beg = level_off_host[k], end = level_int_host[k];
+  for (int k = maxdepth; k >= 0; --k) {
+    const uint32_t beg = level_off_host[k], end = level_off_host[k + 1];
     if (end <= beg) continue;
     const unsigned nb = blocks_for(end - beg, 128);
-#define LEVEL(P) k_geom_level<P><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec)
-    GEOM_ORDERS(LEVEL)
-#undef LEVEL
+    switch (order) {
+      case 0: k_geom_level<0><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 1: k_geom_level<1><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 2: k_geom_level<2><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 3: k_geom_level<3><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+      case 4: k_geom_level<4><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+    }
   }
-  if (top < 0) return;
-  GeomTop lv;
-  for (int k = 0; k <= top; ++k) {
-    lv.off[k] = level_off_host[k];
-    lv.end[k] = level_int_host[k];
-  }
-#define TOP(P) k_geom_top<P><<<1, kGeomTopNodes, 0, s>>>(level_nodes, lv, top, info, xs, ys, zs, ms, hs, rec)
-  GEOM_ORDERS(TOP)
-#undef TOP
-#undef GEOM_ORDERS
 }
 
 void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s) {

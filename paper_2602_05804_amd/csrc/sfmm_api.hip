@@ -37,25 +37,13 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
-  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_OVFLEAF,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
   B_COUNT
 };
 
 // small device scalars (B_SMALL, u64 slots)
 enum SmallId { S_NKEPT = 0, S_NLEAVES, S_MAXDEPTH, S_NITEMS, S_M2LTOT, S_P2PTOT, S_PAIRTOT,
                S_DOFFTOT, S_SORTTOT, S_L2LTOT, S_COUNT };
-
-// pinned host copies of the sizes read back during a solve: the copies of one
-// synchronisation point are queued together and waited for once
-struct HostStage {
-  uint64_t small[S_COUNT];
-  int status[4];
-  uint32_t level_off[kMaxDepthCap + 2];
-  uint32_t level_int[kMaxDepthCap + 2];
-  uint32_t walk_tot[8];
-  int walk_status[4];
-  uint32_t walk_items;
-};
 
 }  // namespace
 
@@ -82,8 +70,6 @@ struct sfmm_ctx {
   std::vector<uint32_t> level_int;  // end of each level's internal nodes
   uint64_t m2l_cap = 0, p2p_cap = 0;
   int64_t items_from_walk = 0;  // P2P work items counted by the level walk
-  // level walk: entries of a leaf's fixed list slots (M2L, P2P)
-  uint32_t leaf_slot_m = 512, leaf_slot_p = 256;
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
@@ -91,7 +77,6 @@ struct sfmm_ctx {
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
   sfmm_stats stats{};
-  HostStage* stage = nullptr;  // pinned (hipHostMalloc), allocated on first use
 };
 
 namespace {
@@ -107,18 +92,6 @@ int fail(sfmm_ctx* c, int code, const std::string& msg) {
     if (e_ != hipSuccess)                                                             \
       return fail(ctx, SFMM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
-
-// the pinned staging area for read-backs (device already set)
-int host_stage(sfmm_ctx* ctx) {
-  if (ctx->stage) return SFMM_OK;
-  void* p = nullptr;
-  if (hipHostMalloc(&p, sizeof(HostStage), hipHostMallocDefault) != hipSuccess || !p) {
-    (void)hipGetLastError();
-    return fail(ctx, SFMM_ENOMEM, "pinned host staging allocation failed");
-  }
-  ctx->stage = static_cast<HostStage*>(p);
-  return SFMM_OK;
-}
 
 // make buffer `id` hold at least `bytes`; contents are not preserved
 int ensure(sfmm_ctx* ctx, int id, size_t bytes) {
@@ -197,7 +170,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
       {B_STATUS, sizeof(int) * 4}, {B_SMALL, sizeof(uint64_t) * S_COUNT},
       {B_KEY0, sizeof(uint64_t) * n}, {B_KEY1, sizeof(uint64_t) * n},
       {B_VAL0, sizeof(uint32_t) * n}, {B_VAL1, sizeof(uint32_t) * n},
-      {B_HIST, sizeof(uint32_t) * 2 * 256 * (size_t)radix_blocks(n)},
+      {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(n)},
       {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(n), 2 * (int64_t)n + 2))},
       {B_XS, sizeof(double) * n}, {B_YS, sizeof(double) * n}, {B_ZS, sizeof(double) * n},
       {B_MS, sizeof(double) * n}, {B_HS, sizeof(double) * n}, {B_HIS, sizeof(double) * n},
@@ -297,12 +270,10 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     launch_leaf_fill(n, P<uint32_t>(ctx, B_LFLAG), lscan, P<int32_t>(ctx, B_LAT), leaf_node, s);
   }
   // ---- sizes to the host (one synchronisation)
-  if ((rc = host_stage(ctx))) return rc;
-  HostStage* hs = ctx->stage;
-  const uint64_t* hsmall = hs->small;
-  const int* hstatus = hs->status;
-  HIPCHK(hipMemcpyAsync(hs->small, small, sizeof(hs->small), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hs->status, status, sizeof(hs->status), hipMemcpyDeviceToHost, s));
+  uint64_t hsmall[S_COUNT];
+  int hstatus[4];
+  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   if (hstatus[0] & ST_NONFINITE)
     return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
@@ -326,7 +297,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
         {B_LEVKEY0, sizeof(uint64_t) * nn}, {B_LEVKEY1, sizeof(uint64_t) * nn},
         {B_LEVIDS, sizeof(uint32_t) * nn}, {B_LEVOFF, sizeof(uint32_t) * (kMaxDepthCap + 2)},
         {B_LEVINT, sizeof(uint32_t) * (kMaxDepthCap + 2)},
-        {B_HIST, sizeof(uint32_t) * 2 * 256 * (size_t)radix_blocks(nn)},
+        {B_HIST, sizeof(uint32_t) * 256 * (size_t)radix_blocks(nn)},
         {B_SCANTMP, sizeof(uint64_t) * scan_tmp_elems(std::max<int64_t>(256 * (int64_t)radix_blocks(nn), 2 * (int64_t)n + 2))}};
     for (auto& q : need2)
       if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
@@ -336,9 +307,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                P<uint64_t>(ctx, B_LEVKEY1), P<uint32_t>(ctx, B_LEVNODES), 0,
                P<uint32_t>(ctx, B_HIST), P<uint32_t>(ctx, B_SCANTMP),
                reinterpret_cast<uint32_t*>(small + S_SORTTOT), s);
-    // (the scanned digit counts of the pass)
-    launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn,
-                         P<uint32_t>(ctx, B_HIST) + 256 * (size_t)radix_blocks(nn),
+    launch_level_offsets(kMaxDepthCap + 1, radix_blocks(nn), nn, P<uint32_t>(ctx, B_HIST),
                          P<uint32_t>(ctx, B_LEVOFF), P<uint32_t>(ctx, B_LEVINT), s);
   }
   if (nsys > 1) {
@@ -355,19 +324,19 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
              P<uint32_t>(ctx, B_SCANTMP), s);
     HIPCHK(hipMemsetAsync(P<uint64_t>(ctx, B_L2BITS), 0, sizeof(uint64_t) * nn, s));
   }
-  HIPCHK(hipMemcpyAsync(hs->small, small, sizeof(hs->small), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hs->level_off, P<uint32_t>(ctx, B_LEVOFF), sizeof(hs->level_off),
-                        hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hs->level_int, P<uint32_t>(ctx, B_LEVINT), sizeof(hs->level_int),
-                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+  ctx->level_off.resize(kMaxDepthCap + 2);
+  ctx->level_int.resize(kMaxDepthCap + 2);
+  HIPCHK(hipMemcpyAsync(ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
+                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ctx->level_int.data(), P<uint32_t>(ctx, B_LEVINT),
+                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  ctx->level_off.assign(hs->level_off, hs->level_off + kMaxDepthCap + 2);
-  ctx->level_int.assign(hs->level_int, hs->level_int + kMaxDepthCap + 2);
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
   if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
   // ---- geometry and moments, level by level from the deepest
-  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(), ctx->level_int.data(), nl,
-                  leaf_node, reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
+  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(),
+                  reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
                   P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
                   P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_REC), s);
   if (nn > 1) {
@@ -469,37 +438,30 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 8))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
-  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_OVFLEAF})
+  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
   if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 1024 + 2)))) return rc;
+  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 4096 + 2)))) return rc;
   if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint32_t) * (kMaxDepthCap + 2)))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
   // (the M2L pool also holds the opened lists of internal nodes)
-  // leaf list slots (entries per leaf), bounded so that the slots of all
-  // leaves stay well inside 32-bit offsets
-  uint32_t slot_m = (uint32_t)std::min<uint64_t>(ctx->leaf_slot_m, (1ull << 30) / std::max(nl, 1));
-  uint32_t slot_p = (uint32_t)std::min<uint64_t>(ctx->leaf_slot_p, (1ull << 28) / std::max(nl, 1));
-  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + (uint64_t)slot_m * nl + 2048);
-  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + (uint64_t)slot_p * nl + 1024);
+  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + 2048);
+  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + 1024);
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
   const uint64_t kPoolMax = 0xF0000000ull;
   for (int attempt = 0;; ++attempt) {
-    // the staging slots share the leaf pass's LDS with the lowering stack
-    // (at most 64 KB in all): without room, every leaf takes the second pass
-    if (ctx->stack_cap + slot_m + 2 * slot_p > 16384) slot_m = slot_p = 0;
     if (ctx->m2l_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
       return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed 2^32 entries");
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint32_t* tot = P<uint32_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 8, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 4, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     NodeWalkArgs a{};
     a.info = P<NodeInfo>(ctx, B_INFO);
@@ -533,9 +495,6 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.stack_cap = ctx->stack_cap;
     a.status = status;
     a.nleaves = nl;
-    a.slot_m = slot_m;
-    a.slot_p = slot_p;
-    a.ovf_leaf = P<uint32_t>(ctx, B_OVFLEAF);
     a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
     a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
@@ -544,35 +503,26 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.src_total = P<uint32_t>(ctx, B_SRCTOT);
     a.item_cnt = P<uint32_t>(ctx, B_ITEMCNT);
     a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
-    // internal nodes level by level (the small top levels in one block),
-    // then every leaf
-    const int top = nodewalk_top_levels(ctx->maxdepth, ctx->level_off.data(), ctx->level_int.data());
-    launch_nodewalk_top(a, top, s);
-    for (int k = top + 1; k <= ctx->maxdepth; ++k)
+    // internal nodes level by level, then every leaf
+    for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
-    // M2L entries proper (the pool also holds the opened lists), P2P entries
+    // M2L entries proper (the pool also holds the opened lists)
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
-    launch_sum_u32(nn, a.p2p_cnt, tot + 4, s);
-    if ((rc = host_stage(ctx))) return rc;
-    HostStage* hs = ctx->stage;
-    const uint32_t* htot = hs->walk_tot;
-    const int* hstatus = hs->walk_status;
-    hs->walk_items = 0;
-    HIPCHK(hipMemcpyAsync(hs->walk_tot, tot, sizeof(hs->walk_tot), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hs->walk_status, status, sizeof(hs->walk_status), hipMemcpyDeviceToHost, s));
+    uint32_t htot[4];
+    int hstatus[4];
+    uint32_t hitems = 0;
+    HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
     if (nl > 0)
-      HIPCHK(hipMemcpyAsync(&hs->walk_items, a.item_off + nl, sizeof(uint32_t),
-                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hitems, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    ctx->items_from_walk = hs->walk_items;
-    // internal regions, the leaves' slots, the lists that did not fit
-    const uint64_t m2l_used = (uint64_t)htot[0] + (uint64_t)slot_m * nl + htot[3];
-    const uint64_t p2p_used = (uint64_t)slot_p * nl + htot[2];
-    const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap;
+    ctx->items_from_walk = hitems;
+    const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
+    const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
-      ctx->p2p_total = htot[4];
+      ctx->p2p_total = htot[2];
       ctx->m2l_unique = htot[1];
       return SFMM_OK;
     }
@@ -584,7 +534,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
       ctx->m2l_cap = grow(ctx->m2l_cap, m2l_used);
-      ctx->p2p_cap = grow(ctx->p2p_cap, p2p_used);
+      ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
     }
     if (stack_over) {
       if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
@@ -812,14 +762,6 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   // measurement overrides
   if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
   if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
-  // leaf list slots "M,P" (0,0: every leaf takes the second pass)
-  if (const char* ls = std::getenv("SFMM_LEAF_SLOTS")) {
-    unsigned sm = 0, sp = 0;
-    if (std::sscanf(ls, "%u,%u", &sm, &sp) == 2 && sm <= 4096 && sp <= 4096) {
-      ctx->leaf_slot_m = sm;
-      ctx->leaf_slot_p = sp;
-    }
-  }
   *out = ctx;
   return SFMM_OK;
 }
@@ -833,7 +775,6 @@ int sfmm_destroy(sfmm_ctx* ctx) {
   if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
   for (auto& b : ctx->buf)
     if (b.p) (void)hipFree(b.p);
-  if (ctx->stage) (void)hipHostFree(ctx->stage);
   delete ctx;
   return SFMM_OK;
 }

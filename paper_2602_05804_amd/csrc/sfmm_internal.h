@@ -58,18 +58,6 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
-// The same idea for work whose cost varies along the range: rounds of
-// kXcds * C blocks, each XCD taking C consecutive blocks of a round, so the
-// XCDs share the range evenly while neighbours stay in one L2 (the blocks of
-// a last, incomplete round keep their order).
-template <unsigned C>
-__device__ __forceinline__ unsigned xcd_chunk_block(unsigned b, unsigned nb) {
-  constexpr unsigned R = kXcds * C;
-  if (b / R == nb / R) return b;
-  const unsigned j = b / kXcds;
-  return (j / C) * R + (b % kXcds) * C + (j % C);
-}
-
 // local (field) coefficients: H_g for 1 <= |g| <= p+1, then P_b for |b| <= p
 __host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 + ncoef(p); }
 // FP32 copy of the moments (SFMM_FP32C): ncoef floats, then the node depth
@@ -94,13 +82,11 @@ void launch_bbox(int n, const double* x, const double* m, const double* h, doubl
 void launch_keys(int n, const double* x, const double* box, uint64_t* key, uint32_t* idx,
                  hipStream_t s);
 int radix_blocks(int64_t n);
-// sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1);
-// hist holds 2 * 256 * radix_blocks(n) counters
+// sorts (key, idx) by key, stable; returns in key0/val0 (ping-pong via key1/val1)
 void radix_sort(int n, uint64_t* key0, uint32_t* val0, uint64_t* key1, uint32_t* val1,
                 uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total, hipStream_t s);
-// one stable pass on the 8-bit digit at `shift`; hist holds 2 * 256 * radix_blocks(n)
-// counters: the tile digit counts, then (from hist + 256 * radix_blocks(n)) their
-// exclusive scan (digit-major), kept after the pass
+// one stable pass on the 8-bit digit at `shift`; hist holds 256 * radix_blocks(n)
+// counters and, after the pass, their exclusive scan (digit-major)
 void radix_pass(int n, const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                 int shift, uint32_t* hist, uint32_t* hist_tmp, uint32_t* scratch_total,
                 hipStream_t s);
@@ -136,10 +122,8 @@ void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                        const int32_t* node_depth, int32_t* leaf_depth, int32_t* p_leaf,
                        int* maxdepth, hipStream_t s);
-// geometry and moments: every leaf, then the internal nodes deepest level
-// first (level_off_host, level_int_host: host copies of the level ranges)
+// geometry and moments, deepest level first (level_off_host: host copy)
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
-                     const uint32_t* level_int_host, int nleaves, const int32_t* leaf_node,
                      const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                      const double* ys, const double* zs, const double* ms, const double* hs,
                      double* rec, hipStream_t s);
@@ -195,21 +179,14 @@ struct NodeWalkArgs {
   uint32_t* exp;  // per internal node: tested-list size of each of its children
   uint32_t* lvl_cnt32;  // [nn] M2L pool region of each internal node, in level order
   uint32_t* lvl_off;    // [nn] its absolute offset in the M2L pool
-  uint32_t* tile_sum;   // [nn / 1024 + 1] region sums per scan tile of a level
+  uint32_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
   uint32_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint32_t* run;      // [8] M2L pool used by internal nodes, M2L entries proper (the
-                      // walk's sum), P2P pool after the slots, M2L pool after the
-                      // slots, P2P entries (the walk's sum), leaves left for the
-                      // second pass
-  // leaves (walked after all levels, in leaf order); leaf l's lists go to
-  // fixed slots (M2L: run[0] + l * slot_m, P2P: l * slot_p) when they fit,
-  // else after all slots: leaf_*_cnt are the lists left for the second pass
-  // (0 for a leaf in its slots), leaf_*_off their scan
+  uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
+                      // walk's sum), P2P pool, M2L pool used by leaves
+  // leaves (walked after all levels, in leaf order)
   int nleaves;
   const int32_t* leaf_node;
-  uint32_t slot_m, slot_p;
   uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt, *leaf_m2l_off, *leaf_p2p_off;
-  uint32_t* ovf_leaf;  // [nleaves] the leaves left for the second pass (run[5] of them)
   // per leaf: particles over its P2P entries, P2P work items and their offsets
   // ([nleaves + 1], the last entry the total)
   uint32_t *src_total, *item_cnt, *item_off;
@@ -231,10 +208,6 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
 // out[0] += sum of x[0..n) (out on the device)
 void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
-// the top levels walked in one block: levels 0 .. top (top = -1: none), the
-// deepest prefix of levels whose internal nodes each fit the block's pass
-int nodewalk_top_levels(int maxdepth, const uint32_t* level_off, const uint32_t* level_int);
-void launch_nodewalk_top(const NodeWalkArgs& a, int top, hipStream_t s);
 
 // per-leaf statistics of node lists: replicated M2L count, L2L count, pairs
 struct LeafStatArgs {

@@ -187,30 +187,6 @@ def test_lists_parity(torch, P, orc, walk):
     assert st["n_p2p_pairs"] == ost["n_p2p_pairs"]
 
 
-@pytest.mark.parametrize("slots", ["0,0", "4,2", "16,8"])
-def test_leaf_slots_overflow(torch, P, orc, slots, monkeypatch):
-    # leaf lists that do not fit their fixed slots take the second leaf pass
-    # (all of them at "0,0", a mix otherwise): the same lists in the same
-    # order, so bit-identical results
-    print(f"case: leaf list slots {slots}, plummer N=4096 seed 1", flush=True)
-    x, m, h = workloads.plummer(4096, seed=1)
-    acc0, pot0, s0 = gpu_solve(torch, P, x, m, h, theta=0.5)
-    st0 = s0.stats()
-    s0.close()
-    monkeypatch.setenv("SFMM_LEAF_SLOTS", slots)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5)
-    assert np.array_equal(acc, acc0) and np.array_equal(pot, pot0)
-    st = s.stats()
-    for k in ("n_m2l", "n_m2l_unique", "n_p2p_leaf_pairs", "n_p2p_pairs"):
-        assert st[k] == st0[k], k
-    g = s.tree(order=3)
-    leaf_nodes, _ = s.leaves()
-    t = orc.Tree(x, m, h, leaf_size=10, order=3)
-    _lists_equal(s, t, g, leaf_nodes, 0.5, same_order=False)
-    _p2p_partitioned(s, g, leaf_nodes)
-    s.close()
-
-
 @pytest.mark.parametrize("theta,walk", [(0.3, "level"), (0.5, "level"), (0.7, "level"),
                                         (0.5, "leaf"), (0.7, "leaf")])
 def test_solve_parity_plummer(torch, P, orc, theta, walk):
