@@ -156,6 +156,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving run (Poisson arrivals at 200/s, N log-uniform "
                          "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
+    ap.add_argument("--serve-fp32c", action="store_true",
+                    help="also serve the trace in FP32C (packed FP32C solves of up to "
+                         "--serve-pack particles)")
     ap.add_argument("--serve-pack", type=float, default=16e6,
                     help="particles per packed solve in the serving run")
     ap.add_argument("--serve-inflight", type=float, default=24e6,
@@ -353,9 +356,10 @@ def main():
 
 
 def serving(args):
-    """Continuous batching of a stream of independent solves: FP64 and FP32C
-    on the same arrival trace with the HBM budget at 0.8 x free memory, then
-    FP64 again under a small budget so that admission queues requests."""
+    """Continuous batching of a stream of independent solves: FP64 (and, with
+    --serve-fp32c, FP32C) on the same arrival trace with the HBM budget at
+    0.8 x free memory, then FP64 again under a small budget so that admission
+    queues requests."""
     import torch
 
     import workloads
@@ -369,7 +373,8 @@ def serving(args):
            "pack_particles": args.serve_pack, "max_particles_in_flight": args.serve_inflight,
            "trace": "Poisson arrivals at 200/s, N = 10^U(3,6), Plummer/polytrope alternating, "
                     "seed 7"}
-    runs = [("fp64", None), ("fp32c", None), ("fp64", 3_000_000)]
+    runs = [("fp64", None)] + ([("fp32c", None)] if args.serve_fp32c else []) + [
+        ("fp64", 3_000_000)]
     for prec, small_budget_n in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
                                leaf_size=args.leaf_size, far=args.far,
