@@ -142,6 +142,8 @@ typedef struct {
   int64_t n_p2p_soft_pairs; /* ordered particle pairs inside a softening kernel
                                (counted by the default P2P kernel shape of either
                                precision; 0 for the other shapes)                  */
+  int32_t walk_attempts;    /* level walks the solve made: 1, plus one more each
+                               time the list pools had to grow                     */
 } sfmm_stats;
 
 /* Fill *cfg with the defaults listed above.  Returns SFMM_EINVAL if cfg is NULL. */

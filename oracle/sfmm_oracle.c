@@ -600,7 +600,7 @@ static void ipush(ilist* l, int32_t x) {
   l->v[l->n++] = x;
 }
 
-/* get_leaf_branch: root ... leaf, returns its length d+1 */
+/* the leaf's ancestors p_0 (root) ... p_d (the leaf); returns d + 1 */
 static int leaf_branch(const orc_tree* t, int32_t leaf, int32_t* br) {
   int d = t->depth[leaf];
   int32_t id = leaf;
@@ -608,40 +608,53 @@ static int leaf_branch(const orc_tree* t, int32_t leaf, int32_t* br) {
   return d + 1;
 }
 
-/* The walk proper.  (k, src) on the stack pairs the k-th ancestor p_k of the
- * leaf with a source node.  check_interactions (Algorithm 2): a node paired
- * with itself is opened; otherwise an accepted pair is an M2L into the
- * ancestor's buffer and a rejected pair is opened.  Opening: two leaves go to
- * the neighbour cache (P2P); a leaf source meets the next ancestor; an
- * internal source is split, its children meeting the next ancestor -- or the
- * same target when the target is already the leaf (the "lowering" of shallow
- * leaves).  Callbacks collect the results. */
+/* Sect. 3: the interaction set of a leaf L with ancestors p_0 .. p_d is found
+ * by testing pairs (p_k, S) of an ancestor and a source node, starting from
+ * (p_0, root).  Each tested pair is classified:
+ *   M2L    S is not p_k and the pair passes both criteria (opening angle and
+ *          softening): S's moments act on p_k's field moments;
+ *   OPEN   otherwise.
+ * An opened pair is resolved by the pairs it leads to:
+ *   S a leaf, p_k = L         -> P2P: L's particles meet S's directly;
+ *   S a leaf, p_k above L     -> (p_{k+1}, S): the same source meets the next
+ *                                ancestor on L's branch;
+ *   S internal                -> (p_j, S_left), (p_j, S_right) with j = k + 1,
+ *                                or j = k once p_k is L itself (a leaf target
+ *                                lowers the source until it meets leaves).
+ * The pairs still to be tested are kept last-in first-out (the right child
+ * is tested first); the order fixes only the order of each list, not its
+ * content.  Callbacks collect the results. */
 typedef void (*m2l_cb)(void* ctx, int k, int32_t src);
 typedef void (*p2p_cb)(void* ctx, int32_t src);
 
+enum { PAIR_M2L = 0, PAIR_OPEN = 1 };
+static int classify_pair(const orc_tree* t, int32_t tgt, int32_t src, double theta,
+                         double r_kern) {
+  if (tgt != src && accept(t, tgt, src, theta, r_kern)) return PAIR_M2L;
+  return PAIR_OPEN;
+}
+
 static void walk_leaf(const orc_tree* t, const int32_t* br, int d, double theta, double r_kern,
                       m2l_cb on_m2l, p2p_cb on_p2p, void* ctx) {
-  stack_t_ st = {0};
-  push(&st, 0, 0);
-  while (st.n > 0) {
-    pair_t e = st.v[--st.n];
-    int32_t tgt = br[e.k];
-    int open = 0;
-    if (tgt == e.src) open = 1;
-    else if (accept(t, tgt, e.src, theta, r_kern)) on_m2l(ctx, e.k, e.src);
-    else open = 1;
-    if (!open) continue;
-    int tgt_leaf = (e.k == d);
+  stack_t_ todo = {0};
+  push(&todo, 0, 0);
+  while (todo.n > 0) {
+    const pair_t e = todo.v[--todo.n];
+    if (classify_pair(t, br[e.k], e.src, theta, r_kern) == PAIR_M2L) {
+      on_m2l(ctx, e.k, e.src);
+      continue;
+    }
+    const int at_leaf = e.k == d;
     if (is_leaf(t, e.src)) {
-      if (tgt_leaf) on_p2p(ctx, e.src);
-      else push(&st, e.k + 1, e.src);
+      if (at_leaf) on_p2p(ctx, e.src);
+      else push(&todo, e.k + 1, e.src);
     } else {
-      int kk = tgt_leaf ? e.k : e.k + 1;
-      push(&st, kk, t->left[e.src]);
-      push(&st, kk, t->right[e.src]);
+      const int j = at_leaf ? e.k : e.k + 1;
+      push(&todo, j, t->left[e.src]);
+      push(&todo, j, t->right[e.src]);
     }
   }
-  free(st.v);
+  free(todo.v);
 }
 
 typedef struct {
@@ -702,7 +715,8 @@ static int solve_leaf(const orc_tree* t, int32_t leaf, double theta, double G, d
   c.dM = calloc((size_t)(d + 1) * nHP, sizeof(double));
   c.nb.v = NULL; c.nb.n = 0; c.nb.cap = 0; c.n_m2l = 0;
   walk_leaf(t, br, d, theta, r_kern, solve_m2l, solve_p2p, &c);
-  /* propagate_to_next_parent: L2L down the branch, adding each buffer */
+  /* carry the field moments down the branch (L2L, Eq. gravmtranslat), adding
+   * each ancestor's own M2L sum on the way */
   double* loc = malloc(nHP * sizeof(double));
   double* tmp = malloc(nHP * sizeof(double));
   memcpy(loc, c.dM, nHP * sizeof(double));

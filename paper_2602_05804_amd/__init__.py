@@ -40,7 +40,16 @@ _PRECISION = {"fp64": SFMM_FP64, "fp32c": SFMM_FP32C}
 
 
 class SfmmError(RuntimeError):
-    pass
+    """A failed call; `code` is the sfmm_status value (0 when the error was
+    found in Python, before any call)."""
+
+    def __init__(self, msg, code: int = 0):
+        super().__init__(msg)
+        self.code = int(code)
+
+
+# sfmm_status values
+SFMM_EINVAL, SFMM_ENOMEM, SFMM_EDEVICE, SFMM_EUNSUPPORTED, SFMM_ENONFINITE = -1, -2, -3, -4, -5
 
 
 class Config(C.Structure):
@@ -59,7 +68,8 @@ class Stats(C.Structure):
                 ("max_depth", C.c_int32), ("n_m2l", C.c_int64), ("n_l2l", C.c_int64),
                 ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("momentum", C.c_double * 3), ("momentum_abs", C.c_double),
-                ("n_m2l_unique", C.c_int64), ("n_p2p_soft_pairs", C.c_int64)]
+                ("n_m2l_unique", C.c_int64), ("n_p2p_soft_pairs", C.c_int64),
+                ("walk_attempts", C.c_int32)]
 
 
 _lib = None
@@ -133,7 +143,7 @@ class Solver:
         if rc != 0:
             msg = lib().sfmm_strerror(rc).decode()
             extra = lib().sfmm_last_error(self._ctx).decode() if self._ctx else ""
-            raise SfmmError(f"{what}: {msg} ({rc}) {extra}".strip())
+            raise SfmmError(f"{what}: {msg} ({rc}) {extra}".strip(), rc)
 
     def _inputs(self, x, m, h):
         torch = self._torch
@@ -226,7 +236,8 @@ class Solver:
                     max_depth=st.max_depth, n_m2l=st.n_m2l, n_l2l=st.n_l2l,
                     n_p2p_leaf_pairs=st.n_p2p_leaf_pairs, n_p2p_pairs=st.n_p2p_pairs,
                     momentum=list(st.momentum), momentum_abs=st.momentum_abs,
-                    n_m2l_unique=st.n_m2l_unique, n_p2p_soft_pairs=st.n_p2p_soft_pairs)
+                    n_m2l_unique=st.n_m2l_unique, n_p2p_soft_pairs=st.n_p2p_soft_pairs,
+                    walk_attempts=st.walk_attempts)
 
     def timing_start(self, max_solves: int):
         """Record HIP events around every phase of the next max_solves solves."""

@@ -1,6 +1,6 @@
 // k_far.hip -- far field of each leaf: M2L on every ancestor, the L2L chain
-// down the branch and L2P at the leaf's particles (Sect. 2.2, Algorithm 1's
-// propagate_to_next_parent, Appendix A.2).
+// down the branch and L2P at the leaf's particles (Sect. 2.2, Algorithm 1,
+// Appendix A.2).
 //
 // A group of SPLIT lanes per leaf.  The leaf's M2L list is grouped by the
 // depth of the target ancestor; the lanes of the group take every SPLIT-th

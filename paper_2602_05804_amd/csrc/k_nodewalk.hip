@@ -90,8 +90,8 @@ __global__ void k_level_offsets(int nlev, int nb, int nn, const uint32_t* __rest
 
 // ---- one level -----------------------------------------------------------------
 struct Emit {
-  // reserved bases (uniform) and running offsets
-  uint32_t m2l_base, open_base, p2p_base;
+  // reserved bases (uniform, 64-bit) and running offsets
+  uint64_t m2l_base, open_base, p2p_base;
   uint32_t m2l_run, open_run, p2p_run;
   // leaf P2P lists: pairs that may fall inside a kernel from the front,
   // pairs beyond both kernels (plain_run of them so far) from the back of
@@ -115,23 +115,23 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
   const uint32_t pm = wave_prefix(nm, tm);
   const uint32_t po = wave_prefix(no, to);
   if (WRITE) {
-    uint32_t k = e.m2l_base + e.m2l_run + pm;
+    uint64_t k = e.m2l_base + e.m2l_run + pm;
     if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
     if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
     if (to_p2p) {
-      uint32_t q = e.p2p_base + e.p2p_run + po;
+      uint64_t q = e.p2p_base + e.p2p_run + po;
       if (sel_o & 1u) { if (q < a.p2p_cap) a.p2p_pool[q] = s0; ++q; }
       if (sel_o & 2u) { if (q < a.p2p_cap) a.p2p_pool[q] = s1; }
     } else {
-      // rank from the end of the node's region
+      // rank from the end of the node's region (r < region <= open_base)
       uint32_t r = e.open_run + po;
       if (sel_o & 1u) {
-        const uint32_t q = e.open_base - 1u - r;
+        const uint64_t q = e.open_base - 1u - r;
         if (q < a.open_cap) a.open_pool[q] = s0;
         ++r;
       }
       if (sel_o & 2u) {
-        const uint32_t q = e.open_base - 1u - r;
+        const uint64_t q = e.open_base - 1u - r;
         if (q < a.open_cap) a.open_pool[q] = s1;
       }
     }
@@ -154,17 +154,17 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
   const uint32_t pp = wave_prefix(np, tp);
   const uint32_t pq = wave_prefix(nq, tq);
   if (WRITE) {
-    uint32_t k = e.m2l_base + e.m2l_run + pm;
+    uint64_t k = e.m2l_base + e.m2l_run + pm;
     if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
     if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
-    uint32_t q = e.p2p_base + e.p2p_run + pp;
+    uint64_t q = e.p2p_base + e.p2p_run + pp;
     if (sel_p & 1u) { if (q < a.p2p_cap) a.p2p_pool[q] = s0; ++q; }
     if (sel_p & 2u) { if (q < a.p2p_cap) a.p2p_pool[q] = s1; }
     uint32_t r = e.plain_run + pq;  // rank from the back
     for (int b = 0; b < 2; ++b) {
       if (!(sel_q & (1u << b))) continue;
       if (r < e.p2p_total) {
-        const uint32_t t = e.p2p_base + (e.p2p_total - 1u - r);
+        const uint64_t t = e.p2p_base + (e.p2p_total - 1u - r);
         if (t < a.p2p_cap) a.p2p_pool[t] = b ? s1 : s0;
       }
       ++r;
@@ -402,14 +402,17 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
   Emit e{};
   e.m2l_base = a.lvl_off[idx];
   e.open_base = e.m2l_base + region;
-  if (lane == 0) a.m2l_off[v] = e.m2l_base;
+  // a region that does not fit gets no offset (the walk goes on counting,
+  // the host grows the pool and walks again)
+  const bool fits = e.open_base <= a.m2l_cap;
+  if (lane == 0) a.m2l_off[v] = fits ? (uint32_t)e.m2l_base : kNoList;
   if (root) {
     // (root, root) is opened: both root children meet both root children
     if (lane == 0) {
-      if (e.m2l_base < a.open_cap) a.open_pool[e.m2l_base] = (uint32_t)v;
+      if (fits) a.open_pool[e.m2l_base] = (uint32_t)v;
       a.m2l_cnt[v] = 0;
       a.open_cnt[v] = 1;
-      a.open_off[v] = e.m2l_base;
+      a.open_off[v] = fits ? (uint32_t)e.m2l_base : kNoList;
       a.exp[v] = 2;
     }
     return;
@@ -424,7 +427,7 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
   if (lane == 0) {
     a.m2l_cnt[v] = e.m2l_run;
     a.open_cnt[v] = e.open_run;
-    a.open_off[v] = e.open_base - e.open_run;
+    a.open_off[v] = fits ? (uint32_t)(e.open_base - e.open_run) : kNoList;
     a.exp[v] = ex;
   }
 }
@@ -470,7 +473,13 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
     e.m2l_base = a.run[0] + a.leaf_m2l_off[l];
     e.p2p_base = a.leaf_p2p_off[l];
     e.p2p_total = a.p2p_cnt[v];  // from the count pass
-    if (lane == 0) { a.m2l_off[v] = e.m2l_base; a.p2p_off[v] = e.p2p_base; a.open_off[v] = 0; }
+    if (lane == 0) {
+      const bool fm = e.m2l_base + a.m2l_cnt[v] <= a.m2l_cap;
+      const bool fp = e.p2p_base + e.p2p_total <= a.p2p_cap;
+      a.m2l_off[v] = fm ? (uint32_t)e.m2l_base : kNoList;
+      a.p2p_off[v] = fp ? (uint32_t)e.p2p_base : kNoList;
+      a.open_off[v] = 0;
+    }
   }
   walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
   if (!FILL) {
@@ -502,11 +511,11 @@ constexpr int SCAN_I = 4;
 constexpr int SCAN_W = SCAN_T / 64;
 constexpr uint32_t kScanTile = SCAN_T * SCAN_I;
 
-__device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
+__device__ __forceinline__ uint64_t wave_incl_u64(uint64_t x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
+    const uint64_t y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   return x;
@@ -514,16 +523,17 @@ __device__ __forceinline__ uint32_t wave_incl_u32(uint32_t x) {
 
 // exclusive scan of c (per thread, SCAN_I consecutive items summed) over the
 // block; returns the exclusive prefix of this thread and the block total
-__device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) {
-  __shared__ uint32_t wt[SCAN_W];
+// (64-bit: a level's regions may add up to more than 2^32 entries)
+__device__ __forceinline__ uint64_t block_excl_u64(uint64_t c, uint64_t& total) {
+  __shared__ uint64_t wt[SCAN_W];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t inc = wave_incl_u32(c);
+  const uint64_t inc = wave_incl_u64(c);
   if (lane == 63) wt[w] = inc;
   __syncthreads();
-  uint32_t pre = inc - c;
+  uint64_t pre = inc - c;
   total = 0;
   for (int k = 0; k < SCAN_W; ++k) {
-    const uint32_t t = wt[k];
+    const uint64_t t = wt[k];
     if (k < w) pre += t;
     total += t;
   }
@@ -532,18 +542,19 @@ __device__ __forceinline__ uint32_t block_excl_u32(uint32_t c, uint32_t& total) 
 }
 
 // one tile: regions of tile t of the level, scanned, written at base
-__device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
-                                              uint32_t t, uint32_t base, bool recompute) {
+__device__ __forceinline__ uint64_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
+                                              uint32_t t, uint64_t base, bool recompute) {
   const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
-  uint32_t r[SCAN_I], c = 0;
+  uint32_t r[SCAN_I];
+  uint64_t c = 0;
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
     r[q] = i < end ? (recompute ? node_region(a, i) : a.lvl_cnt32[i]) : 0u;
     c += r[q];
   }
-  uint32_t total;
-  uint32_t o = base + block_excl_u32(c, total);
+  uint64_t total;
+  uint64_t o = base + block_excl_u64(c, total);
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
@@ -555,8 +566,8 @@ __device__ __forceinline__ uint32_t scan_tile(const NodeWalkArgs& a, uint32_t be
 
 __global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint32_t base = a.levbase[level];
-  const uint32_t total = scan_tile(a, beg, end, 0, base, true);
+  const uint64_t base = a.levbase[level];
+  const uint64_t total = scan_tile(a, beg, end, 0, base, true);
   if (threadIdx.x == 0) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
@@ -567,7 +578,7 @@ __global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int
 __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
-  uint32_t c = 0;
+  uint64_t c = 0;
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
@@ -575,16 +586,16 @@ __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int 
     if (i < end) a.lvl_cnt32[i] = r;
     c += r;
   }
-  uint32_t total;
-  (void)block_excl_u32(c, total);
+  uint64_t total;
+  (void)block_excl_u64(c, total);
   if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  uint32_t base = a.levbase[level];
+  uint64_t base = a.levbase[level];
   for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
-  const uint32_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
+  const uint64_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
   if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
     a.levbase[level + 1] = base + total;
     a.run[0] = base + total;
@@ -615,24 +626,62 @@ __global__ void k_leaf_stats(LeafStatArgs a) {
   a.pairs[l] = src * (uint64_t)li.cnt - (uint64_t)li.cnt;
 }
 
-// out[0] += sum of x[0..n)
+// out[0] += sum of x[0..n) (64-bit)
 __global__ __launch_bounds__(256) void k_sum_u32(int n, const uint32_t* __restrict__ x,
-                                                 uint32_t* out) {
-  __shared__ uint32_t ws[4];
-  uint32_t t = 0;
+                                                 uint64_t* out) {
+  __shared__ uint64_t ws[4];
+  uint64_t t = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) t += x[i];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) t += (uint32_t)__shfl_xor((int)t, o, 64);
+  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(out, ws[0] + ws[1] + ws[2] + ws[3]);
+  if (threadIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(out),
+              (unsigned long long)(ws[0] + ws[1] + ws[2] + ws[3]));
+}
+
+// one thread per node: the lists a consumer reads (M2L of every node, P2P
+// of every leaf) must lie inside the part of the pools this walk wrote, and
+// (check_entries) hold only node ids below nn
+template <bool ENTRIES>
+__global__ __launch_bounds__(256) void k_check_lists(NodeWalkArgs a, int nn) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nn) return;
+  const uint64_t used_m = a.run[0] + a.run[3], used_p = a.run[2];
+  const uint64_t lim_m = used_m < a.m2l_cap ? used_m : a.m2l_cap;
+  const uint64_t lim_p = used_p < a.p2p_cap ? used_p : a.p2p_cap;
+  bool bad = false;
+  const uint32_t mc = a.m2l_cnt[v];
+  if (mc > 0) {
+    const uint64_t off = a.m2l_off[v];
+    if (off + mc > lim_m) bad = true;
+    else if (ENTRIES)
+      for (uint32_t k = 0; k < mc; ++k) bad |= (a.m2l_pool[off + k] & kSrcMask) >= (uint32_t)nn;
+  }
+  if (a.info[v].child < 0) {
+    const uint32_t pc = a.p2p_cnt[v];
+    if (pc > 0) {
+      const uint64_t off = a.p2p_off[v];
+      if (off + pc > lim_p) bad = true;
+      else if (ENTRIES)
+        for (uint32_t k = 0; k < pc; ++k) bad |= a.p2p_pool[off + k] >= (uint32_t)nn;
+    }
+  }
+  if (bad) atomicOr(a.status, ST_BADLIST);
 }
 
 }  // namespace
 
-void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s) {
+void launch_sum_u32(int n, const uint32_t* x, uint64_t* out, hipStream_t s) {
   if (n <= 0) return;
   k_sum_u32<<<std::min(512, (n + 255) / 256), 256, 0, s>>>(n, x, out);
+}
+
+void launch_check_lists(const NodeWalkArgs& a, int nn, bool check_entries, hipStream_t s) {
+  if (nn <= 0) return;
+  if (check_entries) k_check_lists<true><<<blocks_for(nn, 256), 256, 0, s>>>(a, nn);
+  else k_check_lists<false><<<blocks_for(nn, 256), 256, 0, s>>>(a, nn);
 }
 
 void launch_leaf_stats(const LeafStatArgs& a, hipStream_t s) {
@@ -672,8 +721,10 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
   if (a.nleaves <= 0) return;
   const size_t lds = a.stack_cap * sizeof(uint32_t);
   k_nodewalk_leaves<false><<<a.nleaves, 64, lds, s>>>(a);
-  scan_u32(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3, scan_tmp, s);
-  scan_u32(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2, scan_tmp, s);
+  scan_u32_u64(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3,
+               reinterpret_cast<uint64_t*>(scan_tmp), s);
+  scan_u32_u64(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2,
+               reinterpret_cast<uint64_t*>(scan_tmp), s);
   // P2P work items: item_off[nleaves] = their total (read back with the walk's)
   scan_u32(a.item_cnt, a.item_off, a.nleaves, a.item_off + a.nleaves, scan_tmp, s);
   k_nodewalk_leaves<true><<<a.nleaves, 64, lds, s>>>(a);

@@ -28,14 +28,14 @@ __device__ T block_exclusive(T v, T* sh, T* total) {
   return incl - v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const T* in, int64_t n, T* tmp) {
+template <typename TI, typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const TI* in, int64_t n, T* tmp) {
   __shared__ T sh[SCAN_THREADS];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   T s = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k)
-    if (base + k < n) s += in[base + k];
+    if (base + k < n) s += (T)in[base + k];
   T tot;
   block_exclusive<T>(s, sh, &tot);
   if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
@@ -56,8 +56,8 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(T* tmp, int64_t nb, T
   if (threadIdx.x == 0) *total = carry;
 }
 
-template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const T* in, T* out, int64_t n,
+template <typename TI, typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const TI* in, T* out, int64_t n,
                                                             const T* tmp) {
   __shared__ T sh[SCAN_THREADS];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const T* in, T* out,
   T s = 0;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    v[k] = base + k < n ? in[base + k] : T(0);
+    v[k] = base + k < n ? (T)in[base + k] : T(0);
     s += v[k];
   }
   T tot;
@@ -82,16 +82,16 @@ __global__ void k_zero_total(T* total) {
   *total = 0;
 }
 
-template <typename T>
-void scan_impl(const T* in, T* out, int64_t n, T* total, T* tmp, hipStream_t s) {
+template <typename TI, typename T>
+void scan_impl(const TI* in, T* out, int64_t n, T* total, T* tmp, hipStream_t s) {
   if (n <= 0) {
     k_zero_total<T><<<1, 1, 0, s>>>(total);
     return;
   }
   int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-  k_scan_reduce<T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, tmp);
+  k_scan_reduce<TI, T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, tmp);
   k_scan_top<T><<<1, SCAN_THREADS, 0, s>>>(tmp, nb, total);
-  k_scan_down<T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp);
+  k_scan_down<TI, T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp);
 }
 
 }  // namespace
@@ -100,12 +100,17 @@ size_t scan_tmp_elems(int64_t n) { return (size_t)((n + SCAN_TILE - 1) / SCAN_TI
 
 void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
               hipStream_t s) {
-  scan_impl<uint32_t>(in, out, n, total, tmp, s);
+  scan_impl<uint32_t, uint32_t>(in, out, n, total, tmp, s);
 }
 
 void scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total, uint64_t* tmp,
               hipStream_t s) {
-  scan_impl<uint64_t>(in, out, n, total, tmp, s);
+  scan_impl<uint64_t, uint64_t>(in, out, n, total, tmp, s);
+}
+
+void scan_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* total, uint64_t* tmp,
+                  hipStream_t s) {
+  scan_impl<uint32_t, uint64_t>(in, out, n, total, tmp, s);
 }
 
 }  // namespace sfmm

@@ -2,8 +2,7 @@
 //
 // One thread per leaf (leaves in Morton order, so a wave walks 64
 // neighbouring leaves whose branches share their upper part).  Each thread
-//   1. descends from the root to its leaf to get the branch p_0 .. p_d
-//      (get_leaf_branch),
+//   1. descends from the root to its leaf to get the branch p_0 .. p_d,
 //   2. runs the stack walk from (root, root): a node met with itself is
 //      opened; an accepted pair is an M2L of the source on the ancestor p_k;
 //      a rejected pair is opened -- two leaves become a P2P entry, a leaf

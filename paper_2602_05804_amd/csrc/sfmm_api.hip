@@ -76,6 +76,11 @@ struct sfmm_ctx {
   int far_variant = 0;         // kernel shape of the far field (SFMM_FAR_VARIANT)
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
+  // clear the list pools before each walk and check every list entry after
+  // it (SFMM_CHECK_POOLS=1; for tests)
+  bool check_pools = false;
+  uint64_t pool_init = 0;  // first pool size in entries (SFMM_POOL_INIT; 0 = estimate)
+  int walk_attempts = 0;   // walks made by the last solve (pools grown in between)
   sfmm_stats stats{};
 };
 
@@ -438,31 +443,41 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint32_t) * 4))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 4))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
-  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF})
+  for (int id : {B_LWM2LCNT, B_LWP2PCNT})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
+  for (int id : {B_LWM2LOFF, B_LWP2POFF})
+    if ((rc = ensure(ctx, id, sizeof(uint64_t) * std::max(nl, 1)))) return rc;
   if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint32_t) * (nn / 4096 + 2)))) return rc;
-  if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint32_t) * (kMaxDepthCap + 2)))) return rc;
+  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
+  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint64_t) * (nn / 4096 + 2)))) return rc;
+  if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint64_t) * (kMaxDepthCap + 2)))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
   // (the M2L pool also holds the opened lists of internal nodes)
-  ctx->m2l_cap = std::max<uint64_t>(ctx->m2l_cap, 96ull * nn + 2048);
-  ctx->p2p_cap = std::max<uint64_t>(ctx->p2p_cap, 48ull * nl + 1024);
+  // (SFMM_POOL_INIT: start from that many entries instead, so that tests
+  // meet pools too small for the walk)
+  const uint64_t est_m = ctx->pool_init ? ctx->pool_init : 96ull * nn + 2048;
+  const uint64_t est_p = ctx->pool_init ? ctx->pool_init : 48ull * nl + 1024;
+  ctx->m2l_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->m2l_cap, est_m));
+  ctx->p2p_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->p2p_cap, est_p));
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
-  const uint64_t kPoolMax = 0xF0000000ull;
   for (int attempt = 0;; ++attempt) {
-    if (ctx->m2l_cap > kPoolMax || ctx->p2p_cap > kPoolMax)
-      return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed 2^32 entries");
+    ctx->walk_attempts = attempt + 1;
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
-    uint32_t* tot = P<uint32_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint32_t) * 4, s));
+    uint64_t* tot = P<uint64_t>(ctx, B_WALKTOT);
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 4, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
+    if (ctx->check_pools) {
+      // every entry a consumer reads must then come from this walk: clear
+      // the pools to a value no node id takes (checked after the walk)
+      HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_M2LPOOL), 0xff, sizeof(uint32_t) * ctx->m2l_cap, s));
+      HIPCHK(hipMemsetAsync(P<uint32_t>(ctx, B_P2PPOOL), 0xff, sizeof(uint32_t) * ctx->p2p_cap, s));
+    }
     NodeWalkArgs a{};
     a.info = P<NodeInfo>(ctx, B_INFO);
     a.rec = P<double>(ctx, B_REC);
@@ -483,14 +498,14 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.open_pool = a.m2l_pool;
     a.exp = P<uint32_t>(ctx, B_NEXP);
     a.p2p_pool = P<uint32_t>(ctx, B_P2PPOOL);
-    a.m2l_cap = (uint32_t)ctx->m2l_cap;
+    a.m2l_cap = ctx->m2l_cap;
     a.open_cap = a.m2l_cap;
-    a.p2p_cap = (uint32_t)ctx->p2p_cap;
+    a.p2p_cap = ctx->p2p_cap;
     a.lvl_cnt32 = P<uint32_t>(ctx, B_LVLCNT);
-    a.lvl_off = P<uint32_t>(ctx, B_LVLOFF);
-    a.tile_sum = P<uint32_t>(ctx, B_TILESUM);
-    a.levbase = P<uint32_t>(ctx, B_LEVBASE);
-    HIPCHK(hipMemsetAsync(a.levbase, 0, sizeof(uint32_t), s));
+    a.lvl_off = P<uint64_t>(ctx, B_LVLOFF);
+    a.tile_sum = P<uint64_t>(ctx, B_TILESUM);
+    a.levbase = P<uint64_t>(ctx, B_LEVBASE);
+    HIPCHK(hipMemsetAsync(a.levbase, 0, sizeof(uint64_t), s));
     a.run = tot;
     a.stack_cap = ctx->stack_cap;
     a.status = status;
@@ -498,8 +513,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
     a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
-    a.leaf_m2l_off = P<uint32_t>(ctx, B_LWM2LOFF);
-    a.leaf_p2p_off = P<uint32_t>(ctx, B_LWP2POFF);
+    a.leaf_m2l_off = P<uint64_t>(ctx, B_LWM2LOFF);
+    a.leaf_p2p_off = P<uint64_t>(ctx, B_LWP2POFF);
     a.src_total = P<uint32_t>(ctx, B_SRCTOT);
     a.item_cnt = P<uint32_t>(ctx, B_ITEMCNT);
     a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
@@ -509,7 +524,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
     // M2L entries proper (the pool also holds the opened lists)
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
-    uint32_t htot[4];
+    // no consumer reads a list unless it lies in the part of its pool this
+    // walk wrote (and, when checking, holds only node ids)
+    launch_check_lists(a, nn, ctx->check_pools, s);
+    uint64_t htot[4];
     int hstatus[4];
     uint32_t hitems = 0;
     HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
@@ -518,23 +536,30 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       HIPCHK(hipMemcpyAsync(&hitems, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     ctx->items_from_walk = hitems;
-    const uint64_t m2l_used = (uint64_t)htot[0] + htot[3];  // internal regions, then leaves
+    // 64-bit totals: internal regions, then the leaves' M2L lists; the P2P pool
+    const uint64_t m2l_used = htot[0] + htot[3];
     const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
+      if (hstatus[0] & ST_BADLIST)
+        return fail(ctx, SFMM_EDEVICE, "an interaction list lies outside what the walk wrote");
       ctx->p2p_total = htot[2];
       ctx->m2l_unique = htot[1];
       return SFMM_OK;
     }
-    if (attempt >= 8) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
+    if (attempt >= 16) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
     if (pool_over) {
       // a truncated level under-reports the levels below it, so the totals
-      // are lower bounds: grow at least twofold
+      // are lower bounds: grow at least twofold, up to the largest pool
       auto grow = [](uint64_t cap, uint64_t need) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
-      ctx->m2l_cap = grow(ctx->m2l_cap, m2l_used);
-      ctx->p2p_cap = grow(ctx->p2p_cap, htot[2]);
+      if ((m2l_used > ctx->m2l_cap && ctx->m2l_cap >= kPoolMax) ||
+          (htot[2] > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax))
+        return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed the largest list pool (" +
+                                                std::to_string(kPoolMax) + " entries)");
+      ctx->m2l_cap = std::min(kPoolMax, grow(ctx->m2l_cap, m2l_used));
+      ctx->p2p_cap = std::min(kPoolMax, grow(ctx->p2p_cap, htot[2]));
     }
     if (stack_over) {
       if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
@@ -762,6 +787,9 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   // measurement overrides
   if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
   if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
+  if (const char* cp = std::getenv("SFMM_CHECK_POOLS")) ctx->check_pools = std::atoi(cp) != 0;
+  if (const char* pi = std::getenv("SFMM_POOL_INIT"))
+    ctx->pool_init = (uint64_t)std::max(0ll, std::atoll(pi));
   *out = ctx;
   return SFMM_OK;
 }
@@ -847,6 +875,7 @@ int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
   out->num_nodes = ctx->nn;
   out->num_leaves = ctx->nleaves;
   out->max_depth = ctx->maxdepth;
+  out->walk_attempts = ctx->walk_attempts;
   if (ctx->have_lists && ctx->stats_pending) {
     // the level walk's per-leaf totals are only computed when asked for
     const int nl = (int)ctx->nleaves;

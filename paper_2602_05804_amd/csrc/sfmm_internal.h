@@ -64,7 +64,17 @@ __host__ __device__ constexpr int local_count(int p) { return ncoef(p + 1) - 1 +
 __host__ __device__ constexpr int rec32_stride(int p) { return ((ncoef(p) + 1 + 7) / 8) * 8; }
 
 // ---- status bits written by kernels --------------------------------------
-enum : int { ST_NONFINITE = 1, ST_DEPTH = 2, ST_OVERFLOW = 4 };
+// ST_BADLIST: after a walk, a list a consumer would read lies outside the
+// pool part written by that walk, or (pool check mode) holds an entry that is
+// not a node of the tree; the solve stops with an error before any consumer
+// kernel runs
+enum : int { ST_NONFINITE = 1, ST_DEPTH = 2, ST_OVERFLOW = 4, ST_BADLIST = 8 };
+// per-node list offset of a list that did not fit in its pool: any read of
+// it is clamped away ((uint64_t)kNoList + count > every pool capacity)
+constexpr uint32_t kNoList = 0xFFFFFFFFu;
+// list pools hold at most this many entries, so every offset of a list that
+// fits is below kNoList
+constexpr uint64_t kPoolMax = 0xF0000000ull;
 
 // ---- scan ------------------------------------------------------------------
 // Exclusive prefix sum of `in` (n entries) into `out` (may alias in); the
@@ -74,6 +84,9 @@ void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uin
               hipStream_t s);
 void scan_u64(const uint64_t* in, uint64_t* out, int64_t n, uint64_t* total, uint64_t* tmp,
               hipStream_t s);
+// u32 counts, u64 offsets and total
+void scan_u32_u64(const uint32_t* in, uint64_t* out, int64_t n, uint64_t* total, uint64_t* tmp,
+                  hipStream_t s);
 
 // ---- tree ------------------------------------------------------------------
 int bbox_blocks(int64_t n);
@@ -175,18 +188,23 @@ struct NodeWalkArgs {
   // opened sources with internal ones counted twice (their two children).
   uint32_t *m2l_off, *m2l_cnt, *open_off, *open_cnt, *p2p_off, *p2p_cnt;
   uint32_t *m2l_pool, *open_pool, *p2p_pool;  // open_pool: the M2L pool
-  uint32_t m2l_cap, open_cap, p2p_cap;
+  // pool capacities (entries, <= kPoolMax).  Every running offset and total
+  // below is 64-bit, so a demand beyond 2^32 entries is counted, not wrapped;
+  // a list that does not fit gets the per-node offset kNoList and the host
+  // grows the pools and walks again
+  uint64_t m2l_cap, open_cap, p2p_cap;
   uint32_t* exp;  // per internal node: tested-list size of each of its children
   uint32_t* lvl_cnt32;  // [nn] M2L pool region of each internal node, in level order
-  uint32_t* lvl_off;    // [nn] its absolute offset in the M2L pool
-  uint32_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
-  uint32_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint32_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
+  uint64_t* lvl_off;    // [nn] its absolute offset in the M2L pool
+  uint64_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
+  uint64_t* levbase;    // [levels + 1] M2L pool size before each level
+  uint64_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
                       // walk's sum), P2P pool, M2L pool used by leaves
   // leaves (walked after all levels, in leaf order)
   int nleaves;
   const int32_t* leaf_node;
-  uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt, *leaf_m2l_off, *leaf_p2p_off;
+  uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt;
+  uint64_t *leaf_m2l_off, *leaf_p2p_off;
   // per leaf: particles over its P2P entries, P2P work items and their offsets
   // ([nleaves + 1], the last entry the total)
   uint32_t *src_total, *item_cnt, *item_off;
@@ -206,7 +224,12 @@ void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned
 // scan_tmp_elems(nleaves) words
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s);
 // out[0] += sum of x[0..n) (out on the device)
-void launch_sum_u32(int n, const uint32_t* x, uint32_t* out, hipStream_t s);
+void launch_sum_u32(int n, const uint32_t* x, uint64_t* out, hipStream_t s);
+// after a walk: every node's M2L list and every leaf's P2P list must lie in
+// the part of its pool the walk wrote (run[0] + run[3] M2L entries, run[2]
+// P2P entries); with check_entries, each entry must also be a node of the
+// tree (below nn).  Sets ST_BADLIST in *status otherwise.
+void launch_check_lists(const NodeWalkArgs& a, int nn, bool check_entries, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
 
 // per-leaf statistics of node lists: replicated M2L count, L2L count, pairs

@@ -15,7 +15,11 @@ Requests arrive over time; the loop
   * frees a request's slot when its last step is done, so waiting requests
     join at the next tick (the set of systems in a packed solve changes from
     tick to tick);
-  * isolates failures: a solve that raises fails only its own request(s).
+  * isolates failures: a solve that raises fails only its own request(s),
+    as long as the error leaves the device usable (bad input, unsupported
+    configuration, out of memory); a HIP error (SFMM_EDEVICE) may leave the
+    device in a faulted state, so it ends the run (``DeviceFault``) instead
+    of being retried on the same device.
 
 The executor is pluggable so that admission, ordering, slot release and
 failure handling can be exercised without a GPU (``FakeExecutor``).
@@ -28,6 +32,40 @@ from dataclasses import dataclass, field
 from typing import Callable, List, Optional
 
 import numpy as np
+
+
+class DeviceFault(RuntimeError):
+    """A solve failed with a HIP error: the device may be unusable, so the
+    serving loop stops (a caller may start a fresh process)."""
+
+
+# sfmm_status codes after which the device is still usable: the failing
+# systems are retried one by one and only they fail
+RECOVERABLE = (-1, -2, -4, -5)  # EINVAL, ENOMEM, EUNSUPPORTED, ENONFINITE
+
+
+def solve_packs(packs, solve_pack, solve_one, on_result, on_error):
+    """Solve every pack with solve_pack(pack) -> results (one per system).
+    If a pack fails with a recoverable status, its systems are solved one by
+    one with solve_one(job) and only those that fail again get on_error(job,
+    message).  Any other failure (a HIP error, or an error without a status
+    code) raises DeviceFault at once."""
+    for pack in packs:
+        try:
+            res = solve_pack(pack)
+        except Exception as e:
+            if getattr(e, "code", 0) not in RECOVERABLE:
+                raise DeviceFault(f"packed solve failed: {e}") from e
+            for j in pack:
+                try:
+                    on_result(j, solve_one(j))
+                except Exception as e1:
+                    if getattr(e1, "code", 0) not in RECOVERABLE:
+                        raise DeviceFault(f"solve of request {j.rid} failed: {e1}") from e1
+                    on_error(j, str(e1))
+            continue
+        for j, r in zip(pack, res):
+            on_result(j, r)
 
 
 @dataclass
@@ -168,26 +206,26 @@ class GpuExecutor:
 
     def step(self, jobs: List[Job]):
         torch = self.torch
+        packs = self.packs(jobs)
+
+        def solve_pack(pack):
+            for j in pack:
+                self._pre(j)
+            res = self.solver.solve_batch(
+                [(j.state["x"], j.state["m"], j.state["h"]) for j in pack],
+                theta=self.theta, order=self.order, precision=self.precision)
+            return [a.clone() for a, _ in res]
+
+        def solve_one(j):
+            a, _ = self.solver.solve(j.state["x"], j.state["m"], j.state["h"], theta=self.theta,
+                                     order=self.order, precision=self.precision)
+            return a
+
+        def on_error(j, msg):
+            j.error = msg
+
         with torch.cuda.stream(self.stream):
-            for pack in self.packs(jobs):
-                for j in pack:
-                    self._pre(j)
-                try:
-                    res = self.solver.solve_batch(
-                        [(j.state["x"], j.state["m"], j.state["h"]) for j in pack],
-                        theta=self.theta, order=self.order, precision=self.precision)
-                    for j, (a, _) in zip(pack, res):
-                        self._advance(j, a.clone())
-                except Exception:
-                    # isolate: solve the pack's systems one by one
-                    for j in pack:
-                        try:
-                            a, _ = self.solver.solve(j.state["x"], j.state["m"], j.state["h"],
-                                                     theta=self.theta, order=self.order,
-                                                     precision=self.precision)
-                            self._advance(j, a)
-                        except Exception as e:
-                            j.error = str(e)
+            solve_packs(packs, solve_pack, solve_one, self._advance, on_error)
         self.stream.synchronize()
 
 

@@ -82,7 +82,7 @@ def test_batch_against_oracle(torch, P, orc):
         a = res[i][0].cpu().numpy(); p = res[i][1].cpu().numpy()
         nb = np.linalg.norm(oa, axis=1)
         assert (np.linalg.norm(a - oa, axis=1) / nb).max() < 1e-12
-        assert np.abs(p - op).max() / np.abs(op).max() < 1e-12
+        assert (np.abs(p - op) / np.abs(op)).max() < 1e-12
 
 
 def test_batch_fp32c(torch, P, orc):

@@ -57,7 +57,9 @@ def gpu_solve(torch, P, x, m, h, theta=0.5, order=3, solver=None, **cfg):
 
 
 def pot_err(p, q):
-    return np.abs(p - q).max() / np.abs(q).max()
+    """Largest relative potential error per particle (potentials are
+    negative everywhere, so |q| > 0)."""
+    return (np.abs(p - q) / np.abs(q)).max()
 
 
 def test_tree_parity(torch, P, orc):
@@ -266,6 +268,36 @@ def test_p2p_many_work_items(torch, P, orc, precision, near_kernel):
             assert np.sqrt((((pot - dp) / dp) ** 2).mean()) <= tol
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_pools_regrow_checked(torch, P, orc, monkeypatch, precision):
+    """List pools that start far too small: the walk is repeated with larger
+    pools until its lists fit, every list a consumer reads is checked to lie in
+    the part of the pool this walk wrote and to hold node ids only (pools
+    cleared before each walk), and the results are the oracle's."""
+    print(f"case: pools regrow from 64 entries, checked, {precision}", flush=True)
+    monkeypatch.setenv("SFMM_CHECK_POOLS", "1")
+    monkeypatch.setenv("SFMM_POOL_INIT", "64")
+    x, m, h = workloads.plummer(6000, seed=3)
+    s = P.Solver()
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision=precision)
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    st = s.stats()
+    assert st["walk_attempts"] >= 3
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    if precision == "fp64":
+        assert rel_err(acc, oa).max() < TOL and pot_err(pot, op) < TOL
+    else:
+        assert _rms_rel(acc, oa) <= 1e-6
+    # the pools now fit: the next solve walks once, with the same results
+    acc2, pot2 = s.solve(xd, md, hd, theta=0.5, precision=precision)
+    torch.cuda.synchronize()
+    assert s.stats()["walk_attempts"] == 1
+    assert np.array_equal(acc2.cpu().numpy(), acc) and np.array_equal(pot2.cpu().numpy(), pot)
+    s.close()
+
+
 def test_theta_to_zero_equals_direct(torch, P, orc):
     print("case: theta->0 direct", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
@@ -416,6 +448,35 @@ def test_fp32c_p2p_shapes(torch, P, orc, leaf_size, near_kernel):
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
 
 
+def test_fp32c_binary_polytrope_full_size(torch, P, orc):
+    """The binary polytrope at its stated size (two n=1.5 stars of 10^6
+    particles, separation 3R) in FP32C: 1500 sampled targets against the FP64
+    oracle, RMS relative error <= 1e-6, momentum residual <= 1e-7; every list
+    entry checked to come from the walk."""
+    import os
+
+    print("case: fp32c binary polytrope 2x1e6 sampled", flush=True)
+    x, m, h, _ = workloads.binary_polytrope(1_000_000)
+    os.environ["SFMM_CHECK_POOLS"] = "1"
+    try:
+        s = P.Solver()
+    finally:
+        del os.environ["SFMM_CHECK_POOLS"]
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision="fp32c")
+    torch.cuda.synchronize()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+    rng = np.random.default_rng(2)
+    tg = rng.choice(len(m), 1500, replace=False)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    oa, op, _ = t.solve(0.5, targets=tg)
+    assert _rms_rel(acc[tg], oa) <= 1e-6
+    assert np.sqrt((((pot[tg] - op) / op) ** 2).mean()) <= 1e-6
+    s.close()
+
+
 def test_fp32c_binary_polytrope(torch, P, orc):
     """Two n=1.5 stars (the binary-polytrope shape at reduced N), sampled."""
     print("case: fp32c binary polytrope 2x30000", flush=True)
@@ -524,7 +585,7 @@ def test_direct_sum_parity(torch, P, orc):
     acc, pot = s.direct(xd, md, hd, targets=torch.from_numpy(tg).cuda())
     ta, tp = orc.direct(x, m, h, targets=tg)
     assert rel_err(acc.cpu().numpy(), ta).max() < TOL
-    assert np.abs(pot.cpu().numpy() - tp).max() / np.abs(tp).max() < TOL
+    assert pot_err(pot.cpu().numpy(), tp) < TOL
     # an index outside [0, n) is an error, not a read
     with pytest.raises(P.SfmmError, match="out of range"):
         s.direct(xd, md, hd, targets=torch.tensor([3, 20000], device="cuda"))

@@ -134,3 +134,26 @@ def test_edge_cases(orc):
                               include_self=False)
     assert acc[0] == pytest.approx([2.0 / 9.0, 0, 0], rel=1e-14)
     assert acc[1] == pytest.approx([-1.0 / 9.0, 0, 0], rel=1e-14)
+
+
+def test_direct_targets_rows_equal_full_direct(orc):
+    """The subset path of the direct sum (Eq. softdirectsum for listed targets)
+    gives, row for row and bit for bit, the full direct sum's rows of those
+    particles: any index, repeated indices, first and last particle, in the
+    order given; an index outside [0, n) is an error."""
+    import pytest
+
+    x, m, h = workloads.plummer(700, seed=21)
+    h[5] = 50.0  # one particle whose kernel covers every other
+    acc, pot = orc.direct(x, m, h)
+    rng = np.random.default_rng(5)
+    tg = np.concatenate([[699, 0, 5], rng.integers(0, 700, 40), [5, 699]]).astype(np.int64)
+    for include_self in (True, False):
+        fa, fp = orc.direct(x, m, h, include_self=include_self)
+        ta, tp = orc.direct(x, m, h, include_self=include_self, targets=tg)
+        assert ta.shape == (len(tg), 3) and tp.shape == (len(tg),)
+        assert np.array_equal(ta, fa[tg]) and np.array_equal(tp, fp[tg])
+    assert np.array_equal(orc.direct(x, m, h, targets=tg)[0], acc[tg])
+    for bad in ([700], [-1], [3, 700]):
+        with pytest.raises(Exception):
+            orc.direct(x, m, h, targets=np.array(bad, dtype=np.int64))

@@ -95,3 +95,56 @@ def test_max_particles_in_flight():
     rep = serve.Server(ex, hbm_budget=1e12, max_particles=1000).run(_jobs([5000, 10]),
                                                                     realtime=False)
     assert rep.completed == 2 and ex.ticks[0] == [0]
+
+
+class _Err(RuntimeError):
+    def __init__(self, msg, code):
+        super().__init__(msg)
+        self.code = code
+
+
+def _packs_run(fail):
+    """solve_packs over two packs; `fail(kind, rid)` returns a status code to
+    raise with, or None."""
+    jobs = _jobs([10, 20, 30, 40])
+    packs = [jobs[:2], jobs[2:]]
+    results, errors = {}, {}
+
+    def solve_pack(pack):
+        for j in pack:
+            c = fail("pack", j.rid)
+            if c is not None:
+                raise _Err(f"pack with {j.rid}", c)
+        return [f"packed {j.rid}" for j in pack]
+
+    def solve_one(j):
+        c = fail("one", j.rid)
+        if c is not None:
+            raise _Err(f"alone {j.rid}", c)
+        return f"alone {j.rid}"
+
+    serve.solve_packs(packs, solve_pack, solve_one, lambda j, r: results.__setitem__(j.rid, r),
+                      lambda j, m: errors.__setitem__(j.rid, m))
+    return results, errors
+
+
+def test_pack_failure_isolated_for_recoverable_codes():
+    # EINVAL / ENONFINITE / ENOMEM / EUNSUPPORTED: the pack is re-solved system
+    # by system and only the failing system fails
+    for code in (-1, -2, -4, -5):
+        res, err = _packs_run(lambda kind, rid: code if rid == 3 else None)
+        assert res == {0: "packed 0", 1: "packed 1", 2: "alone 2"} and list(err) == [3]
+
+
+def test_pack_device_error_ends_the_run():
+    # a HIP error (EDEVICE) is not retried on the device: DeviceFault at once,
+    # from the packed solve or from a retry
+    import pytest
+
+    with pytest.raises(serve.DeviceFault):
+        _packs_run(lambda kind, rid: -3 if rid == 2 else None)
+    with pytest.raises(serve.DeviceFault):
+        _packs_run(lambda kind, rid: (-1 if kind == "pack" else -3) if rid == 1 else None)
+    # an error without a status code is treated the same way
+    with pytest.raises(serve.DeviceFault):
+        _packs_run(lambda kind, rid: 0 if rid == 0 else None)
