@@ -20,8 +20,9 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 # -ffp-contract=off: every operation rounds as written (no fused multiply-add),
 # which the bit-exact tree/geometry comparisons rely on.
+# -fopenmp: only orc_solve_parallel uses threads (each over whole leaves).
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
-          "-Wall", "-Wno-unused-function"]
+          "-fopenmp", "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:
@@ -74,6 +75,8 @@ def lib():
         L.orc_mutual_pairs.argtypes = [vp, d, d, vp, vp, i64, vp, vp, i64, vp]
         L.orc_solve.restype = C.c_int
         L.orc_solve.argtypes = [vp, d, d, d, C.c_int, C.c_int, i64, vp, vp, vp, vp]
+        L.orc_solve_parallel.restype = C.c_int
+        L.orc_solve_parallel.argtypes = [vp, d, d, d, C.c_int, C.c_int, vp, vp, vp, vp]
         L.orc_sfmm_solve.restype = C.c_int
         L.orc_sfmm_solve.argtypes = [i64, vp, vp, vp, d, C.c_int, C.c_int, d, d, C.c_int,
                                      vp, vp, vp]
@@ -257,6 +260,19 @@ class Tree:
             raise ValueError("orc_solve failed")
         return acc, pot, dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs,
                               n_leaves_done=st.n_leaves_done)
+
+    def solve_parallel(self, theta=0.5, G=1.0, r_kern=2.0, include_self=True, nthreads=0):
+        """Algorithm 1 with the loop over leaves on OpenMP threads (every
+        particle); equal to solve() bit for bit.  Also returns the threads used."""
+        st = Stats()
+        used = C.c_int(0)
+        acc = np.zeros((self.n, 3)); pot = np.zeros(self.n)
+        rc = lib().orc_solve_parallel(self._t, theta, G, r_kern, int(include_self), int(nthreads),
+                                      _p(acc), _p(pot), C.byref(st), C.byref(used))
+        if rc != 0:
+            raise ValueError("orc_solve_parallel failed")
+        return acc, pot, dict(n_m2l=st.n_m2l, n_p2p_pairs=st.n_p2p_pairs,
+                              n_leaves_done=st.n_leaves_done, threads=used.value)
 
 
 def sfmm_solve(x, m, h, theta=0.5, order=3, leaf_size=10, G=1.0, r_kern=2.0,

@@ -18,6 +18,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ======================================================================== */
 /* multi-index tables                                                       */
@@ -911,6 +914,53 @@ int orc_solve(const orc_tree* t, double theta, double G, double r_kern, int incl
     free(acc_s); free(pot_s);
     return rc;
   }
+  for (int64_t i = 0; i < n && !rc; ++i) {
+    int64_t j = t->perm[i];
+    acc[3 * j] = acc_s[3 * i]; acc[3 * j + 1] = acc_s[3 * i + 1];
+    acc[3 * j + 2] = acc_s[3 * i + 2]; pot[j] = pot_s[i];
+  }
+  free(acc_s); free(pot_s);
+  return rc;
+}
+
+/* Algorithm 1 with its loop over leaves shared among OpenMP threads (the
+ * paper parallelises the per-leaf walk over the threads of one node, Sect. 3).
+ * Every leaf reads the tree and writes only its own particles' sums, in the
+ * same order as the serial loop, so the result equals orc_solve's (mode
+ * ORC_MODE_PER_LEAF, every particle) bit for bit.  nthreads <= 0: the OpenMP
+ * default.  *threads_used receives the number of threads that ran. */
+int orc_solve_parallel(const orc_tree* t, double theta, double G, double r_kern, int include_self,
+                       int nthreads, double* acc, double* pot, orc_stats* st, int* threads_used) {
+  if (!t || !(theta > 0.0) || !(r_kern >= 0.0)) return -1;
+  if (st) memset(st, 0, sizeof(*st));
+  int64_t n = t->n;
+  double* acc_s = calloc(3 * n, sizeof(double));
+  double* pot_s = calloc(n, sizeof(double));
+  int rc = 0, used = 1;
+  int64_t m2l = 0, pairs = 0, done = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel reduction(+ : m2l, pairs, done)
+  {
+#ifdef _OPENMP
+#pragma omp single
+    used = omp_get_num_threads();
+#endif
+    orc_stats mine;
+    memset(&mine, 0, sizeof(mine));
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t q = 0; q < t->nleaves; ++q) {
+      if (solve_leaf(t, t->leaves[q], theta, G, r_kern, include_self, ORC_MODE_PER_LEAF, acc_s,
+                     pot_s, &mine)) {
+#pragma omp atomic write
+        rc = -1;
+      }
+    }
+    m2l += mine.n_m2l; pairs += mine.n_p2p_pairs; done += mine.n_leaves_done;
+  }
+  if (st) { st->n_m2l = m2l; st->n_p2p_pairs = pairs; st->n_leaves_done = done; }
+  if (threads_used) *threads_used = used;
   for (int64_t i = 0; i < n && !rc; ++i) {
     int64_t j = t->perm[i];
     acc[3 * j] = acc_s[3 * i]; acc[3 * j + 1] = acc_s[3 * i + 1];

@@ -109,6 +109,12 @@ int orc_solve(const orc_tree* t, double theta, double G, double r_kern, int incl
               int mode, int64_t ntgt, const int64_t* tgt, double* acc, double* pot,
               orc_stats* st);
 
+/* Algorithm 1 with the loop over leaves run by OpenMP threads (nthreads <= 0:
+ * the OpenMP default); every particle; equal to orc_solve in mode
+ * ORC_MODE_PER_LEAF bit for bit.  *threads_used: the threads that ran. */
+int orc_solve_parallel(const orc_tree* t, double theta, double G, double r_kern, int include_self,
+                       int nthreads, double* acc, double* pot, orc_stats* st, int* threads_used);
+
 /* one-shot convenience: build, solve every particle, free */
 int orc_sfmm_solve(int64_t n, const double* x, const double* m, const double* h,
                    double theta, int order, int leaf_size, double G, double r_kern,

@@ -157,3 +157,17 @@ def test_direct_targets_rows_equal_full_direct(orc):
     for bad in ([700], [-1], [3, 700]):
         with pytest.raises(Exception):
             orc.direct(x, m, h, targets=np.array(bad, dtype=np.int64))
+
+
+def test_parallel_per_leaf_equals_serial(orc):
+    """Algorithm 1's loop over leaves on several threads (each leaf writes only
+    its own particles, in the serial order) gives the serial result bit for
+    bit, with the same interaction counts."""
+    x, m, h = workloads.polytrope(6000, seed=8)
+    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    a1, p1, s1 = t.solve(0.5)
+    a2, p2, s2 = t.solve_parallel(0.5, nthreads=4)
+    assert s2["threads"] >= 1
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    assert (s1["n_m2l"], s1["n_p2p_pairs"], s1["n_leaves_done"]) == \
+        (s2["n_m2l"], s2["n_p2p_pairs"], s2["n_leaves_done"])
