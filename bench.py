@@ -47,6 +47,10 @@ KERNELS = {
                             "k_p2p_leaf: softened P2P, targets of a leaf in LDS"),
     ("fp64", "near_thread"): ("void k_near<", ["k_near.hip", "sfmm_internal.h", "softening.h"],
                               "k_near: softened P2P, one target particle per thread"),
+    ("fp64", "near_tile"): ("void k_p2p_tile<", ["k_p2p_tile.hip", "sfmm_internal.h",
+                                                 "softening.h"],
+                            "k_p2p_tile: softened P2P, targets of a leaf in lane stripes, "
+                            "sources staged in LDS"),
     ("fp32c", "near_leaf"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
                              "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
     ("shared", "far"): (("void k_m2l_nodes<", "void k_far_shared<"),
@@ -62,6 +66,8 @@ def near_shape(precision, leaf_size, variant):
         return "near_leaf" if variant == 6 else "near"
     if leaf_size > 16 or variant == 1:
         return "near_thread"
+    if variant == 13:
+        return "near_tile"
     if variant in ((2, 3, 4, 5, 6) if leaf_size <= 10 else (5, 6)):
         return "near_leaf"
     return "near"
@@ -156,9 +162,15 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving run (Poisson arrivals at 200/s, N log-uniform "
                          "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
-    ap.add_argument("--serve-fp32c", action="store_true",
-                    help="also serve the trace in FP32C (packed FP32C solves of up to "
-                         "--serve-pack particles)")
+    ap.add_argument("--no-serve-fp32c", dest="serve_fp32c", action="store_false",
+                    help="serve the trace in FP64 only (by default it is also served in FP32C)")
+    ap.add_argument("--serve-low-rate", type=float, default=100.0,
+                    help="arrival rate of a second FP64 serving run below the GPU's capacity "
+                         "(0 skips it)")
+    ap.add_argument("--fp32c-n", type=int, default=2_000_000,
+                    help="particles of the FP32C block: the binary polytrope (two stars of "
+                         "N/2 at 3R); 0 skips it")
+    ap.add_argument("--fp32c-steps", type=int, default=5)
     ap.add_argument("--serve-pack", type=float, default=16e6,
                     help="particles per packed solve in the serving run")
     ap.add_argument("--serve-inflight", type=float, default=24e6,
@@ -318,6 +330,11 @@ def main():
 
     if not args.no_cpu:
         result.update(cpu_baseline(args, x, m, h, acc, pot, p))
+    if args.fp32c_n > 0 and args.precision == "fp64" and args.workload == "polytrope":
+        del xd, md, hd, acc, pot
+        solver.close()
+        torch.cuda.empty_cache()
+        result["fp32c"] = fp32c_block(args)
     if args.serve_requests > 0:
         result["serving"] = serving(args)
     print(json.dumps(result), flush=True)
@@ -407,11 +424,79 @@ def cpu_baseline(args, x, m, h, acc, pot, p):
     return out
 
 
+PEAK_FP32_TFLOPS = 157.3  # MI355X vector FP32 (packed FP32 issue; this build issues FP32
+                          # unpacked, at the FP64 rate)
+
+
+def fp32c_block(args):
+    """The FP32-compensated form on the binary polytrope (two n=1.5 stars of
+    N/2 particles at 3R): throughput, phase split, the P2P kernel against the
+    FP32 vector peak, and its error against the FP64 oracle on sampled targets
+    with the momentum residual."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2602_05804_amd as sfmm
+    import workloads
+
+    n = args.fp32c_n
+    log(f"fp32c: generating binary polytrope 2 x {n // 2}")
+    x, m, h, _ = workloads.binary_polytrope(n // 2)
+    xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
+    solver = sfmm.Solver(leaf_size=args.leaf_size)
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    pot = torch.empty((n,), dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        solver.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot,
+                     precision="fp32c")
+    torch.cuda.synchronize()
+    solver.timing_start(args.fp32c_steps)
+    t0 = time.perf_counter()
+    for _ in range(args.fp32c_steps):
+        solver.solve(xd, md, hd, theta=args.theta, order=args.order, acc=acc, pot=pot,
+                     precision="fp32c")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.fp32c_steps
+    phases = solver.timing_stop()
+    st = solver.stats()
+    ph = {k: float(np.mean([q[k] for q in phases])) for k in sfmm.PHASES}
+    flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR + st["n_p2p_soft_pairs"] * P2P_FLOPS_SOFT
+    ach = flops / (ph["near_kernel"] * 1e-3) / 1e12
+    a_gpu, p_gpu = acc.cpu().numpy(), pot.cpu().numpy()
+    solver.close()
+    log("fp32c: oracle on 1500 sampled targets")
+    t = oracle.Tree(x, m, h, leaf_size=args.leaf_size, order=args.order)
+    tg = np.random.default_rng(2).choice(n, 1500, replace=False)
+    oa, op, _ = t.solve(args.theta, targets=tg)
+    nb = np.linalg.norm(oa, axis=1)
+    err = np.linalg.norm(a_gpu[tg] - oa, axis=1) / nb
+    perr = np.abs(p_gpu[tg] - op) / np.abs(op)
+    out = {"workload": f"binary n=1.5 polytrope, 2 x {n // 2}, separation 3R, seeds 3/4",
+           "value": n / dt, "unit": "particles/s", "ms_per_step": dt * 1e3,
+           "phases_ms": {k: round(v, 4) for k, v in ph.items()},
+           "roofline": {"bound": "alu", "kernel": "P2P, FP32 pair terms, FP64 sums",
+                        "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                        "flops_per_launch": flops, "ms_per_launch": round(ph["near_kernel"], 4)},
+           "parity_sample": {"targets": 1500, "rms_rel_acc_err": float(np.sqrt((err ** 2).mean())),
+                             "max_rel_acc_err": float(err.max()),
+                             "rms_rel_pot_err": float(np.sqrt((perr ** 2).mean()))},
+           "momentum_residual": float(np.linalg.norm(st["momentum"]) / st["momentum_abs"]),
+           "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "n_m2l_unique",
+                                         "n_p2p_pairs", "n_p2p_soft_pairs")}}
+    log(f"fp32c: {out['value']:.4g} particles/s, rms err {out['parity_sample']['rms_rel_acc_err']:.3g}")
+    del xd, md, hd, acc, pot
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving(args):
-    """Continuous batching of a stream of independent solves: FP64 (and, with
-    --serve-fp32c, FP32C) on the same arrival trace with the HBM budget at
-    0.8 x free memory, then FP64 again under a small budget so that admission
-    queues requests."""
+    """Continuous batching of a stream of independent solves: FP64 and FP32C on
+    the same arrival trace (200 requests/s) with the HBM budget at 0.8 x free
+    memory, FP64 again under a small budget so that admission queues
+    requests, and FP64 with the same trace stretched to a lower arrival rate
+    that the GPU keeps up with (latency then measures service, not queueing)."""
     import torch
 
     import workloads
@@ -425,16 +510,20 @@ def serving(args):
            "pack_particles": args.serve_pack, "max_particles_in_flight": args.serve_inflight,
            "trace": "Poisson arrivals at 200/s, N = 10^U(3,6), Plummer/polytrope alternating, "
                     "seed 7"}
-    runs = [("fp64", None)] + ([("fp32c", None)] if args.serve_fp32c else []) + [
-        ("fp64", 3_000_000)]
-    for prec, small_budget_n in runs:
+    runs = [("fp64", None, 200.0)] + ([("fp32c", None, 200.0)] if args.serve_fp32c else []) + [
+        ("fp64", 3_000_000, 200.0)]
+    if args.serve_low_rate > 0:
+        runs.append(("fp64", None, args.serve_low_rate))
+    for prec, small_budget_n, rate in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
                                leaf_size=args.leaf_size, far=args.far,
                                pack_particles=args.serve_pack)
         free, _ = torch.cuda.mem_get_info()
         budget = 0.8 * free if small_budget_n is None else ex.footprint(small_budget_n)
         jobs = serve.jobs_from_stream(reqs, steps=4)
-        log(f"serving: {prec}, budget {budget / 2**30:.1f} GiB "
+        for j in jobs:  # the same trace, stretched to the run's arrival rate
+            j.arrival *= 200.0 / rate
+        log(f"serving: {prec} at {rate:g}/s, budget {budget / 2**30:.1f} GiB "
             f"({ex.bytes_per_particle} B/particle)")
         rep = serve.Server(ex, hbm_budget=budget,
                            max_particles=args.serve_inflight).run(jobs)
@@ -442,6 +531,8 @@ def serving(args):
         summ["hbm_budget_gib"] = budget / 2 ** 30
         summ["bytes_per_particle"] = ex.bytes_per_particle
         key = prec if small_budget_n is None else f"{prec}_small_budget"
+        if rate != 200.0:
+            key = f"{prec}_rate{rate:g}"
         out[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"serving {key}: " + ", ".join(f"{k}={v}" for k, v in out[key].items()))
         del ex

@@ -101,7 +101,7 @@ typedef struct {
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
   int far_mode;               /* sfmm_far_mode (SFMM_FAR_SHARED)                      */
   int far_kernel;             /* far-field kernel shape, 0..4 (0)                    */
-  int near_kernel;            /* P2P kernel shape, 0..12 (0)                         */
+  int near_kernel;            /* P2P kernel shape, 0..13 (0)                         */
 } sfmm_config;
 /* Kernel shapes (same results up to summation order; picked by the autotuner):
  * far_kernel, SFMM_FAR_SHARED: lanes per node 8 (0; a two-wave register budget
@@ -112,13 +112,16 @@ typedef struct {
  *   queued and evaluated 64 at a time, in passes of 5 targets at four waves
  *   per SIMD (0), 8 at three (7), 10 at two (8), 5 at three (9), 6 at four
  *   (10), 8 at four (11), 5 at four with two groups of 64 sources per step
- *   (12); one thread per particle (1); the earlier
+ *   (12); the targets of the leaf in lanes, in stripes over the sources
+ *   staged through LDS, sources split into near and far by the target leaf's
+ *   sphere and pairs inside a kernel queued per target (13); one thread per
+ *   particle (1); the earlier
  *   wave-per-item kernel with targets in LDS: passes of 10 (2), one pass with
  *   a run-time target loop (3), passes of 4 (4), passes of 5 without the
  *   queue (5), passes of 5 with the queue (6).
  * near_kernel, leaf_size <= 16: scalar-register targets in passes of 8 (0),
- *   6 (7), 16 (8); one thread per particle (1); targets in LDS, passes of 8
- *   without (5) and with (6) the queue.
+ *   6 (7), 16 (8); targets in lanes (13); one thread per particle (1);
+ *   targets in LDS, passes of 8 without (5) and with (6) the queue.
  * near_kernel with SFMM_FP32C: the wave kernel with scalar-register targets
  *   and a queue per target (every value but 6), the earlier shape with the
  *   targets in LDS and the softened branch taken in the pass (6). */

@@ -719,6 +719,12 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   record_mark(km.begin, s);
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
   // variant (the shapes are listed with sfmm_config.near_kernel)
+  if (leaf_size <= 16 && variant == 13) {
+    launch_p2p_tile(node_lists, leaf_size <= 10 ? 10 : 16, a, items, s);
+    record_mark(km.end, s);
+    launch_p2p_reduce(a, leaf_size <= 10 ? 10 : 16, s);
+    return;
+  }
   if (leaf_size <= 10) {
     switch (variant) {
       case 2: NEAR_LAUNCH(10, 10, false); break;

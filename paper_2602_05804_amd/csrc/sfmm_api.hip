@@ -37,7 +37,7 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
-  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_DIRPART,
   B_COUNT
 };
 
@@ -674,6 +674,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.p4 = P<double>(ctx, B_P4);
   a.far = f.far;
   a.rec = f.rec;
+  a.rec_stride = rec_stride(ctx->order);
   a.perm = P<uint32_t>(ctx, B_VAL0);
   a.G = ctx->cfg.G;
   a.include_self = ctx->cfg.include_self_potential;
@@ -738,6 +739,35 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   return SFMM_OK;
 }
 
+// common checks of the two direct-sum entry points (0 = go on, 1 = nothing
+// to do, < 0 = error)
+int direct_args(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+                int64_t nt, const int64_t* targets, double* acc, double* pot) {
+  if (n < 0 || nt < 0 || n >= (int64_t(1) << 30))
+    return fail(ctx, SFMM_EINVAL, "n or target count out of range");
+  if (nt == 0) return 1;
+  if (n == 0) return fail(ctx, SFMM_EINVAL, "targets given for an empty system");
+  if (!x || !m || !h || !acc || !pot) return fail(ctx, SFMM_EINVAL, "NULL array");
+  if (!targets && nt > n) return fail(ctx, SFMM_EINVAL, "more targets than particles");
+  return 0;
+}
+
+// runs the direct sum with the status word and partial sums at the given
+// device addresses, then reads the status back (one synchronisation)
+int direct_run(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
+               int64_t nt, const int64_t* targets, double* acc, double* pot, int* status,
+               double* part, int nchunk) {
+  const hipStream_t s = ctx->stream;
+  launch_direct(n, x, m, h, nt, targets, ctx->cfg.G, ctx->cfg.include_self_potential, acc, pot,
+                status, part, nchunk, s);
+  HIPCHK(hipGetLastError());
+  int hs = 0;
+  HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hs & ST_OVERFLOW) return fail(ctx, SFMM_EINVAL, "target index out of range");
+  return SFMM_OK;
+}
+
 const char* kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP error",
                              "unsupported", "non-finite or non-positive input"};
 
@@ -770,7 +800,7 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
       (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED) || c.far_kernel < 0 ||
-      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 12)
+      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 13)
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -1126,26 +1156,15 @@ int sfmm_direct(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, cons
                 int64_t nt, const int64_t* targets, double* acc, double* pot) {
   if (!ctx) return SFMM_EINVAL;
   ctx->err.clear();
-  if (n < 0 || nt < 0 || n >= (int64_t(1) << 30))
-    return fail(ctx, SFMM_EINVAL, "n or target count out of range");
-  if (nt == 0) return SFMM_OK;
-  if (n == 0) return fail(ctx, SFMM_EINVAL, "targets given for an empty system");
-  if (!x || !m || !h || !acc || !pot) return fail(ctx, SFMM_EINVAL, "NULL array");
-  if (!targets && nt > n) return fail(ctx, SFMM_EINVAL, "more targets than particles");
-  int rc;
+  int rc = direct_args(ctx, n, x, m, h, nt, targets, acc, pot);
+  if (rc) return rc > 0 ? SFMM_OK : rc;
   if ((rc = set_device(ctx))) return rc;
+  const int nchunk = direct_chunks(n, nt, uint64_t(1) << 30);
+  if (nchunk < 1) return fail(ctx, SFMM_EINVAL, "too many targets");
   if ((rc = ensure(ctx, B_STATUS, sizeof(int) * 4))) return rc;
-  const hipStream_t s = ctx->stream;
-  int* status = P<int>(ctx, B_STATUS);
-  HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
-  launch_direct(n, x, m, h, nt, targets, ctx->cfg.G, ctx->cfg.include_self_potential, acc, pot,
-                status, s);
-  HIPCHK(hipGetLastError());
-  int hs = 0;
-  HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (hs & ST_OVERFLOW) return fail(ctx, SFMM_EINVAL, "target index out of range");
-  return SFMM_OK;
+  if ((rc = ensure(ctx, B_DIRPART, sizeof(double) * 4 * (size_t)nt * nchunk))) return rc;
+  return direct_run(ctx, n, x, m, h, nt, targets, acc, pot, P<int>(ctx, B_STATUS),
+                    P<double>(ctx, B_DIRPART), nchunk);
 }
 
 int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const double* acc,

@@ -291,7 +291,8 @@ struct NearArgs {
   const double *xs, *ys, *zs, *ms, *hs, *his;  // his = 1/h
   const double* p4;  // [n][4] x, y, z, m (one record per particle)
   const double* far;
-  const double* rec;  // node records (leaf centres, FP32C)
+  const double* rec;  // node records (leaf centres, FP32C; leaf spheres)
+  int rec_stride;     // doubles per node record
   const uint32_t* perm;
   double G;
   int include_self;
@@ -332,6 +333,10 @@ inline void record_mark(hipEvent_t e, hipStream_t s) {
 }
 void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a, int64_t items,
                  hipStream_t s, KernelMarks km = {});
+// the default P2P kernel: targets of the leaf in lanes (NS stripes of nt
+// lanes), sources staged through LDS and split into far and near sources by
+// the target leaf's sphere (ls = 10 or 16: the partial-sum layout)
+void launch_p2p_tile(bool node_lists, int ls, const NearArgs& a, int64_t items, hipStream_t s);
 // sum of the item partials per target, plus the far field and the self term,
 // written in the caller's order (LS = the P2P kernel's target count)
 void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s);
@@ -355,10 +360,17 @@ void launch_leapfrog(int64_t n, double* x, double* v, const double* acc, double 
                      hipStream_t s);
 
 // softened direct sum over all n sources for nt targets (targets == nullptr:
-// 0..nt-1); an out-of-range target index sets ST_OVERFLOW in *status
+// 0..nt-1), the sources in nchunk chunks whose partial sums go to part
+// ([nchunk][nt][4] doubles) and are added per target in chunk order; *status
+// is cleared first (by a kernel) and an out-of-range target index sets
+// ST_OVERFLOW in it
 void launch_direct(int64_t n, const double* x, const double* m, const double* h, int64_t nt,
                    const int64_t* targets, double G, int include_self, double* acc, double* pot,
-                   int* status, hipStream_t s);
+                   int* status, double* part, int nchunk, hipStream_t s);
+// source chunks for nt targets: enough blocks to fill the chip, at most one
+// per tile of 256 sources and at most what max_part_bytes of partial sums
+// hold (0 when not even one chunk fits)
+int direct_chunks(int64_t n, int64_t nt, uint64_t max_part_bytes);
 
 // ---- momentum diagnostics ----------------------------------------------------
 int momentum_blocks(int64_t n);

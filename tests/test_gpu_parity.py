@@ -243,7 +243,7 @@ def test_large_softening_all_pairs(torch, P, orc):
 
 
 @pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp64", 3),
-                                                   ("fp32c", 0), ("fp32c", 6)])
+                                                   ("fp64", 13), ("fp32c", 0), ("fp32c", 6)])
 def test_p2p_many_work_items(torch, P, orc, precision, near_kernel):
     """Every leaf's sources split into several P2P work items (more than 2048
     source particles per leaf): 7000 particles all inside each other's kernel,
@@ -594,7 +594,7 @@ def test_direct_sum_parity(torch, P, orc):
 
 
 @pytest.mark.parametrize("leaf_size,near_kernel",
-                         [(10, k) for k in range(1, 13)] + [(16, k) for k in (0, 5, 6, 7, 8)])
+                         [(10, k) for k in range(1, 14)] + [(16, k) for k in (0, 5, 6, 7, 8, 13)])
 def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     """Every P2P kernel shape gives the oracle's result (halo leaves with
     large softening lengths, coincident particles)."""
@@ -610,7 +610,8 @@ def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
 
 
-@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp32c", 0)])
+@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp64", 13),
+                                                   ("fp32c", 0)])
 def test_soft_pair_count(torch, P, precision, near_kernel):
     """The P2P kernels count the ordered pairs inside a softening kernel; every
     such pair is a P2P pair (accepted node pairs keep all pairs outside both
