@@ -265,6 +265,20 @@ int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const doubl
 int sfmm_direct(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const double* h,
                 int64_t nt, const int64_t* targets, double* acc, double* pot);
 
+/* sfmm_direct without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and arguments as sfmm_direct; the
+ * status word and the partial sums of the source chunks live in a fixed
+ * 32 MiB device array of the library, one per GPU, held until the process
+ * ends.  Limit: nt <= 1048568 targets per call (SFMM_EINVAL beyond; every
+ * other error as sfmm_direct).  Every call on a GPU uses that GPU's array and
+ * clears what must start at zero: calls that overlap on one GPU (two host
+ * threads, or two streams) race and must be ordered by the caller.  The call
+ * synchronises the context's stream to read the status word back. */
+int sfmm_direct_noalloc(sfmm_ctx* ctx, int64_t n, const double* x, const double* m,
+                        const double* h, int64_t nt, const int64_t* targets, double* acc,
+                        double* pot);
+
 /* Human-readable text of a status code (static storage). */
 const char* sfmm_strerror(int status);
 

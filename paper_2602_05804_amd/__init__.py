@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libsfmm.so")
 EXPORTED = ("sfmm_config_default", "sfmm_create", "sfmm_destroy", "sfmm_set_stream",
             "sfmm_build", "sfmm_solve", "sfmm_solve_batch", "sfmm_get_stats", "sfmm_get_tree", "sfmm_get_leaves",
             "sfmm_get_leaf_lists", "sfmm_timing_start", "sfmm_timing_stop", "sfmm_phase_name",
-            "sfmm_workspace_bytes", "sfmm_leapfrog", "sfmm_direct",
+            "sfmm_workspace_bytes", "sfmm_leapfrog", "sfmm_direct", "sfmm_direct_noalloc",
             "sfmm_strerror", "sfmm_last_error")
 PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum", "near_kernel")
 
@@ -102,6 +102,7 @@ def lib():
         L.sfmm_workspace_bytes.argtypes = [vp, vp]
         L.sfmm_leapfrog.argtypes = [vp, i64, vp, vp, vp, d, d]
         L.sfmm_direct.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp]
+        L.sfmm_direct_noalloc.argtypes = [vp, i64, vp, vp, vp, i64, vp, vp, vp]
         L.sfmm_strerror.restype = C.c_char_p
         L.sfmm_strerror.argtypes = [C.c_int]
         L.sfmm_last_error.restype = C.c_char_p
@@ -213,9 +214,11 @@ class Solver:
                     "sfmm_solve_batch")
         return [(acc[off[i]:off[i + 1]], pot[off[i]:off[i + 1]]) for i in range(len(systems))]
 
-    def direct(self, x, m, h, targets=None):
+    def direct(self, x, m, h, targets=None, no_alloc=False, out=None):
         """Softened direct sum over all particles for `targets` (a device int64
-        tensor of indices, or None for every particle): (acc [nt, 3], pot [nt])."""
+        tensor of indices, or None for every particle): (acc [nt, 3], pot [nt]).
+        no_alloc: through sfmm_direct_noalloc (the library allocates nothing;
+        pass `out` = (acc, pot) to allocate nothing here either)."""
         torch = self._torch
         n = self._inputs(x, m, h)
         if targets is None:
@@ -223,10 +226,19 @@ class Solver:
         else:
             targets = targets.to(device=x.device, dtype=torch.int64).contiguous()
             nt, tp = int(targets.shape[0]), _ptr(targets)
-        acc = torch.empty((nt, 3), dtype=torch.float64, device=x.device)
-        pot = torch.empty((nt,), dtype=torch.float64, device=x.device)
-        self._check(lib().sfmm_direct(self._ctx, n, _ptr(x), _ptr(m), _ptr(h), nt, tp,
-                                      _ptr(acc), _ptr(pot)), "sfmm_direct")
+        if out is None:
+            acc = torch.empty((nt, 3), dtype=torch.float64, device=x.device)
+            pot = torch.empty((nt,), dtype=torch.float64, device=x.device)
+        else:
+            acc, pot = out
+            if tuple(acc.shape) != (nt, 3) or tuple(pot.shape) != (nt,) or \
+                    acc.dtype != torch.float64 or pot.dtype != torch.float64 or \
+                    not acc.is_contiguous() or not pot.is_contiguous():
+                raise SfmmError("out must be contiguous float64 tensors [nt, 3] and [nt]")
+        fn = lib().sfmm_direct_noalloc if no_alloc else lib().sfmm_direct
+        name = "sfmm_direct_noalloc" if no_alloc else "sfmm_direct"
+        self._check(fn(self._ctx, n, _ptr(x), _ptr(m), _ptr(h), nt, tp, _ptr(acc), _ptr(pot)),
+                    name)
         return acc, pot
 
     def stats(self) -> dict:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -768,6 +769,35 @@ int direct_run(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
   return SFMM_OK;
 }
 
+// ---- the direct sum in a fixed device array (no allocation) ----------------
+// Each GPU holds one copy of `scratch` until the process ends: the status
+// word, then the partial sums ([chunk][target][4] doubles).  Host code never
+// uses the array's name as an address: hipGetSymbolAddress gives each
+// device's own copy, once per device, with that device current.
+constexpr size_t kScratchBytes = size_t(32) << 20;  // 32 MiB
+constexpr size_t kScratchStatus = 256;               // bytes before the partial sums
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// the device address of this device's scratch (device already current)
+int scratch_address(sfmm_ctx* ctx, unsigned char** out) {
+  if (ctx->device < 0 || ctx->device >= kMaxScratchDevices)
+    return fail(ctx, SFMM_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ctx, SFMM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                         hipGetErrorString(e));
+    g_scratch_ptr[ctx->device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[ctx->device]);
+  return SFMM_OK;
+}
+
 const char* kStatusText[] = {"ok", "invalid argument", "out of device memory", "HIP error",
                              "unsupported", "non-finite or non-positive input"};
 
@@ -1165,6 +1195,26 @@ int sfmm_direct(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, cons
   if ((rc = ensure(ctx, B_DIRPART, sizeof(double) * 4 * (size_t)nt * nchunk))) return rc;
   return direct_run(ctx, n, x, m, h, nt, targets, acc, pot, P<int>(ctx, B_STATUS),
                     P<double>(ctx, B_DIRPART), nchunk);
+}
+
+int sfmm_direct_noalloc(sfmm_ctx* ctx, int64_t n, const double* x, const double* m,
+                        const double* h, int64_t nt, const int64_t* targets, double* acc,
+                        double* pot) {
+  if (!ctx) return SFMM_EINVAL;
+  ctx->err.clear();
+  int rc = direct_args(ctx, n, x, m, h, nt, targets, acc, pot);
+  if (rc) return rc > 0 ? SFMM_OK : rc;
+  if ((rc = set_device(ctx))) return rc;
+  const int nchunk = direct_chunks(n, nt, kScratchBytes - kScratchStatus);
+  if (nchunk < 1)
+    return fail(ctx, SFMM_EINVAL,
+                "too many targets for the fixed scratch: at most " +
+                    std::to_string((kScratchBytes - kScratchStatus) / (4 * sizeof(double))) +
+                    " targets per call");
+  unsigned char* base = nullptr;
+  if ((rc = scratch_address(ctx, &base))) return rc;
+  return direct_run(ctx, n, x, m, h, nt, targets, acc, pot, reinterpret_cast<int*>(base),
+                    reinterpret_cast<double*>(base + kScratchStatus), nchunk);
 }
 
 int sfmm_leapfrog(void* hip_stream, int64_t n, double* x, double* v, const double* acc,
