@@ -53,6 +53,10 @@ KERNELS = {
                             "sources staged in LDS"),
     ("fp32c", "near_leaf"): ("void k_p2p_leaf32<", ["k_f32c.hip", "sfmm_internal.h"],
                              "k_p2p_leaf32: softened P2P, FP32 terms, FP64 sums"),
+    ("mutual", "far"): (("void k_m2l_mutual<", "void k_far_shared<"),
+                        ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
+                        "k_m2l_mutual + k_far_shared: each unordered node pair's M2L once for "
+                        "both nodes, then per-leaf L2L + L2P"),
     ("shared", "far"): (("void k_m2l_nodes<", "void k_far_shared<"),
                         ["k_far.hip", "expansions_gen.h", "sfmm_internal.h"],
                         "k_m2l_nodes + k_far_shared: per-node M2L sums, then per-leaf L2L + L2P"),
@@ -145,7 +149,7 @@ def main():
     ap.add_argument("--walk", choices=["level", "leaf"], default="level",
                     help="level: each (ancestor, source) test once per level; "
                          "leaf: Algorithm 1 with one stack walk per leaf")
-    ap.add_argument("--far", choices=["leaf", "shared"], default="shared",
+    ap.add_argument("--far", choices=["leaf", "shared", "mutual"], default="shared",
                     help="shared: each node's M2L list once, then L2L per leaf (the caching "
                          "the paper proposes); leaf: every leaf evaluates its ancestors' "
                          "lists (the paper's replicated walk), also timed beside shared")
@@ -254,8 +258,10 @@ def main():
     # algorithmic work of the arithmetic kernels
     p = args.order
     # M2L evaluations actually made: replicated per leaf, or once per node pair
-    n_m2l = st["n_m2l_unique"] if args.far == "shared" else st["n_m2l"]
-    far_flops = (n_m2l * (sfmm.FLOPS["m2l"][p] + 1) + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
+    n_m2l = st["n_m2l_unique"] if args.far in ("shared", "mutual") else st["n_m2l"]
+    m2l_flops = (n_m2l // 2 * (sfmm.FLOPS["m2l_pair"][p] + 1) if args.far == "mutual"
+                 else n_m2l * (sfmm.FLOPS["m2l"][p] + 1))
+    far_flops = (m2l_flops + st["n_l2l"] * sfmm.FLOPS["l2l"][p]
                  + args.n * sfmm.FLOPS["l2p"][p])
     near_flops = st["n_p2p_pairs"] * P2P_FLOPS_PER_PAIR + st["n_p2p_soft_pairs"] * P2P_FLOPS_SOFT
     work = {"far": far_flops, "near": near_flops}
@@ -264,7 +270,7 @@ def main():
     # its own events (phase near_kernel); the far phase is its kernels
     dom_ms = ph_mean["near_kernel"] if dom == "near" and ph_mean["near_kernel"] > 0 else ph_mean[dom]
     achieved = work[dom] / (dom_ms * 1e-3) / 1e12
-    kern = KERNELS[("shared" if args.far == "shared" and dom == "far" else args.precision,
+    kern = KERNELS[(args.far if args.far in ("shared", "mutual") and dom == "far" else args.precision,
                     near_shape(args.precision, args.leaf_size, cfg.get("near_kernel", 0))
                     if dom == "near" else dom)]
     roofline = {"bound": "alu", "kernel": kern[2],

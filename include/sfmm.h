@@ -88,8 +88,18 @@ typedef enum { SFMM_WALK_LEVEL = 0, SFMM_WALK_LEAF = 1 } sfmm_walk_mode;
  *                  rounding (the per-node sums are formed before they are
  *                  added to the translated parent moments).  Needs
  *                  SFMM_WALK_LEVEL.  Default; with SFMM_WALK_LEAF the
- *                  context falls back to SFMM_FAR_LEAF. */
-typedef enum { SFMM_FAR_LEAF = 0, SFMM_FAR_SHARED = 1 } sfmm_far_mode;
+ *                  context falls back to SFMM_FAR_LEAF.
+ * SFMM_FAR_MUTUAL  as SFMM_FAR_SHARED, with each unordered node pair of the
+ *                  interaction set evaluated once: one derivative tensor
+ *                  D(r) for both nodes, the contraction for the second node
+ *                  using D(-r) = (-1)^|k| D(r) (the symmetric one-sided M2L
+ *                  the paper's Sect. 5 points to, after Dehnen 2002) and
+ *                  added to that node's coefficients with atomic adds, so
+ *                  the summation order is not fixed (results agree with
+ *                  SFMM_FAR_SHARED to rounding).  FP64 only
+ *                  (SFMM_EUNSUPPORTED with SFMM_FP32C); needs
+ *                  SFMM_WALK_LEVEL (falls back to SFMM_FAR_LEAF otherwise). */
+typedef enum { SFMM_FAR_LEAF = 0, SFMM_FAR_SHARED = 1, SFMM_FAR_MUTUAL = 2 } sfmm_far_mode;
 
 typedef struct {
   double G;                   /* gravitational constant (default 1)                   */

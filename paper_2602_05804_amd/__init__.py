@@ -31,6 +31,8 @@ PHASES = ("tree", "walk_count", "walk_fill", "far", "near", "momentum", "near_ke
 # from the generated kernels (FMA = 2); see csrc/expansions_gen.h
 FLOPS = {
     "m2l": {0: 24, 1: 97, 2: 280, 3: 659, 4: 1362},
+    # one unordered pair in both directions (the mutual far field)
+    "m2l_pair": {0: 32, 1: 144, 2: 437, 3: 1068, 4: 2278},
     "l2l": {0: 0, 1: 27, 2: 138, 3: 438, 4: 1105},
     "l2p": {0: 4, 1: 31, 2: 88, 3: 184, 4: 329},
 }
@@ -60,7 +62,7 @@ class Config(C.Structure):
 
 
 WALK_MODES = {"level": 0, "leaf": 1}
-FAR_MODES = {"leaf": 0, "shared": 1}
+FAR_MODES = {"leaf": 0, "shared": 1, "mutual": 2}
 
 
 class Stats(C.Structure):

@@ -238,6 +238,83 @@ def gen(P):
         Lm.append(line)
     out += Lm
 
+    # ---- M2L of one node pair in both directions (the one-sided symmetric
+    # form): D(r) once for r = s_S - s_T; the target side as m2l_add; the
+    # source side with D(-r) = (-1)^|k| D(r): with QTs the target's moments
+    # with odd degrees negated (the caller's), H_g -= s and P_b += s, added to
+    # outS atomically
+    c = Counter()
+    L = ["  __device__ __forceinline__ static void m2l_pair(const double* r, const double* QS,",
+         "                                                    const double* QTs, double* local,",
+         "                                                    double* outS) {"]
+    body = []
+    capture = False
+    for line in out[out.index("  __device__ __forceinline__ static void m2l_add(const double* r, const double* Q, double* local) {") + 1:]:
+        if line.startswith("    {") and not capture:
+            capture = True
+        if capture:
+            break
+        body.append(line)
+    L += body  # r2, rinv, D recurrence
+    # flops of the derivative part, from the same counts as m2l_add
+    c.mul += 4; c.add += 2
+    for k, a in enumerate(ms[1:], start=1):
+        n = sum(a)
+        nt = sum(1 for cc in range(3) if a[cc] >= 1) + sum(1 for cc in range(3) if a[cc] >= 2)
+        c.mul += 2 * sum(1 for cc in range(3) if a[cc] >= 1) + sum(1 for cc in range(3) if a[cc] >= 2) + 1
+        c.add += nt - 1
+    c.mul += P + 1
+    for side in ("T", "S"):
+        Q = "QS" if side == "T" else "QTs"
+        for kg, g in enumerate(ms[1:], start=1):
+            ng = sum(g)
+            hslot = kg - 1
+            alist = [a for a in multi(P + 1 - ng)]
+            lines_g = []
+            first = True
+            pdone = False
+            def put(slot, sign):
+                if side == "T":
+                    return f"      local[{slot}] {sign}= s;"
+                return f"      unsafeAtomicAdd(&outS[{slot}], {'-' if sign == '-' else ''}s);"
+            for a in alist:
+                na = sum(a)
+                if ng <= P and not pdone and na > P - ng:
+                    lines_g.append(put(NH - 1 + kg, ('+' if ng % 2 == 0 else '-') if side == "T" else '+'))
+                    c.add += 1
+                    pdone = True
+                if first:
+                    lines_g.append(f"      double s = D[{idx[add(a, g)]}] * {Q}[{idx[a]}];")
+                    c.mul += 1
+                    first = False
+                else:
+                    lines_g.append(f"      s = fma(D[{idx[add(a, g)]}], {Q}[{idx[a]}], s);")
+                    c.fma += 1
+            if ng <= P and not pdone:
+                lines_g.append(put(NH - 1 + kg, ('+' if ng % 2 == 0 else '-') if side == "T" else '+'))
+                c.add += 1
+            lines_g.append(put(hslot, ('+' if (ng + 1) % 2 == 0 else '-') if side == "T" else '-'))
+            c.add += 1
+            L.append("    {")
+            L += lines_g
+            L.append("    }")
+        L.append("    {")
+        first = True
+        for a in multi(P):
+            if first:
+                L.append(f"      double s = D[{idx[a]}] * {Q}[{idx[a]}];")
+                c.mul += 1
+                first = False
+            else:
+                L.append(f"      s = fma(D[{idx[a]}], {Q}[{idx[a]}], s);")
+                c.fma += 1
+        L.append(f"      local[{NH - 1}] += s;" if side == "T" else f"      unsafeAtomicAdd(&outS[{NH - 1}], s);")
+        c.add += 1
+        L.append("    }")
+    L.append("  }")
+    out += L
+    out.append(f"  static constexpr int FLOPS_M2L_PAIR = {c.flops()};  // both directions, + one rsqrt")
+
     # ---- L2L (in place)
     c = Counter()
     L = ["  __device__ __forceinline__ static void l2l(const double* h, double* local) {"]

@@ -369,14 +369,36 @@ struct Wave32Item {
 
 constexpr uint32_t kTQ32 = 128;  // queue slots per target (63 + 64)
 
-template <int K, int LS, int RS>
+// Sums of FP32 pair terms: each term added to an FP64 accumulator (AccD, the
+// default), or compensated in FP32 (AccT: Knuth's TwoSum keeps the rounding
+// error of every addition, hi + lo is rounded to FP64 once at the end).
+struct AccD {
+  double v = 0.0;
+  __device__ __forceinline__ void add(float x) { v += (double)x; }
+  __device__ __forceinline__ double get() const { return v; }
+  __device__ __forceinline__ void keep() { asm volatile("" ::"v"(v)); }
+};
+struct AccT {
+  float hi = 0.f, lo = 0.f;
+  __device__ __forceinline__ void add(float x) {
+    const float s = hi + x;
+    const float bb = s - hi;
+    const float e = (hi - (s - bb)) + (x - bb);
+    hi = s;
+    lo += e;
+  }
+  __device__ __forceinline__ double get() const { return (double)hi + (double)lo; }
+  __device__ __forceinline__ void keep() { asm volatile("" ::"v"(hi), "v"(lo)); }
+};
+
+template <int K, int LS, int RS, typename Acc>
 __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4* __restrict__ pf,
                                                 const float2* __restrict__ phh, const Wave32Item& w,
                                                 int t0, int* qj, float* qc, uint32_t& nsoft) {
   const int lane = threadIdx.x;
   const int tlo = w.tlo;
   float tx[K], ty[K], tz[K], t4[K];
-  double fx[K], fy[K], fz[K], ph[K];
+  Acc fx[K], fy[K], fz[K], ph[K];
   uint32_t qn[K];
 #pragma unroll
   for (int ii = 0; ii < K; ++ii) {
@@ -386,7 +408,7 @@ __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4*
     tz[ii] = wave_uniform_f(o.z);
     const float hu = wave_uniform_f(phh[tlo + t0 + ii].x);
     t4[ii] = 4.0f * hu * hu;
-    fx[ii] = 0.0; fy[ii] = 0.0; fz[ii] = 0.0; ph[ii] = 0.0;
+    fx[ii] = Acc(); fy[ii] = Acc(); fz[ii] = Acc(); ph[ii] = Acc();
     qn[ii] = 0;
   }
   // the first `count` queued pairs of target ii (the rest moves down)
@@ -413,10 +435,10 @@ __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4*
     soft32(r * hj.y, hj.y, hj.x * rinv, rinv, rinv3, g2, p2);
     const float wm = act ? oj.w : 0.f;
     const float mg = wm * (0.5f * (g1 + g2));
-    fx[ii] += (double)(mg * dx);
-    fy[ii] += (double)(mg * dy);
-    fz[ii] += (double)(mg * dz);
-    ph[ii] += (double)(wm * (0.5f * (p1 + p2)));
+    fx[ii].add(mg * dx);
+    fy[ii].add(mg * dy);
+    fz[ii].add(mg * dz);
+    ph[ii].add(wm * (0.5f * (p1 + p2)));
     // the remainder moves to the front of the queue
     const uint32_t rem = qn[ii] - count;
     int tj = 0;
@@ -495,12 +517,12 @@ __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4*
         const float rinv = inside ? 0.f : __builtin_amdgcn_rsqf(r2);
         const float mr = mj * rinv;
         const float mg = mr * (rinv * rinv);
-        fx[ii] += (double)(mg * dx);
-        fy[ii] += (double)(mg * dy);
-        fz[ii] += (double)(mg * dz);
-        ph[ii] += (double)mr;
+        fx[ii].add(mg * dx);
+        fy[ii].add(mg * dy);
+        fz[ii].add(mg * dz);
+        ph[ii].add(mr);
         // (keeps this target's arithmetic ahead of the queue branch)
-        asm volatile("" ::"v"(fx[ii]), "v"(fy[ii]), "v"(fz[ii]), "v"(ph[ii]));
+        fx[ii].keep(); fy[ii].keep(); fz[ii].keep(); ph[ii].keep();
         const bool push = inside && fv && j != tlo + t0 + ii;
         const uint64_t bal = __builtin_amdgcn_ballot_w64(push);
         if (bal) {
@@ -530,8 +552,8 @@ __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4*
   });
 #pragma unroll
   for (int ii = 0; ii < K; ++ii) {
-    const double sx = wave_sum64(fx[ii]), sy = wave_sum64(fy[ii]), sz = wave_sum64(fz[ii]);
-    const double sp = wave_sum64(ph[ii]);
+    const double sx = wave_sum64(fx[ii].get()), sy = wave_sum64(fy[ii].get());
+    const double sz = wave_sum64(fz[ii].get()), sp = wave_sum64(ph[ii].get());
     if (lane == t0 + ii) {
       double* o = a.part + (w.item * LS + t0 + ii) * 4;
       o[0] = sx; o[1] = sy; o[2] = sz; o[3] = sp;
@@ -539,7 +561,7 @@ __device__ __forceinline__ void p2p_wave32_pass(const NearArgs& a, const float4*
   }
 }
 
-template <int LS, bool NODE, int RS, int TG, int WPE>
+template <int LS, bool NODE, int RS, int TG, int WPE, typename Acc>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_p2p_wave32(
     NearArgs a, const float4* __restrict__ pf, const float2* __restrict__ phh) {
   const int lane = threadIdx.x;
@@ -573,12 +595,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   __shared__ float qc[TG * kTQ32 * 3];
   uint32_t nsoft = 0;
   int t0 = 0;
-  for (; t0 + TG <= w.nt; t0 += TG) p2p_wave32_pass<TG, LS, RS>(a, pf, phh, w, t0, qj, qc, nsoft);
+  for (; t0 + TG <= w.nt; t0 += TG)
+    p2p_wave32_pass<TG, LS, RS, Acc>(a, pf, phh, w, t0, qj, qc, nsoft);
   // the remainder, a pass with a fixed target count (uniform branches)
   static_for<TG>([&](auto rc) {
     constexpr int r = decltype(rc)::value;
     if (r > 0 && w.nt - t0 == r)
-      p2p_wave32_pass<(r > 0 ? r : 1), LS, RS>(a, pf, phh, w, t0, qj, qc, nsoft);
+      p2p_wave32_pass<(r > 0 ? r : 1), LS, RS, Acc>(a, pf, phh, w, t0, qj, qc, nsoft);
   });
   if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
@@ -600,8 +623,9 @@ void prep_particles(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                                                                zs, ms, hs, pf, ph);
 }
 
-// variant 0: the wave kernel with scalar-register targets; 6: the earlier
-// shape (targets in LDS, the softened branch taken in the pass)
+// variant 0: the wave kernel with scalar-register targets; 7: the same with
+// TwoSum-compensated FP32 sums instead of FP64 ones; 6: the earlier shape
+// (targets in LDS, the softened branch taken in the pass)
 template <int LS, int RS>
 void p2p32(bool node_lists, int variant, const NearArgs& a, const float4* pf, const float2* ph,
            int64_t items, hipStream_t s, KernelMarks km) {
@@ -611,9 +635,12 @@ void p2p32(bool node_lists, int variant, const NearArgs& a, const float4* pf, co
   if (variant == 6) {
     if (node_lists) k_p2p_leaf32<LS, true, RS, TG><<<nb, 64, 0, s>>>(a, pf, ph);
     else k_p2p_leaf32<LS, false, RS, TG><<<nb, 64, 0, s>>>(a, pf, ph);
+  } else if (variant == 7) {
+    if (node_lists) k_p2p_wave32<LS, true, RS, TG, 4, AccT><<<nb, 64, 0, s>>>(a, pf, ph);
+    else k_p2p_wave32<LS, false, RS, TG, 4, AccT><<<nb, 64, 0, s>>>(a, pf, ph);
   } else {
-    if (node_lists) k_p2p_wave32<LS, true, RS, TG, 4><<<nb, 64, 0, s>>>(a, pf, ph);
-    else k_p2p_wave32<LS, false, RS, TG, 4><<<nb, 64, 0, s>>>(a, pf, ph);
+    if (node_lists) k_p2p_wave32<LS, true, RS, TG, 4, AccD><<<nb, 64, 0, s>>>(a, pf, ph);
+    else k_p2p_wave32<LS, false, RS, TG, 4, AccD><<<nb, 64, 0, s>>>(a, pf, ph);
   }
   record_mark(km.end, s);
   launch_p2p_reduce(a, LS, s);

@@ -11,6 +11,8 @@
 // particles.  Every leaf still evaluates all M2L interactions of all of its
 // ancestors.  Neighbouring leaves (Morton order) share their upper
 // ancestors, so lanes mostly read the same source records.
+#include <algorithm>
+
 #include "sfmm_internal.h"
 
 namespace sfmm {
@@ -195,6 +197,77 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
   }
 }
 
+// The one-sided symmetric M2L (Sect. 5 notes that an interaction can be
+// applied to both nodes of a pair): every unordered pair of the interaction
+// set -- node v's M2L list holds s exactly when s's holds v -- is evaluated
+// once, by the node with the smaller id, with one derivative tensor D(r) for
+// both directions (Exp<P>::m2l_pair): the owner's side is summed in
+// registers as in k_m2l_nodes, the partner's side is added to the partner's
+// local coefficients with FP64 atomic adds, and the owner adds its own sum
+// last, also atomically.  ln must hold zeros before.  The order of the
+// atomic additions is not fixed, so results agree with the directed form to
+// rounding, not bit for bit.
+template <int P, int SPLIT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_m2l_mutual(
+    SharedFarArgs a) {
+  using E = Exp<P>;
+  constexpr int NQ = E::NQ;
+  constexpr int NL = E::NL;
+  constexpr int RS = rec_stride(P);
+  const int lane = threadIdx.x;
+  const int sub = lane % SPLIT;
+  const int g = blockIdx.x * (64 / SPLIT) + lane / SPLIT;
+  const bool active = g < a.nn;
+  const int v = active ? a.level_nodes[g] : 0;
+  const uint32_t cnt = active ? a.m2l_cnt[v] : 0u;
+  const uint32_t off = active ? a.m2l_off[v] : 0u;
+  const double* __restrict__ rec = a.rec;
+  const double* rv = rec + (int64_t)v * RS;
+  const double sv[3] = {rv[0], rv[1], rv[2]};
+  // the owner's moments with odd degrees negated (its side of D(-r))
+  double QTs[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) QTs[q] = rv[8 + q];
+  {
+    int k = 0;
+#pragma unroll
+    for (int n = 0; n <= P; ++n)
+#pragma unroll
+      for (int c = 0; c < (n + 1) * (n + 2) / 2; ++c, ++k)
+        if (n & 1) QTs[k] = -QTs[k];
+  }
+  double L[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) L[q] = 0.0;
+  for (uint32_t e = off + sub; e < off + cnt; e += SPLIT) {
+    const uint32_t src = a.pool[e] & kSrcMask;
+    if ((int)src <= v) continue;  // the partner owns this pair
+    const double* rs = rec + (int64_t)src * RS;
+    const double r[3] = {rs[0] - sv[0], rs[1] - sv[1], rs[2] - sv[2]};
+    double QS[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) QS[q] = rs[8 + q];
+    E::m2l_pair(r, QS, QTs, L, a.ln + (int64_t)src * NL);
+  }
+#pragma unroll
+  for (int o = SPLIT / 2; o > 0; o >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) L[q] += __shfl_xor(L[q], o, 64);
+  }
+  if (active && cnt > 0) {
+    double* out = a.ln + (int64_t)v * NL;
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+      if (q % SPLIT == sub) unsafeAtomicAdd(&out[q], L[q]);
+  }
+}
+
+__global__ void k_zero_f64(int64_t n, double* __restrict__ p) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
 // k_far_shared: one lane per leaf walks its branch from the root
 template <int P>
 __global__ __launch_bounds__(64) void k_far_shared(FarArgs a, const double* __restrict__ ln) {
@@ -255,6 +328,17 @@ void shared_order(const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_
   if (f.nleaves > 0) k_far_shared<P><<<(unsigned)((f.nleaves + 63) / 64), 64, 0, s>>>(f, a.ln);
 }
 
+template <int P>
+void mutual_order(const FarArgs& f, const SharedFarArgs& a, hipStream_t s) {
+  if (a.nn > 0) {
+    const int64_t nz = (int64_t)a.nn * Exp<P>::NL;
+    k_zero_f64<<<(unsigned)std::min<int64_t>((nz + 255) / 256, 4096), 256, 0, s>>>(nz, a.ln);
+    constexpr int SPLIT = 8;
+    k_m2l_mutual<P, SPLIT><<<(unsigned)((a.nn + 64 / SPLIT - 1) / (64 / SPLIT)), 64, 0, s>>>(a);
+  }
+  if (f.nleaves > 0) k_far_shared<P><<<(unsigned)((f.nleaves + 63) / 64), 64, 0, s>>>(f, a.ln);
+}
+
 template <int SPLIT, int WAVES>
 void shared_split(int order, const FarArgs& f, const SharedFarArgs& a, bool f32, hipStream_t s) {
   switch (order) {
@@ -281,6 +365,16 @@ void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFar
       if (f32) shared_split<8, 1>(order, f, a, f32, s);
       else shared_split<8, 2>(order, f, a, f32, s);
       break;
+  }
+}
+
+void launch_far_mutual(int order, const FarArgs& f, const SharedFarArgs& a, hipStream_t s) {
+  switch (order) {
+    case 0: mutual_order<0>(f, a, s); break;
+    case 1: mutual_order<1>(f, a, s); break;
+    case 2: mutual_order<2>(f, a, s); break;
+    case 3: mutual_order<3>(f, a, s); break;
+    case 4: mutual_order<4>(f, a, s); break;
   }
 }
 

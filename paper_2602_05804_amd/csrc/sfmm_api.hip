@@ -590,7 +590,10 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     return fail(ctx, SFMM_EUNSUPPORTED, "several systems need SFMM_WALK_LEVEL");
   // per-node lists exist only with the level walk; the per-leaf walk keeps
   // the per-leaf far field
-  const bool shared = ctx->cfg.far_mode == SFMM_FAR_SHARED && level;
+  const bool mutual = ctx->cfg.far_mode == SFMM_FAR_MUTUAL && level;
+  const bool shared = (ctx->cfg.far_mode == SFMM_FAR_SHARED || mutual) && level;
+  if (mutual && precision == SFMM_FP32C)
+    return fail(ctx, SFMM_EUNSUPPORTED, "SFMM_FAR_MUTUAL is FP64 only");
   if (shared && (rc = ensure(ctx, B_LN, sizeof(double) * local_count(ctx->order) * (size_t)ctx->nn)))
     return rc;
   if (!level) ctx->m2l_unique = 0;
@@ -650,7 +653,8 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     sa.rec32 = f32 ? P<float>(ctx, B_REC32) : nullptr;
     sa.top = ctx->cfg.fp64_top_depth;
     sa.ln = P<double>(ctx, B_LN);
-    launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
+    if (mutual) launch_far_mutual(ctx->order, f, sa, s);
+    else launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
   } else if (f32) {
     launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
   } else {
@@ -829,7 +833,8 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   if (!(c.leaf_size >= 1 && c.leaf_size <= 64) || !(c.r_kern >= 0.0) || !std::isfinite(c.G) ||
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
-      (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED) || c.far_kernel < 0 ||
+      (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED &&
+       c.far_mode != SFMM_FAR_MUTUAL) || c.far_kernel < 0 ||
       c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 13)
     return SFMM_EINVAL;
   int ndev = 0;

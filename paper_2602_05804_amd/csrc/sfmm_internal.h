@@ -277,6 +277,10 @@ struct SharedFarArgs {
 // one wave for FP32C (default), 4 (1), 16 (2), 8 one wave (3), 8 two waves (4)
 void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s);
+// the one-sided symmetric form of the shared far field: each unordered node
+// pair once (one D(r) for both nodes, the partner's side added atomically),
+// then the per-leaf L2L chain and L2P (FP64 only)
+void launch_far_mutual(int order, const FarArgs& f, const SharedFarArgs& a, hipStream_t s);
 
 // ---- near field (P2P) + output in the caller's order ----------------------
 struct NearArgs {

@@ -429,7 +429,7 @@ def test_fp32c_plummer(torch, P, orc, top):
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
 
 
-@pytest.mark.parametrize("leaf_size,near_kernel", [(10, 6), (16, 0), (16, 6)])
+@pytest.mark.parametrize("leaf_size,near_kernel", [(10, 6), (10, 7), (16, 0), (16, 6), (16, 7)])
 def test_fp32c_p2p_shapes(torch, P, orc, leaf_size, near_kernel):
     """The FP32C P2P shapes (the default wave kernel is covered above) within
     the FP32C bound against the oracle, with coincident particles."""
@@ -477,6 +477,46 @@ def test_fp32c_binary_polytrope_full_size(torch, P, orc):
     s.close()
 
 
+@pytest.fixture(scope="module")
+def cloud8e6():
+    """The log-normal clumpy cloud at its stated size (8e6 particles, sigma 2,
+    k^-4 on 128^3, h from 58 neighbours) and its oracle tree."""
+    import oracle
+
+    x, m, h = workloads.lognormal_cloud(8_000_000)
+    return x, m, h, oracle.Tree(x, m, h, leaf_size=10, order=3)
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.5, 0.7])
+def test_fp32c_cloud_full_size(torch, P, cloud8e6, theta):
+    """The clumpy cloud (8e6 particles, softening lengths over 1.7 decades) in
+    FP32C at each stated opening angle: 300 sampled targets against the FP64
+    oracle, RMS relative error <= 1e-6, momentum residual <= 1e-7; every list
+    entry checked to come from the walk."""
+    import os
+
+    print(f"case: fp32c cloud 8e6 theta={theta} sampled", flush=True)
+    x, m, h, t = cloud8e6
+    os.environ["SFMM_CHECK_POOLS"] = "1"
+    try:
+        s = P.Solver()
+    finally:
+        del os.environ["SFMM_CHECK_POOLS"]
+    xd, md, hd = dev(torch, x, m, h)
+    acc, pot = s.solve(xd, md, hd, theta=theta, precision="fp32c")
+    torch.cuda.synchronize()
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-7
+    tg = np.random.default_rng(7).choice(len(m), 300, replace=False)
+    a = acc.cpu().numpy()[tg]
+    p = pot.cpu().numpy()[tg]
+    s.close()
+    del acc, pot, xd, md, hd
+    oa, op, _ = t.solve(theta, targets=tg)
+    assert _rms_rel(a, oa) <= 1e-6
+    assert np.sqrt((((p - op) / op) ** 2).mean()) <= 1e-6
+
+
 def test_fp32c_binary_polytrope(torch, P, orc):
     """Two n=1.5 stars (the binary-polytrope shape at reduced N), sampled."""
     print("case: fp32c binary polytrope 2x30000", flush=True)
@@ -515,6 +555,40 @@ def test_far_shared_parity(torch, P, orc, theta, order):
     assert st["n_m2l"] > st["n_m2l_unique"]
 
 
+@pytest.mark.parametrize("theta,order", [(0.3, 3), (0.5, 3), (0.7, 3), (0.6, 0), (0.6, 1),
+                                         (0.6, 2), (0.6, 4)])
+def test_far_mutual_parity(torch, P, orc, theta, order):
+    """The one-sided symmetric M2L (each unordered node pair once, one D(r)
+    for both nodes): the oracle's results within 1e-12 per particle, the same
+    distinct pair count, momentum conserved."""
+    print(f"case: far mutual theta={theta} order={order}", flush=True)
+    x, m, h = workloads.plummer(4096, seed=1)
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=theta, order=order, far="mutual")
+    oa, op = orc.sfmm_solve(x, m, h, theta=theta, order=order)
+    assert rel_err(acc, oa).max() < TOL
+    assert pot_err(pot, op) < TOL
+    st = s.stats()
+    assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
+    t = orc.Tree(x, m, h, leaf_size=10, order=order)
+    mt, _, _, _ = t.mutual_pairs(theta)
+    assert st["n_m2l_unique"] == len(mt)
+
+
+def test_far_mutual_modes(torch, P, orc):
+    """Mutual far field: FP64 only, and on a polytrope with ragged leaves
+    (leaf size 4) the same results as the shared form to rounding."""
+    print("case: far mutual vs shared, fp32c refused", flush=True)
+    x, m, h = workloads.polytrope(20000, seed=11)
+    a1, p1, _ = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=4, far="mutual")
+    a0, p0, _ = gpu_solve(torch, P, x, m, h, theta=0.5, leaf_size=4, far="shared")
+    assert rel_err(a1, a0).max() < TOL and pot_err(p1, p0) < TOL
+    s = P.Solver(far="mutual")
+    xd, md, hd = dev(torch, x, m, h)
+    with pytest.raises(P.SfmmError, match="FP64 only"):
+        s.solve(xd, md, hd, precision="fp32c")
+    s.close()
+
+
 @pytest.mark.parametrize("n,leaf_size", [(10, 10), (4097, 10), (5000, 1), (5000, 16)])
 def test_far_shared_sizes(torch, P, orc, n, leaf_size):
     print(f"case: far shared n={n} leaf_size={leaf_size}", flush=True)
@@ -536,10 +610,11 @@ def test_leaf_walk_keeps_per_leaf_far(torch, P, orc):
     assert s.stats()["n_m2l_unique"] == 0
 
 
-def test_far_shared_full_size_sampled(torch, P, orc):
-    print("case: far shared N=1e6 polytrope sampled", flush=True)
+@pytest.mark.parametrize("far", ["shared", "mutual"])
+def test_far_shared_full_size_sampled(torch, P, orc, far):
+    print(f"case: far {far} N=1e6 polytrope sampled", flush=True)
     x, m, h = workloads.polytrope(1_000_000, seed=2)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far="shared")
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far=far)
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
     rng = np.random.default_rng(3)
