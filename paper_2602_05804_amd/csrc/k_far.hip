@@ -262,6 +262,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1))) void k_
   }
 }
 
+// Sort key of the node at level position g for the shared M2L: the number
+// of SPLIT-entry steps its list takes, longest first (clamped at 127 steps),
+// after a group bit that puts FP32 targets (FP32C, depth >= top) behind the
+// FP64 ones.  A stable pass on this key gives every wave nodes that take the
+// same number of steps, where level order leaves lanes idle until the
+// longest list of the wave ends; each node's own sum is unchanged.
+__global__ void k_m2l_order_keys(int nn, int split, const int32_t* __restrict__ level_nodes,
+                                 const uint32_t* __restrict__ cnt,
+                                 const int32_t* __restrict__ depth, int top, int f32,
+                                 uint64_t* __restrict__ key, uint32_t* __restrict__ ids) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nn) return;
+  const int v = level_nodes[g];
+  const uint32_t steps = (cnt[v] + (uint32_t)split - 1) / (uint32_t)split;
+  const uint32_t c = steps < 127u ? steps : 127u;
+  const uint32_t grp = (f32 && depth[v] >= top) ? 1u : 0u;
+  key[g] = (uint64_t)((grp << 7) | (127u - c));
+  ids[g] = (uint32_t)v;
+}
+
 __global__ void k_zero_f64(int64_t n, double* __restrict__ p) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -366,6 +386,23 @@ void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFar
       else shared_split<8, 2>(order, f, a, f32, s);
       break;
   }
+}
+
+int far_shared_split(int variant) {
+  switch (variant) {
+    case 1: return 4;
+    case 2: return 16;
+    default: return 8;
+  }
+}
+
+void launch_m2l_order(const SharedFarArgs& a, int variant, bool f32, const M2LOrderBufs& b,
+                      hipStream_t s) {
+  if (a.nn <= 0) return;
+  k_m2l_order_keys<<<(unsigned)((a.nn + 255) / 256), 256, 0, s>>>(
+      a.nn, far_shared_split(variant), a.level_nodes, a.m2l_cnt, a.depth, a.top, f32 ? 1 : 0,
+      b.key0, b.ids0);
+  radix_pass(a.nn, b.key0, b.ids0, b.key1, b.ids1, 0, b.hist, b.hist_tmp, b.total, s);
 }
 
 void launch_far_mutual(int order, const FarArgs& f, const SharedFarArgs& a, hipStream_t s) {

@@ -32,7 +32,7 @@ enum BufId {
   B_LEAFNODE, B_LEAFDEPTH, B_PLEAF,
   B_LDOFF, B_DEPTHCNT, B_M2LCNT, B_P2PCNT, B_PAIRCNT, B_M2L, B_P2P,
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
-  B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES, B_LEVINT,
+  B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES, B_LEVINT, B_M2LORD,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
   B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
   B_REC32, B_PF32, B_PH32,
@@ -596,6 +596,8 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     return fail(ctx, SFMM_EUNSUPPORTED, "SFMM_FAR_MUTUAL is FP64 only");
   if (shared && (rc = ensure(ctx, B_LN, sizeof(double) * local_count(ctx->order) * (size_t)ctx->nn)))
     return rc;
+  if (shared && !mutual && (rc = ensure(ctx, B_M2LORD, sizeof(uint32_t) * (size_t)ctx->nn)))
+    return rc;
   if (!level) ctx->m2l_unique = 0;
   phase_mark(ctx, 1, 0);
   if (level) {
@@ -653,8 +655,23 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     sa.rec32 = f32 ? P<float>(ctx, B_REC32) : nullptr;
     sa.top = ctx->cfg.fp64_top_depth;
     sa.ln = P<double>(ctx, B_LN);
-    if (mutual) launch_far_mutual(ctx->order, f, sa, s);
-    else launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
+    if (mutual) {
+      launch_far_mutual(ctx->order, f, sa, s);
+    } else {
+      // nodes grouped by list length for the M2L kernel (the level sort's
+      // key and id buffers are free once the tree is built)
+      M2LOrderBufs ob{};
+      ob.key0 = P<uint64_t>(ctx, B_LEVKEY0);
+      ob.key1 = P<uint64_t>(ctx, B_LEVKEY1);
+      ob.ids0 = P<uint32_t>(ctx, B_LEVIDS);
+      ob.ids1 = P<uint32_t>(ctx, B_M2LORD);
+      ob.hist = P<uint32_t>(ctx, B_HIST);
+      ob.hist_tmp = P<uint32_t>(ctx, B_SCANTMP);
+      ob.total = reinterpret_cast<uint32_t*>(small + S_SORTTOT);
+      launch_m2l_order(sa, ctx->far_variant, f32, ob, s);
+      sa.level_nodes = reinterpret_cast<const int32_t*>(ob.ids1);
+      launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
+    }
   } else if (f32) {
     launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
   } else {

@@ -265,7 +265,7 @@ void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipSt
 // shared far field: per-node M2L sums, then the per-leaf L2L chain and L2P
 struct SharedFarArgs {
   int nn;
-  const int32_t* level_nodes;  // nodes in level order
+  const int32_t* level_nodes;  // nodes in the order the M2L kernel takes them
   const int32_t* depth;        // node depth
   const uint32_t *m2l_off, *m2l_cnt, *pool;  // per-node M2L lists
   const double* rec;
@@ -277,6 +277,17 @@ struct SharedFarArgs {
 // one wave for FP32C (default), 4 (1), 16 (2), 8 one wave (3), 8 two waves (4)
 void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s);
+// node order for the shared M2L (k_m2l_nodes): nodes grouped by the number of
+// steps their lists take, longest first, stable over level order; result in
+// ids1 (key0/ids0 and key1 are scratch of nn entries, hist/hist_tmp/total as
+// for radix_pass)
+struct M2LOrderBufs {
+  uint64_t *key0, *key1;
+  uint32_t *ids0, *ids1;
+  uint32_t *hist, *hist_tmp, *total;
+};
+void launch_m2l_order(const SharedFarArgs& a, int variant, bool f32, const M2LOrderBufs& b,
+                      hipStream_t s);
 // the one-sided symmetric form of the shared far field: each unordered node
 // pair once (one D(r) for both nodes, the partner's side added atomically),
 // then the per-leaf L2L chain and L2P (FP64 only)
