@@ -72,7 +72,7 @@ def near_shape(precision, leaf_size, variant):
         return "near_thread"
     if variant == 13:
         return "near_tile"
-    if variant in ((2, 3, 4, 5, 6) if leaf_size <= 10 else (5, 6)):
+    if variant == 6:
         return "near_leaf"
     return "near"
 

@@ -110,31 +110,26 @@ typedef struct {
   int walk_mode;              /* sfmm_walk_mode (SFMM_WALK_LEVEL)                     */
   int fp64_top_depth;         /* SFMM_FP32C: M2L on targets above this depth in FP64 (8) */
   int far_mode;               /* sfmm_far_mode (SFMM_FAR_SHARED)                      */
-  int far_kernel;             /* far-field kernel shape, 0..4 (0)                    */
-  int near_kernel;            /* P2P kernel shape, 0..13 (0)                         */
+  int far_kernel;             /* far-field kernel shape: 0 is the only one            */
+  int near_kernel;            /* P2P kernel shape: 0, 1, 6, 7 or 13 (0)               */
 } sfmm_config;
-/* Kernel shapes (same results up to summation order; picked by the autotuner):
- * far_kernel, SFMM_FAR_SHARED: lanes per node 8 (0; a two-wave register budget
- *   in FP64), 4 (1), 16 (2), 8 with one wave (3), 8 with two waves (4);
- *   SFMM_FAR_LEAF: lanes per leaf 4 (0), 4 with two waves (1), 2 (2), 1 (3).
- * near_kernel, leaf_size <= 10: a wave per work item with the targets in
- *   scalar registers, wave-uniform loop control and the pairs inside a kernel
- *   queued and evaluated 64 at a time, in passes of 5 targets at four waves
- *   per SIMD (0), 8 at three (7), 10 at two (8), 5 at three (9), 6 at four
- *   (10), 8 at four (11), 5 at four with two groups of 64 sources per step
- *   (12); the targets of the leaf in lanes, in stripes over the sources
- *   staged through LDS, sources split into near and far by the target leaf's
- *   sphere and pairs inside a kernel queued per target (13); one thread per
- *   particle (1); the earlier
- *   wave-per-item kernel with targets in LDS: passes of 10 (2), one pass with
- *   a run-time target loop (3), passes of 4 (4), passes of 5 without the
- *   queue (5), passes of 5 with the queue (6).
- * near_kernel, leaf_size <= 16: scalar-register targets in passes of 8 (0),
- *   6 (7), 16 (8); targets in lanes (13); one thread per particle (1);
- *   targets in LDS, passes of 8 without (5) and with (6) the queue.
- * near_kernel with SFMM_FP32C: the wave kernel with scalar-register targets
- *   and a queue per target (every value but 6), the earlier shape with the
- *   targets in LDS and the softened branch taken in the pass (6). */
+/* P2P kernel shapes (same results up to summation order; sfmm_create returns
+ * SFMM_EINVAL for any other value, and for far_kernel != 0):
+ *   0  a wave per work item, the targets in scalar registers, wave-uniform
+ *      loop control, the pairs inside a kernel queued per target and
+ *      evaluated 64 at a time; passes of 5 targets at four waves per SIMD
+ *      (leaf_size <= 10) or of 6 at four (leaf_size <= 16);
+ *   13 the targets of a leaf in lanes, in stripes over sources staged through
+ *      LDS, source leaves split into near and far by the target leaf's sphere
+ *      (leaf_size <= 16; faster on the polytrope, slower on a Plummer halo);
+ *   6  a wave per work item with the targets in LDS, passes of 5 (8 for
+ *      leaf_size > 10), the queue shared by the pass; in SFMM_FP32C the same
+ *      layout with the softened branch taken in the pass;
+ *   7  SFMM_FP32C only: shape 0 with each sum kept as a TwoSum pair of FP32
+ *      words instead of an FP64 accumulator (in FP64, shape 0);
+ *   1  one thread per particle (also every leaf_size > 16).
+ * The far field has one shape per mode: 8 lanes per node (SFMM_FAR_SHARED,
+ * two waves per SIMD in FP64, one in FP32C), 4 lanes per leaf (SFMM_FAR_LEAF). */
 
 /* Solve statistics of the last sfmm_solve on a context (host copy). */
 typedef struct {

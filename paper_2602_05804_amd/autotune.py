@@ -1,6 +1,6 @@
 """Autotuner for the solve's free parameters: leaf size, the P2P and
-far-field kernel shapes and, in the FP32-compensated form, the depth above
-which M2L stays in FP64.
+P2P kernel shape and, in the FP32-compensated form, the depth above which
+M2L stays in FP64.
 
 A coordinate search on the caller's (or a synthetic) input: each parameter in
 turn is swept with the others fixed at their best so far, timing the median
@@ -24,8 +24,9 @@ import time
 from typing import Dict, Optional
 
 LEAF_SIZES = (6, 8, 10, 12, 16)
-NEAR_KERNELS = (0, 10, 7, 11, 12, 6)
-FAR_KERNELS_SHARED = (0, 1, 2, 3)
+# the P2P shapes of sfmm_config.near_kernel worth a try per precision (the
+# far field has one shape per mode)
+NEAR_KERNELS = {"fp64": (0, 13, 6), "fp32c": (0, 6, 7)}
 TOP_DEPTHS = (4, 8, 12, 128)  # 128: every M2L in FP64
 
 
@@ -67,8 +68,7 @@ def search(x, m, h, theta=0.5, order=3, precision="fp64", reps=5, log=None,
     time of every configuration tried.  `base` holds fixed Solver arguments
     (walk, far mode, ...); `leaf_sizes` = (k,) keeps the leaf size at k."""
     base = dict(base or {})
-    best = {**base, "leaf_size": 10 if 10 in leaf_sizes else leaf_sizes[0], "near_kernel": 0,
-            "far_kernel": 0}
+    best = {**base, "leaf_size": 10 if 10 in leaf_sizes else leaf_sizes[0], "near_kernel": 0}
     if precision == "fp32c":
         best["fp64_top_depth"] = 8
     tried = []
@@ -80,8 +80,7 @@ def search(x, m, h, theta=0.5, order=3, precision="fp64", reps=5, log=None,
             log(f"autotune {cfg}: {t * 1e3:.3f} ms")
         return t
 
-    axes = [("leaf_size", tuple(leaf_sizes)), ("near_kernel", NEAR_KERNELS),
-            ("far_kernel", FAR_KERNELS_SHARED)]
+    axes = [("leaf_size", tuple(leaf_sizes)), ("near_kernel", NEAR_KERNELS[precision])]
     if precision == "fp32c":
         axes.append(("fp64_top_depth", TOP_DEPTHS))
     t_best = run(dict(best))

@@ -144,6 +144,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) voi
 // stores the coefficients q, q + SPLIT, ...  With F32 the contraction of a
 // target at depth >= top runs on FP32 terms (FP64 sums), as in the per-leaf
 // FP32C kernel.
+constexpr int kSharedSplit = 8;  // lanes per node in k_m2l_nodes
+
 template <int P, int SPLIT, bool F32, int WAVES>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_m2l_nodes(
     SharedFarArgs a) {
@@ -372,36 +374,18 @@ void shared_split(int order, const FarArgs& f, const SharedFarArgs& a, bool f32,
 
 }  // namespace
 
-void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
+void launch_far_shared(int order, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s) {
-  // the FP64 contraction fits a two-wave register budget without spilling;
-  // the FP32 one does not
-  switch (variant) {
-    case 1: shared_split<4, 1>(order, f, a, f32, s); break;
-    case 2: shared_split<16, 1>(order, f, a, f32, s); break;
-    case 3: shared_split<8, 1>(order, f, a, f32, s); break;
-    case 4: shared_split<8, 2>(order, f, a, f32, s); break;
-    default:
-      if (f32) shared_split<8, 1>(order, f, a, f32, s);
-      else shared_split<8, 2>(order, f, a, f32, s);
-      break;
-  }
+  // 8 lanes per node; the FP64 contraction fits a two-wave register budget
+  // without spilling, the FP32 one does not
+  if (f32) shared_split<kSharedSplit, 1>(order, f, a, f32, s);
+  else shared_split<kSharedSplit, 2>(order, f, a, f32, s);
 }
 
-int far_shared_split(int variant) {
-  switch (variant) {
-    case 1: return 4;
-    case 2: return 16;
-    default: return 8;
-  }
-}
-
-void launch_m2l_order(const SharedFarArgs& a, int variant, bool f32, const M2LOrderBufs& b,
-                      hipStream_t s) {
+void launch_m2l_order(const SharedFarArgs& a, bool f32, const M2LOrderBufs& b, hipStream_t s) {
   if (a.nn <= 0) return;
   k_m2l_order_keys<<<(unsigned)((a.nn + 255) / 256), 256, 0, s>>>(
-      a.nn, far_shared_split(variant), a.level_nodes, a.m2l_cnt, a.depth, a.top, f32 ? 1 : 0,
-      b.key0, b.ids0);
+      a.nn, kSharedSplit, a.level_nodes, a.m2l_cnt, a.depth, a.top, f32 ? 1 : 0, b.key0, b.ids0);
   radix_pass(a.nn, b.key0, b.ids0, b.key1, b.ids1, 0, b.hist, b.hist_tmp, b.total, s);
 }
 
@@ -427,22 +411,11 @@ void far_dispatch(int order, const FarArgs& a, hipStream_t s) {
   }
 }
 
-// variant: lanes per leaf (1, 2, 4) x register budget (1 or 2 waves per SIMD)
-template <bool NODE>
-void far_variant(int order, int variant, const FarArgs& a, hipStream_t s) {
-  switch (variant) {
-    case 0: far_dispatch<NODE, 4, 1>(order, a, s); break;
-    case 1: far_dispatch<NODE, 4, 2>(order, a, s); break;
-    case 2: far_dispatch<NODE, 2, 1>(order, a, s); break;
-    case 3: far_dispatch<NODE, 1, 1>(order, a, s); break;
-    default: far_dispatch<NODE, 4, 1>(order, a, s); break;
-  }
-}
-
-void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipStream_t s) {
+void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s) {
   if (a.nleaves <= 0) return;
-  if (node_lists) far_variant<true>(order, variant, a, s);
-  else far_variant<false>(order, variant, a, s);
+  // 4 lanes per leaf, one wave per SIMD
+  if (node_lists) far_dispatch<true, 4, 1>(order, a, s);
+  else far_dispatch<false, 4, 1>(order, a, s);
 }
 
 }  // namespace sfmm

@@ -110,19 +110,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// TG == 0: one pass over the sources for all targets, the loop over the
-//          targets stopping at nt (per-target accumulators indexed at run
-//          time);
-// TG > 0:  passes of TG targets each, fully unrolled (static accumulator
-//          indices; nt is the same on every lane, so the guard is a scalar
-//          branch); the sources are read once per pass.
-// Q: pairs inside a kernel are not evaluated in the wave's pass over the
-// sources (where most lanes would idle through the softening branch) but
-// queued in LDS as (target, source); every 64 queued pairs are evaluated
-// together, one per lane, and added to the same per-target accumulators.
-template <int LS, bool NODE, int TG, bool Q = false>
+// Targets in LDS, in passes of TG targets each, fully unrolled (static
+// accumulator indices; nt is the same on every lane, so the guard is a scalar
+// branch); the sources are read once per pass.  Pairs inside a kernel are not
+// evaluated in the wave's pass over the sources (where most lanes would idle
+// through the softening branch) but queued in LDS as (target, source); every
+// 64 queued pairs are evaluated together, one per lane, and added to the same
+// per-target accumulators.
+template <int LS, bool NODE, int TG>
 __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
-  constexpr int NA = TG > 0 ? TG : LS;  // accumulators per pass
+  constexpr int NA = TG;  // accumulators per pass
   const int lane = threadIdx.x;
   const uint32_t item = blockIdx.x;
   if (item >= a.item_off[a.nleaves]) return;  // the grid is an upper bound
@@ -157,8 +154,8 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
   const uint32_t f_hi = f_lo + kP2PItem < ftot ? f_lo + kP2PItem : ftot;
   uint32_t carry0 = 0;
   if (kitem > 0) { e0 = a.item_e0[item]; carry0 = a.item_c0[item]; }
-  __shared__ int qj[Q ? 128 : 1];
-  __shared__ int qi[Q ? 128 : 1];
+  __shared__ int qj[128];
+  __shared__ int qi[128];
   uint32_t qn = 0;     // queued softened pairs (the same on every lane)
   uint32_t nsoft = 0;  // softened pairs of this item
   for (int t0 = 0; t0 < nt; t0 += NA) {
@@ -235,53 +232,40 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
         const bool fv = f < total;
         const int j = fv ? jj : ti.lo;
         const double xj = a.xs[j], yj = a.ys[j], zj = a.zs[j], mj = a.ms[j];
-        const double hj = a.hs[j], hjinv = a.his[j];
+        const double hjinv = a.his[j];
         const double hj2inv = hjinv * hjinv;
 #pragma unroll
         for (int ii = 0; ii < NA; ++ii) {
           const int i = t0 + ii;
-          if (TG > 0) { if (i >= nt) continue; }
-          else if (i >= nt) break;
+          if (i >= nt) continue;
           const double w = (!fv || j == ti.lo + i) ? 0.0 : mj;  // the pair (i, i) is skipped
           const double thi = tg[i][3];
           const double dx = tg[i][0] - xj, dy = tg[i][1] - yj, dz = tg[i][2] - zj;
           const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
           const double rinv = rsqrt_pair(r2);
           const double rinv3 = rinv * rinv * rinv;
-          double gs = rinv3, ps = rinv;  // both kernels at q >= 2
           const bool inside = fv && ((r2 * (thi * thi) < 4.0) || (r2 * hj2inv < 4.0));
-          double wq = w;
-          if (Q) {
-            const bool push = inside && w != 0.0;
-            const uint64_t bal = __ballot(push);
-            if (bal) {
-              const uint32_t below =
-                  __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-              if (push) { qj[qn + below] = j; qi[qn + below] = i; }
-              qn += (uint32_t)__popcll(bal);
-              nsoft += (uint32_t)__popcll(bal);
-            }
-            if (inside) wq = 0.0;
-          } else if (__ballot(inside)) {
-            const double r = r2 * rinv;
-            double g1, p1, g2, p2;
-            soft_sel(r * thi, thi, tg[i][4] * rinv, rinv, rinv3, g1, p1);
-            soft_sel(r * hjinv, hjinv, hj * rinv, rinv, rinv3, g2, p2);
-            if (inside) {
-              gs = 0.5 * (g1 + g2);
-              ps = 0.5 * (p1 + p2);
-            }
+          const bool push = inside && w != 0.0;
+          const uint64_t bal = __ballot(push);
+          if (bal) {
+            const uint32_t below =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (push) { qj[qn + below] = j; qi[qn + below] = i; }
+            qn += (uint32_t)__popcll(bal);
+            nsoft += (uint32_t)__popcll(bal);
           }
-          const double mg = wq * gs;
+          // both kernels at q >= 2 outside; a pair inside went to the queue
+          const double wq = inside ? 0.0 : w;
+          const double mg = wq * rinv3;
           fx[ii] = fma(mg, dx, fx[ii]);
           fy[ii] = fma(mg, dy, fy[ii]);
           fz[ii] = fma(mg, dz, fz[ii]);
-          ph[ii] = fma(wq, ps, ph[ii]);
-          if (Q && qn >= 64) flush(64);
+          ph[ii] = fma(wq, rinv, ph[ii]);
+          if (qn >= 64) flush(64);
         }
       }
     }
-    if (Q && qn > 0) flush(qn);
+    if (qn > 0) flush(qn);
 #pragma unroll
     for (int ii = 0; ii < NA; ++ii) {
       const int i = t0 + ii;
@@ -294,7 +278,7 @@ __global__ __launch_bounds__(64) void k_p2p_leaf(NearArgs a) {
       }
     }
   }
-  if (Q && lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
+  if (lane == 0 && nsoft) atomicAdd(a.soft_pairs, (unsigned long long)nsoft);
 }
 
 // Wave per item, targets held in scalar registers.  The same sums as
@@ -668,13 +652,6 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
-#define WAVE_LAUNCH_U(LS, TG, WPE, U)                                     \
-  do {                                                                    \
-    if (node_lists) k_p2p_wave<LS, true, TG, WPE, U><<<nbl, 64, 0, s>>>(a); \
-    else k_p2p_wave<LS, false, TG, WPE, U><<<nbl, 64, 0, s>>>(a);         \
-    record_mark(km.end, s);                                               \
-    launch_p2p_reduce(a, LS, s);                                          \
-  } while (0)
 #define WAVE_LAUNCH(LS, TG, WPE)                                          \
   do {                                                                    \
     if (node_lists) k_p2p_wave<LS, true, TG, WPE, 1><<<nbl, 64, 0, s>>>(a); \
@@ -683,10 +660,10 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
     launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
 
-#define NEAR_LAUNCH(LS, TG, QU)                                            \
+#define NEAR_LAUNCH(LS, TG)                                                \
   do {                                                                    \
-    if (node_lists) k_p2p_leaf<LS, true, TG, QU><<<nbl, 64, 0, s>>>(a);   \
-    else k_p2p_leaf<LS, false, TG, QU><<<nbl, 64, 0, s>>>(a);             \
+    if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);       \
+    else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);                 \
     record_mark(km.end, s);                                               \
     launch_p2p_reduce(a, LS, s);                                          \
   } while (0)
@@ -725,29 +702,14 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
     launch_p2p_reduce(a, leaf_size <= 10 ? 10 : 16, s);
     return;
   }
+  // leaf_size <= 10: five targets per pass at four waves per SIMD; <= 16:
+  // six at four (the shapes that won on the polytrope and Plummer workloads)
   if (leaf_size <= 10) {
-    switch (variant) {
-      case 2: NEAR_LAUNCH(10, 10, false); break;
-      case 3: NEAR_LAUNCH(10, 0, false); break;
-      case 4: NEAR_LAUNCH(10, 4, false); break;
-      case 5: NEAR_LAUNCH(10, 5, false); break;
-      case 6: NEAR_LAUNCH(10, 5, true); break;
-      case 7: WAVE_LAUNCH(10, 8, 3); break;
-      case 8: WAVE_LAUNCH(10, 10, 2); break;
-      case 9: WAVE_LAUNCH(10, 5, 3); break;
-      case 10: WAVE_LAUNCH(10, 6, 4); break;
-      case 11: WAVE_LAUNCH(10, 8, 4); break;
-      case 12: WAVE_LAUNCH_U(10, 5, 4, 2); break;
-      default: WAVE_LAUNCH(10, 5, 4); break;
-    }
+    if (variant == 6) NEAR_LAUNCH(10, 5);
+    else WAVE_LAUNCH(10, 5, 4);
   } else if (leaf_size <= 16) {
-    switch (variant) {
-      case 5: NEAR_LAUNCH(16, 8, false); break;
-      case 6: NEAR_LAUNCH(16, 8, true); break;
-      case 7: WAVE_LAUNCH(16, 6, 4); break;
-      case 8: WAVE_LAUNCH(16, 16, 2); break;
-      default: WAVE_LAUNCH(16, 8, 3); break;
-    }
+    if (variant == 6) NEAR_LAUNCH(16, 8);
+    else WAVE_LAUNCH(16, 6, 4);
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);

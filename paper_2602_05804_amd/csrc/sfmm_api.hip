@@ -74,7 +74,6 @@ struct sfmm_ctx {
   uint32_t stack_cap = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
-  int far_variant = 0;         // kernel shape of the far field (SFMM_FAR_VARIANT)
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
   bool have_tree = false, have_lists = false, have_mom = false;
   // clear the list pools before each walk and check every list entry after
@@ -668,14 +667,14 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
       ob.hist = P<uint32_t>(ctx, B_HIST);
       ob.hist_tmp = P<uint32_t>(ctx, B_SCANTMP);
       ob.total = reinterpret_cast<uint32_t*>(small + S_SORTTOT);
-      launch_m2l_order(sa, ctx->far_variant, f32, ob, s);
+      launch_m2l_order(sa, f32, ob, s);
       sa.level_nodes = reinterpret_cast<const int32_t*>(ob.ids1);
-      launch_far_shared(ctx->order, ctx->far_variant, f, sa, f32, s);
+      launch_far_shared(ctx->order, f, sa, f32, s);
     }
   } else if (f32) {
     launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
   } else {
-    launch_far(ctx->order, level, ctx->far_variant, f, s);
+    launch_far(ctx->order, level, f, s);
   }
   phase_mark(ctx, 3, 1);
   NearArgs a{};
@@ -841,6 +840,9 @@ int sfmm_config_default(sfmm_config* cfg) {
   return SFMM_OK;
 }
 
+// the P2P kernel shapes (sfmm_config.near_kernel)
+static bool near_shape_ok(int v) { return v == 0 || v == 1 || v == 6 || v == 7 || v == 13; }
+
 int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config* cfg) {
   if (!out) return SFMM_EINVAL;
   *out = nullptr;
@@ -851,8 +853,7 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
       !std::isfinite(c.r_kern) || (c.walk_mode != SFMM_WALK_LEVEL && c.walk_mode != SFMM_WALK_LEAF) ||
       c.fp64_top_depth < 0 || c.fp64_top_depth > 128 ||
       (c.far_mode != SFMM_FAR_LEAF && c.far_mode != SFMM_FAR_SHARED &&
-       c.far_mode != SFMM_FAR_MUTUAL) || c.far_kernel < 0 ||
-      c.far_kernel > 4 || c.near_kernel < 0 || c.near_kernel > 13)
+       c.far_mode != SFMM_FAR_MUTUAL) || c.far_kernel != 0 || !near_shape_ok(c.near_kernel))
     return SFMM_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -864,11 +865,16 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
   ctx->cfg = c;
-  ctx->far_variant = c.far_kernel;
   ctx->near_variant = c.near_kernel;
-  // measurement overrides
-  if (const char* fv = std::getenv("SFMM_FAR_VARIANT")) ctx->far_variant = std::atoi(fv);
-  if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) ctx->near_variant = std::atoi(nv);
+  // measurement override (an unknown shape is refused)
+  if (const char* nv = std::getenv("SFMM_NEAR_VARIANT")) {
+    const int v = std::atoi(nv);
+    if (!near_shape_ok(v)) {
+      delete ctx;
+      return SFMM_EINVAL;
+    }
+    ctx->near_variant = v;
+  }
   if (const char* cp = std::getenv("SFMM_CHECK_POOLS")) ctx->check_pools = std::atoi(cp) != 0;
   if (const char* pi = std::getenv("SFMM_POOL_INIT"))
     ctx->pool_init = (uint64_t)std::max(0ll, std::atoll(pi));

@@ -258,9 +258,8 @@ struct FarArgs {
   const double *xs, *ys, *zs;
   double* far;  // [n][4]: field x, y, z, potential (before the -G factor)
 };
-// variant: 0 = 4 lanes per leaf (default), 1 = idem with a two-wave register
-// budget, 2 = 2 lanes per leaf, 3 = one lane per leaf
-void launch_far(int order, bool node_lists, int variant, const FarArgs& a, hipStream_t s);
+// replicated per-leaf far field, 4 lanes per leaf
+void launch_far(int order, bool node_lists, const FarArgs& a, hipStream_t s);
 
 // shared far field: per-node M2L sums, then the per-leaf L2L chain and L2P
 struct SharedFarArgs {
@@ -273,9 +272,7 @@ struct SharedFarArgs {
   int top;             // FP32C: targets at depth < top in FP64
   double* ln;          // [nn][NL] per-node local expansions (written where cnt > 0)
 };
-// variant: lanes per node 8 with a two-wave register budget for FP64 and
-// one wave for FP32C (default), 4 (1), 16 (2), 8 one wave (3), 8 two waves (4)
-void launch_far_shared(int order, int variant, const FarArgs& f, const SharedFarArgs& a, bool f32,
+void launch_far_shared(int order, const FarArgs& f, const SharedFarArgs& a, bool f32,
                        hipStream_t s);
 // node order for the shared M2L (k_m2l_nodes): nodes grouped by the number of
 // steps their lists take, longest first, stable over level order; result in
@@ -286,8 +283,7 @@ struct M2LOrderBufs {
   uint32_t *ids0, *ids1;
   uint32_t *hist, *hist_tmp, *total;
 };
-void launch_m2l_order(const SharedFarArgs& a, int variant, bool f32, const M2LOrderBufs& b,
-                      hipStream_t s);
+void launch_m2l_order(const SharedFarArgs& a, bool f32, const M2LOrderBufs& b, hipStream_t s);
 // the one-sided symmetric form of the shared far field: each unordered node
 // pair once (one D(r) for both nodes, the partner's side added atomically),
 // then the per-leaf L2L chain and L2P (FP64 only)

@@ -70,6 +70,11 @@ def test_bad_config_rejected(L):
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
     bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 1, 9, 0)  # unknown far kernel shape
     assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
+    bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 1, 1, 0)  # far shapes other than 0 are gone
+    assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1
+    for shape in (2, 3, 4, 5, 8, 9, 10, 11, 12, 14, -1):  # P2P shapes that do not exist
+        bad = P.Config(1.0, 10, 2.0, 1, 1, 0, 8, 1, 0, shape)
+        assert L.sfmm_create(C.byref(ctx), 0, None, C.byref(bad)) == -1, shape
 
 
 def test_no_device_is_an_error_not_a_fallback(L):

@@ -15,9 +15,8 @@ class _T:
 
 
 def _cost(cfg):
-    # separable bowl: best at leaf 12, near kernel 7, far kernel 2, top depth 12
+    # separable bowl: best at leaf 12, near kernel 7, top depth 12
     c = abs(cfg["leaf_size"] - 12) + abs(cfg["near_kernel"] - 7) * 0.5
-    c += 0.0 if cfg["far_kernel"] == 2 else 1.0
     c += abs(cfg.get("fp64_top_depth", 12) - 12) * 0.1
     return 1.0 + c
 
@@ -27,12 +26,14 @@ def test_search_finds_separable_minimum(monkeypatch):
     monkeypatch.setattr(autotune, "time_config",
                         lambda x, m, h, cfg, *a, **k: calls.append(dict(cfg)) or _cost(cfg))
     res = autotune.search(None, _T(1000), None, precision="fp32c")
-    assert res["config"] == {"leaf_size": 12, "near_kernel": 7, "far_kernel": 2,
-                             "fp64_top_depth": 12}
+    assert res["config"] == {"leaf_size": 12, "near_kernel": 7, "fp64_top_depth": 12}
     assert res["seconds"] == 1.0
     # a coordinate search: one run per value per axis, not the full product
-    assert len(calls) == (1 + (len(autotune.LEAF_SIZES) - 1) + (len(autotune.NEAR_KERNELS) - 1)
-                          + (len(autotune.FAR_KERNELS_SHARED) - 1) + (len(autotune.TOP_DEPTHS) - 1))
+    assert len(calls) == (1 + (len(autotune.LEAF_SIZES) - 1)
+                          + (len(autotune.NEAR_KERNELS["fp32c"]) - 1)
+                          + (len(autotune.TOP_DEPTHS) - 1))
+    # every shape tried is one the library accepts
+    assert all(c["near_kernel"] in (0, 1, 6, 7, 13) for c in calls)
 
 
 def test_cache_roundtrip(monkeypatch, tmp_path):
@@ -43,13 +44,13 @@ def test_cache_roundtrip(monkeypatch, tmp_path):
 
     def fake_search(x, m, h, theta, order, precision, log=None):
         n_search.append(1)
-        return {"config": {"leaf_size": 8, "near_kernel": 0, "far_kernel": 1}, "seconds": 0.1}
+        return {"config": {"leaf_size": 8, "near_kernel": 6}, "seconds": 0.1}
 
     monkeypatch.setattr(autotune, "search", fake_search)
     path = str(tmp_path / "cache.json")
     c1 = autotune.tuned_config(_T(1000), _T(1000), _T(1000), label="plummer", cache_path=path)
     c2 = autotune.tuned_config(_T(1100), _T(1100), _T(1100), label="plummer", cache_path=path)
-    assert c1 == c2 == {"leaf_size": 8, "near_kernel": 0, "far_kernel": 1}
+    assert c1 == c2 == {"leaf_size": 8, "near_kernel": 6}
     assert len(n_search) == 1  # same power-of-two bucket: cached
     autotune.tuned_config(_T(5000), _T(5000), _T(5000), label="plummer", cache_path=path)
     assert len(n_search) == 2  # another bucket

@@ -33,15 +33,17 @@ def test_near_shape_names_the_launched_kernel():
     # the roofline's kernel name follows the near-kernel number and leaf size
     # the same way the C++ dispatch does
     assert bench.near_shape("fp64", 10, 0) == "near"
-    assert bench.near_shape("fp64", 10, 12) == "near"
+    assert bench.near_shape("fp64", 10, 7) == "near"
     assert bench.near_shape("fp64", 10, 1) == "near_thread"
-    assert bench.near_shape("fp64", 10, 4) == "near_leaf"
-    assert bench.near_shape("fp64", 16, 4) == "near"
+    assert bench.near_shape("fp64", 10, 6) == "near_leaf"
+    assert bench.near_shape("fp64", 10, 13) == "near_tile"
+    assert bench.near_shape("fp64", 16, 0) == "near"
     assert bench.near_shape("fp64", 16, 6) == "near_leaf"
     assert bench.near_shape("fp64", 24, 0) == "near_thread"
     assert bench.near_shape("fp32c", 10, 0) == "near"
+    assert bench.near_shape("fp32c", 10, 7) == "near"
     assert bench.near_shape("fp32c", 10, 6) == "near_leaf"
     for prec in ("fp64", "fp32c"):
         for ls in (10, 16, 24):
-            for v in range(13):
+            for v in (0, 1, 6, 7, 13):
                 assert (prec, bench.near_shape(prec, ls, v)) in bench.KERNELS

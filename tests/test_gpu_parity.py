@@ -242,8 +242,8 @@ def test_large_softening_all_pairs(torch, P, orc):
     assert rel_err(acc, da).max() < TOL and pot_err(pot, dp) < TOL
 
 
-@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp64", 3),
-                                                   ("fp64", 13), ("fp32c", 0), ("fp32c", 6)])
+@pytest.mark.parametrize("precision,near_kernel", [("fp64", 0), ("fp64", 6), ("fp64", 13),
+                                                   ("fp32c", 0), ("fp32c", 6)])
 def test_p2p_many_work_items(torch, P, orc, precision, near_kernel):
     """Every leaf's sources split into several P2P work items (more than 2048
     source particles per leaf): 7000 particles all inside each other's kernel,
@@ -669,7 +669,7 @@ def test_direct_sum_parity(torch, P, orc):
 
 
 @pytest.mark.parametrize("leaf_size,near_kernel",
-                         [(10, k) for k in range(1, 14)] + [(16, k) for k in (0, 5, 6, 7, 8, 13)])
+                         [(10, k) for k in (1, 6, 7, 13)] + [(16, k) for k in (0, 6, 13)])
 def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     """Every P2P kernel shape gives the oracle's result (halo leaves with
     large softening lengths, coincident particles)."""
