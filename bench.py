@@ -168,6 +168,9 @@ def main():
                          "in [1e3, 1e6], 4 KDK steps each); 0 skips it")
     ap.add_argument("--no-serve-fp32c", dest="serve_fp32c", action="store_false",
                     help="serve the trace in FP64 only (by default it is also served in FP32C)")
+    ap.add_argument("--no-serve-tuned", dest="serve_tuned", action="store_false",
+                    help="skip the FP64 serving run whose packs take the leaf size and P2P "
+                         "shape the autotuner picked for their size bucket")
     ap.add_argument("--serve-low-rate", type=float, default=100.0,
                     help="arrival rate of a second FP64 serving run below the GPU's capacity "
                          "(0 skips it)")
@@ -502,7 +505,10 @@ def serving(args):
     the same arrival trace (200 requests/s) with the HBM budget at 0.8 x free
     memory, FP64 again under a small budget so that admission queues
     requests, and FP64 with the same trace stretched to a lower arrival rate
-    that the GPU keeps up with (latency then measures service, not queueing)."""
+    that the GPU keeps up with (latency then measures service, not queueing),
+    and FP64 once more with each pack's leaf size and P2P shape taken from the
+    autotuner's pick for its size bucket."""
+    import numpy as np
     import torch
 
     import workloads
@@ -516,14 +522,37 @@ def serving(args):
            "pack_particles": args.serve_pack, "max_particles_in_flight": args.serve_inflight,
            "trace": "Poisson arrivals at 200/s, N = 10^U(3,6), Plummer/polytrope alternating, "
                     "seed 7"}
-    runs = [("fp64", None, 200.0)] + ([("fp32c", None, 200.0)] if args.serve_fp32c else []) + [
-        ("fp64", 3_000_000, 200.0)]
+    runs = [("fp64", None, 200.0, False)] + (
+        [("fp32c", None, 200.0, False)] if args.serve_fp32c else []) + [
+        ("fp64", 3_000_000, 200.0, False)]
     if args.serve_low_rate > 0:
-        runs.append(("fp64", None, args.serve_low_rate))
-    for prec, small_budget_n, rate in runs:
+        runs.append(("fp64", None, args.serve_low_rate, False))
+    tuned = None
+    if args.serve_tuned:
+        # one search per size bucket from 2^10 to the pack cap, on one system
+        # of that size mixing the trace's two kinds (a Plummer sphere and a
+        # polytrope side by side)
+        from paper_2602_05804_amd import autotune
+
+        def make_input(n):
+            xa, ma, ha = workloads.plummer(n // 2, seed=21)
+            xb, mb, hb = workloads.polytrope(n - n // 2, seed=22)
+            xb = xb + np.array([250.0, 0.0, 0.0])  # beyond the sphere's 100 a
+            return tuple(torch.from_numpy(np.ascontiguousarray(np.concatenate(p))).cuda()
+                         for p in ((xa, xb), (ma * 0.5, mb * 0.5), (ha, hb)))
+
+        t0 = time.perf_counter()
+        sizes = [2 ** k for k in range(10, int(np.log2(args.serve_pack)) + 1)]
+        tuned = autotune.tune_buckets(sizes, make_input, theta=args.theta, order=args.order,
+                                      base={"walk": args.walk, "far": args.far}, log=log)
+        out["tuned_buckets"] = {str(k): v for k, v in tuned.items()}
+        out["tuning_s"] = round(time.perf_counter() - t0, 2)
+        runs.append(("fp64", None, 200.0, True))
+    for prec, small_budget_n, rate, use_tuned in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
                                leaf_size=args.leaf_size, far=args.far,
-                               pack_particles=args.serve_pack)
+                               pack_particles=args.serve_pack,
+                               tuned=tuned if use_tuned else None)
         free, _ = torch.cuda.mem_get_info()
         budget = 0.8 * free if small_budget_n is None else ex.footprint(small_budget_n)
         jobs = serve.jobs_from_stream(reqs, steps=4)
@@ -539,6 +568,8 @@ def serving(args):
         key = prec if small_budget_n is None else f"{prec}_small_budget"
         if rate != 200.0:
             key = f"{prec}_rate{rate:g}"
+        if use_tuned:
+            key = f"{prec}_tuned"
         out[key] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
         log(f"serving {key}: " + ", ".join(f"{k}={v}" for k, v in out[key].items()))
         del ex

@@ -36,8 +36,7 @@ def default_cache_path() -> str:
 
 
 def _key(device_name: str, n: int, label: str, precision: str, theta: float, order: int) -> str:
-    nb = 2 ** round(math.log2(max(n, 1)))
-    return f"{device_name}|N~{nb}|{label}|{precision}|theta={theta:g}|p={order}"
+    return f"{device_name}|N~{bucket(n)}|{label}|{precision}|theta={theta:g}|p={order}"
 
 
 def time_config(x, m, h, cfg: Dict, theta=0.5, order=3, precision="fp64", reps=5) -> float:
@@ -93,6 +92,36 @@ def search(x, m, h, theta=0.5, order=3, precision="fp64", reps=5, log=None,
             if t < t_best:
                 best, t_best = cfg, t
     return {"config": best, "seconds": t_best, "tried": tried}
+
+
+def bucket(n: int) -> int:
+    """The power of two nearest to n (on a log scale): the size class the
+    cache and the serving loop tune for."""
+    return 2 ** round(math.log2(max(n, 1)))
+
+
+def config_for(tuned: Dict[int, Dict], n: int) -> Dict:
+    """The tuned Solver arguments for a solve of n particles: those of the
+    tuned bucket nearest to n on a log scale ({} when nothing is tuned)."""
+    if not tuned:
+        return {}
+    b = min(tuned, key=lambda k: (abs(math.log2(k) - math.log2(max(n, 1))), k))
+    return dict(tuned[b])
+
+
+def tune_buckets(sizes, make_input, theta=0.5, order=3, precision="fp64", reps=3, log=None,
+                 base: Optional[Dict] = None) -> Dict[int, Dict]:
+    """Tuned Solver arguments per size bucket: one search per distinct
+    bucket of `sizes`, on the input make_input(n) returns (device x, m, h)."""
+    out = {}
+    for b in sorted({bucket(n) for n in sizes}):
+        x, m, h = make_input(b)
+        res = search(x, m, h, theta, order, precision, reps=reps, log=log, base=base)
+        cfg = {k: v for k, v in res["config"].items() if k not in (base or {})}
+        out[b] = cfg
+        if log:
+            log(f"autotune bucket N~{b}: {cfg} ({res['seconds'] * 1e3:.3f} ms)")
+    return out
 
 
 def tuned_config(x, m, h, label: str = "default", theta=0.5, order=3, precision="fp64",

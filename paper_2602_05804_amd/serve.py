@@ -123,10 +123,12 @@ class GpuExecutor:
     (``Solver.solve_batch``): one pass of every kernel for all of its systems.
     A system larger than the cap is a pack of its own.  When a packed solve
     fails, its systems are solved one by one so that only the failing
-    requests fail."""
+    requests fail.  `tuned` maps size buckets (powers of two) to Solver
+    arguments (autotune.tune_buckets): each pack is solved with those of the
+    bucket nearest to its particle count, one Solver per distinct setting."""
 
     def __init__(self, precision="fp64", theta=0.5, order=3, pack_particles=16_000_000,
-                 bytes_per_particle=None, **solver_cfg):
+                 bytes_per_particle=None, tuned=None, **solver_cfg):
         import torch
 
         import paper_2602_05804_amd as sfmm
@@ -138,7 +140,9 @@ class GpuExecutor:
         self.order = order
         self.pack_particles = int(pack_particles)
         self.solver_cfg = solver_cfg
+        self.tuned = dict(tuned or {})
         self.solver = sfmm.Solver(**solver_cfg)
+        self._solvers = {(): self.solver}
         self.stream = torch.cuda.Stream()
         # per-particle device bytes: the context's workspace plus the request's
         # own buffers (x, v, m, h, acc, pot); measured once if not given
@@ -156,6 +160,16 @@ class GpuExecutor:
         b = s.workspace_bytes() / n
         s.close()
         return int(b * 1.5) + 12 * 8  # slack for list growth + request buffers
+
+    def solver_for(self, n: int):
+        """The Solver for a pack of n particles (tuned, else the default)."""
+        from paper_2602_05804_amd import autotune
+
+        cfg = autotune.config_for(self.tuned, n)
+        key = tuple(sorted(cfg.items()))
+        if key not in self._solvers:
+            self._solvers[key] = self.sfmm.Solver(**{**self.solver_cfg, **cfg})
+        return self._solvers[key]
 
     def footprint(self, n: int) -> int:
         return self.bytes_per_particle * n
@@ -211,14 +225,16 @@ class GpuExecutor:
         def solve_pack(pack):
             for j in pack:
                 self._pre(j)
-            res = self.solver.solve_batch(
+            solver = self.solver_for(sum(j.n for j in pack))
+            res = solver.solve_batch(
                 [(j.state["x"], j.state["m"], j.state["h"]) for j in pack],
                 theta=self.theta, order=self.order, precision=self.precision)
             return [a.clone() for a, _ in res]
 
         def solve_one(j):
-            a, _ = self.solver.solve(j.state["x"], j.state["m"], j.state["h"], theta=self.theta,
-                                     order=self.order, precision=self.precision)
+            a, _ = self.solver_for(j.n).solve(j.state["x"], j.state["m"], j.state["h"],
+                                              theta=self.theta, order=self.order,
+                                              precision=self.precision)
             return a
 
         def on_error(j, msg):

@@ -80,3 +80,33 @@ def test_autotuned_solver_parity(orc):
     acc = acc.cpu().numpy()
     nb = np.linalg.norm(oa, axis=1)
     assert (np.linalg.norm(acc - oa, axis=1) / np.maximum(nb, 1e-6 * np.sqrt((nb ** 2).mean()))).max() < 1e-12
+
+
+def test_bucket_lookup():
+    tuned = {1024: {"leaf_size": 8}, 65536: {"leaf_size": 16, "near_kernel": 13}}
+    assert autotune.bucket(1000) == 1024 and autotune.bucket(3000) == 4096
+    assert autotune.config_for({}, 5000) == {}
+    assert autotune.config_for(tuned, 700) == {"leaf_size": 8}
+    assert autotune.config_for(tuned, 7000) == {"leaf_size": 8}  # log-nearer to 2^10 than 2^16
+    assert autotune.config_for(tuned, 10 ** 6) == {"leaf_size": 16, "near_kernel": 13}
+    # a copy: the caller may change it
+    c = autotune.config_for(tuned, 10 ** 6)
+    c["leaf_size"] = 4
+    assert tuned[65536]["leaf_size"] == 16
+
+
+def test_tune_buckets_one_search_per_bucket(monkeypatch):
+    seen = []
+
+    def fake_search(x, m, h, theta, order, precision, reps=3, log=None, base=None):
+        seen.append(x)
+        return {"config": {**(base or {}), "leaf_size": 8 if x < 5000 else 12, "near_kernel": 0},
+                "seconds": 0.01}
+
+    monkeypatch.setattr(autotune, "search", fake_search)
+    out = autotune.tune_buckets([1000, 1100, 3000, 70000], lambda n: (n, None, None),
+                                base={"walk": "level"})
+    assert seen == [1024, 4096, 65536]
+    assert out == {1024: {"leaf_size": 8, "near_kernel": 0},
+                   4096: {"leaf_size": 8, "near_kernel": 0},
+                   65536: {"leaf_size": 12, "near_kernel": 0}}

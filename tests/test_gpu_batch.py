@@ -166,6 +166,45 @@ def test_serving_loop(torch, P):
         assert np.array_equal(xd.cpu().numpy(), finals[pick.rid])
 
 
+def test_serving_loop_tuned(torch, P):
+    """Serving with per-bucket tuned settings: every request completes, the
+    packs use the Solver of their bucket, and a request larger than the pack
+    cap (a pack of its own, nearest the 2^15 bucket) ends in the state a solo KDK
+    integration with that bucket's settings reaches (bit for bit, FP64)."""
+    print("case: serving loop with tuned buckets", flush=True)
+    from paper_2602_05804_amd import serve
+
+    reqs = workloads.serving_stream(count=16, seed=10, rate=400.0, nmin=50, nmax=30000)
+    jobs = serve.jobs_from_stream(reqs, steps=2)
+    ref = {j.rid: (j.payload, j.dt) for j in jobs}
+    tuned = {1024: {"leaf_size": 6}, 32768: {"leaf_size": 16, "near_kernel": 13}}
+    ex = serve.GpuExecutor(pack_particles=15000, tuned=tuned)
+    finals = {}
+    orig_release = ex.release
+
+    def keep(job):
+        finals[job.rid] = job.state["x"].cpu().numpy()
+        orig_release(job)
+
+    ex.release = keep
+    rep = serve.Server(ex, hbm_budget=ex.footprint(60000)).run(jobs)
+    assert rep.completed == len(jobs) and rep.failed == 0 and rep.rejected == 0
+    used = set(ex._solvers)
+    assert (("leaf_size", 16), ("near_kernel", 13)) in used
+    big = max(jobs, key=lambda j: j.n)
+    assert big.n > 15000
+    (x, m, h), dt = ref[big.rid]
+    s = P.Solver(leaf_size=16, near_kernel=13)
+    xd, md, hd = dev(torch, x, m, h)
+    vd = torch.zeros_like(xd)
+    acc, _ = s.solve(xd, md, hd)
+    for k in range(1, 3):
+        P.leapfrog(xd, vd, acc, 0.5 * dt if k == 1 else dt, dt)
+        acc, _ = s.solve(xd, md, hd)
+    P.leapfrog(xd, vd, acc, 0.5 * dt, 0.0)
+    assert np.array_equal(xd.cpu().numpy(), finals[big.rid])
+
+
 def test_context_reuse_small_then_large(torch, P):
     """A context that solved a small system first sizes its list pools for a
     much larger one (the walk retries with grown pools)."""
