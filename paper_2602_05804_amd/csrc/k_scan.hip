@@ -1,7 +1,9 @@
 // k_scan.hip -- exclusive prefix sums (u32, u64) used to size and place the
 // tree's nodes, the radix-sort digits and the per-leaf interaction lists.
-// Three passes: tile totals, scan of the totals by one block, tile scan with
-// the tile's offset.  Deterministic (integer arithmetic, fixed order).
+// Two passes: tile totals, then the tile scan, each block first adding up the
+// totals of the tiles before its own (a few hundred at most for the sizes
+// here, so this costs less than a launch of its own).  Deterministic (integer
+// arithmetic, fixed order).
 #include "sfmm_internal.h"
 
 namespace sfmm {
@@ -41,25 +43,15 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const TI* in, int6
   if (threadIdx.x == 0) tmp[blockIdx.x] = tot;
 }
 
-template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(T* tmp, int64_t nb, T* total) {
-  __shared__ T sh[SCAN_THREADS];
-  T carry = 0;
-  for (int64_t base = 0; base < nb; base += SCAN_THREADS) {
-    int64_t i = base + threadIdx.x;
-    T v = i < nb ? tmp[i] : T(0);
-    T tot;
-    T ex = block_exclusive<T>(v, sh, &tot);
-    if (i < nb) tmp[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) *total = carry;
-}
-
 template <typename TI, typename T>
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const TI* in, T* out, int64_t n,
-                                                            const T* tmp) {
+                                                            const T* tmp, T* total) {
   __shared__ T sh[SCAN_THREADS];
+  // the totals of the tiles before this one, in a fixed order
+  T pre = 0;
+  for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += SCAN_THREADS) pre += tmp[i];
+  T prefix;
+  block_exclusive<T>(pre, sh, &prefix);
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   T v[SCAN_ITEMS];
   T s = 0;
@@ -69,12 +61,13 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const TI* in, T* out
     s += v[k];
   }
   T tot;
-  T run = block_exclusive<T>(s, sh, &tot) + tmp[blockIdx.x];
+  T run = block_exclusive<T>(s, sh, &tot) + prefix;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = prefix + tot;
 }
 
 template <typename T>
@@ -90,8 +83,7 @@ void scan_impl(const TI* in, T* out, int64_t n, T* total, T* tmp, hipStream_t s)
   }
   int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   k_scan_reduce<TI, T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, n, tmp);
-  k_scan_top<T><<<1, SCAN_THREADS, 0, s>>>(tmp, nb, total);
-  k_scan_down<TI, T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp);
+  k_scan_down<TI, T><<<(unsigned)nb, SCAN_THREADS, 0, s>>>(in, out, n, tmp, total);
 }
 
 }  // namespace

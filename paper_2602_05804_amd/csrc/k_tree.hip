@@ -447,21 +447,19 @@ __global__ void k_leaf_depth(int nleaves, const int32_t* __restrict__ leaf_node,
   for (int p = ni.lo; p < ni.lo + ni.cnt; ++p) p_leaf[p] = l;
 }
 
-// ---- geometry, moments (bottom-up, one launch per depth) ------------------
+// ---- geometry, moments (bottom-up, one level after the other) --------------
 // A leaf sums its particles in sorted order; an internal node combines its
-// two children (children first: the deepest level is launched first).
+// two children (children first: the deepest level comes first).
 template <int P>
-__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
-                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
-                             const double* __restrict__ ys, const double* __restrict__ zs,
-                             const double* __restrict__ ms, const double* __restrict__ hs,
-                             double* __restrict__ rec) {
+__device__ __forceinline__ void geom_node(int v, const NodeInfo* __restrict__ info,
+                                          const double* __restrict__ xs,
+                                          const double* __restrict__ ys,
+                                          const double* __restrict__ zs,
+                                          const double* __restrict__ ms,
+                                          const double* __restrict__ hs, double* rec) {
   using E = Exp<P>;
   constexpr int NQ = E::NQ;
   constexpr int RS = rec_stride(P);
-  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= end) return;
-  const int v = level_nodes[idx];
   const NodeInfo ni = info[v];
   double* r = rec + (int64_t)v * RS;
   double Q[NQ];
@@ -511,6 +509,36 @@ __global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t b
   }
 #pragma unroll
   for (int k = 0; k < NQ; ++k) r[8 + k] = Q[k];
+}
+
+// one level, a thread per node
+template <int P>
+__global__ void k_geom_level(const int32_t* __restrict__ level_nodes, uint32_t beg, uint32_t end,
+                             const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+                             const double* __restrict__ ys, const double* __restrict__ zs,
+                             const double* __restrict__ ms, const double* __restrict__ hs,
+                             double* __restrict__ rec) {
+  const uint32_t idx = beg + blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= end) return;
+  geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
+}
+
+// a run of small levels, deepest first, in one block: a barrier between
+// levels makes the children's records (written by this block) visible
+constexpr int GEOM_RUN_THREADS = 512;
+constexpr uint32_t GEOM_RUN_MAX = 1024;  // nodes of a level that a run takes
+template <int P>
+__global__ __launch_bounds__(GEOM_RUN_THREADS) void k_geom_run(
+    const int32_t* __restrict__ level_nodes, const uint32_t* __restrict__ level_off, int kdeep,
+    int ktop, const NodeInfo* __restrict__ info, const double* __restrict__ xs,
+    const double* __restrict__ ys, const double* __restrict__ zs, const double* __restrict__ ms,
+    const double* __restrict__ hs, double* rec) {
+  for (int k = kdeep; k >= ktop; --k) {
+    const uint32_t beg = level_off[k], end = level_off[k + 1];
+    for (uint32_t idx = beg + threadIdx.x; idx < end; idx += GEOM_RUN_THREADS)
+      geom_node<P>(level_nodes[idx], info, xs, ys, zs, ms, hs, rec);
+    __syncthreads();
+  }
 }
 
 __global__ void k_extent_count(int nn, const NodeInfo* __restrict__ info,
@@ -677,21 +705,46 @@ void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* in
                                                         leaf_depth, p_leaf, maxdepth);
 }
 
-void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
-                     const int32_t* level_nodes, const NodeInfo* info, const double* xs,
-                     const double* ys, const double* zs, const double* ms, const double* hs,
-                     double* rec, hipStream_t s) {
-  for (int k = maxdepth; k >= 0; --k) {
-    const uint32_t beg = level_off_host[k], end = level_off_host[k + 1];
-    if (end <= beg) continue;
-    const unsigned nb = blocks_for(end - beg, 128);
-    switch (order) {
-      case 0: k_geom_level<0><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 1: k_geom_level<1><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 2: k_geom_level<2><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 3: k_geom_level<3><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
-      case 4: k_geom_level<4><<<nb, 128, 0, s>>>(level_nodes, beg, end, info, xs, ys, zs, ms, hs, rec); break;
+template <int P>
+void geometry_order(int maxdepth, const uint32_t* off_h, const uint32_t* off_d,
+                    const int32_t* level_nodes, const NodeInfo* info, const double* xs,
+                    const double* ys, const double* zs, const double* ms, const double* hs,
+                    double* rec, hipStream_t s) {
+  // runs of consecutive levels of at most GEOM_RUN_MAX nodes go to one block
+  // (the top of the tree, and often its deepest levels), the others one
+  // launch each
+  int k = maxdepth;
+  while (k >= 0) {
+    const uint32_t size = off_h[k + 1] - off_h[k];
+    if (size <= GEOM_RUN_MAX) {
+      int top = k;
+      while (top - 1 >= 0 && off_h[top] - off_h[top - 1] <= GEOM_RUN_MAX) --top;
+      if (top < k) {
+        k_geom_run<P><<<1, GEOM_RUN_THREADS, 0, s>>>(level_nodes, off_d, k, top, info, xs, ys,
+                                                     zs, ms, hs, rec);
+        k = top - 1;
+        continue;
+      }
     }
+    if (size > 0)
+      k_geom_level<P><<<blocks_for(size, 128), 128, 0, s>>>(level_nodes, off_h[k], off_h[k + 1],
+                                                             info, xs, ys, zs, ms, hs, rec);
+    --k;
+  }
+}
+
+void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
+                     const uint32_t* level_off_dev, const int32_t* level_nodes,
+                     const NodeInfo* info, const double* xs, const double* ys, const double* zs,
+                     const double* ms, const double* hs, double* rec, hipStream_t s) {
+  switch (order) {
+#define GEOM_CASE(P)                                                                         \
+  case P:                                                                                    \
+    geometry_order<P>(maxdepth, level_off_host, level_off_dev, level_nodes, info, xs, ys, zs, \
+                      ms, hs, rec, s);                                                       \
+    break;
+    GEOM_CASE(0) GEOM_CASE(1) GEOM_CASE(2) GEOM_CASE(3) GEOM_CASE(4)
+#undef GEOM_CASE
   }
 }
 

@@ -48,6 +48,18 @@ enum SmallId { S_NKEPT = 0, S_NLEAVES, S_MAXDEPTH, S_NITEMS, S_M2LTOT, S_P2PTOT,
 
 }  // namespace
 
+// The small device values each synchronisation of a solve reads back, in one
+// pinned host block per context: the copies are then plain asynchronous
+// transfers instead of staged copies into pageable memory.
+struct Readback {
+  uint64_t small[S_COUNT];
+  int status[4];
+  uint32_t level_off[kMaxDepthCap + 2];
+  uint32_t level_int[kMaxDepthCap + 2];
+  uint64_t walk_tot[4];
+  uint32_t items;
+};
+
 struct sfmm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -82,6 +94,7 @@ struct sfmm_ctx {
   uint64_t pool_init = 0;  // first pool size in entries (SFMM_POOL_INIT; 0 = estimate)
   int walk_attempts = 0;   // walks made by the last solve (pools grown in between)
   sfmm_stats stats{};
+  Readback* rb = nullptr;  // pinned host block for the read-backs
 };
 
 namespace {
@@ -89,6 +102,20 @@ namespace {
 int fail(sfmm_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
+}
+
+// the context's pinned read-back block (allocated on first use; null when
+// the allocation fails)
+Readback* readback(sfmm_ctx* ctx) {
+  if (!ctx->rb) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(Readback), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ctx->rb = static_cast<Readback*>(p);
+  }
+  return ctx->rb;
 }
 
 #define HIPCHK(call)                                                                  \
@@ -275,12 +302,13 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
     launch_leaf_fill(n, P<uint32_t>(ctx, B_LFLAG), lscan, P<int32_t>(ctx, B_LAT), leaf_node, s);
   }
   // ---- sizes to the host (one synchronisation)
-  uint64_t hsmall[S_COUNT];
-  int hstatus[4];
-  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+  Readback* hb = readback(ctx);
+  if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
+  const uint64_t* hsmall = hb->small;
+  HIPCHK(hipMemcpyAsync(hb->small, small, sizeof(hb->small), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb->status, status, sizeof(hb->status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (hstatus[0] & ST_NONFINITE)
+  if (hb->status[0] & ST_NONFINITE)
     return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
   if (n <= leaf_size && nsys <= 1) {
     ctx->nn = 1;
@@ -329,18 +357,18 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
              P<uint32_t>(ctx, B_SCANTMP), s);
     HIPCHK(hipMemsetAsync(P<uint64_t>(ctx, B_L2BITS), 0, sizeof(uint64_t) * nn, s));
   }
-  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-  ctx->level_off.resize(kMaxDepthCap + 2);
-  ctx->level_int.resize(kMaxDepthCap + 2);
-  HIPCHK(hipMemcpyAsync(ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
-                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ctx->level_int.data(), P<uint32_t>(ctx, B_LEVINT),
-                        sizeof(uint32_t) * (kMaxDepthCap + 2), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb->small, small, sizeof(hb->small), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb->level_off, P<uint32_t>(ctx, B_LEVOFF), sizeof(hb->level_off),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb->level_int, P<uint32_t>(ctx, B_LEVINT), sizeof(hb->level_int),
+                        hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  ctx->level_off.assign(hb->level_off, hb->level_off + kMaxDepthCap + 2);
+  ctx->level_int.assign(hb->level_int, hb->level_int + kMaxDepthCap + 2);
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
   if (ctx->maxdepth > kMaxDepthCap) return fail(ctx, SFMM_EUNSUPPORTED, "tree deeper than 127");
   // ---- geometry and moments, level by level from the deepest
-  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(),
+  launch_geometry(order, ctx->maxdepth, ctx->level_off.data(), P<uint32_t>(ctx, B_LEVOFF),
                   reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES)), info,
                   P<double>(ctx, B_XS), P<double>(ctx, B_YS), P<double>(ctx, B_ZS),
                   P<double>(ctx, B_MS), P<double>(ctx, B_HS), P<double>(ctx, B_REC), s);
@@ -400,12 +428,13 @@ int walk_per_leaf(sfmm_ctx* ctx, double theta) {
   HIPCHK(hipMemcpyAsync(w.p2p_cnt + nl, small + S_P2PTOT, sizeof(uint64_t),
                         hipMemcpyDeviceToDevice, s));
   phase_mark(ctx, 1, 1);
-  uint64_t hsmall[S_COUNT];
-  int hstatus[4];
-  HIPCHK(hipMemcpyAsync(hsmall, small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+  Readback* hb = readback(ctx);
+  if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
+  const uint64_t* hsmall = hb->small;
+  HIPCHK(hipMemcpyAsync(hb->small, small, sizeof(hb->small), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hb->status, status, sizeof(hb->status), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  if (hstatus[0] & (ST_DEPTH | ST_OVERFLOW))
+  if (hb->status[0] & (ST_DEPTH | ST_OVERFLOW))
     return fail(ctx, SFMM_EDEVICE, "walk stack overflow (tree depth)");
   ctx->m2l_total = hsmall[S_M2LTOT];
   ctx->p2p_total = hsmall[S_P2PTOT];
@@ -527,15 +556,18 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     // no consumer reads a list unless it lies in the part of its pool this
     // walk wrote (and, when checking, holds only node ids)
     launch_check_lists(a, nn, ctx->check_pools, s);
-    uint64_t htot[4];
-    int hstatus[4];
-    uint32_t hitems = 0;
-    HIPCHK(hipMemcpyAsync(htot, tot, sizeof(htot), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hstatus, status, sizeof(hstatus), hipMemcpyDeviceToHost, s));
+    Readback* hb = readback(ctx);
+    if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
+    const uint64_t* htot = hb->walk_tot;
+    const int* hstatus = hb->status;
+    hb->items = 0;
+    HIPCHK(hipMemcpyAsync(hb->walk_tot, tot, sizeof(hb->walk_tot), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hb->status, status, sizeof(hb->status), hipMemcpyDeviceToHost, s));
     if (nl > 0)
-      HIPCHK(hipMemcpyAsync(&hitems, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hb->items, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            s));
     HIPCHK(hipStreamSynchronize(s));
-    ctx->items_from_walk = hitems;
+    ctx->items_from_walk = hb->items;
     // 64-bit totals: internal regions, then the leaves' M2L lists; the P2P pool
     const uint64_t m2l_used = htot[0] + htot[3];
     const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
@@ -721,10 +753,11 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
       launch_p2p_items_count(level, a, P<uint32_t>(ctx, B_SRCTOT), P<uint32_t>(ctx, B_ITEMCNT), s);
       scan_u32(P<uint32_t>(ctx, B_ITEMCNT), item_off, nl, item_off + nl, P<uint32_t>(ctx, B_SCANTMP),
                s);
-      uint32_t htot = 0;
-      HIPCHK(hipMemcpyAsync(&htot, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      Readback* hb = readback(ctx);
+      if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
+      HIPCHK(hipMemcpyAsync(&hb->items, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      items = htot;
+      items = hb->items;
     }
     const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
     struct { int id; size_t bytes; } need5[] = {
@@ -891,6 +924,7 @@ int sfmm_destroy(sfmm_ctx* ctx) {
   if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
   for (auto& b : ctx->buf)
     if (b.p) (void)hipFree(b.p);
+  if (ctx->rb) (void)hipHostFree(ctx->rb);
   delete ctx;
   return SFMM_OK;
 }

@@ -135,11 +135,12 @@ void launch_single_leaf(int n, NodeInfo* info, int32_t* leaf_node, hipStream_t s
 void launch_leaf_depth(int nleaves, const int32_t* leaf_node, const NodeInfo* info,
                        const int32_t* node_depth, int32_t* leaf_depth, int32_t* p_leaf,
                        int* maxdepth, hipStream_t s);
-// geometry and moments, deepest level first (level_off_host: host copy)
+// geometry and moments, deepest level first (level offsets: a host copy for
+// the launch sizes and the device array for runs of small levels)
 void launch_geometry(int order, int maxdepth, const uint32_t* level_off_host,
-                     const int32_t* level_nodes, const NodeInfo* info, const double* xs,
-                     const double* ys, const double* zs, const double* ms, const double* hs,
-                     double* rec, hipStream_t s);
+                     const uint32_t* level_off_dev, const int32_t* level_nodes,
+                     const NodeInfo* info, const double* xs, const double* ys, const double* zs,
+                     const double* ms, const double* hs, double* rec, hipStream_t s);
 void launch_extent_count(int nn, const NodeInfo* info, uint32_t* chunks, hipStream_t s);
 void launch_extent(int order, int nn, int nitems, const NodeInfo* info,
                    const uint32_t* chunk_off, uint32_t* item_node, const double* xs,
