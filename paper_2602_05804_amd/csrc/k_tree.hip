@@ -710,16 +710,17 @@ void geometry_order(int maxdepth, const uint32_t* off_h, const uint32_t* off_d,
                     const int32_t* level_nodes, const NodeInfo* info, const double* xs,
                     const double* ys, const double* zs, const double* ms, const double* hs,
                     double* rec, hipStream_t s) {
-  // runs of consecutive levels of at most GEOM_RUN_MAX nodes go to one block
-  // (the top of the tree, and often its deepest levels), the others one
-  // launch each
+  // runs of four or more consecutive levels of at most GEOM_RUN_MAX nodes
+  // (the top of the tree) go to one block, the others one launch each
   int k = maxdepth;
   while (k >= 0) {
     const uint32_t size = off_h[k + 1] - off_h[k];
     if (size <= GEOM_RUN_MAX) {
       int top = k;
       while (top - 1 >= 0 && off_h[top] - off_h[top - 1] <= GEOM_RUN_MAX) --top;
-      if (top < k) {
+      // (a run pays off from four levels on: one level in the block takes
+      // about two thirds of a launch of its own)
+      if (k - top >= 3) {
         k_geom_run<P><<<1, GEOM_RUN_THREADS, 0, s>>>(level_nodes, off_d, k, top, info, xs, ys,
                                                      zs, ms, hs, rec);
         k = top - 1;

@@ -1,6 +1,7 @@
 // sfmm_api.hip -- the C ABI of libsfmm.so (declared in include/sfmm.h):
 // argument checks, the context's workspace and the order of the phases.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -102,6 +103,20 @@ namespace {
 int fail(sfmm_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
+}
+
+// Wait for the work queued on s.  The waits inside a solve are short (the
+// read-backs of list and tree sizes), and a blocking wait's wake-up costs
+// tens of microseconds, during which the queue is empty and the GPU idles:
+// poll for up to 2 ms, then block.
+hipError_t wait_stream(hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+      return hipStreamSynchronize(s);
+  }
 }
 
 // the context's pinned read-back block (allocated on first use; null when
@@ -307,7 +322,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
   const uint64_t* hsmall = hb->small;
   HIPCHK(hipMemcpyAsync(hb->small, small, sizeof(hb->small), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hb->status, status, sizeof(hb->status), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(wait_stream(s));
   if (hb->status[0] & ST_NONFINITE)
     return fail(ctx, SFMM_ENONFINITE, "non-finite position or non-positive m/h");
   if (n <= leaf_size && nsys <= 1) {
@@ -362,7 +377,7 @@ int do_build(sfmm_ctx* ctx, int64_t n64, const double* x, const double* m, const
                         hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hb->level_int, P<uint32_t>(ctx, B_LEVINT), sizeof(hb->level_int),
                         hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(wait_stream(s));
   ctx->level_off.assign(hb->level_off, hb->level_off + kMaxDepthCap + 2);
   ctx->level_int.assign(hb->level_int, hb->level_int + kMaxDepthCap + 2);
   ctx->maxdepth = (int)(hsmall[S_MAXDEPTH] & 0x7fffffff);
@@ -433,7 +448,7 @@ int walk_per_leaf(sfmm_ctx* ctx, double theta) {
   const uint64_t* hsmall = hb->small;
   HIPCHK(hipMemcpyAsync(hb->small, small, sizeof(hb->small), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hb->status, status, sizeof(hb->status), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(wait_stream(s));
   if (hb->status[0] & (ST_DEPTH | ST_OVERFLOW))
     return fail(ctx, SFMM_EDEVICE, "walk stack overflow (tree depth)");
   ctx->m2l_total = hsmall[S_M2LTOT];
@@ -566,7 +581,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     if (nl > 0)
       HIPCHK(hipMemcpyAsync(&hb->items, a.item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost,
                             s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(wait_stream(s));
     ctx->items_from_walk = hb->items;
     // 64-bit totals: internal regions, then the leaves' M2L lists; the P2P pool
     const uint64_t m2l_used = htot[0] + htot[3];
@@ -756,7 +771,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
       Readback* hb = readback(ctx);
       if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
       HIPCHK(hipMemcpyAsync(&hb->items, item_off + nl, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
+      HIPCHK(wait_stream(s));
       items = hb->items;
     }
     const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
@@ -817,7 +832,7 @@ int direct_run(sfmm_ctx* ctx, int64_t n, const double* x, const double* m, const
   HIPCHK(hipGetLastError());
   int hs = 0;
   HIPCHK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(wait_stream(s));
   if (hs & ST_OVERFLOW) return fail(ctx, SFMM_EINVAL, "target index out of range");
   return SFMM_OK;
 }
