@@ -145,7 +145,16 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--order", type=int, default=3)
-    ap.add_argument("--leaf-size", type=int, default=10)
+    ap.add_argument("--leaf-size", type=int, default=16,
+                    help="leaf size of the headline solve (16: the autotuner's pick for the 1e6 "
+                         "polytrope, 5.8 ms per solve against 6.1 at 10)")
+    ap.add_argument("--near-kernel", type=int, default=13,
+                    help="P2P kernel shape of the headline solve (13, targets in lanes: the "
+                         "autotuner's pick at leaf size 16)")
+    ap.add_argument("--fp32c-leaf-size", type=int, default=10,
+                    help="leaf size of the FP32C block")
+    ap.add_argument("--serve-leaf-size", type=int, default=10,
+                    help="leaf size of the serving runs without tuned settings")
     ap.add_argument("--walk", choices=["level", "leaf"], default="level",
                     help="level: each (ancestor, source) test once per level; "
                          "leaf: Algorithm 1 with one stack walk per leaf")
@@ -220,7 +229,8 @@ def main():
         x, m, h = workloads.plummer(args.n, seed=1)
         wl = f"Plummer sphere a=1 M=1, N={args.n}, seed 1"
     xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
-    cfg = {"leaf_size": args.leaf_size, "walk": args.walk, "far": args.far}
+    cfg = {"leaf_size": args.leaf_size, "walk": args.walk, "far": args.far,
+           "near_kernel": args.near_kernel}
     if args.autotune:
         from paper_2602_05804_amd import autotune
 
@@ -453,7 +463,7 @@ def fp32c_block(args):
     log(f"fp32c: generating binary polytrope 2 x {n // 2}")
     x, m, h, _ = workloads.binary_polytrope(n // 2)
     xd, md, hd = (torch.from_numpy(a).cuda() for a in (x, m, h))
-    solver = sfmm.Solver(leaf_size=args.leaf_size)
+    solver = sfmm.Solver(leaf_size=args.fp32c_leaf_size)
     acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
     pot = torch.empty((n,), dtype=torch.float64, device="cuda")
     for _ in range(2):
@@ -475,7 +485,7 @@ def fp32c_block(args):
     a_gpu, p_gpu = acc.cpu().numpy(), pot.cpu().numpy()
     solver.close()
     log("fp32c: oracle on 1500 sampled targets")
-    t = oracle.Tree(x, m, h, leaf_size=args.leaf_size, order=args.order)
+    t = oracle.Tree(x, m, h, leaf_size=args.fp32c_leaf_size, order=args.order)
     tg = np.random.default_rng(2).choice(n, 1500, replace=False)
     oa, op, _ = t.solve(args.theta, targets=tg)
     nb = np.linalg.norm(oa, axis=1)
@@ -550,7 +560,7 @@ def serving(args):
         runs.append(("fp64", None, 200.0, True))
     for prec, small_budget_n, rate, use_tuned in runs:
         ex = serve.GpuExecutor(precision=prec, theta=args.theta, order=args.order,
-                               leaf_size=args.leaf_size, far=args.far,
+                               leaf_size=args.serve_leaf_size, far=args.far,
                                pack_particles=args.serve_pack,
                                tuned=tuned if use_tuned else None)
         free, _ = torch.cuda.mem_get_info()

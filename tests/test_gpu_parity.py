@@ -385,18 +385,22 @@ def test_deterministic_and_stream(torch, P):
     assert torch.equal(a1, a2) and torch.equal(p1, p2)
 
 
-def test_full_size_sampled(torch, P, orc):
+@pytest.mark.parametrize("leaf_size,near_kernel,far", [(10, 0, "leaf"), (16, 13, "shared")])
+def test_full_size_sampled(torch, P, orc, leaf_size, near_kernel, far):
     """1e6-particle n=1.5 polytrope (the benchmark workload), FP64, p=3,
     theta=0.5: sampled leaves against the oracle, all particles against the
-    momentum bound."""
-    print("case: full-size polytrope N=1e6 sampled", flush=True)
+    momentum bound; also in the benchmark's setting (leaf size 16, the tile
+    P2P kernel, shared far field)."""
+    print(f"case: full-size polytrope N=1e6 sampled, leaf {leaf_size} shape {near_kernel} {far}",
+          flush=True)
     x, m, h = workloads.polytrope(1_000_000, seed=2)
-    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far="leaf")
+    acc, pot, s = gpu_solve(torch, P, x, m, h, theta=0.5, far=far, leaf_size=leaf_size,
+                            near_kernel=near_kernel)
     st = s.stats()
     assert np.linalg.norm(st["momentum"]) / st["momentum_abs"] <= 1e-14
     rng = np.random.default_rng(0)
     tg = rng.choice(len(m), 256, replace=False)
-    t = orc.Tree(x, m, h, leaf_size=10, order=3)
+    t = orc.Tree(x, m, h, leaf_size=leaf_size, order=3)
     oa, op, _ = t.solve(0.5, targets=tg)
     nb = np.linalg.norm(oa, axis=1)
     err = np.linalg.norm(acc[tg] - oa, axis=1) / nb
