@@ -31,6 +31,8 @@
 // Per-lane sums are reduced over the stripes in stripe order at the end of
 // the item (a fixed order: the results do not depend on timing), and the
 // item's partial sums are added per target by k_p2p_reduce in item order.
+#include <type_traits>
+
 #include "sfmm_internal.h"
 #include "softening.h"
 
@@ -56,12 +58,19 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
+// a batch source's softening length squared and particle index (16 bytes,
+// like the other batch arrays, so that one address serves all three)
+struct SrcHJ {
+  double h2;
+  int j;
+  int pad;
+};
+
 template <int LS>
 struct TileLds {
   uint32_t sidx[kWin];           // flattened source particle indices of the window
   double2 b_xy[64], b_zm[64];    // the batch: x, y | z, m
-  double b_h[64];                //            h
-  int b_j[64];                   //            particle index
+  SrcHJ b_hj[64];                //            h^2, particle index
   int queue[LS][kQueue];         // per target: ring of sources whose pair lies inside a kernel
 };
 
@@ -81,6 +90,9 @@ __global__ __launch_bounds__(64) void k_p2p_tile(NearArgs a) {
   const bool lane_ok = s < ns;
   // this lane's target (lanes past the stripes repeat target 0 and add nothing)
   const int tq = lane_ok ? t : 0;
+  // the stripe this lane reads a batch source for (lanes past the stripes
+  // read stripe 0's and keep sums nobody reads: full steps need no masks)
+  const int sq = lane_ok ? s : 0;
   const int it = ti.lo + tq;
   const double xi = a.xs[it], yi = a.ys[it], zi = a.zs[it];
   const double hi = a.hs[it], hiinv = a.his[it];
@@ -126,12 +138,13 @@ __global__ __launch_bounds__(64) void k_p2p_tile(NearArgs a) {
   };
 
   // one far step over batch sources b0 .. b0 + navail - 1 (navail <= ns):
-  // every pair beyond both kernels
-  auto far_step = [&](int b0, int navail) {
-    const bool v = lane_ok && s < navail;
-    const int q = b0 + (v ? s : 0);
+  // every pair beyond both kernels; a full step (navail == ns) needs no mask
+  auto far_step = [&](int b0, int navail, auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
+    const bool v = FULL || (lane_ok && s < navail);
+    const int q = b0 + (FULL ? sq : (v ? s : 0));
     const double2 xy = sh.b_xy[q], zm = sh.b_zm[q];
-    const double w = v ? zm.y : 0.0;
+    const double w = FULL ? zm.y : (v ? zm.y : 0.0);
     const double dx = xi - xy.x, dy = yi - xy.y, dz = zi - zm.x;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
     const double rinv = rsqrt_refined(r2);  // r2 >= 4 h^2 > 0 for a far source
@@ -143,19 +156,26 @@ __global__ __launch_bounds__(64) void k_p2p_tile(NearArgs a) {
     ph += mr;
   };
 
-  // one near step: pairs inside a kernel go to their target's queue
-  auto near_step = [&](int b0, int navail) {
-    const bool v = lane_ok && s < navail;
-    const int q = b0 + (v ? s : 0);
+  // one near step: pairs inside a kernel go to their target's queue; in a
+  // full step the self pair needs no mask either (r^2 = 0 is inside a
+  // kernel, so its 1/r is 0)
+  auto near_step = [&](int b0, int navail, auto fullc) {
+    constexpr bool FULL = decltype(fullc)::value;
+    const bool v = FULL ? lane_ok : (lane_ok && s < navail);
+    const int q = b0 + (FULL ? sq : (v ? s : 0));
     const double2 xy = sh.b_xy[q], zm = sh.b_zm[q];
-    const double hj = sh.b_h[q];
-    const int j = sh.b_j[q];
+    const SrcHJ hj = sh.b_hj[q];
+    const int j = hj.j;
     const double dx = xi - xy.x, dy = yi - xy.y, dz = zi - zm.x;
     const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const bool inside = r2 < h4i || r2 < 4.0 * hj * hj;
+    // r^2 < 4 h_i^2 or r^2 < 4 h_j^2, the second as r^2 / 4 < h_j^2 (scaling
+    // by 4 is exact, so the decision is the same; with two different left
+    // sides the compiler keeps two compares instead of a max that would
+    // canonicalise its operands)
+    const bool inside = r2 < h4i || r2 * 0.25 < hj.h2;
     const bool use = v && j != it;
     const double rinv = inside ? 0.0 : rsqrt_refined(r2);
-    const double w = use ? zm.y : 0.0;
+    const double w = FULL ? zm.y : (use ? zm.y : 0.0);
     const double mr = w * rinv;
     const double mg = mr * (rinv * rinv);
     fx = fma(mg, dx, fx);
@@ -259,16 +279,24 @@ __global__ __launch_bounds__(64) void k_p2p_tile(NearArgs a) {
           const int q = near ? (int)popc64(bn & below) : nn + (int)popc64(bf & below);
           sh.b_xy[q] = xy;
           sh.b_zm[q] = zm;
-          sh.b_h[q] = hj;
-          sh.b_j[q] = j;
+          sh.b_hj[q] = SrcHJ{hj * hj, j, 0};
         }
         if (u0 + 64 < wn) load_src(u0 + 64, j, xy, zm, hj);
         __syncthreads();
-        for (int b0 = 0; b0 < nn; b0 += ns) {
-          near_step(b0, min(ns, nn - b0));
-          while (__any(qlen > qcap)) soft_pass();
+        // (before a near step every queue holds at most qcap = kQueue - ns,
+        // the step adds at most ns to each, and a soft pass takes ns from
+        // every queue above qcap (qcap >= 32 >= ns): one pass restores it)
+        int b0 = 0;
+        for (; b0 + ns <= nn; b0 += ns) {
+          near_step(b0, ns, std::true_type{});
+          if (__any(qlen > qcap)) soft_pass();
         }
-        for (int b0 = nn; b0 < nb; b0 += ns) far_step(b0, min(ns, nb - b0));
+        if (b0 < nn) {
+          near_step(b0, nn - b0, std::false_type{});
+          if (__any(qlen > qcap)) soft_pass();
+        }
+        for (b0 = nn; b0 + ns <= nb; b0 += ns) far_step(b0, ns, std::true_type{});
+        if (b0 < nb) far_step(b0, nb - b0, std::false_type{});
         __syncthreads();  // the batch may be written next
       }
     }
