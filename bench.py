@@ -68,7 +68,7 @@ def near_shape(precision, leaf_size, variant):
     sfmm_config.near_kernel documents)."""
     if precision == "fp32c":
         return "near_leaf" if variant == 6 else "near"
-    if leaf_size > 16 or variant == 1:
+    if leaf_size > 32 or variant == 1:
         return "near_thread"
     if variant == 13:
         return "near_tile"

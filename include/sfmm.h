@@ -118,16 +118,18 @@ typedef struct {
  *   0  a wave per work item, the targets in scalar registers, wave-uniform
  *      loop control, the pairs inside a kernel queued per target and
  *      evaluated 64 at a time; passes of 5 targets at four waves per SIMD
- *      (leaf_size <= 10) or of 6 at four (leaf_size <= 16);
+ *      (leaf_size <= 10), of 6 at four (leaf_size <= 16) or of 8 at three
+ *      (leaf_size <= 32);
  *   13 the targets of a leaf in lanes, in stripes over sources staged through
  *      LDS, source leaves split into near and far by the target leaf's sphere
- *      (leaf_size <= 16; faster on the polytrope, slower on a Plummer halo);
+ *      (leaf_size <= 32; faster on the polytrope, slower on a Plummer halo);
  *   6  a wave per work item with the targets in LDS, passes of 5 (8 for
  *      leaf_size > 10), the queue shared by the pass; in SFMM_FP32C the same
  *      layout with the softened branch taken in the pass;
  *   7  SFMM_FP32C only: shape 0 with each sum kept as a TwoSum pair of FP32
  *      words instead of an FP64 accumulator (in FP64, shape 0);
- *   1  one thread per particle (also every leaf_size > 16).
+ *   1  one thread per particle (also every leaf_size > 32; SFMM_FP32C needs
+ *      leaf_size <= 16).
  * The far field has one shape per mode: 8 lanes per node (SFMM_FAR_SHARED,
  * two waves per SIMD in FP64, one in FP32C), 4 lanes per leaf (SFMM_FAR_LEAF). */
 

@@ -23,7 +23,7 @@ import os
 import time
 from typing import Dict, Optional
 
-LEAF_SIZES = (6, 8, 10, 12, 16)
+LEAF_SIZES = (6, 8, 10, 12, 16, 24, 32)
 # the P2P shapes of sfmm_config.near_kernel worth a try per precision (the
 # far field has one shape per mode)
 NEAR_KERNELS = {"fp64": (0, 13, 6), "fp32c": (0, 6, 7)}

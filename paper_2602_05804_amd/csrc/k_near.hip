@@ -696,20 +696,24 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   record_mark(km.begin, s);
   if (variant == 1) leaf_size = 1 << 20;  // particle per thread
   // variant (the shapes are listed with sfmm_config.near_kernel)
-  if (leaf_size <= 16 && variant == 13) {
-    launch_p2p_tile(node_lists, leaf_size <= 10 ? 10 : 16, a, items, s);
+  if (leaf_size <= 32 && variant == 13) {
+    launch_p2p_tile(node_lists, p2p_leaf_slots(leaf_size), a, items, s);
     record_mark(km.end, s);
-    launch_p2p_reduce(a, leaf_size <= 10 ? 10 : 16, s);
+    launch_p2p_reduce(a, p2p_leaf_slots(leaf_size), s);
     return;
   }
   // leaf_size <= 10: five targets per pass at four waves per SIMD; <= 16:
-  // six at four (the shapes that won on the polytrope and Plummer workloads)
+  // six at four (the shapes that won on the polytrope and Plummer workloads);
+  // <= 32: eight at three
   if (leaf_size <= 10) {
     if (variant == 6) NEAR_LAUNCH(10, 5);
     else WAVE_LAUNCH(10, 5, 4);
   } else if (leaf_size <= 16) {
     if (variant == 6) NEAR_LAUNCH(16, 8);
     else WAVE_LAUNCH(16, 6, 4);
+  } else if (leaf_size <= 32) {
+    if (variant == 6) NEAR_LAUNCH(32, 8);
+    else WAVE_LAUNCH(32, 8, 3);
   } else {
     if (node_lists) k_near<true><<<(a.n + 255) / 256, 256, 0, s>>>(a);
     else k_near<false><<<(a.n + 255) / 256, 256, 0, s>>>(a);

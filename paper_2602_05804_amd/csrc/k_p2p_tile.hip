@@ -330,9 +330,12 @@ void launch_p2p_tile(bool node_lists, int ls, const NearArgs& a, int64_t items, 
   if (ls == 10) {
     if (node_lists) k_p2p_tile<10, true><<<nbl, 64, 0, s>>>(a);
     else k_p2p_tile<10, false><<<nbl, 64, 0, s>>>(a);
-  } else {
+  } else if (ls == 16) {
     if (node_lists) k_p2p_tile<16, true><<<nbl, 64, 0, s>>>(a);
     else k_p2p_tile<16, false><<<nbl, 64, 0, s>>>(a);
+  } else {
+    if (node_lists) k_p2p_tile<32, true><<<nbl, 64, 0, s>>>(a);
+    else k_p2p_tile<32, false><<<nbl, 64, 0, s>>>(a);
   }
 }
 

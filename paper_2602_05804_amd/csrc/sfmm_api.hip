@@ -755,7 +755,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   // P2P work items: runs of at most kP2PItem flattened source particles of
   // one leaf; their number is read back to size the partial sums
   int64_t items = 0;
-  if (ctx->cfg.leaf_size <= 16) {
+  if (ctx->cfg.leaf_size <= 32) {
     // P2P work items: the level walk has counted them (and read their total
     // back with its own totals); the per-leaf walk's lists are counted here
     if ((rc = ensure_item_buffers(ctx))) return rc;
@@ -774,7 +774,7 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
       HIPCHK(wait_stream(s));
       items = hb->items;
     }
-    const int ls = ctx->cfg.leaf_size <= 10 ? 10 : 16;
+    const int ls = p2p_leaf_slots(ctx->cfg.leaf_size);
     struct { int id; size_t bytes; } need5[] = {
         {B_ITEMLEAF, sizeof(int32_t) * (size_t)items}, {B_ITEMK, sizeof(uint32_t) * (size_t)items},
         {B_ITEME0, sizeof(uint32_t) * (size_t)items}, {B_ITEMC0, sizeof(uint32_t) * (size_t)items},

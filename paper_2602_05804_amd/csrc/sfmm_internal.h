@@ -310,7 +310,7 @@ struct NearArgs {
   int include_self;
   double* acc;  // caller order [n][3]
   double* pot;  // caller order [n]
-  // work items (leaf_size <= 16): a leaf's P2P sources, flattened over its
+  // work items (leaf_size <= 32): a leaf's P2P sources, flattened over its
   // list entries (leaves, or whole subtrees), are cut into runs of at most
   // kP2PItem source particles, one wave per run; each item writes partial
   // sums for the leaf's targets, which a second kernel adds in item order
@@ -333,7 +333,10 @@ void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* src_to
 // leaf's first (one wave per leaf)
 void launch_p2p_items_fill(bool node_lists, const NearArgs& a, int32_t* item_leaf,
                            uint32_t* item_k, uint32_t* item_e0, uint32_t* item_c0, hipStream_t s);
-// wave-per-item kernel for leaf_size <= 16 (then the reduction in item
+// target slots per P2P work item: the kernels are built for leaves of at most
+// 10, 16 and 32 particles
+inline int p2p_leaf_slots(int leaf_size) { return leaf_size <= 10 ? 10 : leaf_size <= 16 ? 16 : 32; }
+// wave-per-item kernel for leaf_size <= 32 (then the reduction in item
 // order), particle-per-thread otherwise; items: the bound on the item count
 // HIP events recorded on the stream around the main P2P kernel alone (null:
 // none), for the timing of that kernel

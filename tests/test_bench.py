@@ -39,11 +39,13 @@ def test_near_shape_names_the_launched_kernel():
     assert bench.near_shape("fp64", 10, 13) == "near_tile"
     assert bench.near_shape("fp64", 16, 0) == "near"
     assert bench.near_shape("fp64", 16, 6) == "near_leaf"
-    assert bench.near_shape("fp64", 24, 0) == "near_thread"
+    assert bench.near_shape("fp64", 24, 0) == "near"
+    assert bench.near_shape("fp64", 32, 13) == "near_tile"
+    assert bench.near_shape("fp64", 40, 0) == "near_thread"
     assert bench.near_shape("fp32c", 10, 0) == "near"
     assert bench.near_shape("fp32c", 10, 7) == "near"
     assert bench.near_shape("fp32c", 10, 6) == "near_leaf"
     for prec in ("fp64", "fp32c"):
-        for ls in (10, 16, 24):
+        for ls in (10, 16, 24, 40):
             for v in (0, 1, 6, 7, 13):
                 assert (prec, bench.near_shape(prec, ls, v)) in bench.KERNELS

@@ -673,7 +673,8 @@ def test_direct_sum_parity(torch, P, orc):
 
 
 @pytest.mark.parametrize("leaf_size,near_kernel",
-                         [(10, k) for k in (1, 6, 7, 13)] + [(16, k) for k in (0, 6, 13)])
+                         [(10, k) for k in (1, 6, 7, 13)] + [(16, k) for k in (0, 6, 13)]
+                         + [(24, k) for k in (0, 13)] + [(32, k) for k in (0, 6, 13)])
 def test_p2p_kernel_shapes(torch, P, orc, leaf_size, near_kernel):
     """Every P2P kernel shape gives the oracle's result (halo leaves with
     large softening lengths, coincident particles)."""
