@@ -67,6 +67,8 @@ def search(x, m, h, theta=0.5, order=3, precision="fp64", reps=5, log=None,
     time of every configuration tried.  `base` holds fixed Solver arguments
     (walk, far mode, ...); `leaf_sizes` = (k,) keeps the leaf size at k."""
     base = dict(base or {})
+    if precision == "fp32c":  # the FP32-compensated kernels take leaves of at most 16
+        leaf_sizes = tuple(k for k in leaf_sizes if k <= 16) or (10,)
     best = {**base, "leaf_size": 10 if 10 in leaf_sizes else leaf_sizes[0], "near_kernel": 0}
     if precision == "fp32c":
         best["fp64_top_depth"] = 8

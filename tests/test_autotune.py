@@ -29,11 +29,12 @@ def test_search_finds_separable_minimum(monkeypatch):
     assert res["config"] == {"leaf_size": 12, "near_kernel": 7, "fp64_top_depth": 12}
     assert res["seconds"] == 1.0
     # a coordinate search: one run per value per axis, not the full product
-    assert len(calls) == (1 + (len(autotune.LEAF_SIZES) - 1)
+    assert len(calls) == (1 + (len([k for k in autotune.LEAF_SIZES if k <= 16]) - 1)
                           + (len(autotune.NEAR_KERNELS["fp32c"]) - 1)
                           + (len(autotune.TOP_DEPTHS) - 1))
-    # every shape tried is one the library accepts
+    # every shape tried is one the library accepts, and FP32C leaves stay <= 16
     assert all(c["near_kernel"] in (0, 1, 6, 7, 13) for c in calls)
+    assert all(c["leaf_size"] <= 16 for c in calls)
 
 
 def test_cache_roundtrip(monkeypatch, tmp_path):
