@@ -151,6 +151,9 @@ def main():
     ap.add_argument("--near-kernel", type=int, default=13,
                     help="P2P kernel shape of the headline solve (13, targets in lanes: the "
                          "autotuner's pick at leaf size 16)")
+    ap.add_argument("--no-same-fp32c", dest="same_fp32c", action="store_false",
+                    help="skip the FP32C solve of the headline workload (same input and leaf "
+                         "size, its error measured over every particle by the CPU oracle)")
     ap.add_argument("--fp32c-leaf-size", type=int, default=10,
                     help="leaf size of the FP32C block")
     ap.add_argument("--serve-leaf-size", type=int, default=10,
@@ -347,8 +350,12 @@ def main():
                      precision=args.precision)
         torch.cuda.synchronize()
 
+    same32 = None
+    if args.precision == "fp64" and args.same_fp32c and args.leaf_size <= 16:
+        same32 = fp32c_same_workload(args, xd, md, hd, wl)
+        result["fp32c_same_workload"] = same32["line"]
     if not args.no_cpu:
-        result.update(cpu_baseline(args, x, m, h, acc, pot, p))
+        result.update(cpu_baseline(args, x, m, h, acc, pot, p, same32))
     if args.fp32c_n > 0 and args.precision == "fp64" and args.workload == "polytrope":
         del xd, md, hd, acc, pot
         solver.close()
@@ -384,10 +391,46 @@ PAPER_TIMINGS = ("SFMM wall time +7% vs the paper's FMM at theta=0.5 (+12% mean 
                  "16 cores; O(N log N) scaling, +7% to +26% vs FMM for N > 1e5 (Sect. 4)")
 
 
-def cpu_baseline(args, x, m, h, acc, pot, p):
+def fp32c_same_workload(args, xd, md, hd, wl):
+    """The FP32-compensated form on the headline's input and leaf size, timed
+    like the headline (its error against the oracle is filled in by
+    cpu_baseline, over every particle)."""
+    import numpy as np
+    import torch
+
+    import paper_2602_05804_amd as sfmm
+
+    log("fp32c on the headline workload")
+    s = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far=args.far)
+    a32 = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
+    p32 = torch.empty((args.n,), dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        s.solve(xd, md, hd, theta=args.theta, order=args.order, acc=a32, pot=p32,
+                precision="fp32c")
+    torch.cuda.synchronize()
+    s.timing_start(args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.solve(xd, md, hd, theta=args.theta, order=args.order, acc=a32, pot=p32,
+                precision="fp32c")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ph = s.timing_stop()
+    st = s.stats()
+    s.close()
+    line = {"workload": wl, "leaf_size": args.leaf_size, "value": args.n / dt,
+            "unit": "particles/s", "ms_per_step": dt * 1e3,
+            "phases_ms": {k: round(float(np.mean([q[k] for q in ph])), 4) for k in sfmm.PHASES},
+            "momentum_residual": float(np.linalg.norm(st["momentum"]) / st["momentum_abs"]),
+            "error_vs_fp64_oracle": None}
+    return {"line": line, "acc": a32.cpu().numpy(), "pot": p32.cpu().numpy()}
+
+
+def cpu_baseline(args, x, m, h, acc, pot, p, same32=None):
     """The oracle on the host: Algorithm 1's loop over leaves on all host cores
-    for every particle (also the parity check of every particle), and the
-    serial oracle on one core over a sample of leaves, extrapolated."""
+    for every particle (also the parity check of every particle, of the FP64
+    solve and, when given, of the FP32-compensated one on the same input),
+    and the serial oracle on one core over a sample of leaves, extrapolated."""
     import numpy as np
 
     import oracle
@@ -419,6 +462,12 @@ def cpu_baseline(args, x, m, h, acc, pot, p):
                          "rms_rel_acc_err": float(np.sqrt((err ** 2).mean())),
                          "max_rel_pot_err": float(perr.max()),
                          "rms_rel_pot_err": float(np.sqrt((perr ** 2).mean()))}
+    if same32 is not None:
+        e32 = np.linalg.norm(same32["acc"] - oa, axis=1) / np.maximum(nb, floor)
+        p32 = np.abs(same32["pot"] - op) / np.abs(op)
+        same32["line"]["error_vs_fp64_oracle"] = {
+            "particles": int(args.n), "rms_rel_acc_err": float(np.sqrt((e32 ** 2).mean())),
+            "max_rel_acc_err": float(e32.max()), "rms_rel_pot_err": float(np.sqrt((p32 ** 2).mean()))}
     # the serial oracle on one core: a sample of leaves, extrapolated
     rng = np.random.default_rng(0)
     nl = t.num_leaves
