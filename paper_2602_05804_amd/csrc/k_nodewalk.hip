@@ -324,7 +324,10 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
 template <bool WRITE>
 __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
                           uint32_t nsrc, bool root, Emit& e, uint32_t* stk, int* status) {
-  constexpr int U = kWalkBatch;
+  // three groups of 64 tested sources per step: the leaf kernels then fit
+  // 128 registers (four waves per SIMD for this latency-bound walk; four
+  // groups took 137 and left three)
+  constexpr int U = 3;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t n0 = root ? 1u : nsrc;
   uint32_t sp = 0;
