@@ -371,19 +371,32 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
 // else exp[parent]); leaves take no room at their level (they are walked
 // after all levels); a node over two systems gets empty lists.  This is the
 // region of level node idx (and it clears the lists of a node it owns).
-__device__ __forceinline__ uint32_t node_region(const NodeWalkArgs& a, uint32_t idx) {
-  const int v = a.level_nodes[idx];
-  const NodeInfo vi = a.info[v];
-  const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  if (flag == 0) {
+// (in two halves: the loads of several nodes are issued before any of
+// their stores, which the compiler could not otherwise move loads past)
+struct RegionIn {
+  int v, flag, child;
+  uint32_t expv;
+};
+__device__ __forceinline__ RegionIn node_region_load(const NodeWalkArgs& a, uint32_t idx) {
+  RegionIn r;
+  r.v = a.level_nodes[idx];
+  const NodeInfo vi = a.info[r.v];
+  r.flag = a.node_flag ? (int)a.node_flag[r.v] : (vi.parent < 0 ? 1 : 2);
+  r.child = vi.child;
+  r.expv = (r.flag == 2 && vi.child >= 0) ? a.exp[vi.parent] : 0u;
+  return r;
+}
+__device__ __forceinline__ uint32_t node_region_store(const NodeWalkArgs& a, const RegionIn& r) {
+  const int v = r.v;
+  if (r.flag == 0) {
     a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
     a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
     return 0;
   }
-  if (vi.child < 0) return 0;
+  if (r.child < 0) return 0;
   a.p2p_cnt[v] = 0;
   a.p2p_off[v] = 0;
-  return flag == 1 ? 1u : a.exp[vi.parent];  // (the top node of several systems has flag 0)
+  return r.flag == 1 ? 1u : r.expv;  // (the top node of several systems has flag 0)
 }
 
 // fill pass of one level's internal nodes (one wave per node; the level
@@ -550,12 +563,19 @@ __device__ __forceinline__ uint64_t scan_tile(const NodeWalkArgs& a, uint32_t be
   const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
   uint32_t r[SCAN_I];
   uint64_t c = 0;
+  if (recompute) {
+    RegionIn in[SCAN_I];
 #pragma unroll
-  for (int q = 0; q < SCAN_I; ++q) {
-    const uint32_t i = i0 + q;
-    r[q] = i < end ? (recompute ? node_region(a, i) : a.lvl_cnt32[i]) : 0u;
-    c += r[q];
+    for (int q = 0; q < SCAN_I; ++q)
+      if (i0 + q < end) in[q] = node_region_load(a, i0 + q);
+#pragma unroll
+    for (int q = 0; q < SCAN_I; ++q) r[q] = i0 + q < end ? node_region_store(a, in[q]) : 0u;
+  } else {
+#pragma unroll
+    for (int q = 0; q < SCAN_I; ++q) r[q] = i0 + q < end ? a.lvl_cnt32[i0 + q] : 0u;
   }
+#pragma unroll
+  for (int q = 0; q < SCAN_I; ++q) c += r[q];
   uint64_t total;
   uint64_t o = base + block_excl_u64(c, total);
 #pragma unroll
@@ -582,10 +602,14 @@ __global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int 
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
   const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
   uint64_t c = 0;
+  RegionIn in[SCAN_I];
+#pragma unroll
+  for (int q = 0; q < SCAN_I; ++q)
+    if (i0 + q < end) in[q] = node_region_load(a, i0 + q);
 #pragma unroll
   for (int q = 0; q < SCAN_I; ++q) {
     const uint32_t i = i0 + q;
-    const uint32_t r = i < end ? node_region(a, i) : 0u;
+    const uint32_t r = i < end ? node_region_store(a, in[q]) : 0u;
     if (i < end) a.lvl_cnt32[i] = r;
     c += r;
   }
