@@ -643,7 +643,7 @@ void p2p32(bool node_lists, int variant, const NearArgs& a, const float4* pf, co
     else k_p2p_wave32<LS, false, RS, TG, 4, AccD><<<nb, 64, 0, s>>>(a, pf, ph);
   }
   record_mark(km.end, s);
-  launch_p2p_reduce(a, LS, s);
+  if (!km.skip_reduce) launch_p2p_reduce(a, LS, s);
 }
 
 }  // namespace

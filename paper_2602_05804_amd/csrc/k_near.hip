@@ -652,20 +652,20 @@ __global__ __launch_bounds__(256) void k_momentum_final(int nb, const double* __
 
 }  // namespace
 
-#define WAVE_LAUNCH(LS, TG, WPE)                                          \
-  do {                                                                    \
+#define WAVE_LAUNCH(LS, TG, WPE)                                           \
+  do {                                                                     \
     if (node_lists) k_p2p_wave<LS, true, TG, WPE, 1><<<nbl, 64, 0, s>>>(a); \
-    else k_p2p_wave<LS, false, TG, WPE, 1><<<nbl, 64, 0, s>>>(a);         \
-    record_mark(km.end, s);                                               \
-    launch_p2p_reduce(a, LS, s);                                          \
+    else k_p2p_wave<LS, false, TG, WPE, 1><<<nbl, 64, 0, s>>>(a);          \
+    record_mark(km.end, s);                                                \
+    if (!km.skip_reduce) launch_p2p_reduce(a, LS, s);                      \
   } while (0)
 
 #define NEAR_LAUNCH(LS, TG)                                                \
-  do {                                                                    \
-    if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);       \
-    else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);                 \
-    record_mark(km.end, s);                                               \
-    launch_p2p_reduce(a, LS, s);                                          \
+  do {                                                                     \
+    if (node_lists) k_p2p_leaf<LS, true, TG><<<nbl, 64, 0, s>>>(a);        \
+    else k_p2p_leaf<LS, false, TG><<<nbl, 64, 0, s>>>(a);                  \
+    record_mark(km.end, s);                                                \
+    if (!km.skip_reduce) launch_p2p_reduce(a, LS, s);                      \
   } while (0)
 
 void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* src_total,
@@ -699,7 +699,7 @@ void launch_near(bool node_lists, int leaf_size, int variant, const NearArgs& a,
   if (leaf_size <= 32 && variant == 13) {
     launch_p2p_tile(node_lists, p2p_leaf_slots(leaf_size), a, items, s);
     record_mark(km.end, s);
-    launch_p2p_reduce(a, p2p_leaf_slots(leaf_size), s);
+    if (!km.skip_reduce) launch_p2p_reduce(a, p2p_leaf_slots(leaf_size), s);
     return;
   }
   // leaf_size <= 10: five targets per pass at four waves per SIMD; <= 16:

@@ -103,6 +103,10 @@ struct Emit {
   uint32_t exp_lane;
   // leaf: this lane's share of the particles of the P2P entries
   uint32_t src_lane;
+  // leaf, slot mode: the slot sizes, and the entries beyond both kernels
+  // staged in LDS (in rank order) until the leaf's P2P count is known
+  uint32_t slot_m, slot_p;
+  uint32_t* plain;
 };
 
 template <bool WRITE>
@@ -143,8 +147,14 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
 // a leaf's lists: nm M2L entries (sel_m), np P2P entries that may need
 // softening (sel_p) and nq P2P entries beyond both kernels (sel_q); the
 // latter are written from the end of the leaf's range, so the P2P kernel
-// meets the softened pairs first and the rest in whole chunks without them
-template <bool WRITE>
+// meets the softened pairs first and the rest in whole chunks without them.
+// W = kLeafExact writes at the leaf's exact offsets (its P2P count known);
+// W = kLeafSlot writes the M2L and softening entries into the leaf's fixed
+// slots as far as they fit and stages the others in LDS
+constexpr int kLeafExact = 1;
+constexpr int kLeafSlot = 2;
+
+template <int W>
 __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, uint32_t s0,
                                                 uint32_t s1, uint32_t nm, uint32_t sel_m,
                                                 uint32_t np, uint32_t sel_p, uint32_t nq,
@@ -153,7 +163,18 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
   const uint32_t pm = wave_prefix(nm, tm);
   const uint32_t pp = wave_prefix(np, tp);
   const uint32_t pq = wave_prefix(nq, tq);
-  if (WRITE) {
+  if (W == kLeafSlot) {
+    uint32_t k = e.m2l_run + pm;
+    if (sel_m & 1u) { if (k < e.slot_m && e.m2l_base + k < a.m2l_cap) a.m2l_pool[e.m2l_base + k] = s0; ++k; }
+    if (sel_m & 2u) { if (k < e.slot_m && e.m2l_base + k < a.m2l_cap) a.m2l_pool[e.m2l_base + k] = s1; }
+    uint32_t q = e.p2p_run + pp;
+    if (sel_p & 1u) { if (q < e.slot_p && e.p2p_base + q < a.p2p_cap) a.p2p_pool[e.p2p_base + q] = s0; ++q; }
+    if (sel_p & 2u) { if (q < e.slot_p && e.p2p_base + q < a.p2p_cap) a.p2p_pool[e.p2p_base + q] = s1; }
+    uint32_t r = e.plain_run + pq;
+    if (sel_q & 1u) { if (r < e.slot_p) e.plain[r] = s0; ++r; }
+    if (sel_q & 2u) { if (r < e.slot_p) e.plain[r] = s1; }
+  }
+  if (W == kLeafExact) {
     uint64_t k = e.m2l_base + e.m2l_run + pm;
     if (sel_m & 1u) { if (k < a.m2l_cap) a.m2l_pool[k] = s0; ++k; }
     if (sel_m & 2u) { if (k < a.m2l_cap) a.m2l_pool[k] = s1; }
@@ -269,7 +290,7 @@ __device__ void walk_internal(const NodeWalkArgs& a, int v, const double* rv, co
 // each batch of the tested list, so the stack stays within a few chunks per
 // tree level.  Returns false when the stack would overflow (the walk is then
 // rerun with a larger stack).
-template <bool WRITE, int U>
+template <int W, int U>
 __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const double* rv,
                                           const uint32_t (&t0)[U], const uint32_t (&t1)[U],
                                           const int (&nt)[U], Emit& e, uint32_t* stk,
@@ -307,7 +328,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
         if (q) open1 = true; else open0 = true;
       }
     }
-    emit_leaf_lists<WRITE>(a, e, t0[u], t1[u], nm, selm, np, selp, nq, selq);
+    emit_leaf_lists<W>(a, e, t0[u], t1[u], nm, selm, np, selp, nq, selq);
     const uint32_t npush = (open0 ? 2u : 0u) + (open1 ? 2u : 0u);
     uint32_t tpush;
     const uint32_t pp = wave_prefix(npush, tpush);
@@ -321,7 +342,7 @@ __device__ __forceinline__ bool leaf_step(const NodeWalkArgs& a, int v, const do
   return ok;
 }
 
-template <bool WRITE>
+template <int W>
 __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const uint32_t* src,
                           uint32_t nsrc, bool root, Emit& e, uint32_t* stk, int* status) {
   // three groups of 64 tested sources per step: the leaf kernels then fit
@@ -352,7 +373,7 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
       if (cb[u] < 0) { t0[u] = sb[u]; nt[u] = 1; }
       else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt[u] = 2; }
     }
-    ok = leaf_step<WRITE, U>(a, v, rv, t0, t1, nt, e, stk, sp);
+    ok = leaf_step<W, U>(a, v, rv, t0, t1, nt, e, stk, sp);
     while (ok && sp > 0) {
       const uint32_t k = sp < 64u ? sp : 64u;
       uint32_t d0[1] = {0}, d1[1] = {0};
@@ -360,7 +381,7 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
       if (dn[0]) d0[0] = stk[sp - k + lane];
       __syncthreads();
       sp -= k;
-      ok = leaf_step<WRITE, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
+      ok = leaf_step<W, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
     }
   }
   if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
@@ -451,26 +472,24 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
 // ---- leaves, all levels at once ---------------------------------------------
 // A leaf's lists depend only on its parent's opened list, so the leaves are
 // walked after every level's internal nodes, in leaf order (one wave per
-// leaf): a count pass, a scan over the leaves, and a fill pass that repeats
-// the walk and writes.  Leaf M2L lists follow the internal nodes' regions in
-// the M2L pool; the P2P pool holds only leaf lists.
-template <bool FILL>
-__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
-  extern __shared__ uint32_t stk[];
-  const int l = (int)xcd_block(blockIdx.x, gridDim.x);
-  if (l >= a.nleaves) return;
+// leaf).  One pass writes each leaf's lists into fixed slots (slot_m M2L
+// entries per leaf after the internal nodes' regions in the M2L pool, slot_p
+// P2P entries per leaf at the front of the P2P pool).  A leaf whose lists do
+// not fit its slots is listed (run[5] of them) and walked again by a second
+// pass, which writes its lists after all slots, at offsets from scans of
+// such leaves' counts.
+template <bool OVF>
+__device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
   const int v = a.leaf_node[l];
   const NodeInfo vi = a.info[v];
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
   const uint32_t lane = threadIdx.x & 63;
   if (flag == 0) {  // (a leaf never spans two systems; kept for safety)
     if (lane == 0) {
-      if (FILL) {
-        a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
-      } else {
-        a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
-        a.leaf_m2l_cnt[l] = 0; a.leaf_p2p_cnt[l] = 0;
-      }
+      a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+      a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
+      a.leaf_m2l_cnt[l] = 0; a.leaf_p2p_cnt[l] = 0;
+      a.src_total[l] = 0; a.item_cnt[l] = 1;
     }
     return;
   }
@@ -484,37 +503,76 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
     src = a.open_pool + po;
     if ((uint64_t)po + nsrc > a.open_cap) nsrc = 0;  // pool too small: the walk is rerun
   }
+  const uint64_t nl = (uint64_t)a.nleaves;
   Emit e{};
-  if (FILL) {
-    e.m2l_base = a.run[0] + a.leaf_m2l_off[l];
-    e.p2p_base = a.leaf_p2p_off[l];
-    e.p2p_total = a.p2p_cnt[v];  // from the count pass
+  if (OVF) {
+    e.m2l_base = a.run[0] + nl * a.slot_m + a.leaf_m2l_off[l];
+    e.p2p_base = nl * a.slot_p + a.leaf_p2p_off[l];
+    e.p2p_total = a.p2p_cnt[v];  // from the first pass
     if (lane == 0) {
       const bool fm = e.m2l_base + a.m2l_cnt[v] <= a.m2l_cap;
       const bool fp = e.p2p_base + e.p2p_total <= a.p2p_cap;
       a.m2l_off[v] = fm ? (uint32_t)e.m2l_base : kNoList;
       a.p2p_off[v] = fp ? (uint32_t)e.p2p_base : kNoList;
-      a.open_off[v] = 0;
     }
+    walk_leaf<kLeafExact>(a, v, rv, src, nsrc, root, e, stk, a.status);
+    __syncthreads();  // (the stack is reused by the wave's next leaf)
+    return;
   }
-  walk_leaf<FILL>(a, v, rv, src, nsrc, root, e, stk, a.status);
-  if (!FILL) {
-    uint32_t ns = e.src_lane;
+  e.m2l_base = a.run[0] + (uint64_t)l * a.slot_m;
+  e.p2p_base = (uint64_t)l * a.slot_p;
+  e.slot_m = a.slot_m;
+  e.slot_p = a.slot_p;
+  e.plain = stk + a.stack_cap;
+  walk_leaf<kLeafSlot>(a, v, rv, src, nsrc, root, e, stk, a.status);
+  uint32_t ns = e.src_lane;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
-    if (lane == 0) {
-      const uint32_t np = e.p2p_run + e.plain_run;
-      a.m2l_cnt[v] = e.m2l_run;
-      a.p2p_cnt[v] = np;
-      a.open_cnt[v] = 0;
-      a.leaf_m2l_cnt[l] = e.m2l_run;
-      a.leaf_p2p_cnt[l] = np;
-      // P2P work items of the leaf: runs of at most kP2PItem source particles
-      a.src_total[l] = ns;
-      const uint32_t k = (ns + kP2PItem - 1) / kP2PItem;
-      a.item_cnt[l] = k > 0 ? k : 1u;
+  for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
+  const uint32_t nm = e.m2l_run, np = e.p2p_run, nq = e.plain_run;
+  const bool fits = nm <= a.slot_m && np + nq <= a.slot_p;  // uniform
+  __syncthreads();  // the staged entries are complete
+  if (fits) {
+    // the entries beyond both kernels after the others, in reverse rank
+    // order (as the exact pass writes them)
+    for (uint32_t i = lane; i < nq; i += 64) {
+      const uint64_t t = e.p2p_base + np + i;
+      if (t < a.p2p_cap) a.p2p_pool[t] = e.plain[nq - 1u - i];
     }
   }
+  if (lane == 0) {
+    a.m2l_cnt[v] = nm;
+    a.p2p_cnt[v] = np + nq;
+    a.open_cnt[v] = 0;
+    a.open_off[v] = 0;
+    if (fits) {
+      a.m2l_off[v] = e.m2l_base + nm <= a.m2l_cap ? (uint32_t)e.m2l_base : kNoList;
+      a.p2p_off[v] = e.p2p_base + np + nq <= a.p2p_cap ? (uint32_t)e.p2p_base : kNoList;
+    } else {
+      a.ovf_leaf[atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 5), 1ull)] = (uint32_t)l;
+    }
+    // lists left for the second pass (none when they fit)
+    a.leaf_m2l_cnt[l] = fits ? 0u : nm;
+    a.leaf_p2p_cnt[l] = fits ? 0u : np + nq;
+    // P2P work items of the leaf: runs of at most kP2PItem source particles
+    a.src_total[l] = ns;
+    const uint32_t k = (ns + kP2PItem - 1) / kP2PItem;
+    a.item_cnt[l] = k > 0 ? k : 1u;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
+  extern __shared__ uint32_t stk[];
+  const int l = (int)xcd_block(blockIdx.x, gridDim.x);
+  if (l < a.nleaves) leaf_lists<false>(a, l, stk);
+}
+
+// the second pass: a fixed grid of waves takes the listed leaves in turn
+constexpr unsigned kOvfWaves = 2048;
+
+__global__ __launch_bounds__(64) void k_nodewalk_leaves_ovf(NodeWalkArgs a) {
+  extern __shared__ uint32_t stk[];
+  const uint64_t nov = a.run[5];
+  for (uint64_t i = blockIdx.x; i < nov; i += gridDim.x) leaf_lists<true>(a, (int)a.ovf_leaf[i], stk);
 }
 
 // Places one level's internal nodes: an exclusive scan, in level order, of
@@ -675,7 +733,8 @@ template <bool ENTRIES>
 __global__ __launch_bounds__(256) void k_check_lists(NodeWalkArgs a, int nn) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nn) return;
-  const uint64_t used_m = a.run[0] + a.run[3], used_p = a.run[2];
+  const uint64_t nl = (uint64_t)a.nleaves;
+  const uint64_t used_m = a.run[0] + nl * a.slot_m + a.run[3], used_p = nl * a.slot_p + a.run[2];
   const uint64_t lim_m = used_m < a.m2l_cap ? used_m : a.m2l_cap;
   const uint64_t lim_p = used_p < a.p2p_cap ? used_p : a.p2p_cap;
   bool bad = false;
@@ -747,14 +806,14 @@ void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level,
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s) {
   if (a.nleaves <= 0) return;
   const size_t lds = a.stack_cap * sizeof(uint32_t);
-  k_nodewalk_leaves<false><<<a.nleaves, 64, lds, s>>>(a);
+  k_nodewalk_leaves<<<a.nleaves, 64, lds + a.slot_p * sizeof(uint32_t), s>>>(a);
   scan_u32_u64(a.leaf_m2l_cnt, a.leaf_m2l_off, a.nleaves, a.run + 3,
                reinterpret_cast<uint64_t*>(scan_tmp), s);
   scan_u32_u64(a.leaf_p2p_cnt, a.leaf_p2p_off, a.nleaves, a.run + 2,
                reinterpret_cast<uint64_t*>(scan_tmp), s);
   // P2P work items: item_off[nleaves] = their total (read back with the walk's)
   scan_u32(a.item_cnt, a.item_off, a.nleaves, a.item_off + a.nleaves, scan_tmp, s);
-  k_nodewalk_leaves<true><<<a.nleaves, 64, lds, s>>>(a);
+  k_nodewalk_leaves_ovf<<<std::min<unsigned>(kOvfWaves, (unsigned)a.nleaves), 64, lds, s>>>(a);
 }
 
 }  // namespace sfmm

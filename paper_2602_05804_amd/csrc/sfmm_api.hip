@@ -39,7 +39,7 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
-  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_DIRPART,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_DIRPART, B_OVFLEAF,
   B_COUNT
 };
 
@@ -57,7 +57,7 @@ struct Readback {
   int status[4];
   uint32_t level_off[kMaxDepthCap + 2];
   uint32_t level_int[kMaxDepthCap + 2];
-  uint64_t walk_tot[4];
+  uint64_t walk_tot[6];
   uint32_t items;
 };
 
@@ -85,6 +85,9 @@ struct sfmm_ctx {
   uint64_t m2l_cap = 0, p2p_cap = 0;
   int64_t items_from_walk = 0;  // P2P work items counted by the level walk
   uint32_t stack_cap = 0;
+  // per-leaf list slots of the level walk (entries; doubled, up to
+  // kSlotMax, while more than 1/16 of the leaves overflow them)
+  uint32_t slot_m = 512, slot_p = 256;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
@@ -96,6 +99,12 @@ struct sfmm_ctx {
   int walk_attempts = 0;   // walks made by the last solve (pools grown in between)
   sfmm_stats stats{};
   Readback* rb = nullptr;  // pinned host block for the read-backs
+  // near field beside the far field (SFMM_OVERLAP): the P2P kernel runs on a
+  // second stream of the context while the far field runs on `stream`; the
+  // reduction waits for both (0 off, 1 P2P queued first, 2 far field first)
+  int overlap = 0;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 namespace {
@@ -487,9 +496,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 4))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 6))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
-  for (int id : {B_LWM2LCNT, B_LWP2PCNT})
+  for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_OVFLEAF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   for (int id : {B_LWM2LOFF, B_LWP2POFF})
     if ((rc = ensure(ctx, id, sizeof(uint64_t) * std::max(nl, 1)))) return rc;
@@ -503,18 +512,24 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   // (the M2L pool also holds the opened lists of internal nodes)
   // (SFMM_POOL_INIT: start from that many entries instead, so that tests
   // meet pools too small for the walk)
-  const uint64_t est_m = ctx->pool_init ? ctx->pool_init : 96ull * nn + 2048;
-  const uint64_t est_p = ctx->pool_init ? ctx->pool_init : 48ull * nl + 1024;
+  // (the leaves' slots come first in the estimates, then the internal
+  // nodes' regions and the lists that overflow their slots)
+  const uint64_t est_m =
+      ctx->pool_init ? ctx->pool_init : (uint64_t)ctx->slot_m * nl + 64ull * nn + 2048;
+  const uint64_t est_p = ctx->pool_init ? ctx->pool_init : (uint64_t)ctx->slot_p * nl + 8ull * nl + 1024;
   ctx->m2l_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->m2l_cap, est_m));
   ctx->p2p_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->p2p_cap, est_p));
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
   if (ctx->stack_cap < stack_min) ctx->stack_cap = stack_min;
   for (int attempt = 0;; ++attempt) {
+    // the leaf kernel's LDS (stack and staged P2P entries) stays within 64 KB
+    const uint32_t slot_m = ctx->slot_m;
+    const uint32_t slot_p = std::min<uint32_t>(ctx->slot_p, 16384u - ctx->stack_cap);
     ctx->walk_attempts = attempt + 1;
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint64_t* tot = P<uint64_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 4, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 6, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     if (ctx->check_pools) {
       // every entry a consumer reads must then come from this walk: clear
@@ -555,6 +570,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.status = status;
     a.nleaves = nl;
     a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
+    a.slot_m = slot_m;
+    a.slot_p = slot_p;
+    a.ovf_leaf = P<uint32_t>(ctx, B_OVFLEAF);
     a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
     a.leaf_m2l_off = P<uint64_t>(ctx, B_LWM2LOFF);
@@ -566,8 +584,9 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
-    // M2L entries proper (the pool also holds the opened lists)
+    // M2L entries proper (the pool also holds the opened lists), P2P entries
     launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
+    launch_sum_u32(nn, a.p2p_cnt, tot + 4, s);
     // no consumer reads a list unless it lies in the part of its pool this
     // walk wrote (and, when checking, holds only node ids)
     launch_check_lists(a, nn, ctx->check_pools, s);
@@ -583,15 +602,29 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                             s));
     HIPCHK(wait_stream(s));
     ctx->items_from_walk = hb->items;
-    // 64-bit totals: internal regions, then the leaves' M2L lists; the P2P pool
-    const uint64_t m2l_used = htot[0] + htot[3];
-    const bool pool_over = m2l_used > ctx->m2l_cap || htot[2] > ctx->p2p_cap;
+    // 64-bit totals: internal regions, the leaves' slots, then the lists that
+    // overflow their slots
+    const uint64_t m2l_used = htot[0] + (uint64_t)slot_m * nl + htot[3];
+    const uint64_t p2p_used = (uint64_t)slot_p * nl + htot[2];
+    const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
       if (hstatus[0] & ST_BADLIST)
         return fail(ctx, SFMM_EDEVICE, "an interaction list lies outside what the walk wrote");
-      ctx->p2p_total = htot[2];
+      ctx->p2p_total = htot[4];
       ctx->m2l_unique = htot[1];
+      // larger slots for the next walk when many leaves overflowed these
+      // (and pools that hold them, so that walk still fits at once)
+      if (htot[5] * 16 > (uint64_t)nl) {
+        const uint32_t sm = std::min(kSlotMax, 2 * ctx->slot_m);
+        const uint32_t sp = std::min(kSlotMax / 2, 2 * ctx->slot_p);
+        ctx->m2l_cap = std::min(kPoolMax, std::max(ctx->m2l_cap,
+                                                   m2l_used + (uint64_t)(sm - slot_m) * nl));
+        ctx->p2p_cap = std::min(kPoolMax, std::max(ctx->p2p_cap,
+                                                   p2p_used + (uint64_t)(sp - slot_p) * nl));
+        ctx->slot_m = sm;
+        ctx->slot_p = sp;
+      }
       return SFMM_OK;
     }
     if (attempt >= 16) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
@@ -602,11 +635,11 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
       if ((m2l_used > ctx->m2l_cap && ctx->m2l_cap >= kPoolMax) ||
-          (htot[2] > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax))
+          (p2p_used > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax))
         return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed the largest list pool (" +
                                                 std::to_string(kPoolMax) + " entries)");
       ctx->m2l_cap = std::min(kPoolMax, grow(ctx->m2l_cap, m2l_used));
-      ctx->p2p_cap = std::min(kPoolMax, grow(ctx->p2p_cap, htot[2]));
+      ctx->p2p_cap = std::min(kPoolMax, grow(ctx->p2p_cap, p2p_used));
     }
     if (stack_over) {
       if (ctx->stack_cap >= 16384) return fail(ctx, SFMM_EUNSUPPORTED, "lowering stack > 64 KB");
@@ -683,47 +716,6 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     for (auto& q : need3)
       if ((rc = ensure(ctx, q.id, q.bytes))) return rc;
   }
-  phase_mark(ctx, 3, 0);
-  if (f32) {
-    launch_prep32(ctx->order, (int)ctx->nn, nl, f.leaf_node, f.info, f.rec, P<int32_t>(ctx, B_NDEPTH),
-                  f.xs, f.ys, f.zs, P<double>(ctx, B_MS), P<double>(ctx, B_HS),
-                  P<float>(ctx, B_REC32), P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), s);
-  }
-  if (shared) {
-    SharedFarArgs sa{};
-    sa.nn = (int)ctx->nn;
-    sa.level_nodes = reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES));
-    sa.depth = P<int32_t>(ctx, B_NDEPTH);
-    sa.m2l_off = f.node_m2l_off;
-    sa.m2l_cnt = f.node_m2l_cnt;
-    sa.pool = f.node_m2l_pool;
-    sa.rec = f.rec;
-    sa.rec32 = f32 ? P<float>(ctx, B_REC32) : nullptr;
-    sa.top = ctx->cfg.fp64_top_depth;
-    sa.ln = P<double>(ctx, B_LN);
-    if (mutual) {
-      launch_far_mutual(ctx->order, f, sa, s);
-    } else {
-      // nodes grouped by list length for the M2L kernel (the level sort's
-      // key and id buffers are free once the tree is built)
-      M2LOrderBufs ob{};
-      ob.key0 = P<uint64_t>(ctx, B_LEVKEY0);
-      ob.key1 = P<uint64_t>(ctx, B_LEVKEY1);
-      ob.ids0 = P<uint32_t>(ctx, B_LEVIDS);
-      ob.ids1 = P<uint32_t>(ctx, B_M2LORD);
-      ob.hist = P<uint32_t>(ctx, B_HIST);
-      ob.hist_tmp = P<uint32_t>(ctx, B_SCANTMP);
-      ob.total = reinterpret_cast<uint32_t*>(small + S_SORTTOT);
-      launch_m2l_order(sa, f32, ob, s);
-      sa.level_nodes = reinterpret_cast<const int32_t*>(ob.ids1);
-      launch_far_shared(ctx->order, f, sa, f32, s);
-    }
-  } else if (f32) {
-    launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
-  } else {
-    launch_far(ctx->order, level, f, s);
-  }
-  phase_mark(ctx, 3, 1);
   NearArgs a{};
   a.n = n;
   a.nleaves = nl;
@@ -750,8 +742,6 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
   a.pot = pot;
   if ((rc = ensure(ctx, B_SOFTCNT, sizeof(unsigned long long)))) return rc;
   a.soft_pairs = P<unsigned long long>(ctx, B_SOFTCNT);
-  phase_mark(ctx, 4, 0);
-  HIPCHK(hipMemsetAsync(a.soft_pairs, 0, sizeof(unsigned long long), s));
   // P2P work items: runs of at most kP2PItem flattened source particles of
   // one leaf; their number is read back to size the partial sums
   int64_t items = 0;
@@ -786,16 +776,92 @@ int do_walk_and_eval(sfmm_ctx* ctx, double theta, int precision, const double* m
     a.part = P<double>(ctx, B_PART);
     a.item_e0 = P<uint32_t>(ctx, B_ITEME0);
     a.item_c0 = P<uint32_t>(ctx, B_ITEMC0);
-    launch_p2p_items_fill(level, a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK),
-                          P<uint32_t>(ctx, B_ITEME0), P<uint32_t>(ctx, B_ITEMC0), s);
+  }
+  // the P2P kernel runs beside the far field when it writes only item partial
+  // sums: the reduction, which adds the far field, then waits for both
+  const bool overlap = ctx->overlap != 0 && ctx->cfg.leaf_size <= 32 && ctx->near_variant != 1;
+  if (overlap && !ctx->aux) {
+    HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming));
   }
   KernelMarks km;
   km.begin = phase_event(ctx, 6, 0);
   km.end = phase_event(ctx, 6, 1);
-  if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, ctx->near_variant, a,
-                        P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), items, s, km);
-  else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, s, km);
-  phase_mark(ctx, 4, 1);
+  km.skip_reduce = overlap;
+  auto near_field = [&](hipStream_t ns) -> int {
+    HIPCHK(hipMemsetAsync(a.soft_pairs, 0, sizeof(unsigned long long), ns));
+    if (ctx->cfg.leaf_size <= 32)
+      launch_p2p_items_fill(level, a, P<int32_t>(ctx, B_ITEMLEAF), P<uint32_t>(ctx, B_ITEMK),
+                            P<uint32_t>(ctx, B_ITEME0), P<uint32_t>(ctx, B_ITEMC0), ns);
+    if (f32) launch_near32(ctx->order, level, ctx->cfg.leaf_size, ctx->near_variant, a,
+                          P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), items, ns, km);
+    else launch_near(level, ctx->cfg.leaf_size, ctx->near_variant, a, items, ns, km);
+    return SFMM_OK;
+  };
+  auto far_field = [&]() {
+    if (shared) {
+      SharedFarArgs sa{};
+      sa.nn = (int)ctx->nn;
+      sa.level_nodes = reinterpret_cast<const int32_t*>(P<uint32_t>(ctx, B_LEVNODES));
+      sa.depth = P<int32_t>(ctx, B_NDEPTH);
+      sa.m2l_off = f.node_m2l_off;
+      sa.m2l_cnt = f.node_m2l_cnt;
+      sa.pool = f.node_m2l_pool;
+      sa.rec = f.rec;
+      sa.rec32 = f32 ? P<float>(ctx, B_REC32) : nullptr;
+      sa.top = ctx->cfg.fp64_top_depth;
+      sa.ln = P<double>(ctx, B_LN);
+      if (mutual) {
+        launch_far_mutual(ctx->order, f, sa, s);
+      } else {
+        // nodes grouped by list length for the M2L kernel (the level sort's
+        // key and id buffers are free once the tree is built)
+        M2LOrderBufs ob{};
+        ob.key0 = P<uint64_t>(ctx, B_LEVKEY0);
+        ob.key1 = P<uint64_t>(ctx, B_LEVKEY1);
+        ob.ids0 = P<uint32_t>(ctx, B_LEVIDS);
+        ob.ids1 = P<uint32_t>(ctx, B_M2LORD);
+        ob.hist = P<uint32_t>(ctx, B_HIST);
+        ob.hist_tmp = P<uint32_t>(ctx, B_SCANTMP);
+        ob.total = reinterpret_cast<uint32_t*>(small + S_SORTTOT);
+        launch_m2l_order(sa, f32, ob, s);
+        sa.level_nodes = reinterpret_cast<const int32_t*>(ob.ids1);
+        launch_far_shared(ctx->order, f, sa, f32, s);
+      }
+    } else if (f32) {
+      launch_far32(ctx->order, level, f, P<float>(ctx, B_REC32), ctx->cfg.fp64_top_depth, s);
+    } else {
+      launch_far(ctx->order, level, f, s);
+    }
+  };
+  phase_mark(ctx, 3, 0);
+  if (f32) {
+    launch_prep32(ctx->order, (int)ctx->nn, nl, f.leaf_node, f.info, f.rec, P<int32_t>(ctx, B_NDEPTH),
+                  f.xs, f.ys, f.zs, P<double>(ctx, B_MS), P<double>(ctx, B_HS),
+                  P<float>(ctx, B_REC32), P<float4>(ctx, B_PF32), P<float2>(ctx, B_PH32), s);
+  }
+  if (overlap) {
+    // phase 3 is then the far field with the P2P kernel beside it, phase 4
+    // what is left of the near field after it, with the reduction
+    HIPCHK(hipEventRecord(ctx->fork_ev, s));
+    if (ctx->overlap == 2) far_field();
+    HIPCHK(hipStreamWaitEvent(ctx->aux, ctx->fork_ev, 0));
+    if ((rc = near_field(ctx->aux))) return rc;
+    HIPCHK(hipEventRecord(ctx->join_ev, ctx->aux));
+    if (ctx->overlap == 1) far_field();
+    phase_mark(ctx, 3, 1);
+    phase_mark(ctx, 4, 0);
+    HIPCHK(hipStreamWaitEvent(s, ctx->join_ev, 0));
+    launch_p2p_reduce(a, p2p_leaf_slots(ctx->cfg.leaf_size), s);
+    phase_mark(ctx, 4, 1);
+  } else {
+    far_field();
+    phase_mark(ctx, 3, 1);
+    phase_mark(ctx, 4, 0);
+    if ((rc = near_field(s))) return rc;
+    phase_mark(ctx, 4, 1);
+  }
   phase_mark(ctx, 5, 0);
   launch_momentum(n, m, acc, P<double>(ctx, B_MOMPART), P<double>(ctx, B_MOM), s);
   phase_mark(ctx, 5, 1);
@@ -926,6 +992,25 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   if (const char* cp = std::getenv("SFMM_CHECK_POOLS")) ctx->check_pools = std::atoi(cp) != 0;
   if (const char* pi = std::getenv("SFMM_POOL_INIT"))
     ctx->pool_init = (uint64_t)std::max(0ll, std::atoll(pi));
+  // first per-leaf list slots "m,p" (tests meet leaves that overflow them)
+  if (const char* ls = std::getenv("SFMM_LEAF_SLOTS")) {
+    unsigned sm = 0, sp = 0;
+    if (std::sscanf(ls, "%u,%u", &sm, &sp) != 2 || sm < 1 || sm > kSlotMax || sp < 1 ||
+        sp > kSlotMax / 2) {
+      delete ctx;
+      return SFMM_EINVAL;
+    }
+    ctx->slot_m = sm;
+    ctx->slot_p = sp;
+  }
+  if (const char* ov = std::getenv("SFMM_OVERLAP")) {
+    const int v = std::atoi(ov);
+    if (v < 0 || v > 2) {
+      delete ctx;
+      return SFMM_EINVAL;
+    }
+    ctx->overlap = v;
+  }
   *out = ctx;
   return SFMM_OK;
 }
@@ -937,6 +1022,12 @@ int sfmm_destroy(sfmm_ctx* ctx) {
   else (void)hipDeviceSynchronize();
   free_events(ctx);
   if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
+  if (ctx->join_ev) (void)hipEventDestroy(ctx->join_ev);
   for (auto& b : ctx->buf)
     if (b.p) (void)hipFree(b.p);
   if (ctx->rb) (void)hipHostFree(ctx->rb);

@@ -75,6 +75,8 @@ constexpr uint32_t kNoList = 0xFFFFFFFFu;
 // list pools hold at most this many entries, so every offset of a list that
 // fits is below kNoList
 constexpr uint64_t kPoolMax = 0xF0000000ull;
+// the largest per-leaf M2L list slot of the level walk (P2P: half of it)
+constexpr uint32_t kSlotMax = 1024;
 
 // ---- scan ------------------------------------------------------------------
 // Exclusive prefix sum of `in` (n entries) into `out` (may alias in); the
@@ -199,11 +201,18 @@ struct NodeWalkArgs {
   uint64_t* lvl_off;    // [nn] its absolute offset in the M2L pool
   uint64_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
   uint64_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint64_t* run;      // [4] M2L pool used by internal nodes, M2L entries proper (the
-                      // walk's sum), P2P pool, M2L pool used by leaves
-  // leaves (walked after all levels, in leaf order)
+  uint64_t* run;      // [6] M2L pool used by internal nodes, M2L entries proper (the
+                      // walk's sum), P2P pool used after the leaf slots, M2L pool
+                      // used after the leaf slots, P2P entries proper, leaves whose
+                      // lists did not fit their slots
+  // leaves (walked after all levels, in leaf order): fixed slots of slot_m M2L
+  // and slot_p P2P entries per leaf; the lists of a leaf that do not fit go
+  // after all slots (leaf_*_cnt: their sizes, 0 for a leaf that fits;
+  // ovf_leaf: such leaves, [nleaves])
   int nleaves;
   const int32_t* leaf_node;
+  uint32_t slot_m, slot_p;
+  uint32_t* ovf_leaf;
   uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt;
   uint64_t *leaf_m2l_off, *leaf_p2p_off;
   // per leaf: particles over its P2P entries, P2P work items and their offsets
@@ -221,8 +230,9 @@ void launch_node_depth(int nn, const NodeInfo* info, int32_t* depth, uint64_t* k
 // (digit-major, nb blocks)
 void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned,
                           uint32_t* level_off, uint32_t* level_int, hipStream_t s);
-// every leaf's lists (count, scans over the leaves, fill); scan_tmp holds
-// scan_tmp_elems(nleaves) words
+// every leaf's lists (the slot pass, scans over the leaves, the second pass
+// over leaves whose lists overflow their slots); scan_tmp holds
+// scan_tmp_elems(nleaves) words; LDS of (stack_cap + slot_p) words per wave
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s);
 // out[0] += sum of x[0..n) (out on the device)
 void launch_sum_u32(int n, const uint32_t* x, uint64_t* out, hipStream_t s);
@@ -342,6 +352,9 @@ inline int p2p_leaf_slots(int leaf_size) { return leaf_size <= 10 ? 10 : leaf_si
 // none), for the timing of that kernel
 struct KernelMarks {
   hipEvent_t begin = nullptr, end = nullptr;
+  // the caller launches the reduction itself (after the far field, when the
+  // P2P kernel runs on a stream of its own)
+  bool skip_reduce = false;
 };
 inline void record_mark(hipEvent_t e, hipStream_t s) {
   if (e) (void)hipEventRecord(e, s);

@@ -298,6 +298,39 @@ def test_pools_regrow_checked(torch, P, orc, monkeypatch, precision):
     s.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_leaf_slots_overflow_checked(torch, P, orc, monkeypatch, precision):
+    """Per-leaf list slots far too small (8 entries each): most leaves' lists
+    are written by the second leaf pass, after all slots.  Every list a
+    consumer reads is checked to lie in what this walk wrote and to hold node
+    ids only; the results are the oracle's, and bit-identical to a solve with
+    the default slots (the same lists, in the same order)."""
+    print(f"case: leaf slots of 8 entries, checked, {precision}", flush=True)
+    x, m, h = workloads.plummer(6000, seed=3)
+    xd, md, hd = dev(torch, x, m, h)
+    monkeypatch.setenv("SFMM_CHECK_POOLS", "1")
+    s0 = P.Solver()
+    a0, p0 = s0.solve(xd, md, hd, theta=0.5, precision=precision)
+    torch.cuda.synchronize()
+    st0 = s0.stats()
+    s0.close()
+    monkeypatch.setenv("SFMM_LEAF_SLOTS", "8,8")
+    s = P.Solver()
+    acc, pot = s.solve(xd, md, hd, theta=0.5, precision=precision)
+    torch.cuda.synchronize()
+    st = s.stats()
+    s.close()
+    acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
+    assert np.array_equal(acc, a0.cpu().numpy()) and np.array_equal(pot, p0.cpu().numpy())
+    for k in ("n_m2l_unique", "n_p2p_leaf_pairs", "n_p2p_pairs", "n_p2p_soft_pairs"):
+        assert st[k] == st0[k], k
+    oa, op = orc.sfmm_solve(x, m, h, theta=0.5)
+    if precision == "fp64":
+        assert rel_err(acc, oa).max() < TOL and pot_err(pot, op) < TOL
+    else:
+        assert _rms_rel(acc, oa) <= 1e-6
+
+
 def test_theta_to_zero_equals_direct(torch, P, orc):
     print("case: theta->0 direct", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
