@@ -316,7 +316,9 @@ def main():
         "phases": per_phase,
         "counts": {k: st[k] for k in ("num_nodes", "num_leaves", "max_depth", "n_m2l",
                                       "n_m2l_unique", "n_l2l", "n_p2p_leaf_pairs",
-                                      "n_p2p_pairs", "n_p2p_soft_pairs")},
+                                      "n_p2p_pairs", "n_p2p_soft_pairs", "leaf_slot_m2l",
+                                      "leaf_slot_p2p", "n_leaf_overflow", "max_leaf_m2l",
+                                      "max_leaf_p2p")},
         "momentum_residual": mom,
         "solve_fraction": solve_fraction(args, work, dt * 1e3),
     }

@@ -154,6 +154,12 @@ typedef struct {
                                precision; 0 for the other shapes)                  */
   int32_t walk_attempts;    /* level walks the solve made: 1, plus one more each
                                time the list pools had to grow                     */
+  int32_t leaf_slot_m2l;    /* level walk: per-leaf M2L and P2P list slots of the   */
+  int32_t leaf_slot_p2p;    /* last walk (entries)                                  */
+  int64_t n_leaf_overflow;  /* leaves whose lists did not fit those slots (walked a
+                               second time)                                         */
+  int64_t max_leaf_m2l;     /* longest M2L list and longest P2P list of a leaf      */
+  int64_t max_leaf_p2p;
 } sfmm_stats;
 
 /* Fill *cfg with the defaults listed above.  Returns SFMM_EINVAL if cfg is NULL. */

@@ -71,7 +71,9 @@ class Stats(C.Structure):
                 ("n_p2p_leaf_pairs", C.c_int64), ("n_p2p_pairs", C.c_int64),
                 ("momentum", C.c_double * 3), ("momentum_abs", C.c_double),
                 ("n_m2l_unique", C.c_int64), ("n_p2p_soft_pairs", C.c_int64),
-                ("walk_attempts", C.c_int32)]
+                ("walk_attempts", C.c_int32), ("leaf_slot_m2l", C.c_int32),
+                ("leaf_slot_p2p", C.c_int32), ("n_leaf_overflow", C.c_int64),
+                ("max_leaf_m2l", C.c_int64), ("max_leaf_p2p", C.c_int64)]
 
 
 _lib = None
@@ -251,7 +253,9 @@ class Solver:
                     n_p2p_leaf_pairs=st.n_p2p_leaf_pairs, n_p2p_pairs=st.n_p2p_pairs,
                     momentum=list(st.momentum), momentum_abs=st.momentum_abs,
                     n_m2l_unique=st.n_m2l_unique, n_p2p_soft_pairs=st.n_p2p_soft_pairs,
-                    walk_attempts=st.walk_attempts)
+                    walk_attempts=st.walk_attempts, leaf_slot_m2l=st.leaf_slot_m2l,
+                    leaf_slot_p2p=st.leaf_slot_p2p, n_leaf_overflow=st.n_leaf_overflow,
+                    max_leaf_m2l=st.max_leaf_m2l, max_leaf_p2p=st.max_leaf_p2p)
 
     def timing_start(self, max_solves: int):
         """Record HIP events around every phase of the next max_solves solves."""

@@ -103,10 +103,13 @@ struct Emit {
   uint32_t exp_lane;
   // leaf: this lane's share of the particles of the P2P entries
   uint32_t src_lane;
-  // leaf, slot mode: the slot sizes, and the entries beyond both kernels
-  // staged in LDS (in rank order) until the leaf's P2P count is known
+  // leaf, slot mode: the sizes of the slots written, and the entries beyond
+  // both kernels staged in LDS (in rank order) until the leaf's P2P count is
+  // known, or in global memory (plain_g) once the leaf has a large slot
   uint32_t slot_m, slot_p;
   uint32_t* plain;
+  uint32_t* plain_g;
+  bool big_m, big_p;  // a large slot was asked for (M2L, P2P)
 };
 
 template <bool WRITE>
@@ -154,6 +157,45 @@ __device__ __forceinline__ void emit_lists(const NodeWalkArgs& a, Emit& e, uint3
 constexpr int kLeafExact = 1;
 constexpr int kLeafSlot = 2;
 
+// slot mode: a leaf whose M2L list outgrows its slot moves it to one of the
+// large slots (a.nbig of a.big_m entries after all slots), in one piece; with
+// none left it keeps its slot (and is walked again afterwards)
+__device__ __forceinline__ void promote_m2l(const NodeWalkArgs& a, Emit& e) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t b = 0;
+  if (lane == 0) b = (uint32_t)atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 8), 1ull);
+  b = __builtin_amdgcn_readfirstlane(b);
+  e.big_m = true;
+  if (b >= a.nbig) return;
+  const uint64_t nb = a.run[0] + (uint64_t)a.nleaves * a.slot_m + (uint64_t)b * a.big_m;
+  __threadfence();  // the wave's own slot entries, read back below
+  for (uint32_t i = lane; i < e.m2l_run; i += 64)
+    if (nb + i < a.m2l_cap && e.m2l_base + i < a.m2l_cap) a.m2l_pool[nb + i] = a.m2l_pool[e.m2l_base + i];
+  e.m2l_base = nb;
+  e.slot_m = a.big_m;
+}
+
+// the same for the P2P list: its entries that may need softening move to a
+// large P2P slot, the staged ones to that slot's global staging area
+__device__ __forceinline__ void promote_p2p(const NodeWalkArgs& a, Emit& e) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t b = 0;
+  if (lane == 0) b = (uint32_t)atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 9), 1ull);
+  b = __builtin_amdgcn_readfirstlane(b);
+  e.big_p = true;
+  if (b >= a.nbig) return;
+  const uint64_t nb = (uint64_t)a.nleaves * a.slot_p + (uint64_t)b * a.big_p;
+  uint32_t* g = a.big_plain + (uint64_t)b * a.big_p;
+  __syncthreads();  // the staged entries (LDS)
+  __threadfence();  // the wave's own slot entries
+  for (uint32_t i = lane; i < e.p2p_run; i += 64)
+    if (nb + i < a.p2p_cap && e.p2p_base + i < a.p2p_cap) a.p2p_pool[nb + i] = a.p2p_pool[e.p2p_base + i];
+  for (uint32_t i = lane; i < e.plain_run; i += 64) g[i] = e.plain[i];
+  e.p2p_base = nb;
+  e.slot_p = a.big_p;
+  e.plain_g = g;
+}
+
 template <int W>
 __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, uint32_t s0,
                                                 uint32_t s1, uint32_t nm, uint32_t sel_m,
@@ -164,6 +206,9 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
   const uint32_t pp = wave_prefix(np, tp);
   const uint32_t pq = wave_prefix(nq, tq);
   if (W == kLeafSlot) {
+    // (uniform tests: the wave's totals)
+    if (!e.big_m && e.m2l_run + tm > e.slot_m) promote_m2l(a, e);
+    if (!e.big_p && e.p2p_run + tp + e.plain_run + tq > e.slot_p) promote_p2p(a, e);
     uint32_t k = e.m2l_run + pm;
     if (sel_m & 1u) { if (k < e.slot_m && e.m2l_base + k < a.m2l_cap) a.m2l_pool[e.m2l_base + k] = s0; ++k; }
     if (sel_m & 2u) { if (k < e.slot_m && e.m2l_base + k < a.m2l_cap) a.m2l_pool[e.m2l_base + k] = s1; }
@@ -171,8 +216,9 @@ __device__ __forceinline__ void emit_leaf_lists(const NodeWalkArgs& a, Emit& e, 
     if (sel_p & 1u) { if (q < e.slot_p && e.p2p_base + q < a.p2p_cap) a.p2p_pool[e.p2p_base + q] = s0; ++q; }
     if (sel_p & 2u) { if (q < e.slot_p && e.p2p_base + q < a.p2p_cap) a.p2p_pool[e.p2p_base + q] = s1; }
     uint32_t r = e.plain_run + pq;
-    if (sel_q & 1u) { if (r < e.slot_p) e.plain[r] = s0; ++r; }
-    if (sel_q & 2u) { if (r < e.slot_p) e.plain[r] = s1; }
+    uint32_t* pl = e.plain_g ? e.plain_g : e.plain;
+    if (sel_q & 1u) { if (r < e.slot_p) pl[r] = s0; ++r; }
+    if (sel_q & 2u) { if (r < e.slot_p) pl[r] = s1; }
   }
   if (W == kLeafExact) {
     uint64_t k = e.m2l_base + e.m2l_run + pm;
@@ -506,8 +552,8 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
   const uint64_t nl = (uint64_t)a.nleaves;
   Emit e{};
   if (OVF) {
-    e.m2l_base = a.run[0] + nl * a.slot_m + a.leaf_m2l_off[l];
-    e.p2p_base = nl * a.slot_p + a.leaf_p2p_off[l];
+    e.m2l_base = a.run[0] + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.leaf_m2l_off[l];
+    e.p2p_base = nl * a.slot_p + (uint64_t)a.nbig * a.big_p + a.leaf_p2p_off[l];
     e.p2p_total = a.p2p_cnt[v];  // from the first pass
     if (lane == 0) {
       const bool fm = e.m2l_base + a.m2l_cnt[v] <= a.m2l_cap;
@@ -529,14 +575,16 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) ns += (uint32_t)__shfl_xor((int)ns, o, 64);
   const uint32_t nm = e.m2l_run, np = e.p2p_run, nq = e.plain_run;
-  const bool fits = nm <= a.slot_m && np + nq <= a.slot_p;  // uniform
+  const bool fits = nm <= e.slot_m && np + nq <= e.slot_p;  // uniform
   __syncthreads();  // the staged entries are complete
+  if (e.plain_g) __threadfence();  // (staged in global memory by this wave)
   if (fits) {
     // the entries beyond both kernels after the others, in reverse rank
     // order (as the exact pass writes them)
+    const uint32_t* pl = e.plain_g ? e.plain_g : e.plain;
     for (uint32_t i = lane; i < nq; i += 64) {
       const uint64_t t = e.p2p_base + np + i;
-      if (t < a.p2p_cap) a.p2p_pool[t] = e.plain[nq - 1u - i];
+      if (t < a.p2p_cap) a.p2p_pool[t] = pl[nq - 1u - i];
     }
   }
   if (lane == 0) {
@@ -560,14 +608,14 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
   }
 }
 
-__global__ __launch_bounds__(64) void k_nodewalk_leaves(NodeWalkArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_nodewalk_leaves(NodeWalkArgs a) {
   extern __shared__ uint32_t stk[];
   const int l = (int)xcd_block(blockIdx.x, gridDim.x);
   if (l < a.nleaves) leaf_lists<false>(a, l, stk);
 }
 
 // the second pass: a fixed grid of waves takes the listed leaves in turn
-constexpr unsigned kOvfWaves = 2048;
+constexpr unsigned kOvfWaves = 4096;
 
 __global__ __launch_bounds__(64) void k_nodewalk_leaves_ovf(NodeWalkArgs a) {
   extern __shared__ uint32_t stk[];
@@ -711,63 +759,76 @@ __global__ void k_leaf_stats(LeafStatArgs a) {
   a.pairs[l] = src * (uint64_t)li.cnt - (uint64_t)li.cnt;
 }
 
-// out[0] += sum of x[0..n) (64-bit)
-__global__ __launch_bounds__(256) void k_sum_u32(int n, const uint32_t* __restrict__ x,
-                                                 uint64_t* out) {
-  __shared__ uint64_t ws[4];
-  uint64_t t = 0;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) t += x[i];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(out),
-              (unsigned long long)(ws[0] + ws[1] + ws[2] + ws[3]));
-}
-
 // one thread per node: the lists a consumer reads (M2L of every node, P2P
 // of every leaf) must lie inside the part of the pools this walk wrote, and
-// (check_entries) hold only node ids below nn
+// (check_entries) hold only node ids below nn.  Also the walk's totals:
+// run[1] += M2L entries, run[4] += P2P entries, run[6] / run[7] = max with
+// the longest M2L / P2P list of a leaf.
 template <bool ENTRIES>
 __global__ __launch_bounds__(256) void k_check_lists(NodeWalkArgs a, int nn) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nn) return;
+  __shared__ uint64_t red[4][4];
   const uint64_t nl = (uint64_t)a.nleaves;
-  const uint64_t used_m = a.run[0] + nl * a.slot_m + a.run[3], used_p = nl * a.slot_p + a.run[2];
+  const uint64_t used_m = a.run[0] + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.run[3];
+  const uint64_t used_p = nl * a.slot_p + (uint64_t)a.nbig * a.big_p + a.run[2];
   const uint64_t lim_m = used_m < a.m2l_cap ? used_m : a.m2l_cap;
   const uint64_t lim_p = used_p < a.p2p_cap ? used_p : a.p2p_cap;
   bool bad = false;
-  const uint32_t mc = a.m2l_cnt[v];
-  if (mc > 0) {
-    const uint64_t off = a.m2l_off[v];
-    if (off + mc > lim_m) bad = true;
-    else if (ENTRIES)
-      for (uint32_t k = 0; k < mc; ++k) bad |= (a.m2l_pool[off + k] & kSrcMask) >= (uint32_t)nn;
-  }
-  if (a.info[v].child < 0) {
-    const uint32_t pc = a.p2p_cnt[v];
-    if (pc > 0) {
-      const uint64_t off = a.p2p_off[v];
-      if (off + pc > lim_p) bad = true;
+  uint64_t sm = 0, sp = 0, xm = 0, xp = 0;
+  // (a grid of a few blocks, so that few atomics meet at the totals)
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nn; v += gridDim.x * blockDim.x) {
+    const uint32_t mc = a.m2l_cnt[v];
+    sm += mc;
+    if (mc > 0) {
+      const uint64_t off = a.m2l_off[v];
+      if (off + mc > lim_m) bad = true;
       else if (ENTRIES)
-        for (uint32_t k = 0; k < pc; ++k) bad |= a.p2p_pool[off + k] >= (uint32_t)nn;
+        for (uint32_t k = 0; k < mc; ++k) bad |= (a.m2l_pool[off + k] & kSrcMask) >= (uint32_t)nn;
+    }
+    if (a.info[v].child < 0) {
+      const uint32_t pc = a.p2p_cnt[v];
+      sp += pc;
+      xm = max(xm, (uint64_t)mc);
+      xp = max(xp, (uint64_t)pc);
+      if (pc > 0) {
+        const uint64_t off = a.p2p_off[v];
+        if (off + pc > lim_p) bad = true;
+        else if (ENTRIES)
+          for (uint32_t k = 0; k < pc; ++k) bad |= a.p2p_pool[off + k] >= (uint32_t)nn;
+      }
     }
   }
   if (bad) atomicOr(a.status, ST_BADLIST);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sm += __shfl_xor(sm, o, 64);
+    sp += __shfl_xor(sp, o, 64);
+    xm = max(xm, (uint64_t)__shfl_xor(xm, o, 64));
+    xp = max(xp, (uint64_t)__shfl_xor(xp, o, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { red[0][w] = sm; red[1][w] = sp; red[2][w] = xm; red[3][w] = xp; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t[4] = {red[0][0], red[1][0], red[2][0], red[3][0]};
+    for (int k = 1; k < 4; ++k) {
+      t[0] += red[0][k]; t[1] += red[1][k];
+      t[2] = max(t[2], red[2][k]); t[3] = max(t[3], red[3][k]);
+    }
+    auto* run = reinterpret_cast<unsigned long long*>(a.run);
+    if (t[0]) atomicAdd(run + 1, (unsigned long long)t[0]);
+    if (t[1]) atomicAdd(run + 4, (unsigned long long)t[1]);
+    if (t[2]) atomicMax(run + 6, (unsigned long long)t[2]);
+    if (t[3]) atomicMax(run + 7, (unsigned long long)t[3]);
+  }
 }
 
 }  // namespace
 
-void launch_sum_u32(int n, const uint32_t* x, uint64_t* out, hipStream_t s) {
-  if (n <= 0) return;
-  k_sum_u32<<<std::min(512, (n + 255) / 256), 256, 0, s>>>(n, x, out);
-}
-
 void launch_check_lists(const NodeWalkArgs& a, int nn, bool check_entries, hipStream_t s) {
   if (nn <= 0) return;
-  if (check_entries) k_check_lists<true><<<blocks_for(nn, 256), 256, 0, s>>>(a, nn);
-  else k_check_lists<false><<<blocks_for(nn, 256), 256, 0, s>>>(a, nn);
+  const unsigned nb = std::min<unsigned>(128, blocks_for(nn, 256));
+  if (check_entries) k_check_lists<true><<<nb, 256, 0, s>>>(a, nn);
+  else k_check_lists<false><<<nb, 256, 0, s>>>(a, nn);
 }
 
 void launch_leaf_stats(const LeafStatArgs& a, hipStream_t s) {

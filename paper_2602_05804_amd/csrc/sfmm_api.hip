@@ -39,7 +39,7 @@ enum BufId {
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
-  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_DIRPART, B_OVFLEAF,
+  B_LWM2LCNT, B_LWP2PCNT, B_LWM2LOFF, B_LWP2POFF, B_DIRPART, B_OVFLEAF, B_BIGPLAIN,
   B_COUNT
 };
 
@@ -57,7 +57,7 @@ struct Readback {
   int status[4];
   uint32_t level_off[kMaxDepthCap + 2];
   uint32_t level_int[kMaxDepthCap + 2];
-  uint64_t walk_tot[6];
+  uint64_t walk_tot[10];
   uint32_t items;
 };
 
@@ -85,9 +85,14 @@ struct sfmm_ctx {
   uint64_t m2l_cap = 0, p2p_cap = 0;
   int64_t items_from_walk = 0;  // P2P work items counted by the level walk
   uint32_t stack_cap = 0;
-  // per-leaf list slots of the level walk (entries; doubled, up to
-  // kSlotMax, while more than 1/16 of the leaves overflow them)
-  uint32_t slot_m = 512, slot_p = 256;
+  // per-leaf list slots of the level walk (entries; doubled, up to kSlotMax,
+  // while more than 1/32 of the leaves outgrow them), and nbig large slots
+  // for the leaves that do (the last walk's longest lists and an eighth more)
+  uint32_t slot_m = 512, slot_p = 384;
+  uint32_t nbig = 64, big_m = 4096, big_p = 4096;
+  // the last walk's slots, leaves that overflowed them, longest leaf lists
+  uint32_t walk_slot_m = 0, walk_slot_p = 0;
+  uint64_t leaf_overflow = 0, max_leaf_m = 0, max_leaf_p = 0;
   bool stats_pending = false;  // level walk: totals still on the device
   int nsys = 1;                // systems of the last build (a forest when > 1)
   int near_variant = 0;        // kernel shape of P2P (SFMM_NEAR_VARIANT)
@@ -496,7 +501,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 6))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 10))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
   for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_OVFLEAF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
@@ -514,9 +519,12 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   // meet pools too small for the walk)
   // (the leaves' slots come first in the estimates, then the internal
   // nodes' regions and the lists that overflow their slots)
-  const uint64_t est_m =
-      ctx->pool_init ? ctx->pool_init : (uint64_t)ctx->slot_m * nl + 64ull * nn + 2048;
-  const uint64_t est_p = ctx->pool_init ? ctx->pool_init : (uint64_t)ctx->slot_p * nl + 8ull * nl + 1024;
+  const uint64_t est_m = ctx->pool_init ? ctx->pool_init
+                                         : (uint64_t)ctx->slot_m * nl +
+                                               (uint64_t)ctx->nbig * ctx->big_m + 64ull * nn + 2048;
+  const uint64_t est_p = ctx->pool_init ? ctx->pool_init
+                                         : (uint64_t)ctx->slot_p * nl +
+                                               (uint64_t)ctx->nbig * ctx->big_p + 8ull * nl + 1024;
   ctx->m2l_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->m2l_cap, est_m));
   ctx->p2p_cap = std::min(kPoolMax, std::max<uint64_t>(ctx->p2p_cap, est_p));
   const uint32_t stack_min = (uint32_t)std::min(16384, 64 * (ctx->maxdepth + 4) + 256);
@@ -525,11 +533,13 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     // the leaf kernel's LDS (stack and staged P2P entries) stays within 64 KB
     const uint32_t slot_m = ctx->slot_m;
     const uint32_t slot_p = std::min<uint32_t>(ctx->slot_p, 16384u - ctx->stack_cap);
+    const uint32_t nbig = ctx->nbig, big_m = ctx->big_m, big_p = ctx->big_p;
+    if ((rc = ensure(ctx, B_BIGPLAIN, sizeof(uint32_t) * (size_t)nbig * big_p))) return rc;
     ctx->walk_attempts = attempt + 1;
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint64_t* tot = P<uint64_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 6, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 10, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     if (ctx->check_pools) {
       // every entry a consumer reads must then come from this walk: clear
@@ -572,6 +582,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.leaf_node = P<int32_t>(ctx, B_LEAFNODE);
     a.slot_m = slot_m;
     a.slot_p = slot_p;
+    a.nbig = nbig;
+    a.big_m = big_m;
+    a.big_p = big_p;
+    a.big_plain = P<uint32_t>(ctx, B_BIGPLAIN);
     a.ovf_leaf = P<uint32_t>(ctx, B_OVFLEAF);
     a.leaf_m2l_cnt = P<uint32_t>(ctx, B_LWM2LCNT);
     a.leaf_p2p_cnt = P<uint32_t>(ctx, B_LWP2PCNT);
@@ -584,11 +598,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     for (int k = 0; k <= ctx->maxdepth; ++k)
       launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
-    // M2L entries proper (the pool also holds the opened lists), P2P entries
-    launch_sum_u32(nn, a.m2l_cnt, tot + 1, s);
-    launch_sum_u32(nn, a.p2p_cnt, tot + 4, s);
     // no consumer reads a list unless it lies in the part of its pool this
-    // walk wrote (and, when checking, holds only node ids)
+    // walk wrote (and, when checking, holds only node ids); with the totals
+    // of M2L entries proper (the pool also holds the opened lists) and P2P
+    // entries, and the longest lists of a leaf
     launch_check_lists(a, nn, ctx->check_pools, s);
     Readback* hb = readback(ctx);
     if (!hb) return fail(ctx, SFMM_ENOMEM, "pinned host block for read-backs");
@@ -604,8 +617,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     ctx->items_from_walk = hb->items;
     // 64-bit totals: internal regions, the leaves' slots, then the lists that
     // overflow their slots
-    const uint64_t m2l_used = htot[0] + (uint64_t)slot_m * nl + htot[3];
-    const uint64_t p2p_used = (uint64_t)slot_p * nl + htot[2];
+    const uint64_t m2l_used = htot[0] + (uint64_t)slot_m * nl + (uint64_t)nbig * big_m + htot[3];
+    const uint64_t p2p_used = (uint64_t)slot_p * nl + (uint64_t)nbig * big_p + htot[2];
     const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
@@ -613,18 +626,37 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
         return fail(ctx, SFMM_EDEVICE, "an interaction list lies outside what the walk wrote");
       ctx->p2p_total = htot[4];
       ctx->m2l_unique = htot[1];
-      // larger slots for the next walk when many leaves overflowed these
-      // (and pools that hold them, so that walk still fits at once)
-      if (htot[5] * 16 > (uint64_t)nl) {
-        const uint32_t sm = std::min(kSlotMax, 2 * ctx->slot_m);
-        const uint32_t sp = std::min(kSlotMax / 2, 2 * ctx->slot_p);
-        ctx->m2l_cap = std::min(kPoolMax, std::max(ctx->m2l_cap,
-                                                   m2l_used + (uint64_t)(sm - slot_m) * nl));
-        ctx->p2p_cap = std::min(kPoolMax, std::max(ctx->p2p_cap,
-                                                   p2p_used + (uint64_t)(sp - slot_p) * nl));
-        ctx->slot_m = sm;
-        ctx->slot_p = sp;
+      ctx->walk_slot_m = slot_m;
+      ctx->walk_slot_p = slot_p;
+      ctx->leaf_overflow = htot[5];
+      ctx->max_leaf_m = htot[6];
+      ctx->max_leaf_p = htot[7];
+      // slots for the next walk: the normal ones doubled while more than
+      // 1/32 of the leaves outgrow them, large ones for this walk's longest
+      // lists and an eighth more, twice as many as were asked for (within
+      // 2^28 entries); pools that hold them, so that walk still fits at once
+      const uint64_t asked = std::max(htot[8], htot[9]);
+      uint32_t sm = slot_m, sp = ctx->slot_p;
+      if ((asked + htot[5]) * 32 > (uint64_t)nl) {
+        sm = std::min(kSlotMax, 2 * sm);
+        sp = std::min(kSlotMax / 2, 2 * sp);
       }
+      auto big_for = [](uint64_t longest, uint32_t slot) {
+        const uint64_t w = (longest + longest / 8 + 64) / 64 * 64;
+        return (uint32_t)std::min<uint64_t>(kBigSlotMax, std::max<uint64_t>(2ull * slot, w));
+      };
+      const uint32_t bm = big_for(htot[6], sm), bp = big_for(htot[7], sp);
+      uint64_t nb = std::min<uint64_t>(std::max<uint64_t>(64, 2 * asked), std::max(nl, 64));
+      nb = std::min<uint64_t>(nb, (1ull << 28) / ((uint64_t)bm + 2ull * bp));
+      ctx->slot_m = sm;
+      ctx->slot_p = sp;
+      ctx->nbig = (uint32_t)nb;
+      ctx->big_m = bm;
+      ctx->big_p = bp;
+      const uint64_t need_m = htot[0] + (uint64_t)sm * nl + nb * bm + htot[3];
+      const uint64_t need_p = (uint64_t)sp * nl + nb * bp + htot[2];
+      ctx->m2l_cap = std::min(kPoolMax, std::max(ctx->m2l_cap, need_m));
+      ctx->p2p_cap = std::min(kPoolMax, std::max(ctx->p2p_cap, need_p));
       return SFMM_OK;
     }
     if (attempt >= 16) return fail(ctx, SFMM_EUNSUPPORTED, "interaction walk did not fit");
@@ -1104,6 +1136,11 @@ int sfmm_get_stats(sfmm_ctx* ctx, sfmm_stats* out) {
   out->num_leaves = ctx->nleaves;
   out->max_depth = ctx->maxdepth;
   out->walk_attempts = ctx->walk_attempts;
+  out->leaf_slot_m2l = (int32_t)ctx->walk_slot_m;
+  out->leaf_slot_p2p = (int32_t)ctx->walk_slot_p;
+  out->n_leaf_overflow = (int64_t)ctx->leaf_overflow;
+  out->max_leaf_m2l = (int64_t)ctx->max_leaf_m;
+  out->max_leaf_p2p = (int64_t)ctx->max_leaf_p;
   if (ctx->have_lists && ctx->stats_pending) {
     // the level walk's per-leaf totals are only computed when asked for
     const int nl = (int)ctx->nleaves;

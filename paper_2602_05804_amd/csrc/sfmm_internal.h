@@ -77,6 +77,8 @@ constexpr uint32_t kNoList = 0xFFFFFFFFu;
 constexpr uint64_t kPoolMax = 0xF0000000ull;
 // the largest per-leaf M2L list slot of the level walk (P2P: half of it)
 constexpr uint32_t kSlotMax = 1024;
+// the largest of the level walk's large per-leaf list slots
+constexpr uint32_t kBigSlotMax = 1u << 18;
 
 // ---- scan ------------------------------------------------------------------
 // Exclusive prefix sum of `in` (n entries) into `out` (may alias in); the
@@ -201,17 +203,22 @@ struct NodeWalkArgs {
   uint64_t* lvl_off;    // [nn] its absolute offset in the M2L pool
   uint64_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
   uint64_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint64_t* run;      // [6] M2L pool used by internal nodes, M2L entries proper (the
+  uint64_t* run;      // [10] M2L pool used by internal nodes, M2L entries proper (the
                       // walk's sum), P2P pool used after the leaf slots, M2L pool
                       // used after the leaf slots, P2P entries proper, leaves whose
-                      // lists did not fit their slots
+                      // lists did not fit their slots, the longest M2L and P2P
+                      // lists of a leaf, large M2L and P2P slots asked for
   // leaves (walked after all levels, in leaf order): fixed slots of slot_m M2L
-  // and slot_p P2P entries per leaf; the lists of a leaf that do not fit go
-  // after all slots (leaf_*_cnt: their sizes, 0 for a leaf that fits;
-  // ovf_leaf: such leaves, [nleaves])
+  // and slot_p P2P entries per leaf, then nbig large slots of big_m and big_p
+  // entries for leaves that outgrow theirs (big_plain: [nbig * big_p] staging
+  // of the large P2P slots); the lists of a leaf that fit neither go after
+  // all slots (leaf_*_cnt: their sizes, 0 for a leaf that fits; ovf_leaf:
+  // such leaves, [nleaves])
   int nleaves;
   const int32_t* leaf_node;
   uint32_t slot_m, slot_p;
+  uint32_t nbig, big_m, big_p;
+  uint32_t* big_plain;
   uint32_t* ovf_leaf;
   uint32_t *leaf_m2l_cnt, *leaf_p2p_cnt;
   uint64_t *leaf_m2l_off, *leaf_p2p_off;
@@ -234,12 +241,12 @@ void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned
 // over leaves whose lists overflow their slots); scan_tmp holds
 // scan_tmp_elems(nleaves) words; LDS of (stack_cap + slot_p) words per wave
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s);
-// out[0] += sum of x[0..n) (out on the device)
-void launch_sum_u32(int n, const uint32_t* x, uint64_t* out, hipStream_t s);
 // after a walk: every node's M2L list and every leaf's P2P list must lie in
-// the part of its pool the walk wrote (run[0] + run[3] M2L entries, run[2]
-// P2P entries); with check_entries, each entry must also be a node of the
-// tree (below nn).  Sets ST_BADLIST in *status otherwise.
+// the part of its pool the walk wrote (the internal regions, the leaf slots,
+// then run[3] M2L and run[2] P2P entries); with check_entries, each entry
+// must also be a node of the tree (below nn).  Sets ST_BADLIST in *status
+// otherwise.  Adds the walk's M2L and P2P entries to run[1] and run[4], and
+// takes the longest M2L and P2P lists of a leaf into run[6] and run[7].
 void launch_check_lists(const NodeWalkArgs& a, int nn, bool check_entries, hipStream_t s);
 void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
 
