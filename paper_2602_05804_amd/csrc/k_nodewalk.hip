@@ -167,7 +167,7 @@ __device__ __forceinline__ void promote_m2l(const NodeWalkArgs& a, Emit& e) {
   b = __builtin_amdgcn_readfirstlane(b);
   e.big_m = true;
   if (b >= a.nbig) return;
-  const uint64_t nb = a.run[0] + (uint64_t)a.nleaves * a.slot_m + (uint64_t)b * a.big_m;
+  const uint64_t nb = a.leaf_base + (uint64_t)a.nleaves * a.slot_m + (uint64_t)b * a.big_m;
   __threadfence();  // the wave's own slot entries, read back below
   for (uint32_t i = lane; i < e.m2l_run; i += 64)
     if (nb + i < a.m2l_cap && e.m2l_base + i < a.m2l_cap) a.m2l_pool[nb + i] = a.m2l_pool[e.m2l_base + i];
@@ -435,59 +435,55 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
 
 // ---- internal nodes, level by level ---------------------------------------
 // The M2L pool region of an internal node is its tested list (1 for a root,
-// else exp[parent]); leaves take no room at their level (they are walked
-// after all levels); a node over two systems gets empty lists.  This is the
-// region of level node idx (and it clears the lists of a node it owns).
-// (in two halves: the loads of several nodes are issued before any of
-// their stores, which the compiler could not otherwise move loads past)
-struct RegionIn {
-  int v, flag, child;
-  uint32_t expv;
-};
-__device__ __forceinline__ RegionIn node_region_load(const NodeWalkArgs& a, uint32_t idx) {
-  RegionIn r;
-  r.v = a.level_nodes[idx];
-  const NodeInfo vi = a.info[r.v];
-  r.flag = a.node_flag ? (int)a.node_flag[r.v] : (vi.parent < 0 ? 1 : 2);
-  r.child = vi.child;
-  r.expv = (r.flag == 2 && vi.child >= 0) ? a.exp[vi.parent] : 0u;
-  return r;
-}
-__device__ __forceinline__ uint32_t node_region_store(const NodeWalkArgs& a, const RegionIn& r) {
-  const int v = r.v;
-  if (r.flag == 0) {
-    a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
-    a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
-    return 0;
-  }
-  if (r.child < 0) return 0;
-  a.p2p_cnt[v] = 0;
-  a.p2p_off[v] = 0;
-  return r.flag == 1 ? 1u : r.expv;  // (the top node of several systems has flag 0)
-}
-
-// fill pass of one level's internal nodes (one wave per node; the level
-// scan has placed their regions)
-__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level) {
+// else exp[parent]), known before the node is walked: the node's fixed slot
+// of int_slot entries (by its rank among the internal nodes), or for a
+// larger region a piece of the arena of int_big entries after all slots
+// (run[0] entries of it taken, by run[10] nodes).  Leaves take no room at
+// their level (they are walked after all levels); a node over two systems
+// gets empty lists.
+__global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int level, uint32_t rank0) {
   const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint32_t idx = beg + xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t idx = beg + b;
   if (idx >= end) return;
   const int v = a.level_nodes[idx];
   const NodeInfo vi = a.info[v];
   // a node over two systems (several systems solved together) is never
   // walked; the walk of each system starts at its own root
   const int flag = a.node_flag ? (int)a.node_flag[v] : (vi.parent < 0 ? 1 : 2);
-  if (flag == 0 || vi.child < 0) return;
-  const bool root = flag == 1;
   const uint32_t lane = threadIdx.x & 63;
+  if (flag == 0) {
+    if (lane == 0) {
+      a.m2l_cnt[v] = 0; a.open_cnt[v] = 0; a.p2p_cnt[v] = 0;
+      a.m2l_off[v] = 0; a.open_off[v] = 0; a.p2p_off[v] = 0;
+    }
+    return;
+  }
+  if (vi.child < 0) return;  // (the level's internal nodes come first)
+  if (lane == 0) { a.p2p_cnt[v] = 0; a.p2p_off[v] = 0; }
+  const bool root = flag == 1;
   const double* rv = a.rec + (int64_t)v * a.stride;
   const uint32_t region = root ? 1u : a.exp[vi.parent];
   Emit e{};
-  e.m2l_base = a.lvl_off[idx];
+  bool fits = true;
+  if (region <= a.int_slot) {
+    e.m2l_base = (uint64_t)(rank0 + b) * a.int_slot;
+  } else {
+    uint64_t t = 0;
+    if (lane == 0) {
+      t = atomicAdd(reinterpret_cast<unsigned long long*>(a.run), (unsigned long long)region);
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 10), 1ull);
+    }
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(t >> 32));
+    t = ((uint64_t)hi << 32) | lo;
+    e.m2l_base = (uint64_t)a.int_nodes * a.int_slot + t;
+    fits = t + region <= a.int_big;
+  }
   e.open_base = e.m2l_base + region;
   // a region that does not fit gets no offset (the walk goes on counting,
   // the host grows the pool and walks again)
-  const bool fits = e.open_base <= a.m2l_cap;
+  fits = fits && e.open_base <= a.m2l_cap;
   if (lane == 0) a.m2l_off[v] = fits ? (uint32_t)e.m2l_base : kNoList;
   if (root) {
     // (root, root) is opened: both root children meet both root children
@@ -552,7 +548,7 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
   const uint64_t nl = (uint64_t)a.nleaves;
   Emit e{};
   if (OVF) {
-    e.m2l_base = a.run[0] + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.leaf_m2l_off[l];
+    e.m2l_base = a.leaf_base + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.leaf_m2l_off[l];
     e.p2p_base = nl * a.slot_p + (uint64_t)a.nbig * a.big_p + a.leaf_p2p_off[l];
     e.p2p_total = a.p2p_cnt[v];  // from the first pass
     if (lane == 0) {
@@ -565,7 +561,7 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
     __syncthreads();  // (the stack is reused by the wave's next leaf)
     return;
   }
-  e.m2l_base = a.run[0] + (uint64_t)l * a.slot_m;
+  e.m2l_base = a.leaf_base + (uint64_t)l * a.slot_m;
   e.p2p_base = (uint64_t)l * a.slot_p;
   e.slot_m = a.slot_m;
   e.slot_p = a.slot_p;
@@ -623,118 +619,6 @@ __global__ __launch_bounds__(64) void k_nodewalk_leaves_ovf(NodeWalkArgs a) {
   for (uint64_t i = blockIdx.x; i < nov; i += gridDim.x) leaf_lists<true>(a, (int)a.ovf_leaf[i], stk);
 }
 
-// Places one level's internal nodes: an exclusive scan, in level order, of
-// their region sizes into absolute M2L pool offsets after everything the
-// levels above placed (levbase[level]); levbase[level + 1] and run[0] get
-// the new pool size.  A level of at most one tile (SCAN_T * SCAN_I nodes)
-// is one block; a larger one a pass of tile sums and a pass of tile scans.
-constexpr int SCAN_T = 1024;
-constexpr int SCAN_I = 4;
-constexpr int SCAN_W = SCAN_T / 64;
-constexpr uint32_t kScanTile = SCAN_T * SCAN_I;
-
-__device__ __forceinline__ uint64_t wave_incl_u64(uint64_t x) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint64_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
-
-// exclusive scan of c (per thread, SCAN_I consecutive items summed) over the
-// block; returns the exclusive prefix of this thread and the block total
-// (64-bit: a level's regions may add up to more than 2^32 entries)
-__device__ __forceinline__ uint64_t block_excl_u64(uint64_t c, uint64_t& total) {
-  __shared__ uint64_t wt[SCAN_W];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t inc = wave_incl_u64(c);
-  if (lane == 63) wt[w] = inc;
-  __syncthreads();
-  uint64_t pre = inc - c;
-  total = 0;
-  for (int k = 0; k < SCAN_W; ++k) {
-    const uint64_t t = wt[k];
-    if (k < w) pre += t;
-    total += t;
-  }
-  __syncthreads();
-  return pre;
-}
-
-// one tile: regions of tile t of the level, scanned, written at base
-__device__ __forceinline__ uint64_t scan_tile(const NodeWalkArgs& a, uint32_t beg, uint32_t end,
-                                              uint32_t t, uint64_t base, bool recompute) {
-  const uint32_t i0 = beg + t * kScanTile + threadIdx.x * SCAN_I;
-  uint32_t r[SCAN_I];
-  uint64_t c = 0;
-  if (recompute) {
-    RegionIn in[SCAN_I];
-#pragma unroll
-    for (int q = 0; q < SCAN_I; ++q)
-      if (i0 + q < end) in[q] = node_region_load(a, i0 + q);
-#pragma unroll
-    for (int q = 0; q < SCAN_I; ++q) r[q] = i0 + q < end ? node_region_store(a, in[q]) : 0u;
-  } else {
-#pragma unroll
-    for (int q = 0; q < SCAN_I; ++q) r[q] = i0 + q < end ? a.lvl_cnt32[i0 + q] : 0u;
-  }
-#pragma unroll
-  for (int q = 0; q < SCAN_I; ++q) c += r[q];
-  uint64_t total;
-  uint64_t o = base + block_excl_u64(c, total);
-#pragma unroll
-  for (int q = 0; q < SCAN_I; ++q) {
-    const uint32_t i = i0 + q;
-    if (i < end) a.lvl_off[i] = o;
-    o += r[q];
-  }
-  return total;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_level_scan_small(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint64_t base = a.levbase[level];
-  const uint64_t total = scan_tile(a, beg, end, 0, base, true);
-  if (threadIdx.x == 0) {
-    a.levbase[level + 1] = base + total;
-    a.run[0] = base + total;
-  }
-}
-
-// tile sums (and the regions, kept for the second pass)
-__global__ __launch_bounds__(SCAN_T) void k_level_tile_sums(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  const uint32_t i0 = beg + blockIdx.x * kScanTile + threadIdx.x * SCAN_I;
-  uint64_t c = 0;
-  RegionIn in[SCAN_I];
-#pragma unroll
-  for (int q = 0; q < SCAN_I; ++q)
-    if (i0 + q < end) in[q] = node_region_load(a, i0 + q);
-#pragma unroll
-  for (int q = 0; q < SCAN_I; ++q) {
-    const uint32_t i = i0 + q;
-    const uint32_t r = i < end ? node_region_store(a, in[q]) : 0u;
-    if (i < end) a.lvl_cnt32[i] = r;
-    c += r;
-  }
-  uint64_t total;
-  (void)block_excl_u64(c, total);
-  if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_level_tile_scan(NodeWalkArgs a, int level) {
-  const uint32_t beg = a.level_off[level], end = a.level_int[level];
-  uint64_t base = a.levbase[level];
-  for (uint32_t t = 0; t < blockIdx.x; ++t) base += a.tile_sum[t];  // a few tiles
-  const uint64_t total = scan_tile(a, beg, end, blockIdx.x, base, false);
-  if (threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) {
-    a.levbase[level + 1] = base + total;
-    a.run[0] = base + total;
-  }
-}
-
 __global__ void k_leaf_stats(LeafStatArgs a) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= a.nleaves) return;
@@ -768,7 +652,7 @@ template <bool ENTRIES>
 __global__ __launch_bounds__(256) void k_check_lists(NodeWalkArgs a, int nn) {
   __shared__ uint64_t red[4][4];
   const uint64_t nl = (uint64_t)a.nleaves;
-  const uint64_t used_m = a.run[0] + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.run[3];
+  const uint64_t used_m = a.leaf_base + nl * a.slot_m + (uint64_t)a.nbig * a.big_m + a.run[3];
   const uint64_t used_p = nl * a.slot_p + (uint64_t)a.nbig * a.big_p + a.run[2];
   const uint64_t lim_m = used_m < a.m2l_cap ? used_m : a.m2l_cap;
   const uint64_t lim_p = used_p < a.p2p_cap ? used_p : a.p2p_cap;
@@ -847,21 +731,11 @@ void launch_level_offsets(int nlev, int nb, int nn, const uint32_t* hist_scanned
                                                           level_int);
 }
 
-void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s) {
-  // (nodes_in_level: the level's internal nodes)
-  if (nodes_in_level <= 0) {
-    // an empty level still carries the pool size to the next one
-    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
-    return;
-  }
-  const unsigned tiles = blocks_for(nodes_in_level, (int)kScanTile);
-  if (tiles == 1) {
-    k_level_scan_small<<<1, SCAN_T, 0, s>>>(a, level);
-  } else {
-    k_level_tile_sums<<<tiles, SCAN_T, 0, s>>>(a, level);
-    k_level_tile_scan<<<tiles, SCAN_T, 0, s>>>(a, level);
-  }
-  k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level);
+void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, uint32_t rank0,
+                           hipStream_t s) {
+  // (nodes_in_level: the level's internal nodes, rank0 those of the levels above)
+  if (nodes_in_level <= 0) return;
+  k_nodewalk_internal<<<nodes_in_level, 64, 0, s>>>(a, level, rank0);
 }
 
 void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream_t s) {

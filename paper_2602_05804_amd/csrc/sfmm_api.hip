@@ -35,7 +35,7 @@ enum BufId {
   B_FAR, B_MOMPART, B_MOM, B_L2LCNT,
   B_NDEPTH, B_LEVKEY0, B_LEVKEY1, B_LEVIDS, B_LEVOFF, B_LEVNODES, B_LEVINT, B_M2LORD,
   B_NM2LOFF, B_NM2LCNT, B_NOPENOFF, B_NOPENCNT, B_NP2POFF, B_NP2PCNT,
-  B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT, B_LVLCNT, B_LVLOFF, B_TILESUM, B_LEVBASE,
+  B_M2LPOOL, B_NEXP, B_P2PPOOL, B_WALKTOT,
   B_REC32, B_PF32, B_PH32,
   B_SYSOFF, B_BOXES, B_SYS, B_SYSS, B_SYSSTART, B_SKEY0, B_SKEY1, B_SPOS0, B_SPOS1, B_NFLAG,
   B_LN, B_ITEMCNT, B_ITEMOFF, B_ITEMLEAF, B_ITEMK, B_PART, B_SRCTOT, B_SOFTCNT, B_ITEME0, B_ITEMC0, B_EXTMAP,
@@ -57,7 +57,7 @@ struct Readback {
   int status[4];
   uint32_t level_off[kMaxDepthCap + 2];
   uint32_t level_int[kMaxDepthCap + 2];
-  uint64_t walk_tot[10];
+  uint64_t walk_tot[11];
   uint32_t items;
 };
 
@@ -90,6 +90,10 @@ struct sfmm_ctx {
   // for the leaves that do (the last walk's longest lists and an eighth more)
   uint32_t slot_m = 512, slot_p = 384;
   uint32_t nbig = 64, big_m = 4096, big_p = 4096;
+  // slots of the internal nodes' regions (doubled, up to kIntSlotMax, while
+  // more than 1/32 of the internal nodes need the arena) and the arena
+  uint32_t int_slot = 256;
+  uint64_t int_big = 1u << 16;
   // the last walk's slots, leaves that overflowed them, longest leaf lists
   uint32_t walk_slot_m = 0, walk_slot_p = 0;
   uint64_t leaf_overflow = 0, max_leaf_m = 0, max_leaf_p = 0;
@@ -501,16 +505,12 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 10))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 11))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
   for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_OVFLEAF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
   for (int id : {B_LWM2LOFF, B_LWP2POFF})
     if ((rc = ensure(ctx, id, sizeof(uint64_t) * std::max(nl, 1)))) return rc;
-  if ((rc = ensure(ctx, B_LVLCNT, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_LVLOFF, sizeof(uint64_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_TILESUM, sizeof(uint64_t) * (nn / 4096 + 2)))) return rc;
-  if ((rc = ensure(ctx, B_LEVBASE, sizeof(uint64_t) * (kMaxDepthCap + 2)))) return rc;
   // pools keep the size of the largest walk so far, and never start below a
   // per-node estimate for this tree (a context may go from a small system to
   // a large one)
@@ -519,9 +519,12 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
   // meet pools too small for the walk)
   // (the leaves' slots come first in the estimates, then the internal
   // nodes' regions and the lists that overflow their slots)
+  const uint32_t int_nodes = (uint32_t)(nn - nl);
   const uint64_t est_m = ctx->pool_init ? ctx->pool_init
                                          : (uint64_t)ctx->slot_m * nl +
-                                               (uint64_t)ctx->nbig * ctx->big_m + 64ull * nn + 2048;
+                                               (uint64_t)ctx->nbig * ctx->big_m +
+                                               (uint64_t)ctx->int_slot * int_nodes + ctx->int_big +
+                                               8ull * nl + 2048;
   const uint64_t est_p = ctx->pool_init ? ctx->pool_init
                                          : (uint64_t)ctx->slot_p * nl +
                                                (uint64_t)ctx->nbig * ctx->big_p + 8ull * nl + 1024;
@@ -534,12 +537,15 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     const uint32_t slot_m = ctx->slot_m;
     const uint32_t slot_p = std::min<uint32_t>(ctx->slot_p, 16384u - ctx->stack_cap);
     const uint32_t nbig = ctx->nbig, big_m = ctx->big_m, big_p = ctx->big_p;
+    const uint32_t int_slot = ctx->int_slot;
+    const uint64_t int_big = ctx->int_big;
+    const uint64_t leaf_base = (uint64_t)int_slot * int_nodes + int_big;
     if ((rc = ensure(ctx, B_BIGPLAIN, sizeof(uint32_t) * (size_t)nbig * big_p))) return rc;
     ctx->walk_attempts = attempt + 1;
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint64_t* tot = P<uint64_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 10, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 11, s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     if (ctx->check_pools) {
       // every entry a consumer reads must then come from this walk: clear
@@ -570,11 +576,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.m2l_cap = ctx->m2l_cap;
     a.open_cap = a.m2l_cap;
     a.p2p_cap = ctx->p2p_cap;
-    a.lvl_cnt32 = P<uint32_t>(ctx, B_LVLCNT);
-    a.lvl_off = P<uint64_t>(ctx, B_LVLOFF);
-    a.tile_sum = P<uint64_t>(ctx, B_TILESUM);
-    a.levbase = P<uint64_t>(ctx, B_LEVBASE);
-    HIPCHK(hipMemsetAsync(a.levbase, 0, sizeof(uint64_t), s));
+    a.int_slot = int_slot;
+    a.int_nodes = int_nodes;
+    a.int_big = int_big;
+    a.leaf_base = leaf_base;
     a.run = tot;
     a.stack_cap = ctx->stack_cap;
     a.status = status;
@@ -595,8 +600,12 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     a.item_cnt = P<uint32_t>(ctx, B_ITEMCNT);
     a.item_off = P<uint32_t>(ctx, B_ITEMOFF);
     // internal nodes level by level, then every leaf
-    for (int k = 0; k <= ctx->maxdepth; ++k)
-      launch_nodewalk_level(a, k, (int)(ctx->level_int[k] - ctx->level_off[k]), s);
+    uint32_t rank0 = 0;
+    for (int k = 0; k <= ctx->maxdepth; ++k) {
+      const uint32_t nk = ctx->level_int[k] - ctx->level_off[k];
+      launch_nodewalk_level(a, k, (int)nk, rank0, s);
+      rank0 += nk;
+    }
     launch_nodewalk_leaves(a, P<uint32_t>(ctx, B_SCANTMP), s);
     // no consumer reads a list unless it lies in the part of its pool this
     // walk wrote (and, when checking, holds only node ids); with the totals
@@ -617,9 +626,10 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     ctx->items_from_walk = hb->items;
     // 64-bit totals: internal regions, the leaves' slots, then the lists that
     // overflow their slots
-    const uint64_t m2l_used = htot[0] + (uint64_t)slot_m * nl + (uint64_t)nbig * big_m + htot[3];
+    const uint64_t m2l_used = leaf_base + (uint64_t)slot_m * nl + (uint64_t)nbig * big_m + htot[3];
     const uint64_t p2p_used = (uint64_t)slot_p * nl + (uint64_t)nbig * big_p + htot[2];
-    const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap;
+    const bool arena_over = htot[0] > int_big;
+    const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap || arena_over;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
     if (!pool_over && !stack_over) {
       if (hstatus[0] & ST_BADLIST)
@@ -653,7 +663,13 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       ctx->nbig = (uint32_t)nb;
       ctx->big_m = bm;
       ctx->big_p = bp;
-      const uint64_t need_m = htot[0] + (uint64_t)sm * nl + nb * bm + htot[3];
+      // the internal nodes' slots likewise, the arena for what it held
+      uint32_t is = int_slot;
+      if (htot[10] * 32 > (uint64_t)int_nodes) is = std::min(kIntSlotMax, 2 * is);
+      const uint64_t ib = std::max<uint64_t>(1u << 16, htot[0] + htot[0] / 4 + 4096);
+      ctx->int_slot = is;
+      ctx->int_big = ib;
+      const uint64_t need_m = (uint64_t)is * int_nodes + ib + (uint64_t)sm * nl + nb * bm + htot[3];
       const uint64_t need_p = (uint64_t)sp * nl + nb * bp + htot[2];
       ctx->m2l_cap = std::min(kPoolMax, std::max(ctx->m2l_cap, need_m));
       ctx->p2p_cap = std::min(kPoolMax, std::max(ctx->p2p_cap, need_p));
@@ -666,11 +682,14 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       auto grow = [](uint64_t cap, uint64_t need) {
         return need > cap ? std::max<uint64_t>(2 * cap, need + need / 4 + 1024) : cap;
       };
-      if ((m2l_used > ctx->m2l_cap && ctx->m2l_cap >= kPoolMax) ||
+      // (a larger arena moves the leaves' slots up by as much)
+      if (arena_over) ctx->int_big = std::max<uint64_t>(2 * int_big, htot[0] + htot[0] / 4 + 4096);
+      const uint64_t need_m = m2l_used + (ctx->int_big - int_big);
+      if ((need_m > ctx->m2l_cap && ctx->m2l_cap >= kPoolMax) ||
           (p2p_used > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax))
         return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed the largest list pool (" +
                                                 std::to_string(kPoolMax) + " entries)");
-      ctx->m2l_cap = std::min(kPoolMax, grow(ctx->m2l_cap, m2l_used));
+      ctx->m2l_cap = std::min(kPoolMax, grow(ctx->m2l_cap, need_m));
       ctx->p2p_cap = std::min(kPoolMax, grow(ctx->p2p_cap, p2p_used));
     }
     if (stack_over) {

@@ -79,6 +79,8 @@ constexpr uint64_t kPoolMax = 0xF0000000ull;
 constexpr uint32_t kSlotMax = 1024;
 // the largest of the level walk's large per-leaf list slots
 constexpr uint32_t kBigSlotMax = 1u << 18;
+// the largest slot of an internal node's region in the level walk
+constexpr uint32_t kIntSlotMax = 4096;
 
 // ---- scan ------------------------------------------------------------------
 // Exclusive prefix sum of `in` (n entries) into `out` (may alias in); the
@@ -199,15 +201,17 @@ struct NodeWalkArgs {
   // grows the pools and walks again
   uint64_t m2l_cap, open_cap, p2p_cap;
   uint32_t* exp;  // per internal node: tested-list size of each of its children
-  uint32_t* lvl_cnt32;  // [nn] M2L pool region of each internal node, in level order
-  uint64_t* lvl_off;    // [nn] its absolute offset in the M2L pool
-  uint64_t* tile_sum;   // [nn / 4096 + 1] region sums per scan tile of a level
-  uint64_t* levbase;    // [levels + 1] M2L pool size before each level
-  uint64_t* run;      // [10] M2L pool used by internal nodes, M2L entries proper (the
+  // the regions of the internal nodes: int_nodes slots of int_slot entries,
+  // then an arena of int_big entries for larger ones; the leaves' slots
+  // start at leaf_base = int_nodes * int_slot + int_big
+  uint32_t int_slot, int_nodes;
+  uint64_t int_big, leaf_base;
+  uint64_t* run;      // [11] arena entries taken by internal nodes, M2L entries proper (the
                       // walk's sum), P2P pool used after the leaf slots, M2L pool
                       // used after the leaf slots, P2P entries proper, leaves whose
                       // lists did not fit their slots, the longest M2L and P2P
-                      // lists of a leaf, large M2L and P2P slots asked for
+                      // lists of a leaf, large M2L and P2P slots asked for,
+                      // internal nodes in the arena
   // leaves (walked after all levels, in leaf order): fixed slots of slot_m M2L
   // and slot_p P2P entries per leaf, then nbig large slots of big_m and big_p
   // entries for leaves that outgrow theirs (big_plain: [nbig * big_p] staging
@@ -248,7 +252,8 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
 // otherwise.  Adds the walk's M2L and P2P entries to run[1] and run[4], and
 // takes the longest M2L and P2P lists of a leaf into run[6] and run[7].
 void launch_check_lists(const NodeWalkArgs& a, int nn, bool check_entries, hipStream_t s);
-void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, hipStream_t s);
+void launch_nodewalk_level(const NodeWalkArgs& a, int level, int nodes_in_level, uint32_t rank0,
+                           hipStream_t s);
 
 // per-leaf statistics of node lists: replicated M2L count, L2L count, pairs
 struct LeafStatArgs {
