@@ -543,47 +543,75 @@ __global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __
 
 // item_leaf / item_k of every item, and for each item after a leaf's first
 // the list entry holding its first source and that entry's start in the
-// flattened order (item k starts at source k * kP2PItem).  One wave per leaf.
+// flattened order (item k starts at source k * kP2PItem).  One wave per
+// kFillLeaves leaves: a lane per leaf for the first two, then the whole wave
+// scans the list of each of its leaves with more than one item (a few in a
+// hundred, so a wave meets about one).
+constexpr int kFillLeaves = 16;
+constexpr int kFillGroups = 8;
 template <bool NODE>
 __global__ __launch_bounds__(64) void k_p2p_items_fill(NearArgs a, int32_t* __restrict__ item_leaf,
                                                        uint32_t* __restrict__ item_k,
                                                        uint32_t* __restrict__ item_e0,
                                                        uint32_t* __restrict__ item_c0) {
-  const int l = blockIdx.x;
   const int lane = threadIdx.x;
-  const uint32_t b = a.item_off[l], e = a.item_off[l + 1];
-  for (uint32_t t = b + lane; t < e; t += 64) {
-    item_leaf[t] = l;
-    item_k[t] = t - b;
+  const int lme = blockIdx.x * kFillLeaves + lane;
+  uint32_t nb = 0, ne = 0;
+  if (lane < kFillLeaves && lme < a.nleaves) {
+    nb = a.item_off[lme];
+    ne = a.item_off[lme + 1];
+    for (uint32_t t = nb; t < ne; ++t) {
+      item_leaf[t] = lme;
+      item_k[t] = t - nb;
+    }
   }
-  if (e - b <= 1) return;  // (uniform)
-  uint64_t e0, e1;
-  const int32_t* list;
-  if (NODE) {
-    const int node = a.leaf_node[l];
-    e0 = a.node_p2p_off[node];
-    e1 = e0 + a.node_p2p_cnt[node];
-    list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
-  } else {
-    e0 = a.p2p_off[l];
-    e1 = a.p2p_off[l + 1];
-    list = a.p2p_list;
-  }
-  uint32_t carry = 0;
-  for (uint64_t c0 = e0; c0 < e1; c0 += 64) {
-    const bool in = c0 + lane < e1;
-    const uint32_t c = in ? (uint32_t)a.info[list[c0 + lane]].cnt : 0u;
-    const int incl = wave_incl_scan((int)c);
-    const uint32_t fe = carry + (uint32_t)incl, fb = fe - c;
-    if (in && c > 0) {
-      uint32_t k = (fb + kP2PItem - 1) / kP2PItem;
-      if (k == 0) k = 1;
-      for (; k * kP2PItem < fe && b + k < e; ++k) {
-        item_e0[b + k] = (uint32_t)(c0 + lane);
-        item_c0[b + k] = fb;
+  uint64_t multi = __ballot(ne - nb > 1);
+  while (multi) {
+    const int q = __builtin_ctzll(multi);
+    multi &= multi - 1;
+    const int l = blockIdx.x * kFillLeaves + q;
+    const uint32_t b = (uint32_t)__shfl((int)nb, q, 64), e = (uint32_t)__shfl((int)ne, q, 64);
+    uint64_t e0, e1;
+    const int32_t* list;
+    if (NODE) {
+      const int node = a.leaf_node[l];
+      e0 = a.node_p2p_off[node];
+      e1 = e0 + a.node_p2p_cnt[node];
+      list = reinterpret_cast<const int32_t*>(a.node_p2p_pool);
+    } else {
+      e0 = a.p2p_off[l];
+      e1 = a.p2p_off[l + 1];
+      list = a.p2p_list;
+    }
+    // kFillGroups groups of 64 entries per step, their loads issued together
+    // (the longest lists, a few thousand entries, set this kernel's time)
+    uint32_t carry = 0;
+    for (uint64_t c0 = e0; c0 < e1; c0 += 64 * kFillGroups) {
+      int src[kFillGroups];
+#pragma unroll
+      for (int u = 0; u < kFillGroups; ++u) src[u] = c0 + 64 * u + lane < e1 ? list[c0 + 64 * u + lane] : -1;
+      uint32_t cu[kFillGroups];
+#pragma unroll
+      for (int u = 0; u < kFillGroups; ++u) cu[u] = src[u] >= 0 ? (uint32_t)a.info[src[u]].cnt : 0u;
+#pragma unroll
+      for (int u = 0; u < kFillGroups; ++u) {
+        const uint64_t g0 = c0 + 64 * u;
+        if (g0 >= e1) break;  // (uniform)
+        const bool in = g0 + lane < e1;
+        const uint32_t c = cu[u];
+        const int incl = wave_incl_scan((int)c);
+        const uint32_t fe = carry + (uint32_t)incl, fb = fe - c;
+        if (in && c > 0) {
+          uint32_t k = (fb + kP2PItem - 1) / kP2PItem;
+          if (k == 0) k = 1;
+          for (; k * kP2PItem < fe && b + k < e; ++k) {
+            item_e0[b + k] = (uint32_t)(g0 + lane);
+            item_c0[b + k] = fb;
+          }
+        }
+        carry += (uint32_t)__shfl(incl, 63, 64);
       }
     }
-    carry += (uint32_t)__shfl(incl, 63, 64);
   }
 }
 
@@ -678,10 +706,11 @@ void launch_p2p_items_count(bool node_lists, const NearArgs& a, uint32_t* src_to
 void launch_p2p_items_fill(bool node_lists, const NearArgs& a, int32_t* item_leaf,
                            uint32_t* item_k, uint32_t* item_e0, uint32_t* item_c0, hipStream_t s) {
   if (a.nleaves <= 0) return;
+  const unsigned nb = (unsigned)((a.nleaves + kFillLeaves - 1) / kFillLeaves);
   if (node_lists)
-    k_p2p_items_fill<true><<<a.nleaves, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
+    k_p2p_items_fill<true><<<nb, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
   else
-    k_p2p_items_fill<false><<<a.nleaves, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
+    k_p2p_items_fill<false><<<nb, 64, 0, s>>>(a, item_leaf, item_k, item_e0, item_c0);
 }
 
 void launch_p2p_reduce(const NearArgs& a, int ls, hipStream_t s) {
