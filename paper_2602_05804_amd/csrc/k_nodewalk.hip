@@ -420,14 +420,33 @@ __device__ void walk_leaf(const NodeWalkArgs& a, int v, const double* rv, const 
       else { t0[u] = (uint32_t)cb[u]; t1[u] = (uint32_t)cb[u] + 1u; nt[u] = 2; }
     }
     ok = leaf_step<W, U>(a, v, rv, t0, t1, nt, e, stk, sp);
+    // the stack is drained U groups of 64 at a time while it holds more than
+    // one group and has room for what they may push (2 per entry), else one
+    // group at a time (the leaves with the longest lists lower deep stacks,
+    // and their walks set the pass's time)
     while (ok && sp > 0) {
-      const uint32_t k = sp < 64u ? sp : 64u;
-      uint32_t d0[1] = {0}, d1[1] = {0};
-      int dn[1] = {lane < k ? 1 : 0};
-      if (dn[0]) d0[0] = stk[sp - k + lane];
-      __syncthreads();
-      sp -= k;
-      ok = leaf_step<W, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
+      const uint32_t kw = sp < 64u * U ? sp : 64u * U;
+      if (sp > 64u && sp + kw <= a.stack_cap) {  // (uniform)
+        uint32_t d0[U], d1[U];
+        int dn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          d1[u] = 0;
+          dn[u] = 64u * u + lane < kw ? 1 : 0;
+          d0[u] = dn[u] ? stk[sp - kw + 64u * u + lane] : 0u;
+        }
+        __syncthreads();
+        sp -= kw;
+        ok = leaf_step<W, U>(a, v, rv, d0, d1, dn, e, stk, sp);
+      } else {
+        const uint32_t k = sp < 64u ? sp : 64u;
+        uint32_t d0[1] = {0}, d1[1] = {0};
+        int dn[1] = {lane < k ? 1 : 0};
+        if (dn[0]) d0[0] = stk[sp - k + lane];
+        __syncthreads();
+        sp -= k;
+        ok = leaf_step<W, 1>(a, v, rv, d0, d1, dn, e, stk, sp);
+      }
     }
   }
   if (!ok && lane == 0) atomicOr(status, ST_OVERFLOW);
