@@ -167,7 +167,18 @@ int sfmm_config_default(sfmm_config* cfg);
 
 /* Create a context on HIP device `device` that enqueues its work on
  * `hip_stream` (a hipStream_t; NULL = the default stream).  cfg may be NULL
- * (defaults).  On success *out owns nothing yet; the first build allocates. */
+ * (defaults).  On success *out owns nothing yet; the first build allocates.
+ * Environment read here (measurement and tests; SFMM_EINVAL for a bad value):
+ *   SFMM_NEAR_VARIANT=v  P2P kernel shape v instead of cfg->near_kernel;
+ *   SFMM_OVERLAP=0|1|2   run the P2P kernel on a second stream of the
+ *                        context beside the far field (1: P2P queued first,
+ *                        2: far field first; 0, the default: one stream);
+ *   SFMM_LEAF_SLOTS=m,p  first per-leaf M2L / P2P list slots of the level
+ *                        walk (1..1024 / 1..512; later walks size them from
+ *                        the lists they meet);
+ *   SFMM_CHECK_POOLS=1   clear the list pools before each walk and check
+ *                        every list entry after it;
+ *   SFMM_POOL_INIT=k     start the list pools at k entries. */
 int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config* cfg);
 
 /* Release every device buffer of the context; ctx may be NULL. */
