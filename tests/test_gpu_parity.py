@@ -331,6 +331,41 @@ def test_leaf_slots_overflow_checked(torch, P, orc, monkeypatch, precision):
         assert _rms_rel(acc, oa) <= 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_near_beside_far_same_results(torch, P, monkeypatch, precision):
+    """The P2P kernel on a second stream beside the far field (SFMM_OVERLAP,
+    either launch order) gives bit-identical results and statistics to the
+    one-stream solve, over two solves of one context."""
+    print(f"case: near field beside the far field, {precision}", flush=True)
+    x, m, h = workloads.plummer(6000, seed=5)
+    xd, md, hd = dev(torch, x, m, h)
+    cfg = dict(leaf_size=16, near_kernel=13) if precision == "fp64" else {}
+    ref = None
+    for ov in ("0", "1", "2"):
+        monkeypatch.setenv("SFMM_OVERLAP", ov)
+        s = P.Solver(**cfg)
+        for _ in range(2):
+            acc, pot = s.solve(xd, md, hd, theta=0.5, precision=precision)
+            torch.cuda.synchronize()
+            out = (acc.cpu().numpy(), pot.cpu().numpy(), s.stats()["n_p2p_soft_pairs"])
+            if ref is None:
+                ref = out
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), ov
+            assert out[2] == ref[2]
+        s.close()
+
+
+@pytest.mark.parametrize("var,value", [("SFMM_OVERLAP", "3"), ("SFMM_LEAF_SLOTS", "0,8"),
+                                       ("SFMM_LEAF_SLOTS", "8,600"), ("SFMM_LEAF_SLOTS", "8")])
+def test_bad_environment_refused(torch, P, monkeypatch, var, value):
+    """An out-of-range measurement switch makes sfmm_create fail with
+    SFMM_EINVAL instead of being ignored."""
+    print(f"case: {var}={value} refused", flush=True)
+    monkeypatch.setenv(var, value)
+    with pytest.raises(P.SfmmError):
+        P.Solver()
+
+
 def test_theta_to_zero_equals_direct(torch, P, orc):
     print("case: theta->0 direct", flush=True)
     x, m, h = workloads.plummer(4096, seed=1)
