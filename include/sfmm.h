@@ -173,9 +173,10 @@ int sfmm_config_default(sfmm_config* cfg);
  *   SFMM_OVERLAP=0|1|2   run the P2P kernel on a second stream of the
  *                        context beside the far field (1: P2P queued first,
  *                        2: far field first; 0, the default: one stream);
- *   SFMM_LEAF_SLOTS=m,p  first per-leaf M2L / P2P list slots of the level
- *                        walk (1..1024 / 1..512; later walks size them from
- *                        the lists they meet);
+ *   SFMM_LEAF_SLOTS=m,p[,i]  first per-leaf M2L / P2P list slots of the
+ *                        level walk (1..1024 / 1..512) and, optionally, the
+ *                        internal nodes' region slots (1..4096); later walks
+ *                        adapt them to the lists they meet;
  *   SFMM_CHECK_POOLS=1   clear the list pools before each walk and check
  *                        every list entry after it;
  *   SFMM_POOL_INIT=k     start the list pools at k entries. */

@@ -1043,16 +1043,19 @@ int sfmm_create(sfmm_ctx** out, int device, void* hip_stream, const sfmm_config*
   if (const char* cp = std::getenv("SFMM_CHECK_POOLS")) ctx->check_pools = std::atoi(cp) != 0;
   if (const char* pi = std::getenv("SFMM_POOL_INIT"))
     ctx->pool_init = (uint64_t)std::max(0ll, std::atoll(pi));
-  // first per-leaf list slots "m,p" (tests meet leaves that overflow them)
+  // first per-leaf list slots "m,p", optionally ",i" for the internal nodes'
+  // slots (tests meet lists that overflow them)
   if (const char* ls = std::getenv("SFMM_LEAF_SLOTS")) {
-    unsigned sm = 0, sp = 0;
-    if (std::sscanf(ls, "%u,%u", &sm, &sp) != 2 || sm < 1 || sm > kSlotMax || sp < 1 ||
-        sp > kSlotMax / 2) {
+    unsigned sm = 0, sp = 0, si = ctx->int_slot;
+    const int got = std::sscanf(ls, "%u,%u,%u", &sm, &sp, &si);
+    if (got < 2 || sm < 1 || sm > kSlotMax || sp < 1 || sp > kSlotMax / 2 || si < 1 ||
+        si > kIntSlotMax) {
       delete ctx;
       return SFMM_EINVAL;
     }
     ctx->slot_m = sm;
     ctx->slot_p = sp;
+    ctx->int_slot = si;
   }
   if (const char* ov = std::getenv("SFMM_OVERLAP")) {
     const int v = std::atoi(ov);

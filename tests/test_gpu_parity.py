@@ -300,11 +300,13 @@ def test_pools_regrow_checked(torch, P, orc, monkeypatch, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_leaf_slots_overflow_checked(torch, P, orc, monkeypatch, precision):
-    """Per-leaf list slots far too small (8 entries each): most leaves' lists
-    are written by the second leaf pass, after all slots.  Every list a
-    consumer reads is checked to lie in what this walk wrote and to hold node
-    ids only; the results are the oracle's, and bit-identical to a solve with
-    the default slots (the same lists, in the same order)."""
+    """Per-leaf list slots and internal-node region slots far too small (8
+    entries each): most leaves' lists go to the large slots or the second
+    leaf pass, most internal nodes' regions to the arena, which overflows and
+    grows (the walk is repeated).  Every list a consumer reads is checked to
+    lie in what this walk wrote and to hold node ids only; the results are the
+    oracle's, and bit-identical to a solve with the default slots (the same
+    lists, in the same order)."""
     print(f"case: leaf slots of 8 entries, checked, {precision}", flush=True)
     x, m, h = workloads.plummer(6000, seed=3)
     xd, md, hd = dev(torch, x, m, h)
@@ -314,12 +316,13 @@ def test_leaf_slots_overflow_checked(torch, P, orc, monkeypatch, precision):
     torch.cuda.synchronize()
     st0 = s0.stats()
     s0.close()
-    monkeypatch.setenv("SFMM_LEAF_SLOTS", "8,8")
+    monkeypatch.setenv("SFMM_LEAF_SLOTS", "8,8,8")
     s = P.Solver()
     acc, pot = s.solve(xd, md, hd, theta=0.5, precision=precision)
     torch.cuda.synchronize()
     st = s.stats()
     s.close()
+    assert st["walk_attempts"] >= 2 and st["n_leaf_overflow"] > 0
     acc = acc.cpu().numpy(); pot = pot.cpu().numpy()
     assert np.array_equal(acc, a0.cpu().numpy()) and np.array_equal(pot, p0.cpu().numpy())
     for k in ("n_m2l_unique", "n_p2p_leaf_pairs", "n_p2p_pairs", "n_p2p_soft_pairs"):
@@ -356,7 +359,8 @@ def test_near_beside_far_same_results(torch, P, monkeypatch, precision):
 
 
 @pytest.mark.parametrize("var,value", [("SFMM_OVERLAP", "3"), ("SFMM_LEAF_SLOTS", "0,8"),
-                                       ("SFMM_LEAF_SLOTS", "8,600"), ("SFMM_LEAF_SLOTS", "8")])
+                                       ("SFMM_LEAF_SLOTS", "8,600"), ("SFMM_LEAF_SLOTS", "8"),
+                                       ("SFMM_LEAF_SLOTS", "8,8,0")])
 def test_bad_environment_refused(torch, P, monkeypatch, var, value):
     """An out-of-range measurement switch makes sfmm_create fail with
     SFMM_EINVAL instead of being ignored."""
