@@ -509,7 +509,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 
 // per leaf, the particles over its P2P list entries and its work items:
 // max(1, ceil(sources / kP2PItem)).  One wave per leaf.  (The level walk
-// computes both in its leaf count pass.)
+// computes both in its leaf pass.)
 template <bool NODE>
 __global__ __launch_bounds__(64) void k_p2p_items_count(NearArgs a, uint32_t* __restrict__ src_total,
                                                         uint32_t* __restrict__ cnt) {

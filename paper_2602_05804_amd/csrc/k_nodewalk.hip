@@ -18,16 +18,17 @@
 // M2L lists of p_0 .. p_d plus L's P2P list (same pairs; the order inside a
 // depth differs).
 //
-// One wave (a 64-thread block) per node; lanes take 64 sources at a time.
-// Each level runs three kernels: a count pass (list sizes per node), a
-// one-block scan that places every node's lists after those of the nodes
-// before it (running pool totals stay on the device), and a fill pass that
-// repeats the tests and writes in lane order.  The layout of the pools is
-// therefore the same on every run.  An internal node's M2L and opened lists
-// together are its tested list, whose size its parent records while walking
-// (opened leaves once, opened internal nodes twice), so internal nodes skip
-// the count pass: one region of the M2L pool holds both lists, M2L entries
-// from the front and opened entries from the back.
+// One wave (a 64-thread block) per node; lanes take 64 sources at a time,
+// and entries are written in lane order.  An internal node's M2L and opened
+// lists together are its tested list, whose size its parent records while
+// walking (opened leaves once, opened internal nodes twice).  So one region
+// of the M2L pool holds both lists, M2L entries from the front and opened
+// entries from the back, and its size is known before the node is walked:
+// the region is the node's fixed slot, or a piece of an arena when larger.
+// Each level is then one launch.  The leaves come after all levels, in one
+// pass that writes each leaf's lists into fixed per-leaf slots (or a few
+// large slots).  A second pass, at exact offsets, takes only the leaves that
+// fit neither.
 #include "sfmm_internal.h"
 
 namespace sfmm {
