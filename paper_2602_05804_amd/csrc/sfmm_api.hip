@@ -646,31 +646,43 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       // lists and an eighth more, twice as many as were asked for (within
       // 2^28 entries); pools that hold them, so that walk still fits at once
       const uint64_t asked = std::max(htot[8], htot[9]);
-      uint32_t sm = slot_m, sp = ctx->slot_p;
-      if ((asked + htot[5]) * 32 > (uint64_t)nl) {
-        sm = std::min(kSlotMax, 2 * sm);
-        sp = std::min(kSlotMax / 2, 2 * sp);
-      }
       auto big_for = [](uint64_t longest, uint32_t slot) {
         const uint64_t w = (longest + longest / 8 + 64) / 64 * 64;
         return (uint32_t)std::min<uint64_t>(kBigSlotMax, std::max<uint64_t>(2ull * slot, w));
       };
-      const uint32_t bm = big_for(htot[6], sm), bp = big_for(htot[7], sp);
-      uint64_t nb = std::min<uint64_t>(std::max<uint64_t>(64, 2 * asked), std::max(nl, 64));
-      nb = std::min<uint64_t>(nb, (1ull << 28) / ((uint64_t)bm + 2ull * bp));
+      const uint64_t ib = std::max<uint64_t>(1u << 16, htot[0] + htot[0] / 4 + 4096);
+      uint32_t sm = slot_m, sp = ctx->slot_p, is = int_slot, bm = 0, bp = 0;
+      uint64_t nb = 0, need_m = 0, need_p = 0;
+      auto plan = [&]() {
+        bm = big_for(htot[6], sm);
+        bp = big_for(htot[7], sp);
+        nb = std::min<uint64_t>(std::max<uint64_t>(64, 2 * asked), std::max(nl, 64));
+        nb = std::min<uint64_t>(nb, (1ull << 28) / ((uint64_t)bm + 2ull * bp));
+        need_m = (uint64_t)is * int_nodes + ib + (uint64_t)sm * nl + nb * bm + htot[3];
+        need_p = (uint64_t)sp * nl + nb * bp + htot[2];
+      };
+      // normal slots double while more than 1/32 of the leaves (or internal
+      // nodes) outgrow them, unless that would fill more than half of the
+      // largest pool: then this walk's slots stay
+      if ((asked + htot[5]) * 32 > (uint64_t)nl) {
+        sm = std::min(kSlotMax, 2 * sm);
+        sp = std::min(kSlotMax / 2, 2 * sp);
+      }
+      if (htot[10] * 32 > (uint64_t)int_nodes) is = std::min(kIntSlotMax, 2 * is);
+      plan();
+      if (need_m > kPoolMax / 2 || need_p > kPoolMax / 2) {
+        sm = slot_m;
+        sp = ctx->slot_p;
+        is = int_slot;
+        plan();
+      }
       ctx->slot_m = sm;
       ctx->slot_p = sp;
+      ctx->int_slot = is;
       ctx->nbig = (uint32_t)nb;
       ctx->big_m = bm;
       ctx->big_p = bp;
-      // the internal nodes' slots likewise, the arena for what it held
-      uint32_t is = int_slot;
-      if (htot[10] * 32 > (uint64_t)int_nodes) is = std::min(kIntSlotMax, 2 * is);
-      const uint64_t ib = std::max<uint64_t>(1u << 16, htot[0] + htot[0] / 4 + 4096);
-      ctx->int_slot = is;
       ctx->int_big = ib;
-      const uint64_t need_m = (uint64_t)is * int_nodes + ib + (uint64_t)sm * nl + nb * bm + htot[3];
-      const uint64_t need_p = (uint64_t)sp * nl + nb * bp + htot[2];
       ctx->m2l_cap = std::min(kPoolMax, std::max(ctx->m2l_cap, need_m));
       ctx->p2p_cap = std::min(kPoolMax, std::max(ctx->p2p_cap, need_p));
       return SFMM_OK;
@@ -686,9 +698,18 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       if (arena_over) ctx->int_big = std::max<uint64_t>(2 * int_big, htot[0] + htot[0] / 4 + 4096);
       const uint64_t need_m = m2l_used + (ctx->int_big - int_big);
       if ((need_m > ctx->m2l_cap && ctx->m2l_cap >= kPoolMax) ||
-          (p2p_used > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax))
+          (p2p_used > ctx->p2p_cap && ctx->p2p_cap >= kPoolMax)) {
+        // slots that leave no room: a quarter of their size, and walk again
+        if (slot_m > 16 || ctx->slot_p > 16 || int_slot > 16 || ctx->nbig > 64) {
+          ctx->slot_m = std::max(16u, slot_m / 4);
+          ctx->slot_p = std::max(16u, ctx->slot_p / 4);
+          ctx->int_slot = std::max(16u, int_slot / 4);
+          ctx->nbig = 64;
+          continue;
+        }
         return fail(ctx, SFMM_EUNSUPPORTED, "interaction lists exceed the largest list pool (" +
                                                 std::to_string(kPoolMax) + " entries)");
+      }
       ctx->m2l_cap = std::min(kPoolMax, grow(ctx->m2l_cap, need_m));
       ctx->p2p_cap = std::min(kPoolMax, grow(ctx->p2p_cap, p2p_used));
     }

@@ -568,7 +568,9 @@ def test_fp32c_cloud_full_size(torch, P, cloud8e6, theta):
     """The clumpy cloud (8e6 particles, softening lengths over 1.7 decades) in
     FP32C at each stated opening angle: 300 sampled targets against the FP64
     oracle, RMS relative error <= 1e-6, momentum residual <= 1e-7; every list
-    entry checked to come from the walk."""
+    entry checked to come from the walk.  A second solve in the same context
+    (list slots sized from the first walk, within the largest pool) gives the
+    same results bit for bit."""
     import os
 
     print(f"case: fp32c cloud 8e6 theta={theta} sampled", flush=True)
@@ -586,8 +588,11 @@ def test_fp32c_cloud_full_size(torch, P, cloud8e6, theta):
     tg = np.random.default_rng(7).choice(len(m), 300, replace=False)
     a = acc.cpu().numpy()[tg]
     p = pot.cpu().numpy()[tg]
+    acc2, pot2 = s.solve(xd, md, hd, theta=theta, precision="fp32c")
+    torch.cuda.synchronize()
+    assert np.array_equal(acc2.cpu().numpy()[tg], a) and np.array_equal(pot2.cpu().numpy()[tg], p)
     s.close()
-    del acc, pot, xd, md, hd
+    del acc, pot, acc2, pot2, xd, md, hd
     oa, op, _ = t.solve(theta, targets=tg)
     assert _rms_rel(a, oa) <= 1e-6
     assert np.sqrt((((p - op) / op) ** 2).mean()) <= 1e-6
