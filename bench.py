@@ -156,6 +156,9 @@ def main():
                          "size, its error measured over every particle by the CPU oracle)")
     ap.add_argument("--fp32c-leaf-size", type=int, default=10,
                     help="leaf size of the FP32C block")
+    ap.add_argument("--fp32c-same-near-kernel", type=int, default=6,
+                    help="P2P shape of the FP32C solve on the headline input (leaf size "
+                         "16: shape 6 is the faster FP32C shape there)")
     ap.add_argument("--serve-leaf-size", type=int, default=10,
                     help="leaf size of the serving runs without tuned settings")
     ap.add_argument("--walk", choices=["level", "leaf"], default="level",
@@ -403,7 +406,8 @@ def fp32c_same_workload(args, xd, md, hd, wl):
     import paper_2602_05804_amd as sfmm
 
     log("fp32c on the headline workload")
-    s = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far=args.far)
+    s = sfmm.Solver(leaf_size=args.leaf_size, walk=args.walk, far=args.far,
+                    near_kernel=args.fp32c_same_near_kernel)
     a32 = torch.empty((args.n, 3), dtype=torch.float64, device="cuda")
     p32 = torch.empty((args.n,), dtype=torch.float64, device="cuda")
     for _ in range(max(args.warmup, 1)):
@@ -420,7 +424,8 @@ def fp32c_same_workload(args, xd, md, hd, wl):
     ph = s.timing_stop()
     st = s.stats()
     s.close()
-    line = {"workload": wl, "leaf_size": args.leaf_size, "value": args.n / dt,
+    line = {"workload": wl, "leaf_size": args.leaf_size,
+            "near_kernel": args.fp32c_same_near_kernel, "value": args.n / dt,
             "unit": "particles/s", "ms_per_step": dt * 1e3,
             "phases_ms": {k: round(float(np.mean([q[k] for q in ph])), 4) for k in sfmm.PHASES},
             "momentum_residual": float(np.linalg.norm(st["momentum"]) / st["momentum_abs"]),
