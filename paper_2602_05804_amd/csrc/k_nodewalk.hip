@@ -537,7 +537,8 @@ __global__ __launch_bounds__(64) void k_nodewalk_internal(NodeWalkArgs a, int le
 // leaf).  One pass writes each leaf's lists into fixed slots (slot_m M2L
 // entries per leaf after the internal nodes' regions in the M2L pool, slot_p
 // P2P entries per leaf at the front of the P2P pool).  A leaf whose lists do
-// not fit its slots is listed (run[5] of them) and walked again by a second
+// not fit its slots is listed (in one of kXcds lists by its leaf range,
+// run[11 + range] of them) and walked again by a second
 // pass, which writes its lists after all slots, at offsets from scans of
 // such leaves' counts.
 template <bool OVF>
@@ -612,7 +613,13 @@ __device__ void leaf_lists(const NodeWalkArgs& a, int l, uint32_t* stk) {
       a.m2l_off[v] = e.m2l_base + nm <= a.m2l_cap ? (uint32_t)e.m2l_base : kNoList;
       a.p2p_off[v] = e.p2p_base + np + nq <= a.p2p_cap ? (uint32_t)e.p2p_base : kNoList;
     } else {
-      a.ovf_leaf[atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 5), 1ull)] = (uint32_t)l;
+      // (the list of its range of leaves, the range this XCD walks here and
+      // walks again in the second pass: its lists' sources stay in its L2)
+      const uint32_t seg = ((uint32_t)a.nleaves + kXcds - 1) / kXcds;
+      const uint32_t part = (uint32_t)l / seg;
+      const unsigned long long k =
+          atomicAdd(reinterpret_cast<unsigned long long*>(a.run + 11 + part), 1ull);
+      a.ovf_leaf[(uint64_t)part * seg + k] = (uint32_t)l;
     }
     // lists left for the second pass (none when they fit)
     a.leaf_m2l_cnt[l] = fits ? 0u : nm;
@@ -635,8 +642,13 @@ constexpr unsigned kOvfWaves = 4096;
 
 __global__ __launch_bounds__(64) void k_nodewalk_leaves_ovf(NodeWalkArgs a) {
   extern __shared__ uint32_t stk[];
-  const uint64_t nov = a.run[5];
-  for (uint64_t i = blockIdx.x; i < nov; i += gridDim.x) leaf_lists<true>(a, (int)a.ovf_leaf[i], stk);
+  // block b runs on XCD b % kXcds (the hardware's round-robin) and takes
+  // that range's list
+  const uint32_t part = blockIdx.x % kXcds, stride = gridDim.x / kXcds;
+  const uint32_t seg = ((uint32_t)a.nleaves + kXcds - 1) / kXcds;
+  const uint64_t nov = a.run[11 + part];
+  for (uint64_t i = blockIdx.x / kXcds; i < nov; i += stride)
+    leaf_lists<true>(a, (int)a.ovf_leaf[(uint64_t)part * seg + i], stk);
 }
 
 __global__ void k_leaf_stats(LeafStatArgs a) {
@@ -768,7 +780,8 @@ void launch_nodewalk_leaves(const NodeWalkArgs& a, uint32_t* scan_tmp, hipStream
                reinterpret_cast<uint64_t*>(scan_tmp), s);
   // P2P work items: item_off[nleaves] = their total (read back with the walk's)
   scan_u32(a.item_cnt, a.item_off, a.nleaves, a.item_off + a.nleaves, scan_tmp, s);
-  k_nodewalk_leaves_ovf<<<std::min<unsigned>(kOvfWaves, (unsigned)a.nleaves), 64, lds, s>>>(a);
+  const unsigned ng = std::min<unsigned>(kOvfWaves, ((unsigned)a.nleaves + kXcds - 1) / kXcds * kXcds);
+  k_nodewalk_leaves_ovf<<<ng, 64, lds, s>>>(a);
 }
 
 }  // namespace sfmm

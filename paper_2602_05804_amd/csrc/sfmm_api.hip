@@ -57,7 +57,7 @@ struct Readback {
   int status[4];
   uint32_t level_off[kMaxDepthCap + 2];
   uint32_t level_int[kMaxDepthCap + 2];
-  uint64_t walk_tot[11];
+  uint64_t walk_tot[11 + kXcds];
   uint32_t items;
 };
 
@@ -505,7 +505,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
                              B_NEXP};
   for (int id : node_arrays)
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * nn))) return rc;
-  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * 11))) return rc;
+  if ((rc = ensure(ctx, B_WALKTOT, sizeof(uint64_t) * (11 + kXcds)))) return rc;
   if ((rc = ensure_item_buffers(ctx))) return rc;
   for (int id : {B_LWM2LCNT, B_LWP2PCNT, B_OVFLEAF})
     if ((rc = ensure(ctx, id, sizeof(uint32_t) * std::max(nl, 1)))) return rc;
@@ -545,7 +545,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     if ((rc = ensure(ctx, B_M2LPOOL, sizeof(uint32_t) * ctx->m2l_cap))) return rc;
     if ((rc = ensure(ctx, B_P2PPOOL, sizeof(uint32_t) * ctx->p2p_cap))) return rc;
     uint64_t* tot = P<uint64_t>(ctx, B_WALKTOT);
-    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * 11, s));
+    HIPCHK(hipMemsetAsync(tot, 0, sizeof(uint64_t) * (11 + kXcds), s));
     HIPCHK(hipMemsetAsync(status, 0, sizeof(int), s));
     if (ctx->check_pools) {
       // every entry a consumer reads must then come from this walk: clear
@@ -631,6 +631,8 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
     const bool arena_over = htot[0] > int_big;
     const bool pool_over = m2l_used > ctx->m2l_cap || p2p_used > ctx->p2p_cap || arena_over;
     const bool stack_over = (hstatus[0] & ST_OVERFLOW) != 0;
+    uint64_t ovf_total = 0;  // leaves walked a second time
+    for (unsigned q = 0; q < kXcds; ++q) ovf_total += htot[11 + q];
     if (!pool_over && !stack_over) {
       if (hstatus[0] & ST_BADLIST)
         return fail(ctx, SFMM_EDEVICE, "an interaction list lies outside what the walk wrote");
@@ -638,7 +640,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       ctx->m2l_unique = htot[1];
       ctx->walk_slot_m = slot_m;
       ctx->walk_slot_p = slot_p;
-      ctx->leaf_overflow = htot[5];
+      ctx->leaf_overflow = ovf_total;
       ctx->max_leaf_m = htot[6];
       ctx->max_leaf_p = htot[7];
       // slots for the next walk: the normal ones doubled while more than
@@ -664,7 +666,7 @@ int walk_levels(sfmm_ctx* ctx, double theta) {
       // normal slots double while more than 1/32 of the leaves (or internal
       // nodes) outgrow them, unless that would fill more than half of the
       // largest pool: then this walk's slots stay
-      if ((asked + htot[5]) * 32 > (uint64_t)nl) {
+      if ((asked + ovf_total) * 32 > (uint64_t)nl) {
         sm = std::min(kSlotMax, 2 * sm);
         sp = std::min(kSlotMax / 2, 2 * sp);
       }

@@ -206,12 +206,13 @@ struct NodeWalkArgs {
   // start at leaf_base = int_nodes * int_slot + int_big
   uint32_t int_slot, int_nodes;
   uint64_t int_big, leaf_base;
-  uint64_t* run;      // [11] arena entries taken by internal nodes, M2L entries proper (the
-                      // walk's sum), P2P pool used after the leaf slots, M2L pool
-                      // used after the leaf slots, P2P entries proper, leaves whose
-                      // lists did not fit their slots, the longest M2L and P2P
-                      // lists of a leaf, large M2L and P2P slots asked for,
-                      // internal nodes in the arena
+  uint64_t* run;      // [11 + kXcds] arena entries taken by internal nodes, M2L
+                      // entries proper (the walk's sum), P2P pool used after the
+                      // leaf slots, M2L pool used after the leaf slots, P2P entries
+                      // proper, (unused), the longest M2L and P2P lists of a leaf,
+                      // large M2L and P2P slots asked for, internal nodes in the
+                      // arena, then the leaves of each of kXcds leaf ranges whose
+                      // lists did not fit their slots
   // leaves (walked after all levels, in leaf order): fixed slots of slot_m M2L
   // and slot_p P2P entries per leaf, then nbig large slots of big_m and big_p
   // entries for leaves that outgrow theirs (big_plain: [nbig * big_p] staging
